@@ -1,0 +1,563 @@
+/*
+ * Integral-histogram CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, obviously-correct CPU
+ * implementation of what the GPU path computes, written directly from the
+ * thesis's definitions (Poostchi 2017, arXiv:1711.01656).  Only the tests,
+ * the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product library never links, calls or includes anything here, and nothing
+ * here includes anything from the product.
+ *
+ * Conventions (readings of the thesis, each stated where it is used):
+ *   - image: C planar channels of H x W unsigned integers (8- or 16-bit);
+ *   - plane p = ch * bins + bin; the integral histogram is P x H x W, bin-major
+ *     row-major (Sec. 5.1.1, Fig. 5.1);
+ *   - rectangles are half-open [r0, r1) x [c0, c1) in (row, col), the row being
+ *     the thesis's x and the column its y (Fig. 2.8 caption, Alg. 5).
+ *
+ * Parity status: every function below is pinned by tests in tests/ against
+ * brute force, closed forms or invariants.  No function is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_ERR_ARG (-1)
+#define OR_ERR_RANGE (-2)
+#define OR_ERR_OVERFLOW (-3)
+
+#define OR_U8 0
+#define OR_U16 1
+
+#define OR_CHI2 0
+#define OR_L1 1
+#define OR_PMK 2
+
+/* ------------------------------------------------------------------------ */
+/* Binning Q (Eq. 2.15: Q(I(r,c), b) is 1 when the pixel value falls in bin  */
+/* b).  The thesis leaves the bin edges open; the reading used everywhere    */
+/* here is equal-width bins over the full integer range of a `bits`-bit      */
+/* value: bin(v) = floor(v * bins / 2^bits).                                 */
+/* ------------------------------------------------------------------------ */
+static uint32_t or_value(const void *img, int dtype, int64_t idx) {
+  if (dtype == OR_U8) return ((const uint8_t *)img)[idx];
+  return ((const uint16_t *)img)[idx];
+}
+
+static int or_bin_of(uint32_t v, int bins, int bits) {
+  return (int)(((uint64_t)v * (uint64_t)bins) >> bits);
+}
+
+/* Q(k, I(r, c)) for plane k of channel ch: 1 if the pixel's bin is k. */
+static int or_Q(const void *img, int dtype, int H, int W, int bins, int bits,
+                int p, int r, int c) {
+  int ch = p / bins, k = p % bins;
+  uint32_t v = or_value(img, dtype, ((int64_t)ch * H + r) * W + c);
+  return or_bin_of(v, bins, bits) == k;
+}
+
+static int or_check(int dtype, int H, int W, int C, int bins, int bits) {
+  if (H < 1 || W < 1 || C < 1 || bins < 1) return OR_ERR_ARG;
+  if (dtype != OR_U8 && dtype != OR_U16) return OR_ERR_ARG;
+  if (bits < 1 || bits > (dtype == OR_U8 ? 8 : 16)) return OR_ERR_ARG;
+  if (bins > (1 << bits)) return OR_ERR_ARG;
+  return OR_OK;
+}
+
+/* Every pixel value must lie below 2^bits (otherwise its bin is >= bins). */
+int or_check_values(const void *img, int dtype, int H, int W, int C, int bits) {
+  int64_t n = (int64_t)C * H * W;
+  for (int64_t i = 0; i < n; i++)
+    if ((or_value(img, dtype, i) >> bits) != 0) return OR_ERR_RANGE;
+  return OR_OK;
+}
+
+/* Bin index of every pixel (the per-pixel plane index ch*bins + bin). */
+int or_plane_index(const void *img, int dtype, int H, int W, int C, int bins,
+                   int bits, int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  for (int ch = 0; ch < C; ch++)
+    for (int64_t i = 0; i < (int64_t)H * W; i++)
+      out[(int64_t)ch * H * W + i] =
+          ch * bins + or_bin_of(or_value(img, dtype, (int64_t)ch * H * W + i), bins, bits);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integral histogram, sequential recurrence (Alg. 5):                       */
+/*   H(k,x,y) = H(k,x-1,y) + H(k,x,y-1) - H(k,x-1,y-1) + Q(k, I(x,y)),        */
+/* with H(k,-1,.) = H(k,.,-1) = 0, i.e. the inclusive form of Eq. 2.15.      */
+/* Accumulated in int64 and range-checked into int32.                        */
+/* ------------------------------------------------------------------------ */
+int or_ih_plane(const void *img, int dtype, int H, int W, int C, int bins,
+                int bits, int p, int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (p < 0 || p >= C * bins) return OR_ERR_ARG;
+  int64_t *prev = (int64_t *)calloc((size_t)W, sizeof(int64_t));
+  int64_t *cur = (int64_t *)calloc((size_t)W, sizeof(int64_t));
+  if (!prev || !cur) { free(prev); free(cur); return OR_ERR_ARG; }
+  int rc = OR_OK;
+  for (int x = 0; x < H; x++) {
+    for (int y = 0; y < W; y++) {
+      int64_t up = prev[y];                     /* H(k, x-1, y)   */
+      int64_t left = (y > 0) ? cur[y - 1] : 0;  /* H(k, x, y-1)   */
+      int64_t diag = (y > 0) ? prev[y - 1] : 0; /* H(k, x-1, y-1) */
+      cur[y] = up + left - diag + or_Q(img, dtype, H, W, bins, bits, p, x, y);
+      if (cur[y] > INT32_MAX) rc = OR_ERR_OVERFLOW;
+      out[(int64_t)x * W + y] = (int32_t)cur[y];
+    }
+    int64_t *t = prev; prev = cur; cur = t;
+  }
+  free(prev); free(cur);
+  return rc;
+}
+
+/* All P = C*bins planes, bin-major P x H x W (Fig. 5.1). */
+int or_ih(const void *img, int dtype, int H, int W, int C, int bins, int bits,
+          int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  int P = C * bins, rc = OR_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int p = 0; p < P; p++) {
+    int r = or_ih_plane(img, dtype, H, W, C, bins, bits, p,
+                        out + (int64_t)p * H * W);
+    if (r) {
+#pragma omp critical
+      rc = r;
+    }
+  }
+  return rc;
+}
+
+/* Eq. 2.15 written out as the double sum, for tiny images only. */
+int or_ih_bruteforce(const void *img, int dtype, int H, int W, int C, int bins,
+                     int bits, int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  for (int p = 0; p < C * bins; p++)
+    for (int x = 0; x < H; x++)
+      for (int y = 0; y < W; y++) {
+        int64_t s = 0;
+        for (int r = 0; r <= x; r++)
+          for (int c = 0; c <= y; c++) s += or_Q(img, dtype, H, W, bins, bits, p, r, c);
+        out[((int64_t)p * H + x) * W + y] = (int32_t)s;
+      }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coordinate-moment integral histograms.  Eq. 3.4 builds weighted integral  */
+/* histograms IH_w(x,y,b) = sum_{i<=x, j<=y} delta(Q(f(i,j)) - b) w(i,j) for  */
+/* weights that are affine in (i, j); the weights 1, i and j span all of     */
+/* them, so the count IH plus these two moment IHs carry the same data:      */
+/*   Mx(k,x,y) = sum_{r<=x, c<=y} r * Q(k, I(r,c))                            */
+/*   My(k,x,y) = sum_{r<=x, c<=y} c * Q(k, I(r,c))                            */
+/* Same recurrence as Alg. 5 with the increment weighted; int64.             */
+/* ------------------------------------------------------------------------ */
+int or_moments_plane(const void *img, int dtype, int H, int W, int C, int bins,
+                     int bits, int p, int64_t *mx, int64_t *my) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (p < 0 || p >= C * bins) return OR_ERR_ARG;
+  for (int x = 0; x < H; x++)
+    for (int y = 0; y < W; y++) {
+      int64_t q = or_Q(img, dtype, H, W, bins, bits, p, x, y);
+      int64_t i = (int64_t)x * W + y;
+      int64_t ux = x > 0 ? mx[i - W] : 0, lx = y > 0 ? mx[i - 1] : 0,
+              dx = (x > 0 && y > 0) ? mx[i - W - 1] : 0;
+      int64_t uy = x > 0 ? my[i - W] : 0, ly = y > 0 ? my[i - 1] : 0,
+              dy = (x > 0 && y > 0) ? my[i - W - 1] : 0;
+      mx[i] = ux + lx - dx + (int64_t)x * q;
+      my[i] = uy + ly - dy + (int64_t)y * q;
+    }
+  return OR_OK;
+}
+
+int or_moments(const void *img, int dtype, int H, int W, int C, int bins,
+               int bits, int64_t *mx, int64_t *my) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int p = 0; p < P; p++)
+    or_moments_plane(img, dtype, H, W, C, bins, bits, p,
+                     mx + (int64_t)p * H * W, my + (int64_t)p * H * W);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Region histogram from four corners (Eq. 2.16):                            */
+/*   h(R,b) = H(r+,c+) - H(r-,c+) - H(r+,c-) + H(r-,c-).                     */
+/* With the inclusive H of Eq. 2.15, r+/c+ are the last row/column inside R  */
+/* and r-/c- the row/column just outside it; index -1 reads 0.  Rectangles   */
+/* are half-open {r0, c0, r1, c1}; empty ones give zeros; rectangles outside  */
+/* the frame give -1 in every plane.                                          */
+/* ------------------------------------------------------------------------ */
+static int64_t or_at32(const int32_t *t, int H, int W, int p, int r, int c) {
+  if (r < 0 || c < 0) return 0;
+  return t[((int64_t)p * H + r) * W + c];
+}
+
+static int or_rect_ok(const int32_t *q, int H, int W) {
+  return q[0] >= 0 && q[1] >= 0 && q[0] <= q[2] && q[1] <= q[3] && q[2] <= H &&
+         q[3] <= W;
+}
+
+int or_query_rect(const int32_t *ih, int P, int H, int W, const int32_t *rects,
+                  int64_t n, int32_t *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    for (int p = 0; p < P; p++) {
+      if (!or_rect_ok(q, H, W)) { out[i * P + p] = -1; continue; }
+      if (q[0] == q[2] || q[1] == q[3]) { out[i * P + p] = 0; continue; }
+      int rp = q[2] - 1, cp = q[3] - 1, rm = q[0] - 1, cm = q[1] - 1;
+      int64_t v = or_at32(ih, H, W, p, rp, cp) - or_at32(ih, H, W, p, rm, cp) -
+                  or_at32(ih, H, W, p, rp, cm) + or_at32(ih, H, W, p, rm, cm);
+      out[i * P + p] = (int32_t)v;
+    }
+  }
+  return OR_OK;
+}
+
+/* The region histogram by direct counting (what Eq. 2.16 stands for). */
+int or_query_rect_direct(const void *img, int dtype, int H, int W, int C,
+                         int bins, int bits, const int32_t *rects, int64_t n,
+                         int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    int ok = or_rect_ok(q, H, W);
+    for (int p = 0; p < P; p++) out[i * P + p] = ok ? 0 : -1;
+    if (!ok) continue;
+    for (int ch = 0; ch < C; ch++)
+      for (int r = q[0]; r < q[2]; r++)
+        for (int c = q[1]; c < q[3]; c++) {
+          uint32_t v = or_value(img, dtype, ((int64_t)ch * H + r) * W + c);
+          out[i * P + ch * bins + or_bin_of(v, bins, bits)] += 1;
+        }
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spatially weighted local histogram (Eq. 3.1) with the Manhattan kernel    */
+/* (Eq. 3.3).  The thesis gives no constants; the reading used here: for a   */
+/* window of h rows and w columns with centre (xc, yc) = ((r0+r1-1)/2,        */
+/* (c0+c1-1)/2) (a half-pixel centre for even sides)                         */
+/*   w(x,y) = 1 - ( |x - xc| / (h/2) + |y - yc| / (w/2) ) / 2,   in (0, 1].   */
+/* Its integer form is N(x,y) / (2hw) with                                   */
+/*   N(x,y) = 2hw - w*|2x - X| - h*|2y - Y|,  X = r0+r1-1, Y = c0+c1-1.       */
+/* With l1norm the histogram of each channel is divided by the sum of the    */
+/* weights over the window instead of being left unnormalised.               */
+/* ------------------------------------------------------------------------ */
+
+/* Brute force (Sec. 3.1.1) in FP64, from the real-valued kernel. */
+int or_weighted_bruteforce(const void *img, int dtype, int H, int W, int C,
+                           int bins, int bits, const int32_t *rects, int64_t n,
+                           int l1norm, double *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    double *o = out + i * P;
+    int ok = or_rect_ok(q, H, W);
+    for (int p = 0; p < P; p++) o[p] = ok ? 0.0 : NAN;
+    if (!ok || q[0] == q[2] || q[1] == q[3]) continue;
+    double h = q[2] - q[0], w = q[3] - q[1];
+    double xc = (q[0] + q[2] - 1) / 2.0, yc = (q[1] + q[3] - 1) / 2.0;
+    double wsum = 0.0;
+    for (int r = q[0]; r < q[2]; r++)
+      for (int c = q[1]; c < q[3]; c++)
+        wsum += 1.0 - 0.5 * (fabs(r - xc) / (h / 2.0) + fabs(c - yc) / (w / 2.0));
+    for (int ch = 0; ch < C; ch++) {
+      for (int r = q[0]; r < q[2]; r++)
+        for (int c = q[1]; c < q[3]; c++) {
+          double wt = 1.0 - 0.5 * (fabs(r - xc) / (h / 2.0) + fabs(c - yc) / (w / 2.0));
+          uint32_t v = or_value(img, dtype, ((int64_t)ch * H + r) * W + c);
+          o[ch * bins + or_bin_of(v, bins, bits)] += wt;
+        }
+      if (l1norm)
+        for (int b = 0; b < bins; b++) o[ch * bins + b] /= wsum;
+    }
+  }
+  return OR_OK;
+}
+
+/* Brute-force integer numerators sum_{(x,y) in T, bin = b} N(x,y). */
+int or_weighted_numerator(const void *img, int dtype, int H, int W, int C,
+                          int bins, int bits, const int32_t *rects, int64_t n,
+                          int64_t *num) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    for (int p = 0; p < P; p++) num[i * P + p] = 0;
+    if (!or_rect_ok(q, H, W)) continue;
+    int64_t h = q[2] - q[0], w = q[3] - q[1];
+    int64_t X = q[0] + q[2] - 1, Y = q[1] + q[3] - 1;
+    for (int ch = 0; ch < C; ch++)
+      for (int r = q[0]; r < q[2]; r++)
+        for (int c = q[1]; c < q[3]; c++) {
+          int64_t N = 2 * h * w - w * llabs(2 * (int64_t)r - X) - h * llabs(2 * (int64_t)c - Y);
+          uint32_t v = or_value(img, dtype, ((int64_t)ch * H + r) * W + c);
+          num[i * P + ch * bins + or_bin_of(v, bins, bits)] += N;
+        }
+  }
+  return OR_OK;
+}
+
+/*
+ * SWIH (Sec. 3.1.3), following the thesis's steps in order:
+ *  (1) the Manhattan kernel is split into four quadrants TL, TR, BL, BR at
+ *      rm = r0 + floor(h/2), cm = c0 + floor(w/2); inside each quadrant the
+ *      signs of (2x - X) and (2y - Y) are fixed, so the weight is affine in
+ *      (x, y) there (the four "direction" weights of Eq. 3.4);
+ *  (2) the weighted integral histograms are the count IH and the two moment
+ *      IHs (their span contains every affine weight);
+ *  (3) each quadrant's weighted histogram is read from them with Eq. 2.16
+ *      and translated to the window centre:
+ *        sum_q N = 2hw*n - w*sx*(2*Sx - X*n) - h*sy*(2*Sy - Y*n),
+ *      sx = +1 below the centre row split, -1 above; likewise sy;
+ *  (4) normalisation: divide by 2hw (the kernel's peak), or with l1norm by
+ *      the channel's total weight; division in FP64, rounded to FP32;
+ *  (5) the four quadrant histograms are added.
+ * The integer numerator is also returned for exactness checks.
+ */
+static int64_t or_rect64(const int64_t *t, int H, int W, int p, int r0, int c0,
+                         int r1, int c1) {
+  if (r0 >= r1 || c0 >= c1) return 0;
+#define OR_AT(r, c) (((r) < 0 || (c) < 0) ? 0 : t[((int64_t)p * H + (r)) * W + (c)])
+  return OR_AT(r1 - 1, c1 - 1) - OR_AT(r0 - 1, c1 - 1) - OR_AT(r1 - 1, c0 - 1) +
+         OR_AT(r0 - 1, c0 - 1);
+#undef OR_AT
+}
+
+static int64_t or_rect32(const int32_t *t, int H, int W, int p, int r0, int c0,
+                         int r1, int c1) {
+  if (r0 >= r1 || c0 >= c1) return 0;
+  return or_at32(t, H, W, p, r1 - 1, c1 - 1) - or_at32(t, H, W, p, r0 - 1, c1 - 1) -
+         or_at32(t, H, W, p, r1 - 1, c0 - 1) + or_at32(t, H, W, p, r0 - 1, c0 - 1);
+}
+
+int or_weighted_swih(const int32_t *ih, const int64_t *mx, const int64_t *my,
+                     int P, int H, int W, int C, const int32_t *rects,
+                     int64_t n, int l1norm, int64_t *num, float *out) {
+  if (C < 1 || P % C != 0) return OR_ERR_ARG;
+  int bins = P / C;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    int ok = or_rect_ok(q, H, W);
+    int64_t h = q[2] - q[0], w = q[3] - q[1];
+    for (int p = 0; p < P; p++) {
+      num[i * P + p] = 0;
+      out[i * P + p] = ok ? 0.0f : NAN;
+    }
+    if (!ok || h == 0 || w == 0) continue;
+    int64_t X = q[0] + q[2] - 1, Y = q[1] + q[3] - 1;
+    int rm = q[0] + (int)(h / 2), cm = q[1] + (int)(w / 2);
+    /* quadrant bounds and the signs of (2x-X), (2y-Y) inside them */
+    int qr0[4] = {q[0], q[0], rm, rm}, qr1[4] = {rm, rm, q[2], q[2]};
+    int qc0[4] = {q[1], cm, q[1], cm}, qc1[4] = {cm, q[3], cm, q[3]};
+    int sx[4] = {-1, -1, +1, +1}, sy[4] = {-1, +1, -1, +1};
+    /* the channel's total weight: sum over the window of N(x,y) */
+    int64_t total = 0;
+    for (int64_t r = q[0]; r < q[2]; r++)
+      for (int64_t c = q[1]; c < q[3]; c++)
+        total += 2 * h * w - w * llabs(2 * r - X) - h * llabs(2 * c - Y);
+    for (int p = 0; p < P; p++) {
+      int64_t acc = 0;
+      for (int k = 0; k < 4; k++) {
+        int64_t cnt = or_rect32(ih, H, W, p, qr0[k], qc0[k], qr1[k], qc1[k]);
+        int64_t Sx = or_rect64(mx, H, W, p, qr0[k], qc0[k], qr1[k], qc1[k]);
+        int64_t Sy = or_rect64(my, H, W, p, qr0[k], qc0[k], qr1[k], qc1[k]);
+        acc += 2 * h * w * cnt - w * sx[k] * (2 * Sx - X * cnt) -
+               h * sy[k] * (2 * Sy - Y * cnt);
+      }
+      num[i * P + p] = acc;
+      double den = l1norm ? (double)total : (double)(2 * h * w);
+      out[i * P + p] = (float)((double)acc / den);
+    }
+  }
+  (void)bins;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spatial pyramid descriptor (Alg. 2; layout per Sec. 2.4.4).               */
+/* Level l has 2^l x 2^l cells; cell (i, j) of a window at (r, c) with h     */
+/* rows and w columns covers rows [r + floor(i*h/2^l), r + floor((i+1)*h/2^l))*/
+/* and the same for columns.  The descriptor concatenates, level by level    */
+/* (coarse first), the cells in row-major order, each cell's P-plane counts. */
+/* Alg. 2 as printed accumulates sub-histograms into one sum; the            */
+/* concatenation of Sec. 2.4.4 (dimension k * sum_l 4^l) is followed here.   */
+/* windows: {r, c, h, w}.                                                    */
+/* ------------------------------------------------------------------------ */
+static int or_cells(int levels) {
+  int n = 0;
+  for (int l = 0; l < levels; l++) n += 1 << (2 * l);
+  return n;
+}
+
+static int or_win_ok(const int32_t *q, int H, int W) {
+  return q[2] >= 1 && q[3] >= 1 && q[0] >= 0 && q[1] >= 0 && q[0] + q[2] <= H &&
+         q[1] + q[3] <= W;
+}
+
+int or_pyramid_desc(const int32_t *ih, int P, int H, int W, const int32_t *wins,
+                    int64_t n, int levels, int32_t *out) {
+  if (levels < 1 || levels > 4) return OR_ERR_ARG;
+  int D = or_cells(levels) * P;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = wins + 4 * i;
+    int32_t *o = out + i * D;
+    int ok = or_win_ok(q, H, W), cell = 0;
+    for (int l = 0; l < levels; l++) {
+      int s = 1 << l;
+      for (int a = 0; a < s; a++)
+        for (int b = 0; b < s; b++, cell++) {
+          int r0 = q[0] + (int)((int64_t)a * q[2] / s), r1 = q[0] + (int)((int64_t)(a + 1) * q[2] / s);
+          int c0 = q[1] + (int)((int64_t)b * q[3] / s), c1 = q[1] + (int)((int64_t)(b + 1) * q[3] / s);
+          for (int p = 0; p < P; p++)
+            o[cell * P + p] = ok ? (int32_t)or_rect32(ih, H, W, p, r0, c0, r1, c1) : -1;
+        }
+    }
+  }
+  return OR_OK;
+}
+
+/* The same descriptor by direct counting on the image. */
+int or_pyramid_desc_direct(const void *img, int dtype, int H, int W, int C,
+                           int bins, int bits, const int32_t *wins, int64_t n,
+                           int levels, int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (levels < 1 || levels > 4) return OR_ERR_ARG;
+  int P = C * bins, D = or_cells(levels) * P;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = wins + 4 * i;
+    int32_t *o = out + i * D;
+    int ok = or_win_ok(q, H, W), cell = 0;
+    for (int d = 0; d < D; d++) o[d] = ok ? 0 : -1;
+    if (!ok) continue;
+    for (int l = 0; l < levels; l++) {
+      int s = 1 << l;
+      for (int a = 0; a < s; a++)
+        for (int b = 0; b < s; b++, cell++) {
+          int r0 = q[0] + (int)((int64_t)a * q[2] / s), r1 = q[0] + (int)((int64_t)(a + 1) * q[2] / s);
+          int c0 = q[1] + (int)((int64_t)b * q[3] / s), c1 = q[1] + (int)((int64_t)(b + 1) * q[3] / s);
+          for (int ch = 0; ch < C; ch++)
+            for (int r = r0; r < r1; r++)
+              for (int c = c0; c < c1; c++) {
+                uint32_t v = or_value(img, dtype, ((int64_t)ch * H + r) * W + c);
+                o[cell * P + ch * bins + or_bin_of(v, bins, bits)] += 1;
+              }
+        }
+    }
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pyramid distance between two descriptors.                                 */
+/* Level weights come from the pyramid match kernel (Eq. 2.24):              */
+/*   level 0 -> 1/2^L, level l >= 1 -> 1/2^(L-l+1),  L = levels - 1.         */
+/* Metrics:                                                                  */
+/*   CHI2: sum_l w_l sum_{cells, planes} (a-b)^2/(a+b), 0/0 := 0 (raw counts;  */
+/*         the thesis names chi-square nowhere, this is the reading used);   */
+/*   L1:   sum_l w_l sum |a-b|  (Eq. 2.22 with p = 1);                        */
+/*   PMK:  sum_l w_l sum min(a,b)  (Eq. 2.23-2.24), a similarity.            */
+/* ------------------------------------------------------------------------ */
+double or_level_weight(int levels, int l) {
+  int L = levels - 1;
+  if (l == 0) return ldexp(1.0, -L);
+  return ldexp(1.0, -(L - l + 1));
+}
+
+double or_pyramid_distance(const int32_t *a, const int32_t *b, int P,
+                           int levels, int metric) {
+  double total = 0.0;
+  int cell = 0;
+  for (int l = 0; l < levels; l++) {
+    double lv = 0.0;
+    for (int k = 0; k < (1 << (2 * l)); k++, cell++)
+      for (int p = 0; p < P; p++) {
+        double x = a[cell * P + p], y = b[cell * P + p];
+        if (metric == OR_CHI2) {
+          if (x + y > 0) lv += (x - y) * (x - y) / (x + y);
+        } else if (metric == OR_L1) {
+          lv += fabs(x - y);
+        } else {
+          lv += x < y ? x : y;
+        }
+      }
+    total += or_level_weight(levels, l) * lv;
+  }
+  return total;
+}
+
+/*
+ * Exhaustive candidate search (Sec. 2.4.3-2.4.4): every candidate window
+ * {origin r, origin c, win_h, win_w} is described by the pyramid descriptor
+ * (direct counting) and compared with the template descriptor.  Candidates
+ * not fully inside the frame score +inf (CHI2, L1) or -inf (PMK) and are
+ * never chosen.  best = the lowest index attaining the minimum (CHI2, L1) or
+ * maximum (PMK); -1 when no candidate is inside the frame.
+ */
+int or_match_direct(const void *img, int dtype, int H, int W, int C, int bins,
+                    int bits, const int32_t *tmpl, int win_h, int win_w,
+                    int levels, const int32_t *origins, int64_t n, int metric,
+                    double *dist, int32_t *best) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (levels < 1 || levels > 4 || win_h < 1 || win_w < 1) return OR_ERR_ARG;
+  int P = C * bins, D = or_cells(levels) * P;
+#pragma omp parallel
+  {
+    int32_t *desc = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+      int32_t w4[4] = {origins[2 * i], origins[2 * i + 1], win_h, win_w};
+      if (!or_win_ok(w4, H, W)) {
+        dist[i] = metric == OR_PMK ? -INFINITY : INFINITY;
+        continue;
+      }
+      or_pyramid_desc_direct(img, dtype, H, W, C, bins, bits, w4, 1, levels, desc);
+      dist[i] = or_pyramid_distance(desc, tmpl, P, levels, metric);
+    }
+    free(desc);
+  }
+  int32_t b = -1;
+  for (int64_t i = 0; i < n; i++) {
+    if (isinf(dist[i])) continue;
+    if (b < 0 || (metric == OR_PMK ? dist[i] > dist[b] : dist[i] < dist[b])) b = (int32_t)i;
+  }
+  *best = b;
+  return OR_OK;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
