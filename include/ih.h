@@ -1,0 +1,221 @@
+/*
+ * ih.h - C ABI of the MI355X (gfx950) integral-histogram library, libih.so.
+ *
+ * The library computes the integral histogram of binned image channels and
+ * the constant-time region descriptors built on it, after Poostchi 2017
+ * (arXiv:1711.01656): the integral histogram (Eq. 2.15, Alg. 5), four-corner
+ * region histograms (Eq. 2.16), spatially weighted local histograms (SWIH,
+ * Eq. 3.1, 3.3, 3.4, Sec. 3.1.3), spatial-pyramid descriptors (Alg. 2,
+ * Sec. 2.4.4) and exhaustive pyramid-distance candidate search (Sec. 2.4.3,
+ * Eq. 2.22-2.24).
+ *
+ * General conventions
+ *   - Every pointer argument named as "device" is GPU memory owned by the
+ *     caller; the library never allocates, never frees and keeps no pointer
+ *     after the call returns.  Scratch memory is a caller-supplied workspace.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Argument errors are detected on the host before anything is
+ *     enqueued; the call then returns a negative IH_ERR_* code, enqueues
+ *     nothing, and ih_last_error() describes the problem.  No call aborts or
+ *     throws.  Problems that only the device can see (an out-of-frame
+ *     rectangle) are reported in-band with the sentinels documented per call.
+ *   - Images are C planar channels of H x W unsigned 8- or 16-bit values.
+ *     A value v of a `value_bits`-bit channel falls into bin
+ *     floor(v * bins / 2^value_bits) (equal-width bins; the thesis leaves the
+ *     edges open, Eq. 2.15's Q).  Plane p = channel * bins + bin; P = C * bins.
+ *   - Integral histograms are P x H x W, bin-major and row-major (Sec. 5.1.1,
+ *     Fig. 5.1), inclusive: H(p, r, c) counts pixels of plane p in rows 0..r
+ *     and columns 0..c (Eq. 2.15).  Rows are the thesis's x, columns its y.
+ *   - Rectangles are half-open {r0, c0, r1, c1}: rows r0..r1-1, columns
+ *     c0..c1-1.
+ */
+#ifndef IH_H
+#define IH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IH_OK 0
+#define IH_ERR_INVALID_ARG (-1) /* a size, pointer or enum is invalid       */
+#define IH_ERR_RANGE (-2)       /* a size exceeds what the format can hold   */
+#define IH_ERR_OVERFLOW (-3)    /* counts would not fit their integer type   */
+#define IH_ERR_UNSUPPORTED (-4) /* valid but not implemented combination     */
+#define IH_ERR_HIP (-5)         /* the HIP runtime reported an error         */
+#define IH_ERR_WORKSPACE (-6)   /* workspace missing or smaller than needed  */
+
+typedef enum { IH_U8 = 0, IH_U16 = 1 } ih_dtype;
+typedef enum { IH_CHI2 = 0, IH_L1 = 1, IH_PMK = 2 } ih_metric;
+typedef enum { IH_MANHATTAN = 0 } ih_kernel;
+
+/* Half-open rectangle: rows [r0, r1), columns [c0, c1). */
+typedef struct {
+  int32_t r0, c0, r1, c1;
+} ih_rect;
+
+/*
+ * Tile shape of the build.  A tile is tile_h rows by 64 * cols_per_lane
+ * columns; each wavefront of the final pass owns one tile and
+ * planes_per_wave consecutive planes of one channel.
+ *   tile_h          in [1, 256]
+ *   cols_per_lane   1, 2 or 4
+ *   planes_per_wave 1, 2, 4, 8 or 16
+ * NULL selects a shape from a built-in heuristic.
+ */
+typedef struct {
+  int32_t tile_h;
+  int32_t cols_per_lane;
+  int32_t planes_per_wave;
+} ih_tile_cfg;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int ih_version(void);
+
+/* Thread-local description of the last error returned on this thread. */
+const char *ih_last_error(void);
+
+/*
+ * Bytes of workspace ih_build needs for this shape (0 on invalid arguments).
+ * moments: non-zero when the coordinate-moment tensors will be requested.
+ */
+size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins,
+                               int32_t moments, const ih_tile_cfg *cfg);
+
+/*
+ * ih_build - integral histogram of a binned image (Eq. 2.15; computed by the
+ * recurrence of Alg. 5 reorganised into tiles; Sec. 5.1 describes the
+ * thesis's own GPU variants).
+ *
+ *   img         device, C x H x W values of type dtype (IH_U8 or IH_U16).
+ *   H, W, C     image rows, columns, channels; H, W, C >= 1 and
+ *               H * W < 2^31.
+ *   bins        bins per channel, 1..256 and at most 2^value_bits.
+ *   value_bits  significant bits per value: 1..8 for IH_U8, 1..16 for
+ *               IH_U16.  Every value must be < 2^value_bits; larger values
+ *               give unspecified (but in-bounds) results.
+ *   ih          device, out: P x H x W int32 integral histogram.
+ *   mom_x,      device, out, both NULL or both non-NULL: P x H x W uint32
+ *   mom_y       coordinate-moment integral histograms
+ *                 Mx(p,r,c) = sum over the same region of row    * [bin = p]
+ *                 My(p,r,c) = sum over the same region of column * [bin = p]
+ *               stored modulo 2^32.  These are the weighted integral
+ *               histograms of Eq. 3.4: every weight affine in the pixel
+ *               coordinates is a combination of 1, row and column.  Region
+ *               sums taken from them (four corners, modulo 2^32) are exact
+ *               whenever the true regional sum is below 2^32.
+ *   cfg         tile shape, or NULL for the heuristic.
+ *   ws          device workspace of ws_bytes >= ih_build_workspace_size().
+ *               Its contents on entry do not matter; they are garbage after.
+ *   stream      hipStream_t.
+ * Returns IH_OK or IH_ERR_*.  Outputs must not overlap the image or ws.
+ */
+int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C,
+             int32_t bins, int32_t value_bits, int32_t *ih, uint32_t *mom_x,
+             uint32_t *mom_y, const ih_tile_cfg *cfg, void *ws,
+             size_t ws_bytes, void *stream);
+
+/*
+ * ih_query_rect - region histograms by four corner lookups (Eq. 2.16):
+ *   h(R, p) = H(r1-1, c1-1) - H(r0-1, c1-1) - H(r1-1, c0-1) + H(r0-1, c0-1)
+ * with H(-1, .) = H(., -1) = 0.
+ *   ih      device, P x H x W int32 from ih_build.
+ *   rects   device, n half-open rectangles.
+ *   out     device, out: n x P int32.  An empty rectangle (r0 == r1 or
+ *           c0 == c1) gives zeros; a rectangle not satisfying
+ *           0 <= r0 <= r1 <= H and 0 <= c0 <= c1 <= W gives -1 in every plane.
+ * n may be 0 (nothing is enqueued).
+ */
+int ih_query_rect(const int32_t *ih, int32_t P, int32_t H, int32_t W,
+                  const ih_rect *rects, int64_t n, int32_t *out, void *stream);
+
+/*
+ * ih_query_weighted - spatially weighted local histograms (Eq. 3.1) with the
+ * Manhattan kernel (Eq. 3.3), in O(1) per window by SWIH (Sec. 3.1.3): the
+ * kernel is split into quadrants in which the weight is affine in the pixel
+ * coordinates, and each quadrant is read from the count and moment integral
+ * histograms (Eq. 3.4) and translated to the window centre.
+ *
+ * Weight of pixel (x, y) in a window of h rows and w columns (the thesis
+ * gives no constants; this is the reading used):
+ *   w(x,y) = 1 - ( |x - xc| / (h/2) + |y - yc| / (w/2) ) / 2,
+ *   xc = (r0 + r1 - 1) / 2,  yc = (c0 + c1 - 1) / 2,
+ * so that w = N(x,y) / (2hw) with the integer
+ *   N(x,y) = 2hw - w |2x - (r0+r1-1)| - h |2y - (c0+c1-1)|.
+ * out(q, p) = sum over the window's pixels of plane p of N, as an exact
+ * int64, divided in FP64 by 2hw (or, when l1_normalize is non-zero, by the
+ * sum of N over the whole window, making each channel sum to 1), rounded to
+ * FP32.
+ *
+ *   ih, mom_x, mom_y  device, from ih_build with moments.
+ *   P, H, W, C        their shape; P must be a multiple of C.
+ *   rects             device, n windows.
+ *   kernel            IH_MANHATTAN.
+ *   out               device, out: n x P float.  Empty windows give zeros;
+ *                     windows outside the frame, or with h * w * max(r1, c1)
+ *                     >= 2^32 (where moment sums could wrap), give NaN.
+ */
+int ih_query_weighted(const int32_t *ih, const uint32_t *mom_x,
+                      const uint32_t *mom_y, int32_t P, int32_t H, int32_t W,
+                      int32_t C, const ih_rect *rects, int64_t n,
+                      int32_t kernel, int32_t l1_normalize, float *out,
+                      void *stream);
+
+/*
+ * ih_pyramid_desc - spatial-pyramid region descriptors (Alg. 2 with the
+ * concatenated layout of Sec. 2.4.4).  Level l (0 <= l < levels) splits the
+ * window into 2^l x 2^l cells; cell (i, j) of window {r, c, h, w} covers
+ * rows [r + floor(i h / 2^l), r + floor((i+1) h / 2^l)) and likewise columns.
+ * The descriptor of a window is the concatenation, level by level (coarse
+ * first), of its cells in row-major order, each holding P int32 counts:
+ * cells(levels) = sum_l 4^l (1, 5, 21, 85) cells.
+ *   wins   device, n x 4 int32 {r, c, h, w}.
+ *   levels 1..4.
+ *   out    device, out: n x cells x P int32; windows not inside the frame
+ *          (h < 1, w < 1, r < 0, c < 0, r + h > H or c + w > W) give -1.
+ */
+int ih_pyramid_desc(const int32_t *ih, int32_t P, int32_t H, int32_t W,
+                    const int32_t *wins, int64_t n, int32_t levels,
+                    int32_t *out, void *stream);
+
+/*
+ * ih_match_candidates - exhaustive sliding-window search (Sec. 2.4.3): the
+ * pyramid descriptor of every candidate window {origins[i], win_h, win_w} is
+ * compared with a template descriptor and the best candidate is selected.
+ * Distances sum over levels with the pyramid-match weights of Eq. 2.24
+ * (level 0: 1/2^L, level l >= 1: 1/2^(L-l+1), L = levels - 1):
+ *   IH_CHI2: sum (a-b)^2 / (a+b) over cells and planes, 0/0 := 0, on raw
+ *            counts (the thesis does not define chi-square; reading used);
+ *            per-term FP32, accumulated in FP64;
+ *   IH_L1:   sum |a-b| (Eq. 2.22, p = 1), exact integer arithmetic;
+ *   IH_PMK:  sum min(a,b) (Eq. 2.23), a similarity, exact integer arithmetic.
+ *   tmpl_desc  device, cells(levels) x P int32 template descriptor, as
+ *              written by ih_pyramid_desc.
+ *   origins    device, n x 2 int32 (row, column) candidate origins.
+ *   dist       device, out: n floats.  Candidates not fully inside the frame
+ *              get +inf (CHI2, L1) or -inf (PMK).
+ *   best       device, out: one int32, the lowest candidate index with the
+ *              smallest distance (largest similarity for IH_PMK), or -1 if
+ *              no candidate lies inside the frame.
+ */
+int ih_match_candidates(const int32_t *ih, int32_t P, int32_t H, int32_t W,
+                        const int32_t *tmpl_desc, int32_t win_h, int32_t win_w,
+                        int32_t levels, const int32_t *origins, int64_t n,
+                        int32_t metric, float *dist, int32_t *best,
+                        void *stream);
+
+/*
+ * ih_profile_events - profiling hook.  When both are non-NULL (hipEvent_t),
+ * every later ih_build on this thread records `start` on its stream just
+ * before its final write-out kernel and `stop` just after it, so that the
+ * caller can time that kernel alone.  Passing NULL, NULL turns it off.
+ */
+int ih_profile_events(void *start, void *stop);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IH_H */

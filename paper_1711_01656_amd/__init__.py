@@ -1,0 +1,22 @@
+"""MI355X-native integral-histogram library (gfx950 HIP kernels behind a C ABI).
+
+Integral histograms, O(1) plain and spatially weighted region histograms,
+spatial-pyramid descriptors and exhaustive pyramid-distance candidate search,
+after Poostchi 2017 (arXiv:1711.01656).  See ``include/ih.h`` for the C ABI
+and ``paper_1711_01656_amd.ih`` for the Python binding.
+"""
+from .ih import (  # noqa: F401
+    IHError,
+    TileCfg,
+    cells,
+    ih_build,
+    ih_match_candidates,
+    ih_profile_events,
+    ih_pyramid_desc,
+    ih_query_rect,
+    ih_query_weighted,
+    lib,
+    lib_path,
+    version,
+    workspace_size,
+)

@@ -1,0 +1,91 @@
+// Internal helpers shared by the gfx950 kernels of libih.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ih.h"
+
+namespace ih {
+
+// ---------------------------------------------------------------- errors --
+int set_error(int code, const char *fmt, ...);
+int hip_check(hipError_t e, const char *what);
+hipStream_t as_stream(void *s);
+
+// ------------------------------------------------------ wave primitives --
+// Inclusive prefix sum across the 64 lanes of a wavefront with DPP:
+// Hillis-Steele shifts inside each 16-lane row (row_shr 1, 2, 4, 8), then the
+// row totals are carried across rows with row_bcast:15 (into rows 1 and 3)
+// and row_bcast:31 (into rows 2 and 3).  Lanes whose DPP source lies outside
+// the row read the `old` operand, 0.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+  return x;
+}
+
+// Number of set bits of `mask` in lanes strictly below this lane, plus acc.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t acc) {
+  acc = __builtin_amdgcn_mbcnt_lo((uint32_t)mask, acc);
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), acc);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) {
+  return __builtin_amdgcn_ballot_w64(p);
+}
+
+__device__ __forceinline__ int uniform(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ uint32_t read_lane(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// -------------------------------------------------------------- vectors --
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+template <int N>
+struct vec_of;
+template <>
+struct vec_of<1> { typedef int type; };
+template <>
+struct vec_of<2> { typedef v2i type; };
+template <>
+struct vec_of<4> { typedef v4i type; };
+
+// Streaming store of N consecutive ints (the integral histogram is written
+// once and read by later kernels, so it should not displace cached data).
+template <int N>
+__device__ __forceinline__ void store_stream(int *dst, const int (&v)[N]) {
+  if constexpr (N == 1) {
+    __builtin_nontemporal_store(v[0], dst);
+  } else if constexpr (N == 2) {
+    v2i t = {v[0], v[1]};
+    __builtin_nontemporal_store(t, reinterpret_cast<v2i *>(dst));
+  } else {
+    v4i t = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(t, reinterpret_cast<v4i *>(dst));
+  }
+}
+
+// -------------------------------------------------------- build geometry --
+struct Geom {
+  int H, W, C, bins, P;
+  int TH, CPL, TW, PG;  // tile rows, columns per lane, tile columns, planes per wave
+  int nTR, nTC;         // tile rows / columns of the grid
+  bool mom;
+  // workspace sections (in 4-byte words)
+  size_t off_cc, off_rc, off_tt, off_ccx, off_rcy, off_ttx, off_tty, words;
+};
+
+int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
+              const ih_tile_cfg *cfg, Geom *g);
+
+}  // namespace ih

@@ -1,0 +1,244 @@
+"""Thin Python binding of libih.so (the C ABI declared in include/ih.h).
+
+Argument marshalling only: every computation runs in the library's gfx950
+kernels.  PyTorch supplies device memory and the current HIP stream.  The
+functions keep the C names (``ih_build``, ``ih_query_rect``, ...).  There is
+no fallback: if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libih.so")
+_lib = None
+
+IH_OK = 0
+IH_U8, IH_U16 = 0, 1
+IH_CHI2, IH_L1, IH_PMK = 0, 1, 2
+IH_MANHATTAN = 0
+METRICS = {"chi2": IH_CHI2, "l1": IH_L1, "pmk": IH_PMK}
+
+# C declarations mirrored from include/ih.h: name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+SIGNATURES = {
+    "ih_version": (ctypes.c_int, []),
+    "ih_last_error": (ctypes.c_char_p, []),
+    "ih_build_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I32, _P]),
+    "ih_build": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "ih_query_rect": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I64, _P, _P]),
+    "ih_query_weighted": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _I64, _I32, _I32, _P, _P]),
+    "ih_pyramid_desc": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I64, _I32, _P, _P]),
+    "ih_match_candidates": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P, _I64, _I32, _P, _P, _P]),
+    "ih_profile_events": (ctypes.c_int, [_P, _P]),
+}
+
+
+class IHError(RuntimeError):
+    pass
+
+
+class TileCfg(ctypes.Structure):
+    _fields_ = [("tile_h", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32),
+                ("planes_per_wave", ctypes.c_int32)]
+
+    def __repr__(self):
+        return "TileCfg(tile_h=%d, cols_per_lane=%d, planes_per_wave=%d)" % (
+            self.tile_h, self.cols_per_lane, self.planes_per_wave)
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libih.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise IHError("libih.so not found at %s; build it with "
+                          "`python -m paper_1711_01656_amd.build`" % _LIB_PATH)
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != IH_OK:
+        raise IHError("%s failed (%d): %s" % (what, rc, lib().ih_last_error().decode()))
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise IHError("%s must be a CUDA (HIP) tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise IHError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise IHError("%s must be contiguous" % name)
+    return t
+
+
+def _p(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def version() -> int:
+    return lib().ih_version()
+
+
+def workspace_size(H, W, C, bins, moments=False, cfg: Optional[TileCfg] = None) -> int:
+    n = lib().ih_build_workspace_size(H, W, C, bins, int(bool(moments)),
+                                      ctypes.byref(cfg) if cfg is not None else None)
+    if n == 0:
+        raise IHError("ih_build_workspace_size: %s" % lib().ih_last_error().decode())
+    return n
+
+
+def ih_build(img: torch.Tensor, bins: int, value_bits: Optional[int] = None, moments: bool = False,
+             cfg: Optional[TileCfg] = None, out: Optional[torch.Tensor] = None,
+             mom_out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+             ws: Optional[torch.Tensor] = None):
+    """Integral histogram of a C x H x W (or H x W) uint8/uint16 image.
+
+    Returns ``ih`` (P x H x W int32) or ``(ih, mom_x, mom_y)`` when ``moments``
+    (moment tensors are int32 views of the uint32 values stored modulo 2^32).
+    """
+    _dev(img, "img")
+    if img.dim() == 2:
+        img = img.unsqueeze(0)
+    if img.dtype == torch.uint8:
+        dt, maxbits = IH_U8, 8
+    elif img.dtype == torch.uint16:
+        dt, maxbits = IH_U16, 16
+    else:
+        raise IHError("img must be uint8 or uint16")
+    C, H, W = img.shape
+    bits = maxbits if value_bits is None else value_bits
+    P = C * bins
+    dev = img.device
+    if out is None:
+        out = torch.empty((P, H, W), dtype=torch.int32, device=dev)
+    _dev(out, "out", torch.int32)
+    mx = my = None
+    if moments:
+        if mom_out is None:
+            mx = torch.empty((P, H, W), dtype=torch.int32, device=dev)
+            my = torch.empty((P, H, W), dtype=torch.int32, device=dev)
+        else:
+            mx, my = mom_out
+        _dev(mx, "mom_x", torch.int32)
+        _dev(my, "mom_y", torch.int32)
+    need = workspace_size(H, W, C, bins, moments, cfg)
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    rc = lib().ih_build(_p(img), dt, H, W, C, bins, bits, _p(out), _p(mx), _p(my),
+                        ctypes.byref(cfg) if cfg is not None else None, _p(ws),
+                        ws.numel() * ws.element_size(), _stream(img))
+    _check(rc, "ih_build")
+    return (out, mx, my) if moments else out
+
+
+def _rects(rects: torch.Tensor, name="rects") -> torch.Tensor:
+    _dev(rects, name, torch.int32)
+    if rects.dim() != 2 or rects.shape[1] != 4:
+        raise IHError("%s must be n x 4 int32" % name)
+    return rects
+
+
+def ih_query_rect(ih: torch.Tensor, rects: torch.Tensor, out: Optional[torch.Tensor] = None):
+    """Eq. 2.16 region histograms: n x P int32."""
+    _dev(ih, "ih", torch.int32)
+    P, H, W = ih.shape
+    _rects(rects)
+    n = rects.shape[0]
+    if out is None:
+        out = torch.empty((n, P), dtype=torch.int32, device=ih.device)
+    _dev(out, "out", torch.int32)
+    _check(lib().ih_query_rect(_p(ih), P, H, W, _p(rects), n, _p(out), _stream(ih)), "ih_query_rect")
+    return out
+
+
+def ih_query_weighted(ih: torch.Tensor, mom_x: torch.Tensor, mom_y: torch.Tensor, C: int,
+                      rects: torch.Tensor, l1_normalize: bool = False,
+                      out: Optional[torch.Tensor] = None):
+    """Manhattan-weighted local histograms (SWIH): n x P float32."""
+    _dev(ih, "ih", torch.int32)
+    _dev(mom_x, "mom_x", torch.int32)
+    _dev(mom_y, "mom_y", torch.int32)
+    P, H, W = ih.shape
+    _rects(rects)
+    n = rects.shape[0]
+    if out is None:
+        out = torch.empty((n, P), dtype=torch.float32, device=ih.device)
+    _dev(out, "out", torch.float32)
+    _check(lib().ih_query_weighted(_p(ih), _p(mom_x), _p(mom_y), P, H, W, C, _p(rects), n,
+                                   IH_MANHATTAN, int(bool(l1_normalize)), _p(out), _stream(ih)),
+           "ih_query_weighted")
+    return out
+
+
+def cells(levels: int) -> int:
+    return sum(4 ** l for l in range(levels))
+
+
+def ih_pyramid_desc(ih: torch.Tensor, wins: torch.Tensor, levels: int = 3,
+                    out: Optional[torch.Tensor] = None):
+    """Spatial-pyramid descriptors of windows {r, c, h, w}: n x cells x P int32."""
+    _dev(ih, "ih", torch.int32)
+    P, H, W = ih.shape
+    _rects(wins, "wins")
+    n = wins.shape[0]
+    if out is None:
+        out = torch.empty((n, cells(levels), P), dtype=torch.int32, device=ih.device)
+    _dev(out, "out", torch.int32)
+    _check(lib().ih_pyramid_desc(_p(ih), P, H, W, _p(wins), n, levels, _p(out), _stream(ih)),
+           "ih_pyramid_desc")
+    return out
+
+
+def ih_match_candidates(ih: torch.Tensor, tmpl_desc: torch.Tensor, win_h: int, win_w: int,
+                        origins: torch.Tensor, levels: int = 3, metric: str = "chi2",
+                        dist: Optional[torch.Tensor] = None, best: Optional[torch.Tensor] = None):
+    """Exhaustive candidate search: (n distances float32, best index int32[1])."""
+    _dev(ih, "ih", torch.int32)
+    P, H, W = ih.shape
+    _dev(tmpl_desc, "tmpl_desc", torch.int32)
+    _dev(origins, "origins", torch.int32)
+    if origins.dim() != 2 or origins.shape[1] != 2:
+        raise IHError("origins must be n x 2 int32")
+    if tmpl_desc.numel() != cells(levels) * P:
+        raise IHError("tmpl_desc must hold cells(levels) * P values")
+    n = origins.shape[0]
+    if dist is None:
+        dist = torch.empty(n, dtype=torch.float32, device=ih.device)
+    if best is None:
+        best = torch.empty(1, dtype=torch.int32, device=ih.device)
+    _dev(dist, "dist", torch.float32)
+    _dev(best, "best", torch.int32)
+    _check(lib().ih_match_candidates(_p(ih), P, H, W, _p(tmpl_desc), win_h, win_w, levels, _p(origins), n,
+                                     METRICS[metric], _p(dist), _p(best), _stream(ih)),
+           "ih_match_candidates")
+    return dist, best
+
+
+def ih_profile_events(start: Optional[torch.cuda.Event], stop: Optional[torch.cuda.Event]):
+    """Record `start`/`stop` around the final write-out kernel of later ih_build calls."""
+    if start is None:
+        _check(lib().ih_profile_events(None, None), "ih_profile_events")
+    else:
+        _check(lib().ih_profile_events(ctypes.c_void_p(start.cuda_event), ctypes.c_void_p(stop.cuda_event)),
+               "ih_profile_events")

@@ -22,21 +22,22 @@ import numpy as np
 def smooth(rng: np.random.Generator, H: int, W: int, cell: int, dtype=np.float32) -> np.ndarray:
     """Bilinear upsampling of a uniform [0,1) lattice with spacing ``cell`` px."""
     gh, gw = H // cell + 2, W // cell + 2
-    lat = rng.random((gh, gw)).astype(np.float64)
+    lat = rng.random((gh, gw)).astype(np.float32)
     ys = np.arange(H, dtype=np.float64) / cell
     xs = np.arange(W, dtype=np.float64) / cell
     y0 = np.floor(ys).astype(np.int64)
     x0 = np.floor(xs).astype(np.int64)
-    fy = (ys - y0)[:, None]
-    fx = (xs - x0)[None, :]
+    fy = (ys - y0).astype(np.float32)[:, None]
+    fx = (xs - x0).astype(np.float32)[None, :]
+    # separable: along columns for every lattice row, then along rows
+    across = lat[:, x0] * (1 - fx) + lat[:, x0 + 1] * fx          # gh x W
     out = np.empty((H, W), dtype)
     step = max(1, (1 << 22) // max(W, 1))
     for a in range(0, H, step):
         b = min(H, a + step)
         yy = y0[a:b]
-        t = lat[yy][:, x0] * (1 - fx) + lat[yy][:, x0 + 1] * fx
-        u = lat[yy + 1][:, x0] * (1 - fx) + lat[yy + 1][:, x0 + 1] * fx
-        out[a:b] = (t * (1 - fy[a:b]) + u * fy[a:b]).astype(dtype)
+        f = fy[a:b]
+        out[a:b] = across[yy] * (1 - f) + across[yy + 1] * f
     return out
 
 

@@ -1,0 +1,101 @@
+"""The C-ABI library loads and exports every symbol include/ih.h declares;
+host-side argument checks return error codes without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ih.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ih_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1711_01656_amd as pkg
+    from paper_1711_01656_amd import build as hipbuild
+    if not os.path.exists(pkg.lib_path()):
+        hipbuild.build()
+    return pkg.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("ih_build", "ih_query_rect", "ih_query_weighted", "ih_match_candidates",
+              "ih_pyramid_desc", "ih_build_workspace_size", "ih_last_error", "ih_version"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_symbol():
+    from paper_1711_01656_amd import ih
+    assert set(declared_functions()) == set(ih.SIGNATURES)
+
+
+def test_version_and_error(lib):
+    assert lib.ih_version() >= 100
+    assert isinstance(lib.ih_last_error(), bytes)
+
+
+def test_workspace_size_host_only(lib):
+    from paper_1711_01656_amd import ih
+    n = ih.workspace_size(480, 640, 1, 32)
+    assert n > 0
+    m = ih.workspace_size(480, 640, 1, 32, moments=True)
+    assert m > n
+    # carries are a small fraction of the 39 MB integral histogram
+    assert n < 0.2 * 480 * 640 * 32 * 4
+    assert lib.ih_build_workspace_size(0, 640, 1, 32, 0, None) == 0
+    assert lib.ih_build_workspace_size(480, 640, 1, 300, 0, None) == 0
+    assert b"bins" in lib.ih_last_error()
+
+
+def test_host_argument_errors(lib):
+    from paper_1711_01656_amd import ih
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    # NULL image
+    assert lib.ih_build(None, 0, 4, 4, 1, 2, 8, fake, None, None, None, fake, 1 << 20, None) == -1
+    # only one moment pointer
+    assert lib.ih_build(fake, 0, 4, 4, 1, 2, 8, fake, fake, None, None, fake, 1 << 20, None) == -1
+    # bad dtype, bad bits, bins beyond 2^bits
+    assert lib.ih_build(fake, 7, 4, 4, 1, 2, 8, fake, None, None, None, fake, 1 << 20, None) == -1
+    assert lib.ih_build(fake, 0, 4, 4, 1, 2, 9, fake, None, None, None, fake, 1 << 20, None) == -1
+    assert lib.ih_build(fake, 0, 4, 4, 1, 8, 2, fake, None, None, None, fake, 1 << 20, None) == -1
+    # too small a workspace
+    assert lib.ih_build(fake, 0, 64, 64, 1, 8, 8, fake, None, None, None, fake, 16, None) == -6
+    # H*W beyond int32 counts
+    assert lib.ih_build(fake, 0, 65536, 65536, 1, 8, 8, fake, None, None, None, fake, 1 << 20, None) == -3
+    # bad tile configurations
+    for cfg in (ih.TileCfg(0, 1, 1), ih.TileCfg(32, 3, 1), ih.TileCfg(32, 1, 3), ih.TileCfg(256, 4, 1)):
+        assert lib.ih_build(fake, 0, 64, 64, 1, 8, 8, fake, None, None, ctypes.byref(cfg), fake,
+                            1 << 30, None) < 0
+    # queries
+    assert lib.ih_query_rect(fake, 0, 4, 4, fake, 1, fake, None) == -1
+    assert lib.ih_query_rect(fake, 2, 4, 4, fake, -1, fake, None) == -1
+    assert lib.ih_query_rect(None, 2, 4, 4, None, 0, None, None) == 0       # nothing to do
+    assert lib.ih_query_weighted(fake, fake, fake, 6, 4, 4, 4, fake, 1, 0, 0, fake, None) == -1
+    assert lib.ih_query_weighted(fake, fake, fake, 8, 4, 4, 1, fake, 1, 9, 0, fake, None) == -4
+    assert lib.ih_pyramid_desc(fake, 8, 4, 4, fake, 1, 5, fake, None) == -1
+    assert lib.ih_match_candidates(fake, 8, 4, 4, fake, 2, 2, 3, fake, 1, 7, fake, fake, None) == -1
+    assert lib.ih_match_candidates(fake, 8, 4, 4, fake, 0, 2, 3, fake, 1, 0, fake, fake, None) == -1
+    assert lib.ih_profile_events(fake, None) == -1
+
+
+def test_product_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_1711_01656_amd")
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dp, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "ih_oracle" not in txt, f
