@@ -3,11 +3,11 @@
 One step = one pass of the whole path over one synthetic 1920x1080 frame with
 7 uint8 feature channels x 16 bins (112 planes):
   1. ih_build with coordinate moments (binning, row/column scans, carries,
-     write-out of three 112 x 1080 x 1920 tensors);
+     write-out of three 112 x 1080 x 1920 int32 tensors);
   2. 100,000 Manhattan-weighted local histograms (SWIH), windows 16-256 px;
   3. 100,000 plain four-corner region histograms over the same windows;
-  4. 3-level pyramid chi-square search of a 32x32 template over a 129 x 129
-     grid of candidate origins.
+  4. a 3-level pyramid descriptor of a 32x32 template and the pyramid
+     chi-square search over a 129 x 129 grid of candidate origins.
 Inputs are resident in HBM before timing.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -33,36 +33,107 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--layout", choices=["hwb", "bhw"], default="hwb",
+                    help="memory layout of the integral histograms for the headline step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
+    ap.add_argument("--no-other", action="store_true", help="skip timing the other layout")
     ap.add_argument("--copy-calib", type=int, default=0,
-                    help="also run one device copy of this many MiB (counter calibration)")
-    ap.add_argument("--tile", type=str, default="", help="tile_h,cols_per_lane,planes_per_wave")
+                    help="also run one device fill and one copy of this many MiB (counter calibration)")
+    ap.add_argument("--tile", type=str, default="", help="tile_h,tile_w,planes_per_wave")
     return ap.parse_args()
 
 
-def cpu_baseline(w, windows_sample=1000):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+def cpu_baseline(w, origins, tmpl_win, min_seconds=10.0):
+    """The oracle, as it stands, on the same workload, repeated for >= min_seconds."""
     import oracle
-    t0 = time.perf_counter()
-    ih = oracle.ih(w.img, w.bins, w.bits)
-    mx, my = oracle.moments(w.img, w.bins, w.bits)
-    t_build = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.weighted_swih(ih, mx, my, w.C, w.windows[:windows_sample])
-    t_q = time.perf_counter() - t0
-    del ih, mx, my
-    n_q = len(w.windows)
-    t_step = t_build + t_q * (n_q / windows_sample)
+    reps, t_build, t_wq, t_rq, t_m = 0, 0.0, 0.0, 0.0, 0.0
+    t_start = time.perf_counter()
+    while reps == 0 or time.perf_counter() - t_start < min_seconds:
+        t0 = time.perf_counter()
+        ih = oracle.ih(w.img, w.bins, w.bits)
+        mx, my = oracle.moments(w.img, w.bins, w.bits)
+        t1 = time.perf_counter()
+        oracle.weighted_swih(ih, mx, my, w.C, w.windows)
+        t2 = time.perf_counter()
+        oracle.query_rect(ih, w.windows)
+        t3 = time.perf_counter()
+        tmpl = oracle.pyramid_desc(ih, [tmpl_win], 3)[0]
+        oracle.match_direct(w.img, w.bins, w.bits, tmpl, 32, 32, 3, origins, "chi2")
+        t4 = time.perf_counter()
+        del ih, mx, my
+        reps += 1
+        t_build += t1 - t0
+        t_wq += t2 - t1
+        t_rq += t3 - t2
+        t_m += t4 - t3
+    t_step = (t_build + t_wq + t_rq + t_m) / reps
     return {
         "value": round(w.H * w.W * w.P / t_step / 1e9, 4),
         "unit": "Gpx·bins/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": ("count + moment integral histograms of the full 1920x1080x112 frame (%.2f s) and "
-                   "%d of the %d weighted queries (%.3f s, scaled x%d); rect queries and matching "
-                   "not included" % (t_build, windows_sample, n_q, t_q, n_q // windows_sample)),
+        "sample": ("the full step (count + moment IHs by the Alg. 5 recurrence, 100k SWIH queries, 100k "
+                   "rect queries, 129x129 pyramid chi2 search) repeated %d times in %.1f s; per step: "
+                   "build %.3f s, weighted %.3f s, rect %.3f s, match %.3f s"
+                   % (reps, t_build + t_wq + t_rq + t_m, t_build / reps, t_wq / reps, t_rq / reps, t_m / reps)),
         "host": platform.processor() or platform.machine(),
     }
+
+
+class Step:
+    """Preallocated buffers and the five calls of one step, in one layout."""
+
+    def __init__(self, ih, torch, w, img, wins, origins, tmpl_win, layout, cfg):
+        dev = img.device
+        self.ih, self.torch, self.layout, self.cfg = ih, torch, layout, cfg
+        self.img, self.wins, self.origins, self.tmpl_win = img, wins, origins, tmpl_win
+        self.C, self.bins, P = w.C, w.bins, w.P
+        shp = ih.shape_of(P, w.H, w.W, layout)
+        self.out = torch.empty(shp, dtype=torch.int32, device=dev)
+        self.mx = torch.empty_like(self.out)
+        self.my = torch.empty_like(self.out)
+        self.ws = torch.empty(ih.workspace_size(w.H, w.W, w.C, w.bins, True, cfg, layout), dtype=torch.uint8,
+                              device=dev)
+        n = wins.shape[0]
+        self.wq = torch.empty((n, P), dtype=torch.float32, device=dev)
+        self.rq = torch.empty((n, P), dtype=torch.int32, device=dev)
+        self.desc = torch.empty((1, 21, P), dtype=torch.int32, device=dev)
+        self.dist = torch.empty(origins.shape[0], dtype=torch.float32, device=dev)
+        self.best = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def build(self):
+        self.ih.ih_build(self.img, self.bins, moments=True, cfg=self.cfg, out=self.out, mom_out=(self.mx, self.my),
+                         ws=self.ws, layout=self.layout)
+
+    def weighted(self):
+        self.ih.ih_query_weighted(self.out, self.mx, self.my, self.C, self.wins, out=self.wq, layout=self.layout)
+
+    def rect(self):
+        self.ih.ih_query_rect(self.out, self.wins, out=self.rq, layout=self.layout)
+
+    def match(self):
+        self.ih.ih_pyramid_desc(self.out, self.tmpl_win, 3, out=self.desc, layout=self.layout)
+        self.ih.ih_match_candidates(self.out, self.desc, 32, 32, self.origins, 3, "chi2", dist=self.dist,
+                                    best=self.best, layout=self.layout)
+
+    def __call__(self):
+        self.build()
+        self.weighted()
+        self.rect()
+        self.match()
+
+
+def time_calls(torch, fn, n):
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(n):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / n
 
 
 def main():
@@ -79,45 +150,32 @@ def main():
     dev = torch.device("cuda:0")
     w = synth.config2()
     rng_win = np.random.default_rng(205)
+    C, H, W, P, bins = w.C, w.H, w.W, w.P, w.bins
     img = torch.from_numpy(w.img).to(dev)
     wins = torch.from_numpy(w.windows).to(dev)
-    C, H, W, P, bins = w.C, w.H, w.W, w.P, w.bins
     cfg = None
     if args.tile:
-        th, cpl, pg = (int(v) for v in args.tile.split(","))
-        cfg = ih.TileCfg(th, cpl, pg)
+        cfg = ih.TileCfg(*(int(v) for v in args.tile.split(",")))
     # template: a 32x32 window of the frame; candidates: 129 x 129 origins around it
     tr = int(rng_win.integers(64, H - 32 - 64))
     tc = int(rng_win.integers(64, W - 32 - 64))
-    origins = torch.from_numpy(synth.grid_origins(tr - 64, tc - 64, 129, 129)).to(dev)
+    origins_np = synth.grid_origins(tr - 64, tc - 64, 129, 129)
+    origins = torch.from_numpy(origins_np).to(dev)
     tmpl_win = torch.tensor([[tr, tc, 32, 32]], dtype=torch.int32, device=dev)
 
-    out = torch.empty((P, H, W), dtype=torch.int32, device=dev)
-    mx = torch.empty_like(out)
-    my = torch.empty_like(out)
-    ws = torch.empty(ih.workspace_size(H, W, C, bins, True, cfg), dtype=torch.uint8, device=dev)
-    wq = torch.empty((len(w.windows), P), dtype=torch.float32, device=dev)
-    rq = torch.empty((len(w.windows), P), dtype=torch.int32, device=dev)
-    desc = torch.empty((1, 21, P), dtype=torch.int32, device=dev)
-    dist = torch.empty(origins.shape[0], dtype=torch.float32, device=dev)
-    best = torch.empty(1, dtype=torch.int32, device=dev)
-
-    def step():
-        ih.ih_build(img, bins, moments=True, cfg=cfg, out=out, mom_out=(mx, my), ws=ws)
-        ih.ih_query_weighted(out, mx, my, C, wins, out=wq)
-        ih.ih_query_rect(out, wins, out=rq)
-        ih.ih_pyramid_desc(out, tmpl_win, 3, out=desc)
-        ih.ih_match_candidates(out, desc, 32, 32, origins, 3, "chi2", dist=dist, best=best)
-
+    step = Step(ih, torch, w, img, wins, origins, tmpl_win, args.layout, cfg)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     print("warmup done", file=sys.stderr, flush=True)
 
-    # timed region; the final write-out kernel of each build is bracketed by
-    # events on the same stream
+    # timed region; the write-out kernel of each build is bracketed by events
+    # recorded by the library on the same stream
     ev_k = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in range(args.steps)]
+    for a, b in ev_k:          # torch creates the HIP event on first record
+        a.record()
+        b.record()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -134,27 +192,22 @@ def main():
     k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_k]))
     print("timed %d steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
 
-    # separate per-stage timing (not part of the headline figure)
-    def time_it(fn, n=5):
-        fn()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(n):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / n
-
-    t_build = time_it(lambda: ih.ih_build(img, bins, moments=True, cfg=cfg, out=out, mom_out=(mx, my), ws=ws))
-    t_wq = time_it(lambda: ih.ih_query_weighted(out, mx, my, C, wins, out=wq))
-    t_rq = time_it(lambda: ih.ih_query_rect(out, wins, out=rq))
-    t_match = time_it(lambda: ih.ih_match_candidates(out, desc, 32, 32, origins, 3, "chi2", dist=dist, best=best))
+    stages = {s: round(time_calls(torch, getattr(step, s), 5), 4) for s in ("build", "weighted", "rect", "match")}
+    stages["final_kernel"] = round(k_ms, 4)
+    other = None
+    if not args.no_other:
+        lo = "bhw" if args.layout == "hwb" else "hwb"
+        so = Step(ih, torch, w, img, wins, origins, tmpl_win, lo, None)
+        oms = time_calls(torch, so, 5)
+        other = {"layout": lo, "ms_per_step": round(oms, 4),
+                 "stages_ms": {s: round(time_calls(torch, getattr(so, s), 5), 4)
+                               for s in ("build", "weighted", "rect", "match")}}
+        del so
 
     if args.copy_calib:
         n = args.copy_calib << 20
-        a = torch.empty(n // 4, dtype=torch.int32, device=dev).fill_(1)
+        a = torch.empty(n // 4, dtype=torch.int32, device=dev)
+        a.fill_(1)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)
@@ -163,6 +216,7 @@ def main():
     alg_bytes = 3 * P * H * W * 4 + C * H * W   # three int32 tensors written, u8 image read
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     gpx = H * W * P / (ms * 1e-3) / 1e9
+    nq = int(wins.shape[0])
     res = {
         "metric": METRIC,
         "value": round(gpx, 3),
@@ -180,18 +234,17 @@ def main():
             "workload": "1920x1080 frame, 7 u8 channels x 16 bins (112 planes), count + 2 moment IHs; "
                         "100k weighted + 100k plain window queries (16-256 px); 129x129 pyramid chi2 search",
             "H": H, "W": W, "channels": C, "bins_per_channel": bins, "planes": P,
-            "weighted_queries": len(w.windows), "rect_queries": len(w.windows),
-            "candidates": int(origins.shape[0]), "tile": str(cfg) if cfg else "heuristic",
+            "weighted_queries": nq, "rect_queries": nq, "candidates": int(origins.shape[0]),
+            "layout": args.layout, "tile": repr(cfg) if cfg else "heuristic",
         },
-        "stages_ms": {"build": round(t_build, 4), "final_kernel": round(k_ms, 4),
-                      "weighted_queries": round(t_wq, 4), "rect_queries": round(t_rq, 4),
-                      "match": round(t_match, 4)},
-        "build_gpxbins_per_s": round(H * W * P / (t_build * 1e-3) / 1e9, 3),
-        "weighted_queries_per_s": round(len(w.windows) / (t_wq * 1e-3), 1),
-        "rect_queries_per_s": round(len(w.windows) / (t_rq * 1e-3), 1),
+        "stages_ms": stages,
+        "build_gpxbins_per_s": round(H * W * P / (stages["build"] * 1e-3) / 1e9, 3),
+        "weighted_queries_per_s": round(nq / (stages["weighted"] * 1e-3), 1),
+        "rect_queries_per_s": round(nq / (stages["rect"] * 1e-3), 1),
+        "other_layout": other,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_final (integral-histogram write-out, with moments)",
+            "kernel": "integral-histogram write-out (%s, with moments)" % args.layout,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -202,7 +255,7 @@ def main():
     }
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(w)
+        res["cpu_baseline"] = cpu_baseline(w, origins_np, (tr, tc, 32, 32))
     print(json.dumps(res), flush=True)
 
 

@@ -23,9 +23,11 @@
  *     A value v of a `value_bits`-bit channel falls into bin
  *     floor(v * bins / 2^value_bits) (equal-width bins; the thesis leaves the
  *     edges open, Eq. 2.15's Q).  Plane p = channel * bins + bin; P = C * bins.
- *   - Integral histograms are P x H x W, bin-major and row-major (Sec. 5.1.1,
- *     Fig. 5.1), inclusive: H(p, r, c) counts pixels of plane p in rows 0..r
- *     and columns 0..c (Eq. 2.15).  Rows are the thesis's x, columns its y.
+ *   - Integral histograms hold P x H x W int32 values, inclusive: H(p, r, c)
+ *     counts pixels of plane p in rows 0..r and columns 0..c (Eq. 2.15).
+ *     Rows are the thesis's x, columns its y.  They are stored bin-major
+ *     (IH_BHW, the thesis's layout, Sec. 5.1.1, Fig. 5.1) or planes-innermost
+ *     (IH_HWB); see ih_layout.
  *   - Rectangles are half-open {r0, c0, r1, c1}: rows r0..r1-1, columns
  *     c0..c1-1.
  */
@@ -51,23 +53,36 @@ typedef enum { IH_U8 = 0, IH_U16 = 1 } ih_dtype;
 typedef enum { IH_CHI2 = 0, IH_L1 = 1, IH_PMK = 2 } ih_metric;
 typedef enum { IH_MANHATTAN = 0 } ih_kernel;
 
+/*
+ * Memory layout of integral-histogram tensors (and their moment tensors).
+ *   IH_BHW  P x H x W, bin-major (Sec. 5.1.1, Fig. 5.1): element (p, r, c) at
+ *           (p * H + r) * W + c.  Each plane is contiguous.
+ *   IH_HWB  H x W x P, planes innermost: element (p, r, c) at
+ *           (r * W + c) * P + p.  The P-bin histogram at one pixel is
+ *           contiguous, so a four-corner query reads 4 runs of P values
+ *           instead of 4 P scattered values (for query-heavy workloads).
+ */
+typedef enum { IH_BHW = 0, IH_HWB = 1 } ih_layout;
+
 /* Half-open rectangle: rows [r0, r1), columns [c0, c1). */
 typedef struct {
   int32_t r0, c0, r1, c1;
 } ih_rect;
 
 /*
- * Tile shape of the build.  A tile is tile_h rows by 64 * cols_per_lane
- * columns; each wavefront of the final pass owns one tile and
- * planes_per_wave consecutive planes of one channel.
- *   tile_h          in [1, 256]
- *   cols_per_lane   1, 2 or 4
- *   planes_per_wave 1, 2, 4, 8 or 16
+ * Tile shape of the build: tiles of tile_h rows by tile_w columns.
+ *   IH_BHW: each wavefront of the write-out pass owns one tile and
+ *           planes_per_wave consecutive planes of one channel; its lanes map
+ *           to columns.  tile_h in [1, 256]; tile_w 64, 128 or 256;
+ *           planes_per_wave 1, 2, 4, 8 or 16.
+ *   IH_HWB: each wavefront owns one tile and 64 consecutive planes; its lanes
+ *           map to planes.  tile_h in [1, 256]; tile_w 16, 32 or 64;
+ *           planes_per_wave must be 64.
  * NULL selects a shape from a built-in heuristic.
  */
 typedef struct {
   int32_t tile_h;
-  int32_t cols_per_lane;
+  int32_t tile_w;
   int32_t planes_per_wave;
 } ih_tile_cfg;
 
@@ -82,7 +97,8 @@ const char *ih_last_error(void);
  * moments: non-zero when the coordinate-moment tensors will be requested.
  */
 size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins,
-                               int32_t moments, const ih_tile_cfg *cfg);
+                               int32_t moments, int32_t layout,
+                               const ih_tile_cfg *cfg);
 
 /*
  * ih_build - integral histogram of a binned image (Eq. 2.15; computed by the
@@ -96,9 +112,10 @@ size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins,
  *   value_bits  significant bits per value: 1..8 for IH_U8, 1..16 for
  *               IH_U16.  Every value must be < 2^value_bits; larger values
  *               give unspecified (but in-bounds) results.
- *   ih          device, out: P x H x W int32 integral histogram.
+ *   layout      IH_BHW or IH_HWB, for ih and the moment tensors.
+ *   ih          device, out: P x H x W int32 integral histogram (in layout).
  *   mom_x,      device, out, both NULL or both non-NULL: P x H x W uint32
- *   mom_y       coordinate-moment integral histograms
+ *   mom_y       coordinate-moment integral histograms (in layout)
  *                 Mx(p,r,c) = sum over the same region of row    * [bin = p]
  *                 My(p,r,c) = sum over the same region of column * [bin = p]
  *               stored modulo 2^32.  These are the weighted integral
@@ -113,15 +130,15 @@ size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins,
  * Returns IH_OK or IH_ERR_*.  Outputs must not overlap the image or ws.
  */
 int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C,
-             int32_t bins, int32_t value_bits, int32_t *ih, uint32_t *mom_x,
-             uint32_t *mom_y, const ih_tile_cfg *cfg, void *ws,
-             size_t ws_bytes, void *stream);
+             int32_t bins, int32_t value_bits, int32_t layout, int32_t *ih,
+             uint32_t *mom_x, uint32_t *mom_y, const ih_tile_cfg *cfg,
+             void *ws, size_t ws_bytes, void *stream);
 
 /*
  * ih_query_rect - region histograms by four corner lookups (Eq. 2.16):
  *   h(R, p) = H(r1-1, c1-1) - H(r0-1, c1-1) - H(r1-1, c0-1) + H(r0-1, c0-1)
  * with H(-1, .) = H(., -1) = 0.
- *   ih      device, P x H x W int32 from ih_build.
+ *   ih      device, P x H x W int32 from ih_build, in `layout`.
  *   rects   device, n half-open rectangles.
  *   out     device, out: n x P int32.  An empty rectangle (r0 == r1 or
  *           c0 == c1) gives zeros; a rectangle not satisfying
@@ -129,7 +146,8 @@ int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C,
  * n may be 0 (nothing is enqueued).
  */
 int ih_query_rect(const int32_t *ih, int32_t P, int32_t H, int32_t W,
-                  const ih_rect *rects, int64_t n, int32_t *out, void *stream);
+                  int32_t layout, const ih_rect *rects, int64_t n,
+                  int32_t *out, void *stream);
 
 /*
  * ih_query_weighted - spatially weighted local histograms (Eq. 3.1) with the
@@ -149,7 +167,7 @@ int ih_query_rect(const int32_t *ih, int32_t P, int32_t H, int32_t W,
  * sum of N over the whole window, making each channel sum to 1), rounded to
  * FP32.
  *
- *   ih, mom_x, mom_y  device, from ih_build with moments.
+ *   ih, mom_x, mom_y  device, from ih_build with moments, in `layout`.
  *   P, H, W, C        their shape; P must be a multiple of C.
  *   rects             device, n windows.
  *   kernel            IH_MANHATTAN.
@@ -159,9 +177,9 @@ int ih_query_rect(const int32_t *ih, int32_t P, int32_t H, int32_t W,
  */
 int ih_query_weighted(const int32_t *ih, const uint32_t *mom_x,
                       const uint32_t *mom_y, int32_t P, int32_t H, int32_t W,
-                      int32_t C, const ih_rect *rects, int64_t n,
-                      int32_t kernel, int32_t l1_normalize, float *out,
-                      void *stream);
+                      int32_t C, int32_t layout, const ih_rect *rects,
+                      int64_t n, int32_t kernel, int32_t l1_normalize,
+                      float *out, void *stream);
 
 /*
  * ih_pyramid_desc - spatial-pyramid region descriptors (Alg. 2 with the
@@ -177,8 +195,8 @@ int ih_query_weighted(const int32_t *ih, const uint32_t *mom_x,
  *          (h < 1, w < 1, r < 0, c < 0, r + h > H or c + w > W) give -1.
  */
 int ih_pyramid_desc(const int32_t *ih, int32_t P, int32_t H, int32_t W,
-                    const int32_t *wins, int64_t n, int32_t levels,
-                    int32_t *out, void *stream);
+                    int32_t layout, const int32_t *wins, int64_t n,
+                    int32_t levels, int32_t *out, void *stream);
 
 /*
  * ih_match_candidates - exhaustive sliding-window search (Sec. 2.4.3): the
@@ -201,10 +219,10 @@ int ih_pyramid_desc(const int32_t *ih, int32_t P, int32_t H, int32_t W,
  *              no candidate lies inside the frame.
  */
 int ih_match_candidates(const int32_t *ih, int32_t P, int32_t H, int32_t W,
-                        const int32_t *tmpl_desc, int32_t win_h, int32_t win_w,
-                        int32_t levels, const int32_t *origins, int64_t n,
-                        int32_t metric, float *dist, int32_t *best,
-                        void *stream);
+                        int32_t layout, const int32_t *tmpl_desc,
+                        int32_t win_h, int32_t win_w, int32_t levels,
+                        const int32_t *origins, int64_t n, int32_t metric,
+                        float *dist, int32_t *best, void *stream);
 
 /*
  * ih_profile_events - profiling hook.  When both are non-NULL (hipEvent_t),

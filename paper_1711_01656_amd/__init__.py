@@ -18,5 +18,6 @@ from .ih import (  # noqa: F401
     lib,
     lib_path,
     version,
+    shape_of,
     workspace_size,
 )

@@ -1,8 +1,8 @@
 // Integral-histogram build for gfx950 (Eq. 2.15; the Alg. 5 recurrence
 // reorganised into independent tiles).
 //
-// The image is cut into tiles of TH rows x TW = 64*CPL columns.  For a pixel
-// (r, c) of plane p in the tile whose top-left pixel is (R0, C0):
+// The image is cut into tiles of TH rows x TW columns.  For a pixel (r, c)
+// of plane p in the tile whose top-left pixel is (R0, C0):
 //
 //   H(p,r,c) = H(p,R0-1,c) + sum_{R0<=r'<=r} [ LC(p,r',C0) + #{C0<=c'<=c : bin(r',c')=p} ]
 //   H(p,R0-1,c) = H(p,R0-1,C0-1) + sum_{C0<=c'<=c} A(p,R0,c')
@@ -15,16 +15,18 @@
 //   2. carry_scan - exclusive scans of those over tile rows (-> A), over tile
 //                   columns (-> LC) and the 2-D exclusive scan of tile totals
 //                   (-> the corner H(p,R0-1,C0-1));
-//   3. final      - each wavefront owns one tile and a few planes: lanes map
-//                   to columns; the row prefix of a one-hot plane is a ballot
-//                   plus mbcnt, the column prefix a per-lane register sum; the
-//                   result is written once with streaming stores.
-// The carry arrays are 1/TH + 1/TW of the output.  Moment tensors (weights
-// row and column, Eq. 3.4) ride along in the same passes: their row-direction
-// carries are row * LC and need no array; the column-direction ones are kept.
-#include <stdarg.h>
-#include <stdio.h>
-
+//   3. final      - the write-out, in one of two forms:
+//        bin-major (BHW): a wavefront owns a tile and a few planes of one
+//          channel; lanes map to columns.  The row prefix of a one-hot plane
+//          is a ballot plus mbcnt, the column prefix a per-lane register sum.
+//        planes-innermost (HWB): a wavefront owns a tile and 64 planes; lanes
+//          map to planes.  The row prefix is a per-lane running count along
+//          the row, the column prefix one register per tile column.
+//        Either way each store instruction writes one contiguous run.
+// The carry arrays are about 1/TH + 1/TW of the output.  Moment tensors
+// (weights row and column, Eq. 3.4) ride along in the same passes: their
+// row-direction carry is row * LC and needs no array; the column-direction
+// ones are kept.
 #include "ih_internal.h"
 
 namespace ih {
@@ -47,45 +49,64 @@ static int pick_bc(const Geom &g, int *bc, size_t *lds) {
   return IH_OK;
 }
 
-int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
+int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, int32_t layout,
               const ih_tile_cfg *cfg, Geom *g) {
   if (H < 1 || W < 1 || C < 1)
     return set_error(IH_ERR_INVALID_ARG, "image shape %dx%dx%d must be positive", C, H, W);
   if ((int64_t)H * W >= ((int64_t)1 << 31))
     return set_error(IH_ERR_OVERFLOW, "H*W = %lld does not fit int32 counts", (long long)H * W);
-  if (bins < 1 || bins > 256)
-    return set_error(IH_ERR_INVALID_ARG, "bins %d outside 1..256", bins);
+  if (bins < 1 || bins > 256) return set_error(IH_ERR_INVALID_ARG, "bins %d outside 1..256", bins);
   if ((int64_t)C * bins > (1 << 20))
     return set_error(IH_ERR_RANGE, "C*bins = %lld too large", (long long)C * bins);
+  if (layout != IH_BHW && layout != IH_HWB) return set_error(IH_ERR_INVALID_ARG, "layout %d unknown", layout);
   g->H = H; g->W = W; g->C = C; g->bins = bins; g->P = C * bins;
   g->mom = moments != 0;
-  int TH, CPL, PG;
+  g->layout = layout;
+  int TH, TW, PG;
   if (cfg) {
-    TH = cfg->tile_h; CPL = cfg->cols_per_lane; PG = cfg->planes_per_wave;
+    TH = cfg->tile_h; TW = cfg->tile_w; PG = cfg->planes_per_wave;
     if (TH < 1 || TH > 256) return set_error(IH_ERR_INVALID_ARG, "tile_h %d outside 1..256", TH);
-    if (CPL != 1 && CPL != 2 && CPL != 4)
-      return set_error(IH_ERR_INVALID_ARG, "cols_per_lane %d not 1, 2 or 4", CPL);
-    if (PG != 1 && PG != 2 && PG != 4 && PG != 8 && PG != 16)
-      return set_error(IH_ERR_INVALID_ARG, "planes_per_wave %d not 1, 2, 4, 8 or 16", PG);
-    if (g->mom && PG * CPL > 32)
-      return set_error(IH_ERR_UNSUPPORTED, "with moments planes_per_wave*cols_per_lane must be <= 32");
-  } else {
-    CPL = W >= 2048 ? 4 : (W >= 384 ? 2 : 1);
+    if (layout == IH_BHW) {
+      if (TW != 64 && TW != 128 && TW != 256)
+        return set_error(IH_ERR_INVALID_ARG, "tile_w %d not 64, 128 or 256 for IH_BHW", TW);
+      if (PG != 1 && PG != 2 && PG != 4 && PG != 8 && PG != 16)
+        return set_error(IH_ERR_INVALID_ARG, "planes_per_wave %d not 1, 2, 4, 8 or 16", PG);
+      if (g->mom && PG * (TW / 64) > 32)
+        return set_error(IH_ERR_UNSUPPORTED, "with moments planes_per_wave*tile_w/64 must be <= 32");
+    } else {
+      if (TW != 16 && TW != 32 && TW != 64)
+        return set_error(IH_ERR_INVALID_ARG, "tile_w %d not 16, 32 or 64 for IH_HWB", TW);
+      if (PG != 64) return set_error(IH_ERR_INVALID_ARG, "planes_per_wave must be 64 for IH_HWB");
+      if (g->mom && TW > 32) return set_error(IH_ERR_UNSUPPORTED, "with moments tile_w must be <= 32 for IH_HWB");
+    }
+  } else if (layout == IH_BHW) {
+    const int CPL = W >= 2048 ? 4 : (W >= 384 ? 2 : 1);
+    TW = 64 * CPL;
     TH = H >= 1024 ? 64 : 32;
     PG = g->mom ? (CPL == 4 ? 8 : 16) : 16;
     if (PG > bins) PG = bins >= 16 ? 16 : bins >= 8 ? 8 : bins >= 4 ? 4 : bins >= 2 ? 2 : 1;
     auto waves = [&](int th, int pg) {
-      int64_t ntr = (H + th - 1) / th, ntc = (W + 64 * CPL - 1) / (64 * CPL);
+      int64_t ntr = (H + th - 1) / th, ntc = (W + TW - 1) / TW;
       return ntr * ntc * C * ((bins + pg - 1) / pg);
     };
     while (PG > 1 && waves(TH, PG) < 4096) PG >>= 1;
     while (TH > 16 && waves(TH, PG) < 2048) TH >>= 1;
+  } else {
+    PG = 64;
+    TW = g->mom ? 32 : 64;
+    TH = 32;
+    auto waves = [&](int th, int tw) {
+      int64_t ntr = (H + th - 1) / th, ntc = (W + tw - 1) / tw;
+      return ntr * ntc * ((g->P + 63) / 64);
+    };
+    while (TW > 16 && waves(TH, TW) < 4096) TW >>= 1;
+    while (TH > 8 && waves(TH, TW) < 4096) TH >>= 1;
   }
-  g->TH = TH; g->CPL = CPL; g->TW = 64 * CPL; g->PG = PG;
-  if ((int64_t)TH * g->TW > 32768)
-    return set_error(IH_ERR_UNSUPPORTED, "tile %dx%d larger than 32768 pixels", TH, g->TW);
+  g->TH = TH; g->TW = TW; g->PG = PG;
+  g->CPL = layout == IH_BHW ? TW / 64 : 1;
+  if ((int64_t)TH * TW > 32768) return set_error(IH_ERR_UNSUPPORTED, "tile %dx%d larger than 32768 pixels", TH, TW);
   g->nTR = (H + TH - 1) / TH;
-  g->nTC = (W + g->TW - 1) / g->TW;
+  g->nTC = (W + TW - 1) / TW;
   const size_t P = (size_t)g->P;
   size_t o = 0;
   g->off_cc = o;  o = align64(o + P * g->nTR * (size_t)W);
@@ -105,11 +126,18 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
   return pick_bc(*g, &bc, &lds);
 }
 
+// Column-count carry arrays (CC, CCX) are indexed [p][I][c] for the bin-major
+// write-out and [I][c][p] for the planes-innermost one, so that each form
+// reads them with unit stride.
+__host__ __device__ __forceinline__ int64_t cc_index(const Geom &g, int64_t p, int I, int64_t c) {
+  return g.layout == IH_BHW ? (p * g.nTR + I) * (int64_t)g.W + c : ((int64_t)I * g.W + c) * g.P + p;
+}
+
 // --------------------------------------------------------------------------
 // 1. Per-tile histograms.  One workgroup per (channel, tile).
-//    CC[p][I][c]          plane-p count of column c over the tile's rows
-//    RC[ch][j][r][bin]    plane count of row r over the tile's columns
-//    TT[p][I][j]          tile totals
+//    CC  (p, I, c)        plane-p count of column c over the tile's rows
+//    RC  [ch][j][r][bin]  plane count of row r over the tile's columns
+//    TT  [p][I][j]        tile totals
 //    CCX (sum of rows), RCY (sum of columns), TTX, TTY for the moments.
 // --------------------------------------------------------------------------
 template <typename T>
@@ -140,29 +168,28 @@ __global__ __launch_bounds__(256) void k_tile_hist(const T *__restrict__ img, Ge
 
   for (int b0 = 0; b0 < g.bins; b0 += bc) {
     const int nb = min(bc, g.bins - b0);
-    // ---- columns: each lane owns a column, rows split over segments
-    const int nseg = 256 / g.TW;  // TW <= 256
+    // ---- columns: each thread owns a column, rows split over segments
+    const int nseg = g.TW >= 256 ? 1 : 256 / g.TW;
     const int colw = g.TW * stride;
     __syncthreads();
     for (int i = tid; i < colw * (g.mom ? 2 : 1); i += 256) hist[i] = 0;
     __syncthreads();
-    {
-      const int cl = tid % g.TW, seg = tid / g.TW;
-      if (cl < tw && seg < nseg) {
-        for (int r = seg; r < th; r += nseg) {
-          const int b = (int)bin_s[r * twp + cl] - b0;
-          if (b >= 0 && b < nb) {
-            atomicAdd(&hist[cl * stride + b], 1u);
-            if (g.mom) atomicAdd(&hist[colw + cl * stride + b], (uint32_t)(R0 + r));
-          }
+    for (int idx = tid; idx < tw * nseg; idx += 256) {
+      const int cl = idx % tw, seg = idx / tw;
+      for (int r = seg; r < th; r += nseg) {
+        const int b = (int)bin_s[r * twp + cl] - b0;
+        if (b >= 0 && b < nb) {
+          atomicAdd(&hist[cl * stride + b], 1u);
+          if (g.mom) atomicAdd(&hist[colw + cl * stride + b], (uint32_t)(R0 + r));
         }
       }
     }
     __syncthreads();
     for (int i = tid; i < nb * tw; i += 256) {
-      const int k = i / tw, cl = i - k * tw;
-      const size_t p = (size_t)ch * g.bins + b0 + k;
-      const size_t o = (p * g.nTR + I) * (size_t)g.W + C0 + cl;
+      int k, cl;
+      if (g.layout == IH_BHW) { k = i / tw; cl = i - k * tw; }     // unit stride along columns
+      else { cl = i / nb; k = i - cl * nb; }                       // unit stride along planes
+      const int64_t o = cc_index(g, (int64_t)ch * g.bins + b0 + k, I, C0 + cl);
       CC[o] = hist[cl * stride + k];
       if (g.mom) CCX[o] = hist[colw + cl * stride + k];
     }
@@ -178,7 +205,7 @@ __global__ __launch_bounds__(256) void k_tile_hist(const T *__restrict__ img, Ge
       TT[o] = s;
       if (g.mom) { TTX[o] = sx; TTY[o] = sy; }
     }
-    // ---- rows: each lane owns a row, columns split over segments
+    // ---- rows: each thread owns a row, columns split over segments
     const int rseg = g.TH >= 256 ? 1 : 256 / g.TH;
     const int roww = g.TH * stride;
     __syncthreads();
@@ -217,17 +244,20 @@ __global__ __launch_bounds__(256) void k_carry_scan(Geom g, int64_t nblk_a, int6
   if (blk < nblk_a) {
     const int64_t idx = blk * 256 + threadIdx.x;
     if (idx >= (int64_t)g.P * g.W) return;
-    const int64_t p = idx / g.W, c = idx - p * g.W;
-    uint32_t *a = ws + g.off_cc + p * g.nTR * (int64_t)g.W + c;
-    uint32_t *ax = ws + g.off_ccx + p * g.nTR * (int64_t)g.W + c;
+    int64_t p, c;
+    if (g.layout == IH_BHW) { p = idx / g.W; c = idx - p * g.W; }
+    else { c = idx / g.P; p = idx - c * g.P; }
+    const int64_t step = cc_index(g, p, 1, c) - cc_index(g, p, 0, c);
+    uint32_t *a = ws + g.off_cc + cc_index(g, p, 0, c);
+    uint32_t *ax = ws + g.off_ccx + cc_index(g, p, 0, c);
     uint32_t run = 0, runx = 0;
     for (int I = 0; I < g.nTR; ++I) {
-      const uint32_t v = a[(int64_t)I * g.W];
-      a[(int64_t)I * g.W] = run;
+      const uint32_t v = a[I * step];
+      a[I * step] = run;
       run += v;
       if (g.mom) {
-        const uint32_t vx = ax[(int64_t)I * g.W];
-        ax[(int64_t)I * g.W] = runx;
+        const uint32_t vx = ax[I * step];
+        ax[I * step] = runx;
         runx += vx;
       }
     }
@@ -278,8 +308,8 @@ __global__ __launch_bounds__(256) void k_carry_scan(Geom g, int64_t nblk_a, int6
 }
 
 // --------------------------------------------------------------------------
-// 3. Final pass.  Block x = (channel, tile), block y * waves + wave = plane
-//    group of PG planes.  Lane l owns columns C0 + l*CPL .. + CPL-1.
+// 3a. Bin-major write-out.  Block x = (channel, tile), block y * waves + wave
+//     = plane group of PG planes.  Lane l owns columns C0 + l*CPL .. + CPL-1.
 // --------------------------------------------------------------------------
 struct FinalArgs {
   const void *img;
@@ -287,7 +317,7 @@ struct FinalArgs {
   uint32_t *mx, *my;
   const uint32_t *ws;
   int bits;
-  int vec_ok;  // W divisible by CPL and the outputs 16-byte aligned
+  int vec_ok;  // bin-major: W divisible by CPL and the outputs 16-byte aligned
 };
 
 template <int CPL>
@@ -415,6 +445,93 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a, Geom g) {
   }
 }
 
+// --------------------------------------------------------------------------
+// 3b. Planes-innermost write-out.  One wavefront per (tile, chunk of 64
+//     planes); lane = plane.  The lane keeps one register per tile column
+//     (the column prefix) and walks each row left to right keeping the row
+//     prefix; every (row, column) step stores 64 consecutive planes.
+// --------------------------------------------------------------------------
+template <typename T, int TW, bool MOM>
+__global__ __launch_bounds__(256) void k_final_hwb(FinalArgs a, Geom g) {
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform(threadIdx.x >> 6);
+  const int nchunk = (g.P + 63) >> 6;
+  const int64_t unit = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (unit >= (int64_t)g.nTR * g.nTC * nchunk) return;
+  const int chunk = (int)(unit % nchunk);
+  const int64_t tile = unit / nchunk;
+  const int j = (int)(tile % g.nTC), I = (int)(tile / g.nTC);
+  const int p = chunk * 64 + lane;
+  const bool live = p < g.P;
+  const int ch = live ? p / g.bins : 0;
+  const int k = live ? p - ch * g.bins : 0;
+  const int R0 = I * g.TH, C0 = j * TW;
+  const int cols = min(TW, g.W - C0), rows = min(g.TH, g.H - R0);
+  // pixel values of bin k are those in [lo, hi): floor(v * bins / 2^bits) = k
+  const uint32_t lo = (uint32_t)((((uint64_t)k << a.bits) + g.bins - 1) / g.bins);
+  const uint32_t width = (uint32_t)((((uint64_t)(k + 1) << a.bits) + g.bins - 1) / g.bins) - lo;
+  const T *img = reinterpret_cast<const T *>(a.img) + (int64_t)ch * g.H * g.W;
+  const int64_t P = g.P;
+
+  uint32_t col[TW];
+  uint32_t colx[MOM ? TW : 1], coly[MOM ? TW : 1];
+  {
+    const int64_t cidx = ((int64_t)(live ? p : 0) * g.nTR + I) * g.nTC + j;
+    uint32_t run = live ? a.ws[g.off_tt + cidx] : 0u;
+    uint32_t runx = 0, runy = 0;
+    if constexpr (MOM) {
+      runx = live ? a.ws[g.off_ttx + cidx] : 0u;
+      runy = live ? a.ws[g.off_tty + cidx] : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        const int64_t o = ((int64_t)I * g.W + C0 + c) * P + p;
+        const uint32_t v = live ? a.ws[g.off_cc + o] : 0u;
+        run += v;
+        col[c] = run;
+        if constexpr (MOM) {
+          runx += live ? a.ws[g.off_ccx + o] : 0u;
+          runy += v * (uint32_t)(C0 + c);
+          colx[c] = runx;
+          coly[c] = runy;
+        }
+      }
+    }
+  }
+  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  for (int rr = 0; rr < rows; ++rr) {
+    const int r = R0 + rr;
+    const T *row = img + (int64_t)r * g.W + C0;
+    uint32_t v[TW];
+#pragma unroll
+    for (int c = 0; c < TW; ++c) v[c] = c < cols ? (uint32_t)row[c] : 0u;
+    uint32_t rc = live ? lc[(int64_t)r * g.bins] : 0u;
+    uint32_t ry = 0;
+    if constexpr (MOM) ry = live ? lcy[(int64_t)r * g.bins] : 0u;
+    const int64_t base = ((int64_t)r * g.W + C0) * P + p;
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        const uint32_t hit = (v[c] - lo) < width ? 1u : 0u;
+        rc += hit;
+        col[c] += rc;
+        if (live) __builtin_nontemporal_store((int)col[c], a.ih + base + c * P);
+        if constexpr (MOM) {
+          colx[c] += (uint32_t)r * rc;
+          ry += hit * (uint32_t)(C0 + c);
+          coly[c] += ry;
+          if (live) {
+            __builtin_nontemporal_store(colx[c], a.mx + base + c * P);
+            __builtin_nontemporal_store(coly[c], a.my + base + c * P);
+          }
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ host --
 struct ProfileHook {
   hipEvent_t start = nullptr, stop = nullptr;
@@ -440,19 +557,34 @@ static final_fn pick_final_t(int CPL, int PG) {
   return nullptr;
 }
 
-static final_fn pick_final(int dtype, bool mom, int CPL, int PG) {
-  if (dtype == IH_U8) return mom ? pick_final_t<uint8_t, true>(CPL, PG) : pick_final_t<uint8_t, false>(CPL, PG);
-  return mom ? pick_final_t<uint16_t, true>(CPL, PG) : pick_final_t<uint16_t, false>(CPL, PG);
+template <typename T, bool MOM>
+static final_fn pick_hwb_t(int TW) {
+  if (TW == 16) return &k_final_hwb<T, 16, MOM>;
+  if (TW == 32) return &k_final_hwb<T, 32, MOM>;
+  if constexpr (!MOM) {
+    if (TW == 64) return &k_final_hwb<T, 64, MOM>;
+  }
+  return nullptr;
+}
+
+static final_fn pick_final(int dtype, const Geom &g) {
+  const bool u8 = dtype == IH_U8;
+  if (g.layout == IH_HWB) {
+    if (u8) return g.mom ? pick_hwb_t<uint8_t, true>(g.TW) : pick_hwb_t<uint8_t, false>(g.TW);
+    return g.mom ? pick_hwb_t<uint16_t, true>(g.TW) : pick_hwb_t<uint16_t, false>(g.TW);
+  }
+  if (u8) return g.mom ? pick_final_t<uint8_t, true>(g.CPL, g.PG) : pick_final_t<uint8_t, false>(g.CPL, g.PG);
+  return g.mom ? pick_final_t<uint16_t, true>(g.CPL, g.PG) : pick_final_t<uint16_t, false>(g.CPL, g.PG);
 }
 
 }  // namespace ih
 
 using namespace ih;
 
-extern "C" size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins,
-                                          int32_t moments, const ih_tile_cfg *cfg) {
+extern "C" size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
+                                          int32_t layout, const ih_tile_cfg *cfg) {
   Geom g;
-  if (make_geom(H, W, C, bins, moments, cfg, &g) != IH_OK) return 0;
+  if (make_geom(H, W, C, bins, moments, layout, cfg, &g) != IH_OK) return 0;
   return g.words * 4;
 }
 
@@ -464,10 +596,9 @@ extern "C" int ih_profile_events(void *start, void *stop) {
   return IH_OK;
 }
 
-extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C,
-                        int32_t bins, int32_t value_bits, int32_t *ih, uint32_t *mom_x,
-                        uint32_t *mom_y, const ih_tile_cfg *cfg, void *ws, size_t ws_bytes,
-                        void *stream) {
+extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C, int32_t bins,
+                        int32_t value_bits, int32_t layout, int32_t *ih, uint32_t *mom_x, uint32_t *mom_y,
+                        const ih_tile_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
   if (!img || !ih) return set_error(IH_ERR_INVALID_ARG, "img and ih must be non-NULL");
   if ((mom_x == nullptr) != (mom_y == nullptr))
     return set_error(IH_ERR_INVALID_ARG, "mom_x and mom_y must be both NULL or both set");
@@ -475,17 +606,17 @@ extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, in
   const int maxbits = dtype == IH_U8 ? 8 : 16;
   if (value_bits < 1 || value_bits > maxbits)
     return set_error(IH_ERR_INVALID_ARG, "value_bits %d outside 1..%d", value_bits, maxbits);
-  if (bins > (1 << value_bits))
-    return set_error(IH_ERR_INVALID_ARG, "bins %d exceed 2^value_bits", bins);
+  if (bins > (1 << value_bits)) return set_error(IH_ERR_INVALID_ARG, "bins %d exceed 2^value_bits", bins);
   const bool mom = mom_x != nullptr;
   Geom g;
-  int e = make_geom(H, W, C, bins, mom, cfg, &g);
+  int e = make_geom(H, W, C, bins, mom, layout, cfg, &g);
   if (e) return e;
   if (!ws || ws_bytes < g.words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.words * 4,
                      ws ? ws_bytes : (size_t)0);
-  final_fn fin = pick_final(dtype, mom, g.CPL, g.PG);
-  if (!fin) return set_error(IH_ERR_UNSUPPORTED, "no final kernel for cols_per_lane %d planes_per_wave %d", g.CPL, g.PG);
+  final_fn fin = pick_final(dtype, g);
+  if (!fin)
+    return set_error(IH_ERR_UNSUPPORTED, "no write-out kernel for tile_w %d planes_per_wave %d", g.TW, g.PG);
   int bc;
   size_t lds;
   if ((e = pick_bc(g, &bc, &lds))) return e;
@@ -507,13 +638,21 @@ extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, in
   hipLaunchKernelGGL(k_carry_scan, dim3((unsigned)(nA + nB + nC)), dim3(256), 0, s, g, nA, nB, w32);
   if ((e = hip_check(hipGetLastError(), "carry_scan launch"))) return e;
 
-  const int groups = (bins + g.PG - 1) / g.PG;
-  const int wpb = groups < 4 ? groups : 4;
-  const bool aligned = ((uintptr_t)ih % 16 == 0) && ((uintptr_t)mom_x % 16 == 0) &&
-                       ((uintptr_t)mom_y % 16 == 0);
+  const bool aligned = ((uintptr_t)ih % 16 == 0) && ((uintptr_t)mom_x % 16 == 0) && ((uintptr_t)mom_y % 16 == 0);
   FinalArgs fa{img, ih, mom_x, mom_y, w32, value_bits, (W % g.CPL == 0 && aligned) ? 1 : 0};
+  dim3 grid, block;
+  if (layout == IH_BHW) {
+    const int groups = (bins + g.PG - 1) / g.PG;
+    const int wpb = groups < 4 ? groups : 4;
+    grid = dim3(tiles, (unsigned)((groups + wpb - 1) / wpb));
+    block = dim3(64 * wpb);
+  } else {
+    const int64_t units = (int64_t)g.nTR * g.nTC * ((g.P + 63) / 64);
+    grid = dim3((unsigned)((units + 3) / 4));
+    block = dim3(256);
+  }
   if (g_hook.start && (e = hip_check(hipEventRecord(g_hook.start, s), "profile start"))) return e;
-  hipLaunchKernelGGL(fin, dim3(tiles, (unsigned)((groups + wpb - 1) / wpb)), dim3(64 * wpb), 0, s, fa, g);
+  hipLaunchKernelGGL(fin, grid, block, 0, s, fa, g);
   if ((e = hip_check(hipGetLastError(), "final launch"))) return e;
   if (g_hook.stop && (e = hip_check(hipEventRecord(g_hook.stop, s), "profile stop"))) return e;
   return IH_OK;

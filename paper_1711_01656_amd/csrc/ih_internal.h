@@ -78,14 +78,15 @@ __device__ __forceinline__ void store_stream(int *dst, const int (&v)[N]) {
 // -------------------------------------------------------- build geometry --
 struct Geom {
   int H, W, C, bins, P;
-  int TH, CPL, TW, PG;  // tile rows, columns per lane, tile columns, planes per wave
+  int TH, CPL, TW, PG;  // tile rows, columns per lane (bin-major), tile columns, planes per wave
   int nTR, nTC;         // tile rows / columns of the grid
   bool mom;
+  int layout;           // IH_BHW or IH_HWB
   // workspace sections (in 4-byte words)
   size_t off_cc, off_rc, off_tt, off_ccx, off_rcy, off_ttx, off_tty, words;
 };
 
-int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
+int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, int32_t layout,
               const ih_tile_cfg *cfg, Geom *g);
 
 }  // namespace ih

@@ -4,25 +4,32 @@
 //     Sec. 3.1.3);
 //   - spatial-pyramid descriptors (Alg. 2, Sec. 2.4.4).
 // One thread per (window, plane); lanes of a wavefront take consecutive
-// planes of the same window, so outputs are written contiguously.  The reads
-// are gathers: in the bin-major layout every corner of every plane lies in
-// its own cache line.
+// planes of the same window, so outputs are written contiguously.  In the
+// planes-innermost layout each corner read is one contiguous run across the
+// wavefront; in the bin-major layout every plane's corner lies in its own
+// cache line.
 #include "ih_internal.h"
 
 namespace ih {
 
-__device__ __forceinline__ int32_t at(const int32_t *__restrict__ t, int64_t plane_off, int W, int r, int c) {
-  return (r < 0 || c < 0) ? 0 : t[plane_off + (int64_t)r * W + c];
-}
-__device__ __forceinline__ uint32_t atu(const uint32_t *__restrict__ t, int64_t plane_off, int W, int r, int c) {
-  return (r < 0 || c < 0) ? 0u : t[plane_off + (int64_t)r * W + c];
-}
+// Addressing of element (p, r, c): base(p) + r * rs + c * cs.
+struct Addr {
+  int64_t base, rs, cs;
+  __device__ __forceinline__ Addr(int layout, int p, int P, int H, int W) {
+    if (layout == IH_BHW) { base = (int64_t)p * H * W; rs = W; cs = 1; }
+    else { base = p; rs = (int64_t)W * P; cs = P; }
+  }
+  template <typename T>
+  __device__ __forceinline__ T at(const T *__restrict__ t, int r, int c) const {
+    return (r < 0 || c < 0) ? (T)0 : t[base + r * rs + c * cs];
+  }
+};
 
 // Windows per block for one-thread-per-(window, plane) kernels.
 __host__ __device__ __forceinline__ int per_block(int P) { return P >= 256 ? 1 : 256 / P; }
 
 // ------------------------------------------------------------- Eq. 2.16 --
-__global__ __launch_bounds__(256) void k_query_rect(const int32_t *__restrict__ ih, int P, int H, int W,
+__global__ __launch_bounds__(256) void k_query_rect(const int32_t *__restrict__ ih, int P, int H, int W, int layout,
                                                     const ih_rect *__restrict__ rects, int64_t n,
                                                     int32_t *__restrict__ out) {
   const int qpb = per_block(P);
@@ -37,9 +44,9 @@ __global__ __launch_bounds__(256) void k_query_rect(const int32_t *__restrict__ 
     } else if (R.r0 == R.r1 || R.c0 == R.c1) {
       v = 0;
     } else {
-      const int64_t po = (int64_t)p * H * W;
-      v = at(ih, po, W, R.r1 - 1, R.c1 - 1) - at(ih, po, W, R.r0 - 1, R.c1 - 1) -
-          at(ih, po, W, R.r1 - 1, R.c0 - 1) + at(ih, po, W, R.r0 - 1, R.c0 - 1);
+      const Addr A(layout, p, P, H, W);
+      v = A.at(ih, R.r1 - 1, R.c1 - 1) - A.at(ih, R.r0 - 1, R.c1 - 1) - A.at(ih, R.r1 - 1, R.c0 - 1) +
+          A.at(ih, R.r0 - 1, R.c0 - 1);
     }
     out[q * P + p] = v;
   }
@@ -59,8 +66,8 @@ __global__ __launch_bounds__(256) void k_query_rect(const int32_t *__restrict__ 
 __global__ __launch_bounds__(256) void k_query_weighted(const int32_t *__restrict__ ih,
                                                         const uint32_t *__restrict__ mx,
                                                         const uint32_t *__restrict__ my, int P, int H,
-                                                        int W, const ih_rect *__restrict__ rects, int64_t n,
-                                                        int l1, float *__restrict__ out) {
+                                                        int W, int layout, const ih_rect *__restrict__ rects,
+                                                        int64_t n, int l1, float *__restrict__ out) {
   const int qpb = per_block(P);
   for (int idx = threadIdx.x; idx < qpb * P; idx += blockDim.x) {
     const int ql = idx / P, p = idx - ql * P;
@@ -77,19 +84,19 @@ __global__ __launch_bounds__(256) void k_query_weighted(const int32_t *__restric
     } else if ((uint64_t)(h * w) * (uint64_t)far >= ((uint64_t)1 << 32)) {
       res = __builtin_nanf("");
     } else {
-      const int64_t po = (int64_t)p * H * W;
+      const Addr A(layout, p, P, H, W);
       const int ra = R.r0 - 1, rm = R.r0 + (int)(h / 2) - 1, rb = R.r1 - 1;
       const int ca = R.c0 - 1, cm = R.c0 + (int)(w / 2) - 1, cb = R.c1 - 1;
-      const int64_t n_aa = at(ih, po, W, ra, ca), n_ab = at(ih, po, W, ra, cb);
-      const int64_t n_ba = at(ih, po, W, rb, ca), n_bb = at(ih, po, W, rb, cb);
-      const int64_t n_ma = at(ih, po, W, rm, ca), n_mb = at(ih, po, W, rm, cb);
-      const int64_t n_am = at(ih, po, W, ra, cm), n_bm = at(ih, po, W, rb, cm);
-      const uint32_t x_aa = atu(mx, po, W, ra, ca), x_ab = atu(mx, po, W, ra, cb);
-      const uint32_t x_ma = atu(mx, po, W, rm, ca), x_mb = atu(mx, po, W, rm, cb);
-      const uint32_t x_ba = atu(mx, po, W, rb, ca), x_bb = atu(mx, po, W, rb, cb);
-      const uint32_t y_aa = atu(my, po, W, ra, ca), y_am = atu(my, po, W, ra, cm);
-      const uint32_t y_ab = atu(my, po, W, ra, cb), y_ba = atu(my, po, W, rb, ca);
-      const uint32_t y_bm = atu(my, po, W, rb, cm), y_bb = atu(my, po, W, rb, cb);
+      const int64_t n_aa = A.at(ih, ra, ca), n_ab = A.at(ih, ra, cb);
+      const int64_t n_ba = A.at(ih, rb, ca), n_bb = A.at(ih, rb, cb);
+      const int64_t n_ma = A.at(ih, rm, ca), n_mb = A.at(ih, rm, cb);
+      const int64_t n_am = A.at(ih, ra, cm), n_bm = A.at(ih, rb, cm);
+      const uint32_t x_aa = A.at(mx, ra, ca), x_ab = A.at(mx, ra, cb);
+      const uint32_t x_ma = A.at(mx, rm, ca), x_mb = A.at(mx, rm, cb);
+      const uint32_t x_ba = A.at(mx, rb, ca), x_bb = A.at(mx, rb, cb);
+      const uint32_t y_aa = A.at(my, ra, ca), y_am = A.at(my, ra, cm);
+      const uint32_t y_ab = A.at(my, ra, cb), y_ba = A.at(my, rb, ca);
+      const uint32_t y_bm = A.at(my, rb, cm), y_bb = A.at(my, rb, cb);
       const int64_t nA = n_bb - n_ab - n_ba + n_aa;
       const int64_t nT = n_mb - n_ab - n_ma + n_aa, nB = nA - nT;
       const int64_t nL = n_bm - n_am - n_ba + n_aa, nR = nA - nL;
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(256) void k_query_weighted(const int32_t *__restric
 // ------------------------------------------------------ pyramid cells ----
 template <int LEVELS>
 __global__ __launch_bounds__(256) void k_pyramid_desc(const int32_t *__restrict__ ih, int P, int H, int W,
-                                                      const int32_t *__restrict__ wins, int64_t n,
+                                                      int layout, const int32_t *__restrict__ wins, int64_t n,
                                                       int32_t *__restrict__ out) {
   constexpr int G = 1 << (LEVELS - 1);
   constexpr int CELLS = ((1 << (2 * LEVELS)) - 1) / 3;
@@ -132,13 +139,13 @@ __global__ __launch_bounds__(256) void k_pyramid_desc(const int32_t *__restrict_
       for (int k = 0; k < CELLS; ++k) o[k * P] = -1;
       continue;
     }
-    const int64_t po = (int64_t)p * H * W;
+    const Addr A(layout, p, P, H, W);
     int32_t v[G + 1][G + 1];
 #pragma unroll
     for (int a = 0; a <= G; ++a)
 #pragma unroll
       for (int b = 0; b <= G; ++b)
-        v[a][b] = at(ih, po, W, r + (int)((int64_t)a * h / G) - 1, c + (int)((int64_t)b * w / G) - 1);
+        v[a][b] = A.at(ih, r + (int)((int64_t)a * h / G) - 1, c + (int)((int64_t)b * w / G) - 1);
     int k = 0;
 #pragma unroll
     for (int l = 0; l < LEVELS; ++l) {
@@ -152,57 +159,65 @@ __global__ __launch_bounds__(256) void k_pyramid_desc(const int32_t *__restrict_
   }
 }
 
+static int check_common(int32_t P, int32_t H, int32_t W, int32_t layout, int64_t n) {
+  if (P < 1 || H < 1 || W < 1) return set_error(IH_ERR_INVALID_ARG, "P, H, W must be positive");
+  if (layout != IH_BHW && layout != IH_HWB) return set_error(IH_ERR_INVALID_ARG, "layout %d unknown", layout);
+  if (n < 0) return set_error(IH_ERR_INVALID_ARG, "n must be >= 0");
+  return IH_OK;
+}
+
 }  // namespace ih
 
 using namespace ih;
 
-extern "C" int ih_query_rect(const int32_t *ihp, int32_t P, int32_t H, int32_t W, const ih_rect *rects,
-                             int64_t n, int32_t *out, void *stream) {
-  if (P < 1 || H < 1 || W < 1) return set_error(IH_ERR_INVALID_ARG, "P, H, W must be positive");
-  if (n < 0) return set_error(IH_ERR_INVALID_ARG, "n must be >= 0");
+extern "C" int ih_query_rect(const int32_t *ihp, int32_t P, int32_t H, int32_t W, int32_t layout,
+                             const ih_rect *rects, int64_t n, int32_t *out, void *stream) {
+  int e = check_common(P, H, W, layout, n);
+  if (e) return e;
   if (n == 0) return IH_OK;
   if (!ihp || !rects || !out) return set_error(IH_ERR_INVALID_ARG, "NULL pointer");
   const int qpb = per_block(P);
   const int64_t blocks = (n + qpb - 1) / qpb;
   if (blocks > 0x7fffffff) return set_error(IH_ERR_RANGE, "too many queries");
-  hipLaunchKernelGGL(k_query_rect, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), ihp, P, H, W,
+  hipLaunchKernelGGL(k_query_rect, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), ihp, P, H, W, layout,
                      rects, n, out);
   return hip_check(hipGetLastError(), "query_rect launch");
 }
 
 extern "C" int ih_query_weighted(const int32_t *ihp, const uint32_t *mom_x, const uint32_t *mom_y, int32_t P,
-                                 int32_t H, int32_t W, int32_t C, const ih_rect *rects, int64_t n,
+                                 int32_t H, int32_t W, int32_t C, int32_t layout, const ih_rect *rects, int64_t n,
                                  int32_t kernel, int32_t l1_normalize, float *out, void *stream) {
-  if (P < 1 || H < 1 || W < 1 || C < 1) return set_error(IH_ERR_INVALID_ARG, "P, H, W, C must be positive");
-  if (P % C != 0) return set_error(IH_ERR_INVALID_ARG, "P=%d not a multiple of C=%d", P, C);
+  int e = check_common(P, H, W, layout, n);
+  if (e) return e;
+  if (C < 1 || P % C != 0) return set_error(IH_ERR_INVALID_ARG, "P=%d not a positive multiple of C=%d", P, C);
   if (kernel != IH_MANHATTAN) return set_error(IH_ERR_UNSUPPORTED, "kernel %d not implemented", kernel);
-  if (n < 0) return set_error(IH_ERR_INVALID_ARG, "n must be >= 0");
   if (n == 0) return IH_OK;
   if (!ihp || !mom_x || !mom_y || !rects || !out) return set_error(IH_ERR_INVALID_ARG, "NULL pointer");
   const int qpb = per_block(P);
   const int64_t blocks = (n + qpb - 1) / qpb;
   if (blocks > 0x7fffffff) return set_error(IH_ERR_RANGE, "too many queries");
   hipLaunchKernelGGL(k_query_weighted, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), ihp, mom_x,
-                     mom_y, P, H, W, rects, n, l1_normalize ? 1 : 0, out);
+                     mom_y, P, H, W, layout, rects, n, l1_normalize ? 1 : 0, out);
   return hip_check(hipGetLastError(), "query_weighted launch");
 }
 
-extern "C" int ih_pyramid_desc(const int32_t *ihp, int32_t P, int32_t H, int32_t W, const int32_t *wins,
-                               int64_t n, int32_t levels, int32_t *out, void *stream) {
-  if (P < 1 || H < 1 || W < 1) return set_error(IH_ERR_INVALID_ARG, "P, H, W must be positive");
+extern "C" int ih_pyramid_desc(const int32_t *ihp, int32_t P, int32_t H, int32_t W, int32_t layout,
+                               const int32_t *wins, int64_t n, int32_t levels, int32_t *out, void *stream) {
+  int e = check_common(P, H, W, layout, n);
+  if (e) return e;
   if (levels < 1 || levels > 4) return set_error(IH_ERR_INVALID_ARG, "levels %d outside 1..4", levels);
-  if (n < 0) return set_error(IH_ERR_INVALID_ARG, "n must be >= 0");
   if (n == 0) return IH_OK;
   if (!ihp || !wins || !out) return set_error(IH_ERR_INVALID_ARG, "NULL pointer");
   const int qpb = per_block(P);
   const int64_t blocks = (n + qpb - 1) / qpb;
   if (blocks > 0x7fffffff) return set_error(IH_ERR_RANGE, "too many windows");
   hipStream_t s = as_stream(stream);
+  const dim3 g((unsigned)blocks), b(256);
   switch (levels) {
-    case 1: hipLaunchKernelGGL(k_pyramid_desc<1>, dim3((unsigned)blocks), dim3(256), 0, s, ihp, P, H, W, wins, n, out); break;
-    case 2: hipLaunchKernelGGL(k_pyramid_desc<2>, dim3((unsigned)blocks), dim3(256), 0, s, ihp, P, H, W, wins, n, out); break;
-    case 3: hipLaunchKernelGGL(k_pyramid_desc<3>, dim3((unsigned)blocks), dim3(256), 0, s, ihp, P, H, W, wins, n, out); break;
-    default: hipLaunchKernelGGL(k_pyramid_desc<4>, dim3((unsigned)blocks), dim3(256), 0, s, ihp, P, H, W, wins, n, out); break;
+    case 1: hipLaunchKernelGGL(k_pyramid_desc<1>, g, b, 0, s, ihp, P, H, W, layout, wins, n, out); break;
+    case 2: hipLaunchKernelGGL(k_pyramid_desc<2>, g, b, 0, s, ihp, P, H, W, layout, wins, n, out); break;
+    case 3: hipLaunchKernelGGL(k_pyramid_desc<3>, g, b, 0, s, ihp, P, H, W, layout, wins, n, out); break;
+    default: hipLaunchKernelGGL(k_pyramid_desc<4>, g, b, 0, s, ihp, P, H, W, layout, wins, n, out); break;
   }
   return hip_check(hipGetLastError(), "pyramid_desc launch");
 }

@@ -4,6 +4,9 @@ Argument marshalling only: every computation runs in the library's gfx950
 kernels.  PyTorch supplies device memory and the current HIP stream.  The
 functions keep the C names (``ih_build``, ``ih_query_rect``, ...).  There is
 no fallback: if the library is missing or fails to load, every call raises.
+
+Layouts: ``"bhw"`` tensors are P x H x W (bin-major, the thesis's layout);
+``"hwb"`` tensors are H x W x P (planes innermost).
 """
 from __future__ import annotations
 
@@ -20,7 +23,9 @@ IH_OK = 0
 IH_U8, IH_U16 = 0, 1
 IH_CHI2, IH_L1, IH_PMK = 0, 1, 2
 IH_MANHATTAN = 0
+IH_BHW, IH_HWB = 0, 1
 METRICS = {"chi2": IH_CHI2, "l1": IH_L1, "pmk": IH_PMK}
+LAYOUTS = {"bhw": IH_BHW, "hwb": IH_HWB}
 
 # C declarations mirrored from include/ih.h: name -> (restype, argtypes)
 _P = ctypes.c_void_p
@@ -30,12 +35,13 @@ _SZ = ctypes.c_size_t
 SIGNATURES = {
     "ih_version": (ctypes.c_int, []),
     "ih_last_error": (ctypes.c_char_p, []),
-    "ih_build_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I32, _P]),
-    "ih_build": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
-    "ih_query_rect": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I64, _P, _P]),
-    "ih_query_weighted": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _I64, _I32, _I32, _P, _P]),
-    "ih_pyramid_desc": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I64, _I32, _P, _P]),
-    "ih_match_candidates": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P, _I64, _I32, _P, _P, _P]),
+    "ih_build_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I32, _I32, _P]),
+    "ih_build": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "ih_query_rect": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I64, _P, _P]),
+    "ih_query_weighted": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _I64, _I32, _I32, _P, _P]),
+    "ih_pyramid_desc": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I64, _I32, _P, _P]),
+    "ih_match_candidates": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P, _I64, _I32,
+                                           _P, _P, _P]),
     "ih_profile_events": (ctypes.c_int, [_P, _P]),
 }
 
@@ -45,12 +51,15 @@ class IHError(RuntimeError):
 
 
 class TileCfg(ctypes.Structure):
-    _fields_ = [("tile_h", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32),
+    """Tile shape of the build (see ih_tile_cfg in include/ih.h)."""
+    _fields_ = [("tile_h", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("planes_per_wave", ctypes.c_int32)]
 
     def __repr__(self):
-        return "TileCfg(tile_h=%d, cols_per_lane=%d, planes_per_wave=%d)" % (
-            self.tile_h, self.cols_per_lane, self.planes_per_wave)
+        return "TileCfg(%d, %d, %d)" % (self.tile_h, self.tile_w, self.planes_per_wave)
+
+    def key(self):
+        return (self.tile_h, self.tile_w, self.planes_per_wave)
 
 
 def lib_path() -> str:
@@ -96,12 +105,32 @@ def _p(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _layout(layout: str) -> int:
+    if layout not in LAYOUTS:
+        raise IHError("layout must be 'bhw' or 'hwb'")
+    return LAYOUTS[layout]
+
+
+def shape_of(P: int, H: int, W: int, layout: str = "bhw"):
+    return (P, H, W) if _layout(layout) == IH_BHW else (H, W, P)
+
+
+def _phw(t: torch.Tensor, layout: str):
+    if t.dim() != 3:
+        raise IHError("integral histogram must be 3-D")
+    if _layout(layout) == IH_BHW:
+        P, H, W = t.shape
+    else:
+        H, W, P = t.shape
+    return P, H, W
+
+
 def version() -> int:
     return lib().ih_version()
 
 
-def workspace_size(H, W, C, bins, moments=False, cfg: Optional[TileCfg] = None) -> int:
-    n = lib().ih_build_workspace_size(H, W, C, bins, int(bool(moments)),
+def workspace_size(H, W, C, bins, moments=False, cfg: Optional[TileCfg] = None, layout: str = "bhw") -> int:
+    n = lib().ih_build_workspace_size(H, W, C, bins, int(bool(moments)), _layout(layout),
                                       ctypes.byref(cfg) if cfg is not None else None)
     if n == 0:
         raise IHError("ih_build_workspace_size: %s" % lib().ih_last_error().decode())
@@ -111,11 +140,12 @@ def workspace_size(H, W, C, bins, moments=False, cfg: Optional[TileCfg] = None) 
 def ih_build(img: torch.Tensor, bins: int, value_bits: Optional[int] = None, moments: bool = False,
              cfg: Optional[TileCfg] = None, out: Optional[torch.Tensor] = None,
              mom_out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
-             ws: Optional[torch.Tensor] = None):
+             ws: Optional[torch.Tensor] = None, layout: str = "bhw"):
     """Integral histogram of a C x H x W (or H x W) uint8/uint16 image.
 
-    Returns ``ih`` (P x H x W int32) or ``(ih, mom_x, mom_y)`` when ``moments``
-    (moment tensors are int32 views of the uint32 values stored modulo 2^32).
+    Returns ``ih`` or ``(ih, mom_x, mom_y)`` when ``moments`` (moment tensors
+    are int32 views of the uint32 values stored modulo 2^32); shapes follow
+    ``layout``.
     """
     _dev(img, "img")
     if img.dim() == 2:
@@ -130,22 +160,27 @@ def ih_build(img: torch.Tensor, bins: int, value_bits: Optional[int] = None, mom
     bits = maxbits if value_bits is None else value_bits
     P = C * bins
     dev = img.device
+    shp = shape_of(P, H, W, layout)
     if out is None:
-        out = torch.empty((P, H, W), dtype=torch.int32, device=dev)
+        out = torch.empty(shp, dtype=torch.int32, device=dev)
     _dev(out, "out", torch.int32)
+    if out.numel() != P * H * W:
+        raise IHError("out must hold P*H*W values")
     mx = my = None
     if moments:
         if mom_out is None:
-            mx = torch.empty((P, H, W), dtype=torch.int32, device=dev)
-            my = torch.empty((P, H, W), dtype=torch.int32, device=dev)
+            mx = torch.empty(shp, dtype=torch.int32, device=dev)
+            my = torch.empty(shp, dtype=torch.int32, device=dev)
         else:
             mx, my = mom_out
         _dev(mx, "mom_x", torch.int32)
         _dev(my, "mom_y", torch.int32)
-    need = workspace_size(H, W, C, bins, moments, cfg)
+        if mx.numel() != P * H * W or my.numel() != P * H * W:
+            raise IHError("moment outputs must hold P*H*W values")
+    need = workspace_size(H, W, C, bins, moments, cfg, layout)
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    rc = lib().ih_build(_p(img), dt, H, W, C, bins, bits, _p(out), _p(mx), _p(my),
+    rc = lib().ih_build(_p(img), dt, H, W, C, bins, bits, _layout(layout), _p(out), _p(mx), _p(my),
                         ctypes.byref(cfg) if cfg is not None else None, _p(ws),
                         ws.numel() * ws.element_size(), _stream(img))
     _check(rc, "ih_build")
@@ -159,33 +194,35 @@ def _rects(rects: torch.Tensor, name="rects") -> torch.Tensor:
     return rects
 
 
-def ih_query_rect(ih: torch.Tensor, rects: torch.Tensor, out: Optional[torch.Tensor] = None):
+def ih_query_rect(ih: torch.Tensor, rects: torch.Tensor, out: Optional[torch.Tensor] = None,
+                  layout: str = "bhw"):
     """Eq. 2.16 region histograms: n x P int32."""
     _dev(ih, "ih", torch.int32)
-    P, H, W = ih.shape
+    P, H, W = _phw(ih, layout)
     _rects(rects)
     n = rects.shape[0]
     if out is None:
         out = torch.empty((n, P), dtype=torch.int32, device=ih.device)
     _dev(out, "out", torch.int32)
-    _check(lib().ih_query_rect(_p(ih), P, H, W, _p(rects), n, _p(out), _stream(ih)), "ih_query_rect")
+    _check(lib().ih_query_rect(_p(ih), P, H, W, _layout(layout), _p(rects), n, _p(out), _stream(ih)),
+           "ih_query_rect")
     return out
 
 
 def ih_query_weighted(ih: torch.Tensor, mom_x: torch.Tensor, mom_y: torch.Tensor, C: int,
                       rects: torch.Tensor, l1_normalize: bool = False,
-                      out: Optional[torch.Tensor] = None):
+                      out: Optional[torch.Tensor] = None, layout: str = "bhw"):
     """Manhattan-weighted local histograms (SWIH): n x P float32."""
     _dev(ih, "ih", torch.int32)
     _dev(mom_x, "mom_x", torch.int32)
     _dev(mom_y, "mom_y", torch.int32)
-    P, H, W = ih.shape
+    P, H, W = _phw(ih, layout)
     _rects(rects)
     n = rects.shape[0]
     if out is None:
         out = torch.empty((n, P), dtype=torch.float32, device=ih.device)
     _dev(out, "out", torch.float32)
-    _check(lib().ih_query_weighted(_p(ih), _p(mom_x), _p(mom_y), P, H, W, C, _p(rects), n,
+    _check(lib().ih_query_weighted(_p(ih), _p(mom_x), _p(mom_y), P, H, W, C, _layout(layout), _p(rects), n,
                                    IH_MANHATTAN, int(bool(l1_normalize)), _p(out), _stream(ih)),
            "ih_query_weighted")
     return out
@@ -196,26 +233,27 @@ def cells(levels: int) -> int:
 
 
 def ih_pyramid_desc(ih: torch.Tensor, wins: torch.Tensor, levels: int = 3,
-                    out: Optional[torch.Tensor] = None):
+                    out: Optional[torch.Tensor] = None, layout: str = "bhw"):
     """Spatial-pyramid descriptors of windows {r, c, h, w}: n x cells x P int32."""
     _dev(ih, "ih", torch.int32)
-    P, H, W = ih.shape
+    P, H, W = _phw(ih, layout)
     _rects(wins, "wins")
     n = wins.shape[0]
     if out is None:
         out = torch.empty((n, cells(levels), P), dtype=torch.int32, device=ih.device)
     _dev(out, "out", torch.int32)
-    _check(lib().ih_pyramid_desc(_p(ih), P, H, W, _p(wins), n, levels, _p(out), _stream(ih)),
+    _check(lib().ih_pyramid_desc(_p(ih), P, H, W, _layout(layout), _p(wins), n, levels, _p(out), _stream(ih)),
            "ih_pyramid_desc")
     return out
 
 
 def ih_match_candidates(ih: torch.Tensor, tmpl_desc: torch.Tensor, win_h: int, win_w: int,
                         origins: torch.Tensor, levels: int = 3, metric: str = "chi2",
-                        dist: Optional[torch.Tensor] = None, best: Optional[torch.Tensor] = None):
+                        dist: Optional[torch.Tensor] = None, best: Optional[torch.Tensor] = None,
+                        layout: str = "bhw"):
     """Exhaustive candidate search: (n distances float32, best index int32[1])."""
     _dev(ih, "ih", torch.int32)
-    P, H, W = ih.shape
+    P, H, W = _phw(ih, layout)
     _dev(tmpl_desc, "tmpl_desc", torch.int32)
     _dev(origins, "origins", torch.int32)
     if origins.dim() != 2 or origins.shape[1] != 2:
@@ -229,8 +267,8 @@ def ih_match_candidates(ih: torch.Tensor, tmpl_desc: torch.Tensor, win_h: int, w
         best = torch.empty(1, dtype=torch.int32, device=ih.device)
     _dev(dist, "dist", torch.float32)
     _dev(best, "best", torch.int32)
-    _check(lib().ih_match_candidates(_p(ih), P, H, W, _p(tmpl_desc), win_h, win_w, levels, _p(origins), n,
-                                     METRICS[metric], _p(dist), _p(best), _stream(ih)),
+    _check(lib().ih_match_candidates(_p(ih), P, H, W, _layout(layout), _p(tmpl_desc), win_h, win_w, levels,
+                                     _p(origins), n, METRICS[metric], _p(dist), _p(best), _stream(ih)),
            "ih_match_candidates")
     return dist, best
 
@@ -240,5 +278,7 @@ def ih_profile_events(start: Optional[torch.cuda.Event], stop: Optional[torch.cu
     if start is None:
         _check(lib().ih_profile_events(None, None), "ih_profile_events")
     else:
+        if not start.cuda_event or not stop.cuda_event:
+            raise IHError("events must have been recorded once (torch creates them lazily)")
         _check(lib().ih_profile_events(ctypes.c_void_p(start.cuda_event), ctypes.c_void_p(stop.cuda_event)),
                "ih_profile_events")

@@ -1,0 +1,119 @@
+"""Autotuner for the build's tile shape.
+
+For one image shape (H, W, C, bins, dtype, moments, layout) it times every
+legal tile shape of ``ih_build`` on the device with HIP events and keeps the
+fastest.  Results are cached in a JSON file (``IH_TUNE_CACHE``, default
+``tune_cache.json`` next to this module) keyed by the shape and the device
+name, so a shape is tuned once per device.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import threading
+from typing import Dict, List, Optional, Tuple
+
+import torch
+
+from . import ih
+
+_CACHE_PATH = os.environ.get("IH_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                          "tune_cache.json"))
+_lock = threading.Lock()
+_cache: Optional[Dict[str, List[int]]] = None
+
+
+def _load() -> Dict[str, List[int]]:
+    global _cache
+    if _cache is None:
+        try:
+            with open(_CACHE_PATH) as f:
+                _cache = json.load(f)
+        except (OSError, ValueError):
+            _cache = {}
+    return _cache
+
+
+def _save():
+    tmp = _CACHE_PATH + ".tmp%d" % os.getpid()
+    try:
+        with open(tmp, "w") as f:
+            json.dump(_cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, _CACHE_PATH)
+    except OSError:
+        pass
+
+
+def key(H, W, C, bins, dtype, moments, layout, device=None) -> str:
+    name = torch.cuda.get_device_name(device) if torch.cuda.is_available() else "cpu"
+    return "%s|%dx%dx%d|b%d|%s|m%d|%s" % (name, C, H, W, bins, str(dtype).replace("torch.", ""),
+                                          int(bool(moments)), layout)
+
+
+def candidates(H, W, C, bins, moments, layout) -> List[ih.TileCfg]:
+    """Every tile shape the library accepts for this image (filtered by size)."""
+    out = []
+    if layout == "bhw":
+        for th, tw, pg in itertools.product((8, 16, 32, 64, 128), (64, 128, 256), (1, 2, 4, 8, 16)):
+            if th * tw > 32768 or (moments and pg * tw // 64 > 32) or pg > max(1, 2 * bins):
+                continue
+            if th > 2 * H or tw > 2 * max(W, 64):
+                continue
+            out.append(ih.TileCfg(th, tw, pg))
+    else:
+        for th, tw in itertools.product((4, 8, 16, 32, 64), (16, 32, 64)):
+            if moments and tw > 32:
+                continue
+            if th > 2 * H or tw > 2 * max(W, 16):
+                continue
+            out.append(ih.TileCfg(th, tw, 64))
+    return out
+
+
+def _time(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(img: torch.Tensor, bins: int, value_bits: Optional[int] = None, moments: bool = False,
+         layout: str = "bhw", reps: int = 5, force: bool = False, verbose: bool = False
+         ) -> Tuple[ih.TileCfg, Dict[str, float]]:
+    """Return the fastest tile shape for this image shape (cached per device)."""
+    if img.dim() == 2:
+        img = img.unsqueeze(0)
+    C, H, W = img.shape
+    k = key(H, W, C, bins, img.dtype, moments, layout, img.device)
+    with _lock:
+        cache = _load()
+        if not force and k in cache:
+            return ih.TileCfg(*cache[k]), {}
+    P = C * bins
+    shp = ih.shape_of(P, H, W, layout)
+    out = torch.empty(shp, dtype=torch.int32, device=img.device)
+    mom = (torch.empty_like(out), torch.empty_like(out)) if moments else None
+    cands = candidates(H, W, C, bins, moments, layout)
+    ws_need = max(ih.workspace_size(H, W, C, bins, moments, c, layout) for c in cands)
+    ws = torch.empty(ws_need, dtype=torch.uint8, device=img.device)
+    times: Dict[str, float] = {}
+    best, best_t = None, float("inf")
+    for cfg in cands:
+        t = _time(lambda: ih.ih_build(img, bins, value_bits, moments, cfg, out, mom, ws, layout), reps)
+        times[repr(cfg)] = t
+        if verbose:
+            print("tune %s %s: %.4f ms" % (k, cfg, t), flush=True)
+        if t < best_t:
+            best, best_t = cfg, t
+    with _lock:
+        cache = _load()
+        cache[k] = list(best.key())
+        _save()
+    return best, times

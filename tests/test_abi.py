@@ -54,40 +54,49 @@ def test_workspace_size_host_only(lib):
     assert m > n
     # carries are a small fraction of the 39 MB integral histogram
     assert n < 0.2 * 480 * 640 * 32 * 4
-    assert lib.ih_build_workspace_size(0, 640, 1, 32, 0, None) == 0
-    assert lib.ih_build_workspace_size(480, 640, 1, 300, 0, None) == 0
+    assert ih.workspace_size(480, 640, 1, 32, layout="hwb") > 0
+    assert lib.ih_build_workspace_size(0, 640, 1, 32, 0, 0, None) == 0
+    assert lib.ih_build_workspace_size(480, 640, 1, 300, 0, 0, None) == 0
     assert b"bins" in lib.ih_last_error()
+    assert lib.ih_build_workspace_size(480, 640, 1, 32, 0, 5, None) == 0
+    assert b"layout" in lib.ih_last_error()
 
 
 def test_host_argument_errors(lib):
     from paper_1711_01656_amd import ih
     P = ctypes.c_void_p
     fake = P(0x1000)
-    # NULL image
-    assert lib.ih_build(None, 0, 4, 4, 1, 2, 8, fake, None, None, None, fake, 1 << 20, None) == -1
-    # only one moment pointer
-    assert lib.ih_build(fake, 0, 4, 4, 1, 2, 8, fake, fake, None, None, fake, 1 << 20, None) == -1
-    # bad dtype, bad bits, bins beyond 2^bits
-    assert lib.ih_build(fake, 7, 4, 4, 1, 2, 8, fake, None, None, None, fake, 1 << 20, None) == -1
-    assert lib.ih_build(fake, 0, 4, 4, 1, 2, 9, fake, None, None, None, fake, 1 << 20, None) == -1
-    assert lib.ih_build(fake, 0, 4, 4, 1, 8, 2, fake, None, None, None, fake, 1 << 20, None) == -1
-    # too small a workspace
-    assert lib.ih_build(fake, 0, 64, 64, 1, 8, 8, fake, None, None, None, fake, 16, None) == -6
-    # H*W beyond int32 counts
-    assert lib.ih_build(fake, 0, 65536, 65536, 1, 8, 8, fake, None, None, None, fake, 1 << 20, None) == -3
-    # bad tile configurations
-    for cfg in (ih.TileCfg(0, 1, 1), ih.TileCfg(32, 3, 1), ih.TileCfg(32, 1, 3), ih.TileCfg(256, 4, 1)):
-        assert lib.ih_build(fake, 0, 64, 64, 1, 8, 8, fake, None, None, ctypes.byref(cfg), fake,
-                            1 << 30, None) < 0
+    big = 1 << 30
+
+    def build(img=fake, dt=0, H=64, W=64, C=1, bins=8, bits=8, layout=0, out=fake, mx=None, my=None,
+              cfg=None, ws=fake, wsb=big):
+        return lib.ih_build(img, dt, H, W, C, bins, bits, layout, out, mx, my, cfg, ws, wsb, None)
+
+    assert build(img=None) == -1                      # NULL image
+    assert build(mx=fake) == -1                       # only one moment pointer
+    assert build(dt=7) == -1                          # unknown dtype
+    assert build(bits=9) == -1                        # more bits than uint8 holds
+    assert build(bins=8, bits=2) == -1                # bins beyond 2^bits
+    assert build(layout=3) == -1                      # unknown layout
+    assert build(wsb=16) == -6                        # workspace too small
+    assert build(ws=None) == -6                       # no workspace
+    assert build(H=65536, W=65536) == -3              # H*W beyond int32 counts
+    for layout, cfg in ((0, ih.TileCfg(0, 64, 1)), (0, ih.TileCfg(32, 3, 1)), (0, ih.TileCfg(32, 64, 3)),
+                        (0, ih.TileCfg(256, 256, 1)), (1, ih.TileCfg(32, 128, 64)), (1, ih.TileCfg(32, 32, 8)),
+                        (0, ih.TileCfg(32, 256, 16))):
+        mom = fake if cfg.key() == (32, 256, 16) else None
+        assert build(layout=layout, cfg=ctypes.byref(cfg), mx=mom, my=mom) < 0, cfg
     # queries
-    assert lib.ih_query_rect(fake, 0, 4, 4, fake, 1, fake, None) == -1
-    assert lib.ih_query_rect(fake, 2, 4, 4, fake, -1, fake, None) == -1
-    assert lib.ih_query_rect(None, 2, 4, 4, None, 0, None, None) == 0       # nothing to do
-    assert lib.ih_query_weighted(fake, fake, fake, 6, 4, 4, 4, fake, 1, 0, 0, fake, None) == -1
-    assert lib.ih_query_weighted(fake, fake, fake, 8, 4, 4, 1, fake, 1, 9, 0, fake, None) == -4
-    assert lib.ih_pyramid_desc(fake, 8, 4, 4, fake, 1, 5, fake, None) == -1
-    assert lib.ih_match_candidates(fake, 8, 4, 4, fake, 2, 2, 3, fake, 1, 7, fake, fake, None) == -1
-    assert lib.ih_match_candidates(fake, 8, 4, 4, fake, 0, 2, 3, fake, 1, 0, fake, fake, None) == -1
+    assert lib.ih_query_rect(fake, 0, 4, 4, 0, fake, 1, fake, None) == -1
+    assert lib.ih_query_rect(fake, 2, 4, 4, 0, fake, -1, fake, None) == -1
+    assert lib.ih_query_rect(fake, 2, 4, 4, 9, fake, 1, fake, None) == -1
+    assert lib.ih_query_rect(None, 2, 4, 4, 0, None, 0, None, None) == 0       # nothing to do
+    assert lib.ih_query_weighted(fake, fake, fake, 6, 4, 4, 4, 0, fake, 1, 0, 0, fake, None) == -1
+    assert lib.ih_query_weighted(fake, fake, fake, 8, 4, 4, 1, 0, fake, 1, 9, 0, fake, None) == -4
+    assert lib.ih_pyramid_desc(fake, 8, 4, 4, 0, fake, 1, 5, fake, None) == -1
+    assert lib.ih_match_candidates(fake, 8, 4, 4, 0, fake, 2, 2, 3, fake, 1, 7, fake, fake, None) == -1
+    assert lib.ih_match_candidates(fake, 8, 4, 4, 0, fake, 0, 2, 3, fake, 1, 0, fake, fake, None) == -1
+    assert lib.ih_match_candidates(fake, 8, 4, 4, 2, fake, 2, 2, 3, fake, 1, 0, fake, fake, None) == -1
     assert lib.ih_profile_events(fake, None) == -1
 
 

@@ -1,4 +1,4 @@
-"""GPU parity of ih_build against the CPU oracle (bit-exact)."""
+"""GPU parity of ih_build against the CPU oracle (bit-exact), both layouts."""
 import itertools
 
 import numpy as np
@@ -10,6 +10,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
+LAYOUTS = ["bhw", "hwb"]
 
 
 def ihlib():
@@ -23,6 +24,12 @@ def gpu(a):
 
 def say(*a):
     print(*a, flush=True)
+
+
+def bhw(t, layout):
+    """GPU tensor in `layout` -> numpy P x H x W."""
+    a = t.cpu().numpy()
+    return a if layout == "bhw" else np.ascontiguousarray(a.transpose(2, 0, 1))
 
 
 def rand_img(seed, C, H, W, bits):
@@ -52,29 +59,32 @@ SHAPES = [
     (3, 64, 64, 256, 8),
     (1, 70, 1030, 64, 16),
     (1, 33, 2049, 3, 8),
+    (7, 45, 77, 16, 8),
 ]
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("C,H,W,bins,bits", SHAPES)
-def test_build_bit_exact(C, H, W, bins, bits):
-    say("ih_build", C, H, W, bins, bits)
+def test_build_bit_exact(C, H, W, bins, bits, layout):
+    say("ih_build", layout, C, H, W, bins, bits)
     ih = ihlib()
     for maker in (rand_img, smooth_img):
         img = maker(H * 7 + W, C, H, W, bits)
-        out = ih.ih_build(gpu(img), bins, bits).cpu().numpy()
-        assert np.array_equal(out, oracle.ih(img, bins, bits))
+        out = ih.ih_build(gpu(img), bins, bits, layout=layout)
+        assert np.array_equal(bhw(out, layout), oracle.ih(img, bins, bits))
 
 
-@pytest.mark.parametrize("C,H,W,bins,bits", SHAPES[:6])
-def test_build_moments_exact_mod_2_32(C, H, W, bins, bits):
-    say("ih_build moments", C, H, W, bins, bits)
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("C,H,W,bins,bits", SHAPES[:6] + SHAPES[8:])
+def test_build_moments_exact_mod_2_32(C, H, W, bins, bits, layout):
+    say("ih_build moments", layout, C, H, W, bins, bits)
     ih = ihlib()
     img = rand_img(H + W, C, H, W, bits)
-    out, mx, my = ih.ih_build(gpu(img), bins, bits, moments=True)
+    out, mx, my = ih.ih_build(gpu(img), bins, bits, moments=True, layout=layout)
     omx, omy = oracle.moments(img, bins, bits)
-    assert np.array_equal(out.cpu().numpy(), oracle.ih(img, bins, bits))
-    assert np.array_equal(mod32(mx.cpu().numpy()), mod32(omx))
-    assert np.array_equal(mod32(my.cpu().numpy()), mod32(omy))
+    assert np.array_equal(bhw(out, layout), oracle.ih(img, bins, bits))
+    assert np.array_equal(mod32(bhw(mx, layout)), mod32(omx))
+    assert np.array_equal(mod32(bhw(my, layout)), mod32(omy))
 
 
 def test_build_every_tile_shape():
@@ -84,15 +94,21 @@ def test_build_every_tile_shape():
     ref = oracle.ih(img, bins, 8)
     omx, omy = oracle.moments(img, bins, 8)
     t = gpu(img)
-    for th, cpl, pg in itertools.product((1, 7, 32, 64, 128), (1, 2, 4), (1, 2, 4, 8, 16)):
-        cfg = ih.TileCfg(th, cpl, pg)
-        say("tile", cfg)
-        assert np.array_equal(ih.ih_build(t, bins, cfg=cfg).cpu().numpy(), ref), cfg
-        if pg * cpl <= 32:
-            o, mx, my = ih.ih_build(t, bins, cfg=cfg, moments=True)
-            assert np.array_equal(o.cpu().numpy(), ref), cfg
-            assert np.array_equal(mod32(mx.cpu().numpy()), mod32(omx)), cfg
-            assert np.array_equal(mod32(my.cpu().numpy()), mod32(omy)), cfg
+    shapes = [("bhw", th, tw, pg) for th, tw, pg in itertools.product((1, 7, 32, 64, 128), (64, 128, 256),
+                                                                      (1, 2, 4, 8, 16))]
+    shapes += [("hwb", th, tw, 64) for th, tw in itertools.product((1, 7, 32, 64, 256), (16, 32, 64))]
+    for layout, th, tw, pg in shapes:
+        if th * tw > 32768:
+            continue
+        cfg = ih.TileCfg(th, tw, pg)
+        say("tile", layout, cfg)
+        assert np.array_equal(bhw(ih.ih_build(t, bins, cfg=cfg, layout=layout), layout), ref), cfg
+        mom_ok = (pg * tw // 64 <= 32) if layout == "bhw" else tw <= 32
+        if mom_ok:
+            o, mx, my = ih.ih_build(t, bins, cfg=cfg, moments=True, layout=layout)
+            assert np.array_equal(bhw(o, layout), ref), cfg
+            assert np.array_equal(mod32(bhw(mx, layout)), mod32(omx)), cfg
+            assert np.array_equal(mod32(bhw(my, layout)), mod32(omy)), cfg
 
 
 def test_build_unaligned_output_uses_scalar_stores():
@@ -100,40 +116,47 @@ def test_build_unaligned_output_uses_scalar_stores():
     img = rand_img(6, 1, 40, 256, 8)
     flat = torch.empty(8 * 40 * 256 + 1, dtype=torch.int32, device=DEV)
     out = flat[1:].view(8, 40, 256)           # 4-byte aligned, not 16-byte aligned
-    ih.ih_build(gpu(img), 8, cfg=ih.TileCfg(16, 4, 4), out=out)
+    ih.ih_build(gpu(img), 8, cfg=ih.TileCfg(16, 256, 4), out=out)
     assert np.array_equal(out.cpu().numpy(), oracle.ih(img, 8, 8))
 
 
-def test_build_deterministic_and_workspace_garbage():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_build_deterministic_and_workspace_garbage(layout):
     ih = ihlib()
     img = smooth_img(8, 1, 211, 517, 8)
     t = gpu(img)
-    ws = torch.full((ih.workspace_size(211, 517, 1, 32) // 4 + 16,), -7, dtype=torch.int32, device=DEV)
-    first = ih.ih_build(t, 32, ws=ws.view(torch.uint8))
+    ws = torch.full((ih.workspace_size(211, 517, 1, 32, layout=layout) // 4 + 16,), -7, dtype=torch.int32,
+                    device=DEV)
+    first = ih.ih_build(t, 32, ws=ws.view(torch.uint8), layout=layout)
     for i in range(30):
-        again = ih.ih_build(t, 32, ws=ws.view(torch.uint8))
+        again = ih.ih_build(t, 32, ws=ws.view(torch.uint8), layout=layout)
         assert torch.equal(first, again), i
-    assert np.array_equal(first.cpu().numpy(), oracle.ih(img, 32, 8))
+    assert np.array_equal(bhw(first, layout), oracle.ih(img, 32, 8))
 
 
 def test_build_config1_full():
     ih = ihlib()
     w = synth.config1()
     say("config 640x480x32")
-    out = ih.ih_build(gpu(w.img), w.bins).cpu().numpy()
-    assert np.array_equal(out, oracle.ih(w.img, w.bins, w.bits))
+    ref = oracle.ih(w.img, w.bins, w.bits)
+    for layout in LAYOUTS:
+        out = ih.ih_build(gpu(w.img), w.bins, layout=layout)
+        assert np.array_equal(bhw(out, layout), ref), layout
 
 
-def test_build_config2_full_sampled():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_build_config2_full_sampled(layout):
     ih = ihlib()
     w = synth.config2()
-    say("config 1920x1080, 7ch x 16 bins + moments")
-    out, mx, my = ih.ih_build(gpu(w.img), w.bins, moments=True)
+    say("config 1920x1080, 7ch x 16 bins + moments", layout)
+    out, mx, my = ih.ih_build(gpu(w.img), w.bins, moments=True, layout=layout)
+    if layout == "hwb":      # planes-outermost views for the checks below
+        out, mx, my = (t.permute(2, 0, 1) for t in (out, mx, my))
     H, W = w.H, w.W
     # invariants over the whole tensor, evaluated on the device
     r = torch.arange(1, H + 1, device=DEV).view(H, 1)
     c = torch.arange(1, W + 1, device=DEV).view(1, W)
-    per_ch = out.view(w.C, w.bins, H, W).sum(1, dtype=torch.int64)
+    per_ch = out.reshape(w.C, w.bins, H, W).sum(1, dtype=torch.int64)
     assert bool((per_ch == (r * c).unsqueeze(0)).all())
     idx = oracle.plane_index(w.img, w.bins, w.bits)
     counts = np.bincount(idx.ravel(), minlength=w.P)

@@ -28,16 +28,17 @@ def rand_rects(seed, H, W, n, lo=1, hi=None):
     return synth.rects_uniform(seed, H, W, n, lo, hi)
 
 
-@pytest.fixture(scope="module")
-def scene():
+@pytest.fixture(scope="module", params=["bhw", "hwb"])
+def scene(request):
+    layout = request.param
     img = synth.feature_channels(77, 123, 301)[:3]          # 3 channels
     bins = 8
     ih = ihlib()
     t = gpu(img)
-    H_, mx, my = ih.ih_build(t, bins, moments=True)
+    H_, mx, my = ih.ih_build(t, bins, moments=True, layout=layout)
     ref = oracle.ih(img, bins, 8)
     omx, omy = oracle.moments(img, bins, 8)
-    return dict(img=img, bins=bins, t=t, H=H_, mx=mx, my=my, ref=ref, omx=omx, omy=omy, C=3)
+    return dict(img=img, bins=bins, t=t, H=H_, mx=mx, my=my, ref=ref, omx=omx, omy=omy, C=3, L=layout)
 
 
 def test_query_rect_exact(scene):
@@ -46,14 +47,14 @@ def test_query_rect_exact(scene):
     extra = np.array([[0, 0, 123, 301], [5, 5, 5, 9], [0, 0, 1, 1], [122, 300, 123, 301],
                       [-1, 0, 4, 4], [0, 0, 124, 3], [10, 10, 9, 12], [3, 7, 3, 7]], np.int32)
     rects = np.concatenate([rects, extra])
-    out = ih.ih_query_rect(scene["H"], gpu(rects)).cpu().numpy()
+    out = ih.ih_query_rect(scene["H"], gpu(rects), layout=scene["L"]).cpu().numpy()
     assert np.array_equal(out, oracle.query_rect(scene["ref"], rects))
     assert np.array_equal(out[:5000], oracle.query_rect_direct(scene["img"], scene["bins"], 8, rects[:5000]))
 
 
 def test_query_rect_empty_batch(scene):
     ih = ihlib()
-    out = ih.ih_query_rect(scene["H"], torch.empty((0, 4), dtype=torch.int32, device=DEV))
+    out = ih.ih_query_rect(scene["H"], torch.empty((0, 4), dtype=torch.int32, device=DEV), layout=scene["L"])
     assert out.shape == (0, 24)
 
 
@@ -65,7 +66,7 @@ def test_query_weighted_bit_exact_and_tolerance(scene):
     for l1 in (False, True):
         say("weighted l1 =", l1)
         out = ih.ih_query_weighted(scene["H"], scene["mx"], scene["my"], scene["C"], gpu(rects),
-                                   l1_normalize=l1).cpu().numpy()
+                                   l1_normalize=l1, layout=scene["L"]).cpu().numpy()
         _, ref = oracle.weighted_swih(scene["ref"], scene["omx"], scene["omy"], scene["C"], rects, l1norm=l1)
         assert np.array_equal(np.isnan(out), np.isnan(ref))
         ok = ~np.isnan(ref)
@@ -82,6 +83,12 @@ def test_query_weighted_wrap_guard():
     H_, mx, my = ih.ih_build(gpu(img), 2, moments=True)
     out = ih.ih_query_weighted(H_, mx, my, 1, gpu(np.array([[0, 0, 64, 64]], np.int32))).cpu().numpy()
     assert np.all(np.isfinite(out))
+    # a window whose moment sums could pass 2^32 is refused with NaN
+    img = np.zeros((1, 2048, 2048), np.uint8)
+    H_, mx, my = ih.ih_build(gpu(img), 2, moments=True)
+    out = ih.ih_query_weighted(H_, mx, my, 1, gpu(np.array([[0, 0, 2048, 2048], [0, 0, 1024, 1024]],
+                                                           np.int32))).cpu().numpy()
+    assert np.all(np.isnan(out[0])) and np.all(np.isfinite(out[1]))
 
 
 def test_pyramid_desc_exact(scene):
@@ -95,7 +102,7 @@ def test_pyramid_desc_exact(scene):
     wins = np.array(wins, np.int32)
     for levels in (1, 2, 3, 4):
         say("pyramid levels", levels)
-        out = ih.ih_pyramid_desc(scene["H"], gpu(wins), levels).cpu().numpy()
+        out = ih.ih_pyramid_desc(scene["H"], gpu(wins), levels, layout=scene["L"]).cpu().numpy()
         assert np.array_equal(out, oracle.pyramid_desc(scene["ref"], wins, levels))
 
 
@@ -108,7 +115,8 @@ def test_match_candidates(scene, metric, levels):
     tr, tc, th, tw = 40, 120, 24, 20
     tmpl = oracle.pyramid_desc_direct(img, bins, 8, [[tr, tc, th, tw]], levels)[0]
     origins = synth.grid_origins(tr - 45, tc - 30, 91, 61)   # partly outside the frame
-    d, b = ih.ih_match_candidates(scene["H"], gpu(tmpl), th, tw, gpu(origins), levels, metric)
+    d, b = ih.ih_match_candidates(scene["H"], gpu(tmpl), th, tw, gpu(origins), levels, metric,
+                                  layout=scene["L"])
     d = d.cpu().numpy().astype(np.float64)
     b = int(b.item())
     od, ob = oracle.match_direct(img, bins, 8, tmpl, th, tw, levels, origins, metric)
@@ -127,24 +135,26 @@ def test_match_no_candidate_inside(scene):
     ih = ihlib()
     tmpl = np.zeros((21, 24), np.int32)
     origins = np.array([[-5, -5], [200, 0]], np.int32)
-    d, b = ih.ih_match_candidates(scene["H"], gpu(tmpl), 8, 8, gpu(origins), 3, "chi2")
+    d, b = ih.ih_match_candidates(scene["H"], gpu(tmpl), 8, 8, gpu(origins), 3, "chi2", layout=scene["L"])
     assert int(b.item()) == -1 and np.all(np.isinf(d.cpu().numpy()))
 
 
-def test_config1_rect_queries_full():
+@pytest.mark.parametrize("layout", ["bhw", "hwb"])
+def test_config1_rect_queries_full(layout):
     ih = ihlib()
     w = synth.config1()
-    H_ = ih.ih_build(gpu(w.img), w.bins)
-    out = ih.ih_query_rect(H_, gpu(w.rects)).cpu().numpy()
+    H_ = ih.ih_build(gpu(w.img), w.bins, layout=layout)
+    out = ih.ih_query_rect(H_, gpu(w.rects), layout=layout).cpu().numpy()
     assert np.array_equal(out, oracle.query_rect_direct(w.img, w.bins, w.bits, w.rects))
 
 
-def test_config2_weighted_full_sampled():
+@pytest.mark.parametrize("layout", ["bhw", "hwb"])
+def test_config2_weighted_full_sampled(layout):
     ih = ihlib()
     w = synth.config2()
-    say("config 1920x1080 weighted 100k")
-    H_, mx, my = ih.ih_build(gpu(w.img), w.bins, moments=True)
-    out = ih.ih_query_weighted(H_, mx, my, w.C, gpu(w.windows)).cpu().numpy()
+    say("config 1920x1080 weighted 100k", layout)
+    H_, mx, my = ih.ih_build(gpu(w.img), w.bins, moments=True, layout=layout)
+    out = ih.ih_query_weighted(H_, mx, my, w.C, gpu(w.windows), layout=layout).cpu().numpy()
     assert np.all(np.isfinite(out))
     idx = np.random.default_rng(5).choice(len(w.windows), 300, replace=False)
     bf = oracle.weighted_bruteforce(w.img, w.bins, w.bits, w.windows[idx])
