@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--no-other", action="store_true", help="skip timing the other layout")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run one device fill and one copy of this many MiB (counter calibration)")
-    ap.add_argument("--tile", type=str, default="", help="tile_h,tile_w,planes_per_wave")
+    ap.add_argument("--tile", type=str, default="",
+                    help="tile_h,tile_w,planes_per_wave (default: autotuned at start-up)")
     return ap.parse_args()
 
 
@@ -153,9 +154,12 @@ def main():
     C, H, W, P, bins = w.C, w.H, w.W, w.P, w.bins
     img = torch.from_numpy(w.img).to(dev)
     wins = torch.from_numpy(w.windows).to(dev)
-    cfg = None
     if args.tile:
         cfg = ih.TileCfg(*(int(v) for v in args.tile.split(",")))
+    else:
+        from paper_1711_01656_amd import tune
+        cfg, _ = tune.tune(img, bins, moments=True, layout=args.layout, reps=3)
+        print("autotuned tile %r" % cfg, file=sys.stderr, flush=True)
     # template: a 32x32 window of the frame; candidates: 129 x 129 origins around it
     tr = int(rng_win.integers(64, H - 32 - 64))
     tc = int(rng_win.integers(64, W - 32 - 64))
@@ -197,9 +201,11 @@ def main():
     other = None
     if not args.no_other:
         lo = "bhw" if args.layout == "hwb" else "hwb"
-        so = Step(ih, torch, w, img, wins, origins, tmpl_win, lo, None)
+        from paper_1711_01656_amd import tune
+        ocfg, _ = tune.tune(img, bins, moments=True, layout=lo, reps=3)
+        so = Step(ih, torch, w, img, wins, origins, tmpl_win, lo, ocfg)
         oms = time_calls(torch, so, 5)
-        other = {"layout": lo, "ms_per_step": round(oms, 4),
+        other = {"layout": lo, "tile": repr(ocfg), "ms_per_step": round(oms, 4),
                  "stages_ms": {s: round(time_calls(torch, getattr(so, s), 5), 4)
                                for s in ("build", "weighted", "rect", "match")}}
         del so
@@ -235,7 +241,7 @@ def main():
                         "100k weighted + 100k plain window queries (16-256 px); 129x129 pyramid chi2 search",
             "H": H, "W": W, "channels": C, "bins_per_channel": bins, "planes": P,
             "weighted_queries": nq, "rect_queries": nq, "candidates": int(origins.shape[0]),
-            "layout": args.layout, "tile": repr(cfg) if cfg else "heuristic",
+            "layout": args.layout, "tile": repr(cfg),
         },
         "stages_ms": stages,
         "build_gpxbins_per_s": round(H * W * P / (stages["build"] * 1e-3) / 1e9, 3),

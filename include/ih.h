@@ -225,6 +225,65 @@ int ih_match_candidates(const int32_t *ih, int32_t P, int32_t H, int32_t W,
                         float *dist, int32_t *best, void *stream);
 
 /*
+ * Batched build and search over many frames of uneven size and bin count in
+ * one persistent launch (the device-resident analogue of the thesis's
+ * dual-buffered frame pipeline, Alg. 10): every frame's integral histogram
+ * (bin-major), optionally its template descriptor and its candidate search
+ * (3-level pyramid, as ih_pyramid_desc / ih_match_candidates).  A frame's
+ * candidate search starts as soon as its own histogram is complete, while
+ * other frames are still being built.  The call enqueues two kernels (a
+ * counter reset and the persistent kernel), allocates nothing and does not
+ * synchronise, so it may be captured in a HIP graph and replayed.
+ */
+typedef struct {
+  const void *img;          /* device, C x H x W values of the batch dtype   */
+  int32_t *ih;              /* device, out: P x H x W int32 (bin-major)      */
+  int32_t H, W, C, bins, value_bits;
+  ih_tile_cfg tile;         /* tile shape; tile_h == 0 selects the heuristic.
+                               planes_per_wave must be 1, 2, 4 or 8          */
+  /* candidate search; n_cand == 0 skips it for this frame                   */
+  const int32_t *tmpl_desc; /* device, 21 x P template descriptor, or NULL to
+                               compute it from tmpl_win of this frame       */
+  int32_t tmpl_win[4];      /* {r, c, h, w}, used when tmpl_desc is NULL     */
+  int32_t *tmpl_out;        /* device, out: 21 x P, when tmpl_desc is NULL   */
+  int32_t win_h, win_w;     /* candidate window                              */
+  const int32_t *origins;   /* device, n_cand x 2 (row, column)              */
+  int64_t n_cand;
+  float *dist;              /* device, out: n_cand distances                 */
+  int32_t *best;            /* device, out: best candidate index or -1       */
+} ih_frame;
+
+/* Bytes of the plan for n frames (0 when n < 1). */
+size_t ih_batch_plan_bytes(int32_t n);
+
+/*
+ * ih_batch_plan - host-only: validate n frames, choose their tile shapes and
+ * ticket ranges, and write the plan (plan_bytes >= ih_batch_plan_bytes(n)).
+ * dtype (IH_U8 / IH_U16) and metric (IH_CHI2 / IH_L1 / IH_PMK) are shared by
+ * the batch.  *ws_bytes receives the workspace size ih_build_batch needs.  The
+ * caller copies the plan to device memory once; it stays valid for every
+ * launch with the same frames and buffers.
+ */
+int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype,
+                  int32_t metric, void *plan, size_t plan_bytes,
+                  size_t *ws_bytes);
+
+/*
+ * ih_build_batch - enqueue the batch described by a plan.
+ *   plan_host  the plan as written by ih_batch_plan (host memory).
+ *   plan_dev   a device copy of the same bytes.
+ *   ws         device workspace of ws_bytes (contents on entry do not matter).
+ * After the launch completes, the 32-bit word at ws + ih_batch_error_offset(n)
+ * is non-zero if a dependency wait hit its safety bound (results then
+ * unreliable); it is zero in every correct run.
+ */
+int ih_build_batch(const void *plan_host, const void *plan_dev, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* Byte offset in the batch workspace of the error word (see ih_build_batch). */
+size_t ih_batch_error_offset(int32_t n);
+
+/*
  * ih_profile_events - profiling hook.  When both are non-NULL (hipEvent_t),
  * every later ih_build on this thread records `start` on its stream just
  * before its final write-out kernel and `stop` just after it, so that the

@@ -6,6 +6,7 @@ after Poostchi 2017 (arXiv:1711.01656).  See ``include/ih.h`` for the C ABI
 and ``paper_1711_01656_amd.ih`` for the Python binding.
 """
 from .ih import (  # noqa: F401
+    Batch,
     IHError,
     TileCfg,
     cells,

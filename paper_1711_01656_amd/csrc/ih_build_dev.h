@@ -1,0 +1,412 @@
+// Device bodies of the integral-histogram build passes, shared by the
+// stand-alone kernels (ih_build.hip) and the persistent batched kernel
+// (ih_batch.hip).  Each body processes one work unit given by index.
+#pragma once
+
+#include "ih_internal.h"
+
+namespace ih {
+
+// Column-count carry arrays (CC, CCX) are indexed [p][I][c] for the bin-major
+// write-out and [I][c][p] for the planes-innermost one, so that each form
+// reads them with unit stride.
+__host__ __device__ __forceinline__ int64_t cc_index(const Geom &g, int64_t p, int I, int64_t c) {
+  return g.layout == IH_BHW ? (p * g.nTR + I) * (int64_t)g.W + c : ((int64_t)I * g.W + c) * g.P + p;
+}
+
+// --------------------------------------------------------------------------
+// 1. Per-tile histograms.  One workgroup per (channel, tile).
+//    CC  (p, I, c)        plane-p count of column c over the tile's rows
+//    RC  [ch][j][r][bin]  plane count of row r over the tile's columns
+//    TT  [p][I][j]        tile totals
+//    CCX (sum of rows), RCY (sum of columns), TTX, TTY for the moments.
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const Geom &g, int bits, int bc,
+                                               uint32_t *__restrict__ ws, int blkid, uint32_t *lds) {
+  const int twp = g.TW + 4;
+  uint8_t *bin_s = reinterpret_cast<uint8_t *>(lds);
+  uint32_t *hist = lds + (((size_t)g.TH * twp + 3) >> 2);
+  const int tid = threadIdx.x;
+  int blk = blkid;
+  const int j = blk % g.nTC; blk /= g.nTC;
+  const int I = blk % g.nTR;
+  const int ch = blk / g.nTR;
+  const int R0 = I * g.TH, C0 = j * g.TW;
+  const int th = min(g.TH, g.H - R0), tw = min(g.TW, g.W - C0);
+  const T *src = img + (int64_t)ch * g.H * g.W;
+
+  for (int idx = tid; idx < th * tw; idx += 256) {
+    const int r = idx / tw, c = idx - r * tw;
+    const uint32_t v = src[(int64_t)(R0 + r) * g.W + C0 + c];
+    bin_s[r * twp + c] = (uint8_t)(((uint64_t)v * g.bins) >> bits);
+  }
+  uint32_t *CC = ws + g.off_cc, *RC = ws + g.off_rc, *TT = ws + g.off_tt;
+  uint32_t *CCX = ws + g.off_ccx, *RCY = ws + g.off_rcy;
+  uint32_t *TTX = ws + g.off_ttx, *TTY = ws + g.off_tty;
+  const int stride = bc + 1;
+
+  for (int b0 = 0; b0 < g.bins; b0 += bc) {
+    const int nb = min(bc, g.bins - b0);
+    // ---- columns: each thread owns a column, rows split over segments
+    const int nseg = g.TW >= 256 ? 1 : 256 / g.TW;
+    const int colw = g.TW * stride;
+    __syncthreads();
+    for (int i = tid; i < colw * (g.mom ? 2 : 1); i += 256) hist[i] = 0;
+    __syncthreads();
+    for (int idx = tid; idx < tw * nseg; idx += 256) {
+      const int cl = idx % tw, seg = idx / tw;
+      for (int r = seg; r < th; r += nseg) {
+        const int b = (int)bin_s[r * twp + cl] - b0;
+        if (b >= 0 && b < nb) {
+          atomicAdd(&hist[cl * stride + b], 1u);
+          if (g.mom) atomicAdd(&hist[colw + cl * stride + b], (uint32_t)(R0 + r));
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nb * tw; i += 256) {
+      int k, cl;
+      if (g.layout == IH_BHW) { k = i / tw; cl = i - k * tw; }     // unit stride along columns
+      else { cl = i / nb; k = i - cl * nb; }                       // unit stride along planes
+      const int64_t o = cc_index(g, (int64_t)ch * g.bins + b0 + k, I, C0 + cl);
+      CC[o] = hist[cl * stride + k];
+      if (g.mom) CCX[o] = hist[colw + cl * stride + k];
+    }
+    for (int k = tid; k < nb; k += 256) {
+      uint32_t s = 0, sx = 0, sy = 0;
+      for (int cl = 0; cl < tw; ++cl) {
+        const uint32_t n = hist[cl * stride + k];
+        s += n;
+        if (g.mom) { sx += hist[colw + cl * stride + k]; sy += n * (uint32_t)(C0 + cl); }
+      }
+      const size_t p = (size_t)ch * g.bins + b0 + k;
+      const size_t o = (p * g.nTR + I) * (size_t)g.nTC + j;
+      TT[o] = s;
+      if (g.mom) { TTX[o] = sx; TTY[o] = sy; }
+    }
+    // ---- rows: each thread owns a row, columns split over segments
+    const int rseg = g.TH >= 256 ? 1 : 256 / g.TH;
+    const int roww = g.TH * stride;
+    __syncthreads();
+    for (int i = tid; i < roww * (g.mom ? 2 : 1); i += 256) hist[i] = 0;
+    __syncthreads();
+    for (int idx = tid; idx < th * rseg; idx += 256) {
+      const int r = idx % th, seg = idx / th;
+      for (int cl = seg; cl < tw; cl += rseg) {
+        const int b = (int)bin_s[r * twp + cl] - b0;
+        if (b >= 0 && b < nb) {
+          atomicAdd(&hist[r * stride + b], 1u);
+          if (g.mom) atomicAdd(&hist[roww + r * stride + b], (uint32_t)(C0 + cl));
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < th * nb; i += 256) {
+      const int r = i / nb, k = i - r * nb;
+      const size_t o = (((size_t)ch * g.nTC + j) * g.H + R0 + r) * g.bins + b0 + k;
+      RC[o] = hist[r * stride + k];
+      if (g.mom) RCY[o] = hist[roww + r * stride + k];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// 2. Carry scans.  Three independent jobs in one launch, by block range:
+//    A: for every (plane, column) exclusive scan of CC (and CCX) over tile rows
+//    B: for every (channel, row, bin) exclusive scan of RC (and RCY) over tile
+//       columns
+//    C: for every plane, 2-D exclusive scan of TT (and TTX, TTY)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void carry_scan_body(const Geom &g, int64_t nblk_a, int64_t nblk_b,
+                                                uint32_t *__restrict__ ws, int64_t blk) {
+  if (blk < nblk_a) {
+    const int64_t idx = blk * 256 + threadIdx.x;
+    if (idx >= (int64_t)g.P * g.W) return;
+    int64_t p, c;
+    if (g.layout == IH_BHW) { p = idx / g.W; c = idx - p * g.W; }
+    else { c = idx / g.P; p = idx - c * g.P; }
+    const int64_t step = cc_index(g, p, 1, c) - cc_index(g, p, 0, c);
+    uint32_t *a = ws + g.off_cc + cc_index(g, p, 0, c);
+    uint32_t *ax = ws + g.off_ccx + cc_index(g, p, 0, c);
+    uint32_t run = 0, runx = 0;
+    for (int I = 0; I < g.nTR; ++I) {
+      const uint32_t v = a[I * step];
+      a[I * step] = run;
+      run += v;
+      if (g.mom) {
+        const uint32_t vx = ax[I * step];
+        ax[I * step] = runx;
+        runx += vx;
+      }
+    }
+  } else if (blk < nblk_a + nblk_b) {
+    const int64_t idx = (blk - nblk_a) * 256 + threadIdx.x;
+    const int64_t per_ch = (int64_t)g.H * g.bins;
+    if (idx >= per_ch * g.C) return;
+    const int64_t ch = idx / per_ch, rk = idx - ch * per_ch;
+    uint32_t *a = ws + g.off_rc + ch * g.nTC * per_ch + rk;
+    uint32_t *ay = ws + g.off_rcy + ch * g.nTC * per_ch + rk;
+    uint32_t run = 0, runy = 0;
+    for (int j = 0; j < g.nTC; ++j) {
+      const uint32_t v = a[j * per_ch];
+      a[j * per_ch] = run;
+      run += v;
+      if (g.mom) {
+        const uint32_t vy = ay[j * per_ch];
+        ay[j * per_ch] = runy;
+        runy += vy;
+      }
+    }
+  } else {
+    const int64_t p = blk - nblk_a - nblk_b;
+    const int arrays = g.mom ? 3 : 1;
+    for (int a = 0; a < arrays; ++a) {
+      const size_t off = a == 0 ? g.off_tt : a == 1 ? g.off_ttx : g.off_tty;
+      uint32_t *t = ws + off + p * g.nTR * (int64_t)g.nTC;
+      for (int I = threadIdx.x; I < g.nTR; I += 256) {
+        uint32_t run = 0;
+        for (int j = 0; j < g.nTC; ++j) {
+          const uint32_t v = t[I * g.nTC + j];
+          t[I * g.nTC + j] = run;
+          run += v;
+        }
+      }
+      __syncthreads();
+      for (int j = threadIdx.x; j < g.nTC; j += 256) {
+        uint32_t run = 0;
+        for (int I = 0; I < g.nTR; ++I) {
+          const uint32_t v = t[I * g.nTC + j];
+          t[I * g.nTC + j] = run;
+          run += v;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// 3a. Bin-major write-out.  Block x = (channel, tile), block y * waves + wave
+//     = plane group of PG planes.  Lane l owns columns C0 + l*CPL .. + CPL-1.
+// --------------------------------------------------------------------------
+struct FinalArgs {
+  const void *img;
+  int32_t *ih;
+  uint32_t *mx, *my;
+  const uint32_t *ws;
+  int bits;
+  int vec_ok;  // bin-major: W divisible by CPL and the outputs 16-byte aligned
+};
+
+template <int CPL>
+__device__ __forceinline__ void put(int32_t *dst, const uint32_t (&v)[CPL], int cf, int W, bool vec_ok) {
+  if (vec_ok && cf + CPL <= W) {
+    int t[CPL];
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) t[e] = (int)v[e];
+    store_stream<CPL>(dst, t);
+  } else {
+#pragma unroll
+    for (int e = 0; e < CPL; ++e)
+      if (cf + e < W) __builtin_nontemporal_store((int)v[e], dst + e);
+  }
+}
+
+template <typename T, int CPL, int PG, bool MOM>
+__device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, int bx, int by, int wave, int wpb) {
+  const int lane = threadIdx.x & 63;
+  const int grp = by * wpb + wave;
+  const int kb = grp * PG;
+  if (kb >= g.bins) return;
+  const int nk = min(PG, g.bins - kb);
+  int blk = bx;
+  const int j = blk % g.nTC; blk /= g.nTC;
+  const int I = blk % g.nTR;
+  const int ch = blk / g.nTR;
+  const int R0 = I * g.TH, C0 = j * g.TW;
+  const int cf = C0 + lane * CPL;
+  const int rows = min(g.TH, g.H - R0);
+  const int64_t HW = (int64_t)g.H * g.W;
+  const bool vec_ok = a.vec_ok != 0;
+  const T *img = reinterpret_cast<const T *>(a.img) + ch * HW;
+
+  uint32_t col[PG][CPL];
+  uint32_t colx[MOM ? PG : 1][CPL], coly[MOM ? PG : 1][CPL];
+
+  // top boundary row H(p, R0-1, c) (and its moments)
+#pragma unroll
+  for (int k = 0; k < PG; ++k) {
+    if (k < nk) {
+      const int64_t p = (int64_t)ch * g.bins + kb + k;
+      const int64_t crow = (p * g.nTR + I) * (int64_t)g.W;
+      const int64_t cidx = (p * g.nTR + I) * (int64_t)g.nTC + j;
+      uint32_t v[CPL], raw[CPL];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) raw[e] = (cf + e < g.W) ? a.ws[g.off_cc + crow + cf + e] : 0u;
+      v[0] = raw[0];
+#pragma unroll
+      for (int e = 1; e < CPL; ++e) v[e] = v[e - 1] + raw[e];
+      const uint32_t excl = wave_incl_scan(v[CPL - 1]) - v[CPL - 1];
+      const uint32_t corner = a.ws[g.off_tt + cidx];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) col[k][e] = corner + excl + v[e];
+      if constexpr (MOM) {
+        uint32_t vx[CPL], vy[CPL];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          vx[e] = (cf + e < g.W) ? a.ws[g.off_ccx + crow + cf + e] : 0u;
+          vy[e] = raw[e] * (uint32_t)(cf + e);
+        }
+#pragma unroll
+        for (int e = 1; e < CPL; ++e) { vx[e] += vx[e - 1]; vy[e] += vy[e - 1]; }
+        const uint32_t ex = wave_incl_scan(vx[CPL - 1]) - vx[CPL - 1];
+        const uint32_t ey = wave_incl_scan(vy[CPL - 1]) - vy[CPL - 1];
+        const uint32_t cx = a.ws[g.off_ttx + cidx], cy = a.ws[g.off_tty + cidx];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) { colx[k][e] = cx + ex + vx[e]; coly[k][e] = cy + ey + vy[e]; }
+      }
+    }
+  }
+
+  const uint32_t *lc_base = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + kb;
+  const uint32_t *lcy_base = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + kb;
+  int32_t *out_base = a.ih + ((int64_t)ch * g.bins + kb) * HW + cf;
+  uint32_t *mx_base = MOM ? a.mx + ((int64_t)ch * g.bins + kb) * HW + cf : nullptr;
+  uint32_t *my_base = MOM ? a.my + ((int64_t)ch * g.bins + kb) * HW + cf : nullptr;
+
+  for (int rr = 0; rr < rows; ++rr) {
+    const int r = R0 + rr;
+    int b[CPL];
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) {
+      const int c = cf + e;
+      b[e] = c < g.W ? (int)(((uint64_t)img[(int64_t)r * g.W + c] * g.bins) >> a.bits) - kb : -1;
+    }
+    const uint32_t *lc = lc_base + (int64_t)r * g.bins;
+    const uint32_t *lcy = lcy_base + (int64_t)r * g.bins;
+    const int64_t orow = (int64_t)r * g.W;
+#pragma unroll
+    for (int k = 0; k < PG; ++k) {
+      if (k < nk) {
+        uint32_t t = lc[k];
+        uint64_t m[CPL];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) m[e] = ballot(b[e] == k);
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) t = lanes_below(m[e], t);
+        uint32_t pre[CPL];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          t += (b[e] == k) ? 1u : 0u;
+          pre[e] = t;
+          col[k][e] += t;
+        }
+        put<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec_ok);
+        if constexpr (MOM) {
+          uint32_t y[CPL];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            colx[k][e] += (uint32_t)r * pre[e];
+            y[e] = (b[e] == k) ? (uint32_t)(cf + e) : 0u;
+          }
+#pragma unroll
+          for (int e = 1; e < CPL; ++e) y[e] += y[e - 1];
+          const uint32_t ey = wave_incl_scan(y[CPL - 1]) - y[CPL - 1] + lcy[k];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) coly[k][e] += ey + y[e];
+          put<CPL>(reinterpret_cast<int32_t *>(mx_base) + k * HW + orow, colx[k], cf, g.W, vec_ok);
+          put<CPL>(reinterpret_cast<int32_t *>(my_base) + k * HW + orow, coly[k], cf, g.W, vec_ok);
+        }
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// 3b. Planes-innermost write-out.  One wavefront per (tile, chunk of 64
+//     planes); lane = plane.  The lane keeps one register per tile column
+//     (the column prefix) and walks each row left to right keeping the row
+//     prefix; every (row, column) step stores 64 consecutive planes.
+// --------------------------------------------------------------------------
+template <typename T, int TW, bool MOM>
+__device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g, int64_t unit) {
+  const int lane = threadIdx.x & 63;
+  const int nchunk = (g.P + 63) >> 6;
+  if (unit >= (int64_t)g.nTR * g.nTC * nchunk) return;
+  const int chunk = (int)(unit % nchunk);
+  const int64_t tile = unit / nchunk;
+  const int j = (int)(tile % g.nTC), I = (int)(tile / g.nTC);
+  const int p = chunk * 64 + lane;
+  const bool live = p < g.P;
+  const int ch = live ? p / g.bins : 0;
+  const int k = live ? p - ch * g.bins : 0;
+  const int R0 = I * g.TH, C0 = j * TW;
+  const int cols = min(TW, g.W - C0), rows = min(g.TH, g.H - R0);
+  // pixel values of bin k are those in [lo, hi): floor(v * bins / 2^bits) = k
+  const uint32_t lo = (uint32_t)((((uint64_t)k << a.bits) + g.bins - 1) / g.bins);
+  const uint32_t width = (uint32_t)((((uint64_t)(k + 1) << a.bits) + g.bins - 1) / g.bins) - lo;
+  const T *img = reinterpret_cast<const T *>(a.img) + (int64_t)ch * g.H * g.W;
+  const int64_t P = g.P;
+
+  uint32_t col[TW];
+  uint32_t colx[MOM ? TW : 1], coly[MOM ? TW : 1];
+  {
+    const int64_t cidx = ((int64_t)(live ? p : 0) * g.nTR + I) * g.nTC + j;
+    uint32_t run = live ? a.ws[g.off_tt + cidx] : 0u;
+    uint32_t runx = 0, runy = 0;
+    if constexpr (MOM) {
+      runx = live ? a.ws[g.off_ttx + cidx] : 0u;
+      runy = live ? a.ws[g.off_tty + cidx] : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        const int64_t o = ((int64_t)I * g.W + C0 + c) * P + p;
+        const uint32_t v = live ? a.ws[g.off_cc + o] : 0u;
+        run += v;
+        col[c] = run;
+        if constexpr (MOM) {
+          runx += live ? a.ws[g.off_ccx + o] : 0u;
+          runy += v * (uint32_t)(C0 + c);
+          colx[c] = runx;
+          coly[c] = runy;
+        }
+      }
+    }
+  }
+  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  for (int rr = 0; rr < rows; ++rr) {
+    const int r = R0 + rr;
+    const T *row = img + (int64_t)r * g.W + C0;
+    uint32_t v[TW];
+#pragma unroll
+    for (int c = 0; c < TW; ++c) v[c] = c < cols ? (uint32_t)row[c] : 0u;
+    uint32_t rc = live ? lc[(int64_t)r * g.bins] : 0u;
+    uint32_t ry = 0;
+    if constexpr (MOM) ry = live ? lcy[(int64_t)r * g.bins] : 0u;
+    const int64_t base = ((int64_t)r * g.W + C0) * P + p;
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        const uint32_t hit = (v[c] - lo) < width ? 1u : 0u;
+        rc += hit;
+        col[c] += rc;
+        if (live) __builtin_nontemporal_store((int)col[c], a.ih + base + c * P);
+        if constexpr (MOM) {
+          colx[c] += (uint32_t)r * rc;
+          ry += hit * (uint32_t)(C0 + c);
+          coly[c] += ry;
+          if (live) {
+            __builtin_nontemporal_store(colx[c], a.mx + base + c * P);
+            __builtin_nontemporal_store(coly[c], a.my + base + c * P);
+          }
+        }
+      }
+    }
+  }
+}
+
+
+}  // namespace ih

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "ih.h"
 
@@ -75,6 +76,19 @@ __device__ __forceinline__ void store_stream(int *dst, const int (&v)[N]) {
   }
 }
 
+// Addressing of element (p, r, c): base(p) + r * rs + c * cs.
+struct Addr {
+  int64_t base, rs, cs;
+  __device__ __forceinline__ Addr(int layout, int p, int P, int H, int W) {
+    if (layout == IH_BHW) { base = (int64_t)p * H * W; rs = W; cs = 1; }
+    else { base = p; rs = (int64_t)W * P; cs = P; }
+  }
+  template <typename T>
+  __device__ __forceinline__ T at(const T *__restrict__ t, int r, int c) const {
+    return (r < 0 || c < 0) ? (T)0 : t[base + r * rs + c * cs];
+  }
+};
+
 // -------------------------------------------------------- build geometry --
 struct Geom {
   int H, W, C, bins, P;
@@ -88,5 +102,12 @@ struct Geom {
 
 int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, int32_t layout,
               const ih_tile_cfg *cfg, Geom *g);
+
+// LDS budget of the tile-histogram pass of the stand-alone build (bytes).
+constexpr int kLdsBudget = 64 * 1024;
+
+// Bins per histogram pass (bc) and dynamic LDS bytes of the tile-histogram
+// pass for a tile shape within lds_budget bytes.
+int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds);
 
 }  // namespace ih

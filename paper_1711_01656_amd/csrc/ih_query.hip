@@ -8,22 +8,9 @@
 // planes-innermost layout each corner read is one contiguous run across the
 // wavefront; in the bin-major layout every plane's corner lies in its own
 // cache line.
-#include "ih_internal.h"
+#include "ih_match_dev.h"
 
 namespace ih {
-
-// Addressing of element (p, r, c): base(p) + r * rs + c * cs.
-struct Addr {
-  int64_t base, rs, cs;
-  __device__ __forceinline__ Addr(int layout, int p, int P, int H, int W) {
-    if (layout == IH_BHW) { base = (int64_t)p * H * W; rs = W; cs = 1; }
-    else { base = p; rs = (int64_t)W * P; cs = P; }
-  }
-  template <typename T>
-  __device__ __forceinline__ T at(const T *__restrict__ t, int r, int c) const {
-    return (r < 0 || c < 0) ? (T)0 : t[base + r * rs + c * cs];
-  }
-};
 
 // Windows per block for one-thread-per-(window, plane) kernels.
 __host__ __device__ __forceinline__ int per_block(int P) { return P >= 256 ? 1 : 256 / P; }
@@ -125,37 +112,13 @@ template <int LEVELS>
 __global__ __launch_bounds__(256) void k_pyramid_desc(const int32_t *__restrict__ ih, int P, int H, int W,
                                                       int layout, const int32_t *__restrict__ wins, int64_t n,
                                                       int32_t *__restrict__ out) {
-  constexpr int G = 1 << (LEVELS - 1);
   constexpr int CELLS = ((1 << (2 * LEVELS)) - 1) / 3;
   const int qpb = per_block(P);
   for (int idx = threadIdx.x; idx < qpb * P; idx += blockDim.x) {
     const int ql = idx / P, p = idx - ql * P;
     const int64_t q = (int64_t)blockIdx.x * qpb + ql;
     if (q >= n) return;
-    const int r = wins[4 * q], c = wins[4 * q + 1], h = wins[4 * q + 2], w = wins[4 * q + 3];
-    int32_t *o = out + q * CELLS * P + p;
-    const bool ok = h >= 1 && w >= 1 && r >= 0 && c >= 0 && (int64_t)r + h <= H && (int64_t)c + w <= W;
-    if (!ok) {
-      for (int k = 0; k < CELLS; ++k) o[k * P] = -1;
-      continue;
-    }
-    const Addr A(layout, p, P, H, W);
-    int32_t v[G + 1][G + 1];
-#pragma unroll
-    for (int a = 0; a <= G; ++a)
-#pragma unroll
-      for (int b = 0; b <= G; ++b)
-        v[a][b] = A.at(ih, r + (int)((int64_t)a * h / G) - 1, c + (int)((int64_t)b * w / G) - 1);
-    int k = 0;
-#pragma unroll
-    for (int l = 0; l < LEVELS; ++l) {
-      const int s = G >> l;
-#pragma unroll
-      for (int a = 0; a < (1 << l); ++a)
-#pragma unroll
-        for (int b = 0; b < (1 << l); ++b, ++k)
-          o[k * P] = v[(a + 1) * s][(b + 1) * s] - v[a * s][(b + 1) * s] - v[(a + 1) * s][b * s] + v[a * s][b * s];
-    }
+    pyramid_cells<LEVELS>(ih, P, H, W, layout, wins + 4 * q, p, out + q * CELLS * P + p);
   }
 }
 

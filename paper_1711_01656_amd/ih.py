@@ -43,6 +43,10 @@ SIGNATURES = {
     "ih_match_candidates": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P, _I64, _I32,
                                            _P, _P, _P]),
     "ih_profile_events": (ctypes.c_int, [_P, _P]),
+    "ih_batch_plan_bytes": (_SZ, [_I32]),
+    "ih_batch_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _SZ, ctypes.POINTER(_SZ)]),
+    "ih_build_batch": (ctypes.c_int, [_P, _P, _P, _SZ, _P]),
+    "ih_batch_error_offset": (_SZ, [_I32]),
 }
 
 
@@ -60,6 +64,18 @@ class TileCfg(ctypes.Structure):
 
     def key(self):
         return (self.tile_h, self.tile_w, self.planes_per_wave)
+
+
+class Frame(ctypes.Structure):
+    """One frame of a batch (ih_frame in include/ih.h)."""
+    _fields_ = [("img", ctypes.c_void_p), ("ih", ctypes.c_void_p),
+                ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32),
+                ("bins", ctypes.c_int32), ("value_bits", ctypes.c_int32),
+                ("tile", TileCfg),
+                ("tmpl_desc", ctypes.c_void_p), ("tmpl_win", ctypes.c_int32 * 4), ("tmpl_out", ctypes.c_void_p),
+                ("win_h", ctypes.c_int32), ("win_w", ctypes.c_int32),
+                ("origins", ctypes.c_void_p), ("n_cand", ctypes.c_int64),
+                ("dist", ctypes.c_void_p), ("best", ctypes.c_void_p)]
 
 
 def lib_path() -> str:
@@ -282,3 +298,86 @@ def ih_profile_events(start: Optional[torch.cuda.Event], stop: Optional[torch.cu
             raise IHError("events must have been recorded once (torch creates them lazily)")
         _check(lib().ih_profile_events(ctypes.c_void_p(start.cuda_event), ctypes.c_void_p(stop.cuda_event)),
                "ih_profile_events")
+
+
+class Batch:
+    """Many frames of uneven size built (and searched) in one persistent launch.
+
+    ``frames`` is a list of dicts with keys ``img`` (C x H x W uint8/uint16
+    CUDA tensor), ``bins``, optional ``value_bits``, ``tile`` (TileCfg),
+    and, for the candidate search, ``origins`` (n x 2 int32 tensor),
+    ``win`` ((h, w)) and either ``tmpl_desc`` (21 x P int32 tensor) or
+    ``tmpl_win`` ((r, c, h, w) in this frame).  Output tensors are allocated
+    once; ``run()`` enqueues the batch on the current stream and may be
+    captured in a CUDA (HIP) graph.
+    """
+
+    def __init__(self, frames, metric: str = "chi2"):
+        if not frames:
+            raise IHError("empty batch")
+        dt = frames[0]["img"].dtype
+        if dt not in (torch.uint8, torch.uint16):
+            raise IHError("img must be uint8 or uint16")
+        self.dtype = IH_U8 if dt == torch.uint8 else IH_U16
+        self.metric = METRICS[metric]
+        n = len(frames)
+        arr = (Frame * n)()
+        self.ih, self.dist, self.best, self.tmpl, self._keep = [], [], [], [], []
+        for i, fr in enumerate(frames):
+            img = _dev(fr["img"], "img")
+            if img.dim() == 2:
+                img = img.unsqueeze(0)
+            if img.dtype != dt:
+                raise IHError("all frames of a batch share one dtype")
+            C, H, W = img.shape
+            bins = int(fr["bins"])
+            bits = int(fr.get("value_bits", 8 if dt == torch.uint8 else 16))
+            out = torch.empty((C * bins, H, W), dtype=torch.int32, device=img.device)
+            a = arr[i]
+            a.img, a.ih = img.data_ptr(), out.data_ptr()
+            a.H, a.W, a.C, a.bins, a.value_bits = H, W, C, bins, bits
+            if fr.get("tile") is not None:
+                a.tile = fr["tile"]
+            keep = [img, out]
+            dist = best = tm = None
+            if fr.get("origins") is not None:
+                org = _dev(fr["origins"], "origins", torch.int32)
+                nc = org.shape[0]
+                dist = torch.empty(nc, dtype=torch.float32, device=img.device)
+                best = torch.empty(1, dtype=torch.int32, device=img.device)
+                a.origins, a.n_cand = org.data_ptr(), nc
+                a.dist, a.best = dist.data_ptr(), best.data_ptr()
+                a.win_h, a.win_w = (int(v) for v in fr["win"])
+                if fr.get("tmpl_desc") is not None:
+                    tm = _dev(fr["tmpl_desc"], "tmpl_desc", torch.int32)
+                    a.tmpl_desc = tm.data_ptr()
+                else:
+                    tm = torch.empty((21, C * bins), dtype=torch.int32, device=img.device)
+                    a.tmpl_out = tm.data_ptr()
+                    for k, v in enumerate(fr["tmpl_win"]):
+                        a.tmpl_win[k] = int(v)
+                keep += [org, dist, best, tm]
+            self.ih.append(out)
+            self.dist.append(dist)
+            self.best.append(best)
+            self.tmpl.append(tm)
+            self._keep.append(keep)
+        self.frames = arr
+        nbytes = lib().ih_batch_plan_bytes(n)
+        self.plan_host = (ctypes.c_uint8 * nbytes)()
+        ws = _SZ(0)
+        _check(lib().ih_batch_plan(ctypes.byref(arr), n, self.dtype, self.metric, self.plan_host, nbytes,
+                                   ctypes.byref(ws)), "ih_batch_plan")
+        dev = frames[0]["img"].device
+        self.plan_dev = torch.frombuffer(bytearray(self.plan_host), dtype=torch.uint8).to(dev)
+        self.ws = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+        self.device = dev
+
+    def error_flag(self) -> int:
+        """Non-zero if a dependency wait of the last run hit its safety bound."""
+        off = lib().ih_batch_error_offset(len(self.ih))
+        return int(self.ws[off:off + 4].view(torch.int32).item())
+
+    def run(self):
+        _check(lib().ih_build_batch(self.plan_host, _p(self.plan_dev), _p(self.ws), self.ws.numel(),
+                                    _stream(self.ws)), "ih_build_batch")

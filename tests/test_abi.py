@@ -108,3 +108,37 @@ def test_product_does_not_import_oracle():
                 txt = open(os.path.join(dp, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "ih_oracle" not in txt, f
+
+
+def test_batch_plan_host_only(lib):
+    from paper_1711_01656_amd import ih
+    n = 3
+    arr = (ih.Frame * n)()
+    for i, (H, W, bins) in enumerate(((240, 320, 8), (1000, 777, 64), (5, 3, 1))):
+        a = arr[i]
+        a.img, a.ih = 0x1000, 0x2000
+        a.H, a.W, a.C, a.bins, a.value_bits = H, W, 1, bins, 8
+    nb = lib.ih_batch_plan_bytes(n)
+    assert nb > 0 and lib.ih_batch_plan_bytes(0) == 0
+    buf = (ctypes.c_uint8 * nb)()
+    ws = ctypes.c_size_t(0)
+    assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, nb, ctypes.byref(ws)) == 0
+    assert ws.value > 0
+    # a search needs its buffers
+    arr[0].n_cand = 10
+    assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, nb, ctypes.byref(ws)) == -1
+    arr[0].origins, arr[0].dist, arr[0].best, arr[0].tmpl_out = 0x3000, 0x4000, 0x5000, 0x6000
+    arr[0].win_h = arr[0].win_w = 8
+    assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, nb, ctypes.byref(ws)) == 0
+    # planes per wave above 8 is refused in a batch; bad dtype, metric, size
+    arr[1].tile = ih.TileCfg(32, 64, 16)
+    assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, nb, ctypes.byref(ws)) == -4
+    arr[1].tile = ih.TileCfg(0, 0, 0)
+    assert lib.ih_batch_plan(ctypes.byref(arr), n, 2, 0, buf, nb, ctypes.byref(ws)) == -1
+    assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 5, buf, nb, ctypes.byref(ws)) == -1
+    assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, 16, ctypes.byref(ws)) == -1
+    # launching an uninitialised plan or with a short workspace is refused
+    zero = (ctypes.c_uint8 * nb)()
+    assert lib.ih_build_batch(zero, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 30, None) == -1
+    assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, nb, ctypes.byref(ws)) == 0
+    assert lib.ih_build_batch(buf, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 16, None) == -6
