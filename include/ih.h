@@ -225,15 +225,13 @@ int ih_match_candidates(const int32_t *ih, int32_t P, int32_t H, int32_t W,
                         float *dist, int32_t *best, void *stream);
 
 /*
- * Batched build and search over many frames of uneven size and bin count in
- * one persistent launch (the device-resident analogue of the thesis's
- * dual-buffered frame pipeline, Alg. 10): every frame's integral histogram
- * (bin-major), optionally its template descriptor and its candidate search
- * (3-level pyramid, as ih_pyramid_desc / ih_match_candidates).  A frame's
- * candidate search starts as soon as its own histogram is complete, while
- * other frames are still being built.  The call enqueues two kernels (a
- * counter reset and the persistent kernel), allocates nothing and does not
- * synchronise, so it may be captured in a HIP graph and replayed.
+ * Batched build and search over many frames of uneven size and bin count
+ * (the device-resident analogue of the thesis's dual-buffered frame
+ * pipeline, Alg. 10): every frame's integral histogram (bin-major),
+ * optionally its template descriptor and its candidate search (3-level
+ * pyramid, as ih_pyramid_desc / ih_match_candidates), over all frames at
+ * once.  The calls allocate nothing and do not synchronise; the phased mode
+ * may be captured in a HIP graph and replayed.
  */
 typedef struct {
   const void *img;          /* device, C x H x W values of the batch dtype   */
@@ -258,7 +256,7 @@ size_t ih_batch_plan_bytes(int32_t n);
 
 /*
  * ih_batch_plan - host-only: validate n frames, choose their tile shapes and
- * ticket ranges, and write the plan (plan_bytes >= ih_batch_plan_bytes(n)).
+ * work ranges, and write the plan (plan_bytes >= ih_batch_plan_bytes(n)).
  * dtype (IH_U8 / IH_U16) and metric (IH_CHI2 / IH_L1 / IH_PMK) are shared by
  * the batch.  *ws_bytes receives the workspace size ih_build_batch needs.  The
  * caller copies the plan to device memory once; it stays valid for every
@@ -268,20 +266,25 @@ int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype,
                   int32_t metric, void *plan, size_t plan_bytes,
                   size_t *ws_bytes);
 
+/* How ih_build_batch runs a plan. */
+typedef enum {
+  IH_BATCH_PHASED = 0,      /* one launch per phase, each over all frames   */
+  IH_BATCH_COOPERATIVE = 1  /* one cooperative persistent launch; phases are
+                               separated by the runtime's grid barrier       */
+} ih_batch_mode;
+
 /*
  * ih_build_batch - enqueue the batch described by a plan.
  *   plan_host  the plan as written by ih_batch_plan (host memory).
  *   plan_dev   a device copy of the same bytes.
  *   ws         device workspace of ws_bytes (contents on entry do not matter).
- * After the launch completes, the 32-bit word at ws + ih_batch_error_offset(n)
- * is non-zero if a dependency wait hit its safety bound (results then
- * unreliable); it is zero in every correct run.
+ *   mode       ih_batch_mode; both produce identical results.
+ * Phases: tile histograms, carry scans, write-out, template descriptors,
+ * candidate scoring, best candidate; each phase of a frame depends only on
+ * earlier phases of the same frame.
  */
 int ih_build_batch(const void *plan_host, const void *plan_dev, void *ws,
-                   size_t ws_bytes, void *stream);
-
-/* Byte offset in the batch workspace of the error word (see ih_build_batch). */
-size_t ih_batch_error_offset(int32_t n);
+                   size_t ws_bytes, int32_t mode, void *stream);
 
 /*
  * ih_profile_events - profiling hook.  When both are non-NULL (hipEvent_t),

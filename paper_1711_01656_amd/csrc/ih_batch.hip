@@ -1,17 +1,20 @@
-// Batched build + search of many uneven frames in one persistent launch.
+// Batched build + search of many uneven frames.
 //
-// Work is cut into tickets in six phases, phase-major and frame-minor:
-//   0 tile histograms, 1 carry scans, 2 write-out, 3 template descriptor,
-//   4 candidate scoring (64 candidates per ticket), 5 best candidate.
-// A fixed grid of resident workgroups takes tickets from an atomic counter in
-// increasing order.  A ticket of phase k of frame f first waits until every
-// ticket of the phase it depends on for the same frame has completed
-// (per-frame, per-phase completion counters, released and acquired at device
-// scope); because tickets are taken in order, everything a ticket waits on
-// was taken earlier by a running workgroup, so every wait ends.  The bodies
-// are the same device code as the stand-alone kernels.
+// Work is cut into units in six phases: 0 tile histograms, 1 carry scans,
+// 2 write-out, 3 template descriptor, 4 candidate scoring (64 candidates per
+// unit), 5 best candidate.  A phase of a frame depends only on earlier
+// phases of the same frame.  Two ways to run a plan:
+//   phased:      one launch per non-empty phase, each a grid-stride loop over
+//                that phase's units of all frames (kernel boundaries order the
+//                phases);
+//   cooperative: one cooperative launch whose resident workgroups loop over
+//                the units of each phase in turn, separated by the runtime's
+//                grid-wide barrier.
+// The unit bodies are the same device code as the stand-alone kernels.
 #include "ih_build_dev.h"
 #include "ih_match_dev.h"
+
+#include <hip/hip_cooperative_groups.h>
 
 namespace ih {
 
@@ -24,10 +27,10 @@ struct FramePlan {
   int32_t *ih;
   int32_t bits, bc, gy, vec_ok;
   int64_t tiles;           // tiles of the grid (x channels)
-  int64_t ws_off;          // word offset of this frame's carries in the carry area
+  int64_t ws_off;          // word offset of this frame's carries in the workspace
   int64_t nA, nB;          // carry-scan job split
-  int64_t cnt[NPH];        // tickets of this frame per phase
-  int64_t start[NPH];      // first global ticket of this frame per phase
+  int64_t cnt[NPH];        // units of this frame per phase
+  int64_t start[NPH];      // first unit of this frame in the phase's numbering
   const int32_t *tmpl_desc;
   int32_t *tmpl_out;
   int32_t tmpl_win[4];
@@ -39,9 +42,8 @@ struct FramePlan {
 };
 
 struct BatchHeader {
-  int32_t n, dtype, metric, lds;  // lds: dynamic LDS bytes of the persistent kernel
-  int64_t phase_start[NPH + 1];
-  int64_t counter_words;          // counters at the start of the workspace
+  int32_t n, dtype, metric, lds;  // lds: dynamic LDS bytes of the batch kernels
+  int64_t phase_start[NPH + 1];   // unit numbering: phase-major, frame-minor
   int64_t ws_words;
 };
 
@@ -55,24 +57,6 @@ __device__ __forceinline__ int find_frame(const FramePlan *__restrict__ fr, int 
   return lo;
 }
 
-// Bounded wait for a completion counter.  Every wait is for tickets taken
-// earlier, so it ends; the bound only guarantees that no wave can spin
-// forever should that invariant ever be broken: the wait then gives up,
-// raises the batch's error flag and carries on.
-constexpr uint32_t kSpinLimit = 1u << 24;
-
-__device__ __forceinline__ void wait_count(uint32_t *c, int64_t need, uint32_t *err) {
-  uint32_t spins = 0;
-  while ((int64_t)__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-    if (++spins >= kSpinLimit) {
-      __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
 template <typename T>
 __device__ __forceinline__ void final_dispatch(const FinalArgs &a, const Geom &g, int bx, int by) {
   const int wave = uniform(threadIdx.x >> 6);
@@ -84,87 +68,82 @@ __device__ __forceinline__ void final_dispatch(const FinalArgs &a, const Geom &g
 #undef IH_B
 }
 
-__global__ void k_batch_reset(uint32_t *__restrict__ ws, int64_t words) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
-    ws[i] = 0;
-}
-
+// One unit of phase ph: the u-th unit of frame F.
 template <typename T, int METRIC>
-__global__ __launch_bounds__(256) void k_batch(const BatchHeader *__restrict__ hdr, const FramePlan *__restrict__ fr,
-                                               uint32_t *__restrict__ ws) {
-  extern __shared__ uint32_t lds[];
-  __shared__ int64_t s_ticket;
-  const int n = hdr->n;
-  const int64_t total = hdr->phase_start[NPH];
-  uint32_t *ticket = ws;
-  uint32_t *done = ws + 1;
-  uint32_t *err = ws + 1 + NPH * n;
-  uint32_t *carry = ws + hdr->counter_words;
-  for (;;) {
-    if (threadIdx.x == 0)
-      s_ticket = (int64_t)__hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int64_t t = s_ticket;
-    if (t >= total) break;
-    int ph = 0;
-    while (t >= hdr->phase_start[ph + 1]) ++ph;
-    const int f = find_frame(fr, n, ph, t);
-    const FramePlan &F = fr[f];
-    const int64_t u = t - F.start[ph];
-    if (threadIdx.x == 0) {
-      if (ph >= 1 && ph <= 3) wait_count(&done[(ph - 1) * n + f], F.cnt[ph - 1], err);
-      if (ph == 4) {
-        wait_count(&done[2 * n + f], F.cnt[2], err);
-        wait_count(&done[3 * n + f], F.cnt[3], err);
-      }
-      if (ph == 5) wait_count(&done[4 * n + f], F.cnt[4], err);
+__device__ __forceinline__ void run_unit(const FramePlan &F, int ph, int64_t u, uint32_t *ws, uint32_t *lds) {
+  uint32_t *fws = ws + F.ws_off;
+  const Geom &g = F.g;
+  switch (ph) {
+    case 0:
+      tile_hist_body<T>(reinterpret_cast<const T *>(F.img), g, F.bits, F.bc, fws, (int)u, lds);
+      break;
+    case 1:
+      carry_scan_body(g, F.nA, F.nB, fws, u);
+      break;
+    case 2: {
+      const FinalArgs a{F.img, F.ih, nullptr, nullptr, fws, F.bits, F.vec_ok};
+      final_dispatch<T>(a, g, (int)(u % F.tiles), (int)(u / F.tiles));
+      break;
     }
-    __syncthreads();
-    uint32_t *fws = carry + F.ws_off;
-    const Geom &g = F.g;
-    switch (ph) {
-      case 0:
-        tile_hist_body<T>(reinterpret_cast<const T *>(F.img), g, F.bits, F.bc, fws, (int)u, lds);
-        break;
-      case 1:
-        carry_scan_body(g, F.nA, F.nB, fws, u);
-        break;
-      case 2: {
-        const FinalArgs a{F.img, F.ih, nullptr, nullptr, fws, F.bits, F.vec_ok};
-        final_dispatch<T>(a, g, (int)(u % F.tiles), (int)(u / F.tiles));
-        break;
-      }
-      case 3:
-        for (int p = threadIdx.x; p < g.P; p += blockDim.x)
-          pyramid_cells<3>(F.ih, g.P, g.H, g.W, IH_BHW, F.tmpl_win, p, F.tmpl_out + p);
-        break;
-      case 4: {
-        const int32_t *tm = F.tmpl_desc ? F.tmpl_desc : F.tmpl_out;
-        match_body<3, METRIC>(F.ih, g.P, g.H, g.W, tm, F.win_h, F.win_w, F.origins, F.n_cand, F.dist, u,
-                              reinterpret_cast<double *>(lds), reinterpret_cast<long long *>(lds) + 64 * kMatchWaves);
-        break;
-      }
-      default:
-        argbest_body<METRIC == IH_PMK>(F.dist, F.n_cand, F.best, reinterpret_cast<float *>(lds),
-                                       reinterpret_cast<int64_t *>(lds) + 256);
-        break;
+    case 3:
+      for (int p = threadIdx.x; p < g.P; p += blockDim.x)
+        pyramid_cells<3>(F.ih, g.P, g.H, g.W, IH_BHW, F.tmpl_win, p, F.tmpl_out + p);
+      break;
+    case 4: {
+      const int32_t *tm = F.tmpl_desc ? F.tmpl_desc : F.tmpl_out;
+      match_body<3, METRIC>(F.ih, g.P, g.H, g.W, tm, F.win_h, F.win_w, F.origins, F.n_cand, F.dist, u,
+                            reinterpret_cast<double *>(lds), reinterpret_cast<long long *>(lds) + 64 * kMatchWaves);
+      break;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[ph * n + f], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    default:
+      argbest_body<METRIC == IH_PMK>(F.dist, F.n_cand, F.best, reinterpret_cast<float *>(lds),
+                                     reinterpret_cast<int64_t *>(lds) + 256);
+      break;
   }
 }
 
-typedef void (*batch_fn)(const BatchHeader *, const FramePlan *, uint32_t *);
-
-template <typename T>
-static batch_fn pick_batch_t(int metric) {
-  if (metric == IH_CHI2) return &k_batch<T, IH_CHI2>;
-  if (metric == IH_L1) return &k_batch<T, IH_L1>;
-  return &k_batch<T, IH_PMK>;
+// All units of phase ph, grid-stride.  The unit of a workgroup iteration is
+// uniform across the workgroup, so the bodies' barriers are reached by all.
+template <typename T, int METRIC>
+__device__ __forceinline__ void run_phase(const BatchHeader *__restrict__ hdr, const FramePlan *__restrict__ fr,
+                                          uint32_t *__restrict__ ws, int ph, uint32_t *lds) {
+  const int n = hdr->n;
+  const int64_t end = hdr->phase_start[ph + 1];
+  for (int64_t t = hdr->phase_start[ph] + blockIdx.x; t < end; t += gridDim.x) {
+    const int f = find_frame(fr, n, ph, t);
+    run_unit<T, METRIC>(fr[f], ph, t - fr[f].start[ph], ws, lds);
+    __syncthreads();
+  }
 }
 
-static batch_fn pick_batch(int dtype, int metric) {
-  return dtype == IH_U8 ? pick_batch_t<uint8_t>(metric) : pick_batch_t<uint16_t>(metric);
+template <typename T, int METRIC>
+__global__ __launch_bounds__(256) void k_batch_phase(const BatchHeader *__restrict__ hdr,
+                                                     const FramePlan *__restrict__ fr, uint32_t *__restrict__ ws,
+                                                     int ph) {
+  extern __shared__ uint32_t lds[];
+  run_phase<T, METRIC>(hdr, fr, ws, ph, lds);
+}
+
+template <typename T, int METRIC>
+__global__ __launch_bounds__(256) void k_batch_coop(const BatchHeader *__restrict__ hdr,
+                                                    const FramePlan *__restrict__ fr, uint32_t *__restrict__ ws) {
+  extern __shared__ uint32_t lds[];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int ph = 0; ph < NPH; ++ph) {
+    if (hdr->phase_start[ph + 1] == hdr->phase_start[ph]) continue;  // the same for every workgroup
+    run_phase<T, METRIC>(hdr, fr, ws, ph, lds);
+    grid.sync();
+  }
+}
+
+typedef void (*phase_fn)(const BatchHeader *, const FramePlan *, uint32_t *, int);
+typedef void (*coop_fn)(const BatchHeader *, const FramePlan *, uint32_t *);
+
+template <typename T>
+static void pick_t(int metric, phase_fn *pf, coop_fn *cf) {
+  if (metric == IH_CHI2) { *pf = &k_batch_phase<T, IH_CHI2>; *cf = &k_batch_coop<T, IH_CHI2>; }
+  else if (metric == IH_L1) { *pf = &k_batch_phase<T, IH_L1>; *cf = &k_batch_coop<T, IH_L1>; }
+  else { *pf = &k_batch_phase<T, IH_PMK>; *cf = &k_batch_coop<T, IH_PMK>; }
 }
 
 static size_t a64(size_t w) { return (w + 63) & ~(size_t)63; }
@@ -247,49 +226,58 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
     }
   }
   h->phase_start[NPH] = s;
-  if (s >= ((int64_t)1 << 31)) return set_error(IH_ERR_RANGE, "batch of %lld tickets too large", (long long)s);
+  if (s >= ((int64_t)1 << 40)) return set_error(IH_ERR_RANGE, "batch of %lld units too large", (long long)s);
   h->n = n;
   h->dtype = dtype;
   h->metric = metric;
   h->lds = (int32_t)lds;
-  h->counter_words = (int64_t)a64(2 + (size_t)NPH * n);  // ticket, done[NPH][n], error flag
-  h->ws_words = h->counter_words + (int64_t)carry;
+  h->ws_words = carry > 0 ? (int64_t)carry : 64;
   *ws_bytes = (size_t)h->ws_words * 4;
   return IH_OK;
 }
 
-extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void *ws, size_t ws_bytes, void *stream) {
+extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void *ws, size_t ws_bytes, int32_t mode,
+                              void *stream) {
   if (!plan_host || !plan_dev) return set_error(IH_ERR_INVALID_ARG, "plan_host and plan_dev must be non-NULL");
   const BatchHeader *h = reinterpret_cast<const BatchHeader *>(plan_host);
   if (h->n < 1 || (h->dtype != IH_U8 && h->dtype != IH_U16))
     return set_error(IH_ERR_INVALID_ARG, "plan not initialised by ih_batch_plan");
+  if (mode != IH_BATCH_PHASED && mode != IH_BATCH_COOPERATIVE)
+    return set_error(IH_ERR_INVALID_ARG, "batch mode %d unknown", mode);
   if (!ws || ws_bytes < (size_t)h->ws_words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)h->ws_words * 4);
   hipStream_t s = as_stream(stream);
-  batch_fn fn = pick_batch(h->dtype, h->metric);
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    int e;
-    if ((e = hip_check(hipGetDevice(&dev), "hipGetDevice"))) return e;
-    if ((e = hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties"))) return e;
-    cus = prop.multiProcessorCount;
-  }
+  phase_fn pf;
+  coop_fn cf;
+  if (h->dtype == IH_U8) pick_t<uint8_t>(h->metric, &pf, &cf);
+  else pick_t<uint16_t>(h->metric, &pf, &cf);
+  int dev = 0, e;
+  if ((e = hip_check(hipGetDevice(&dev), "hipGetDevice"))) return e;
+  int cus = 0;
+  if ((e = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count"))) return e;
   int per_cu = 0;
-  int e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, h->lds), "occupancy");
+  if (mode == IH_BATCH_PHASED)
+    e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pf, 256, h->lds), "occupancy");
+  else
+    e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cf, 256, h->lds), "occupancy");
   if (e) return e;
-  if (per_cu < 1) per_cu = 1;
-  const int64_t total = h->phase_start[NPH];
-  int64_t blocks = (int64_t)per_cu * cus;
-  if (blocks > total) blocks = total > 0 ? total : 1;
-  uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, w32, h->counter_words);
-  if ((e = hip_check(hipGetLastError(), "batch reset launch"))) return e;
+  if (per_cu < 1) return set_error(IH_ERR_UNSUPPORTED, "batch kernel cannot be resident (LDS %d)", h->lds);
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(plan_dev);
   const FramePlan *fd = reinterpret_cast<const FramePlan *>(hd + 1);
-  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(256), h->lds, s, hd, fd, w32);
-  return hip_check(hipGetLastError(), "batch launch");
+  uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
+  const int64_t resident = (int64_t)per_cu * cus;
+  if (mode == IH_BATCH_PHASED) {
+    for (int ph = 0; ph < NPH; ++ph) {
+      const int64_t units = h->phase_start[ph + 1] - h->phase_start[ph];
+      if (units == 0) continue;
+      const int64_t blocks = units < 4 * resident ? units : 4 * resident;
+      hipLaunchKernelGGL(pf, dim3((unsigned)blocks), dim3(256), h->lds, s, hd, fd, w32, ph);
+      if ((e = hip_check(hipGetLastError(), "batch phase launch"))) return e;
+    }
+    return IH_OK;
+  }
+  void *args[] = {(void *)&hd, (void *)&fd, (void *)&w32};
+  return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(cf), dim3((unsigned)resident), dim3(256),
+                                              args, (unsigned)h->lds, s),
+                   "cooperative batch launch");
 }
-
-extern "C" size_t ih_batch_error_offset(int32_t n) { return n < 1 ? 0 : (size_t)(1 + NPH * (size_t)n) * 4; }

@@ -26,6 +26,7 @@ IH_MANHATTAN = 0
 IH_BHW, IH_HWB = 0, 1
 METRICS = {"chi2": IH_CHI2, "l1": IH_L1, "pmk": IH_PMK}
 LAYOUTS = {"bhw": IH_BHW, "hwb": IH_HWB}
+BATCH_MODES = {"phased": 0, "cooperative": 1}
 
 # C declarations mirrored from include/ih.h: name -> (restype, argtypes)
 _P = ctypes.c_void_p
@@ -45,8 +46,7 @@ SIGNATURES = {
     "ih_profile_events": (ctypes.c_int, [_P, _P]),
     "ih_batch_plan_bytes": (_SZ, [_I32]),
     "ih_batch_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _SZ, ctypes.POINTER(_SZ)]),
-    "ih_build_batch": (ctypes.c_int, [_P, _P, _P, _SZ, _P]),
-    "ih_batch_error_offset": (_SZ, [_I32]),
+    "ih_build_batch": (ctypes.c_int, [_P, _P, _P, _SZ, _I32, _P]),
 }
 
 
@@ -309,7 +309,7 @@ class Batch:
     ``win`` ((h, w)) and either ``tmpl_desc`` (21 x P int32 tensor) or
     ``tmpl_win`` ((r, c, h, w) in this frame).  Output tensors are allocated
     once; ``run()`` enqueues the batch on the current stream and may be
-    captured in a CUDA (HIP) graph.
+    captured in a CUDA (HIP) graph (phased mode).
     """
 
     def __init__(self, frames, metric: str = "chi2"):
@@ -373,11 +373,9 @@ class Batch:
         self.ws = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
         self.device = dev
 
-    def error_flag(self) -> int:
-        """Non-zero if a dependency wait of the last run hit its safety bound."""
-        off = lib().ih_batch_error_offset(len(self.ih))
-        return int(self.ws[off:off + 4].view(torch.int32).item())
-
-    def run(self):
-        _check(lib().ih_build_batch(self.plan_host, _p(self.plan_dev), _p(self.ws), self.ws.numel(),
+    def run(self, mode: str = "phased"):
+        """Enqueue the batch: ``"phased"`` (one launch per phase) or
+        ``"cooperative"`` (one cooperative persistent launch)."""
+        m = BATCH_MODES[mode]
+        _check(lib().ih_build_batch(self.plan_host, _p(self.plan_dev), _p(self.ws), self.ws.numel(), m,
                                     _stream(self.ws)), "ih_build_batch")

@@ -139,6 +139,7 @@ def test_batch_plan_host_only(lib):
     assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, 16, ctypes.byref(ws)) == -1
     # launching an uninitialised plan or with a short workspace is refused
     zero = (ctypes.c_uint8 * nb)()
-    assert lib.ih_build_batch(zero, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 30, None) == -1
+    assert lib.ih_build_batch(zero, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 30, 0, None) == -1
     assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, nb, ctypes.byref(ws)) == 0
-    assert lib.ih_build_batch(buf, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 16, None) == -6
+    assert lib.ih_build_batch(buf, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 16, 0, None) == -6
+    assert lib.ih_build_batch(buf, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 30, 7, None) == -1
