@@ -11,8 +11,8 @@ only the best-scored candidates need exact pyramid scoring.
 Network (shared definition with the GPU kernels, written independently):
   x   : 7 x 128 x 128 features (u8 / 255), rounded to BF16
   a1  = bf16(relu(conv(x,  W1, stride 2, pad 1) + b1))     32 x 64 x 64
-  a2  = bf16(relu(conv(a1, W2, dilation 2, pad 2) + b2))   32 x 64 x 64
-  a3  = bf16(relu(conv(a2, W3, dilation 4, pad 4) + b3))   32 x 64 x 64
+  a2  = bf16(relu(conv(a1, W2, dilation 3, pad 3) + b2))   32 x 64 x 64
+  a3  = bf16(relu(conv(a2, W3, dilation 9, pad 9) + b3))   32 x 64 x 64
   s   = sum_c wh[c] a3[c] + bh                             64 x 64
   L(dy,dx) = bilinear sample of s at (32 + dy/2, 32 + dx/2), dy,dx in [-32,32]
   loss = mean over the batch of -log softmax(L)[label]
@@ -28,7 +28,8 @@ import numpy as np
 
 C_IN, C_MID, CROP, SMAP, RADIUS = 7, 32, 128, 64, 32
 NOFF = 2 * RADIUS + 1           # 65 offsets per axis
-LAYERS = ((C_IN, 2, 1, 1), (C_MID, 1, 2, 2), (C_MID, 1, 4, 4))   # (cin, stride, dilation, pad)
+# (cin, stride, dilation, pad); receptive field 3 + 2*3*2 + 2*9*2 = 51 input pixels
+LAYERS = ((C_IN, 2, 1, 1), (C_MID, 1, 3, 3), (C_MID, 1, 9, 9))
 
 
 # --------------------------------------------------------------- rounding --
@@ -121,6 +122,22 @@ def sample_transpose(dl):
     np.add.at(ds, (slice(None), u0, slice(None)), ds_cols * (1 - fu)[None, :, None])
     np.add.at(ds, (slice(None), u1, slice(None)), ds_cols * fu[None, :, None])
     return ds
+
+
+# ------------------------------------------------------------------ input --
+def crop(feat, centers, side=CROP):
+    """x[b,c,i,j] = bf16(feat[c, r - side/2 + i, q - side/2 + j] / 255) for the
+    centre (r, q) of crop b; zero where the window leaves the frame."""
+    C, H, W = feat.shape
+    out = np.zeros((len(centers), C, side, side))
+    for b, (r, q) in enumerate(centers):
+        r0, q0 = int(r) - side // 2, int(q) - side // 2
+        for i in range(side):
+            if 0 <= r0 + i < H:
+                for j in range(side):
+                    if 0 <= q0 + j < W:
+                        out[b, :, i, j] = feat[:, r0 + i, q0 + j] / 255.0
+    return bf16(out)
 
 
 # ------------------------------------------------------------ the network --

@@ -27,7 +27,7 @@ def loop_conv(x, w, stride, dil, pad):
     return out
 
 
-@pytest.mark.parametrize("stride,dil,pad", [(1, 1, 1), (2, 1, 1), (1, 2, 2), (1, 4, 4), (2, 2, 1)])
+@pytest.mark.parametrize("stride,dil,pad", [(1, 1, 1), (2, 1, 1), (1, 2, 2), (1, 3, 3), (1, 9, 9), (2, 2, 1)])
 def test_conv_equals_loop_nest(stride, dil, pad):
     rng = np.random.default_rng(stride * 10 + dil)
     x = rng.standard_normal((2, 3, 11, 9))
@@ -36,7 +36,7 @@ def test_conv_equals_loop_nest(stride, dil, pad):
                                atol=1e-12)
 
 
-@pytest.mark.parametrize("stride,dil,pad", [(1, 2, 2), (2, 1, 1), (1, 4, 4)])
+@pytest.mark.parametrize("stride,dil,pad", [(1, 3, 3), (2, 1, 1), (1, 9, 9)])
 def test_conv_adjoint_identities(stride, dil, pad):
     rng = np.random.default_rng(7 + dil)
     x = rng.standard_normal((2, 3, 16, 13))
@@ -110,3 +110,15 @@ def test_sgd_step():
     v = {"a": np.array([1.0, 0.0], np.float32)}
     p2, v2 = cnn.sgd_step(p, g, v, lr=0.1, momentum=0.9, weight_decay=0.0)
     assert np.allclose(v2["a"], [1.4, 0.5]) and np.allclose(p2["a"], [0.86, -2.05])
+
+
+def test_crop_window_and_border():
+    feat = np.arange(3 * 5 * 6, dtype=np.uint8).reshape(3, 5, 6) * 2
+    x = cnn.crop(feat, [(2, 3), (0, 0)], side=4)
+    # centre (2,3): rows 0..3, columns 1..4 of the frame
+    np.testing.assert_array_equal(x[0], cnn.bf16(feat[:, 0:4, 1:5] / 255.0))
+    # centre (0,0): rows -2..1, columns -2..1; only the lower-right 2x2 is inside
+    assert np.all(x[1, :, :2, :] == 0) and np.all(x[1, :, :, :2] == 0)
+    np.testing.assert_array_equal(x[1, :, 2:, 2:], cnn.bf16(feat[:, 0:2, 0:2] / 255.0))
+    full = cnn.crop(np.full((1, 2, 2), 255, np.uint8), [(1, 1)], side=2)
+    assert np.all(full == 1.0)
