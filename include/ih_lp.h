@@ -1,0 +1,166 @@
+/*
+ * ih_lp.h - C ABI of the learned candidate proposal (libih.so).
+ *
+ * The thesis scores every candidate window of the search region with the
+ * spatial-pyramid distance (Chapter 2, Eqs. 2.23-2.24) and names learned
+ * models as a direction it does not build.  This library adds one: a small
+ * convolutional network that looks at a crop of the 7 feature channels
+ * (R, G, B, intensity, gradient orientation, gradient magnitude, edges; the
+ * fused features of the tracker in Chapter 4) centred on the previous target
+ * position and scores each of the 65 x 65 candidate offsets (-32..32 pixels per
+ * axis).  The tracker then scores only the k best-ranked offsets exactly.
+ *
+ * Network, for one crop (all tensors NCHW, batch-major, device memory):
+ *   x  [7][128][128]   bf16(feature / 255), 0 outside the frame
+ *   a1 [32][64][64]    bf16(relu(conv3x3(x,  W1, stride 2, pad 1) + b1))
+ *   a2 [32][64][64]    bf16(relu(conv3x3(a1, W2, dilation 3, pad 3) + b2))
+ *   a3 [32][64][64]    bf16(relu(conv3x3(a2, W3, dilation 9, pad 9) + b3))
+ *   s  [64][64]        sum_c wh[c] a3[c] + bh
+ *   logits[dy][dx]     bilinear(s, 32 + dy/2, 32 + dx/2)      [65][65]
+ * Training minimises the softmax cross-entropy of the logits against the
+ * offset of the true target, by SGD with momentum.
+ *
+ * Parameters live in one FP32 array (20,577 floats, the master copy):
+ *   W1[32][7][3][3] b1[32] W2[32][32][3][3] b2[32] W3[32][32][3][3] b3[32]
+ *   wh[32] bh[1]
+ * ih_lp_pack derives the BF16 operands the convolutions read.  bf16 values
+ * are passed as uint16_t bit patterns; every rounding to bf16 is
+ * round-to-nearest-even.  Convolutions, input gradients and weight gradients
+ * run on the BF16 matrix cores with FP32 accumulation; every reduction runs in
+ * a fixed order, so results are deterministic.
+ *
+ * All functions are asynchronous on `stream` (a hipStream_t, NULL = default
+ * stream) and return IH_OK or a negative ih_status from ih.h after host-side
+ * argument checks; ih_last_error() describes the failure.  No function
+ * allocates device memory: the caller owns every buffer.
+ */
+#ifndef IH_LP_H
+#define IH_LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * ih_lp_conv - 3x3 convolution with 32 output channels.
+ *   in    [B][Cin][Hin][Win] bf16.
+ *   w     [32][Kpad] bf16, Kpad = Cin*9 rounded up to a multiple of 8, zero
+ *         padded; column k = ci*9 + kh*3 + kw.
+ *   out   [B][32][Hout][Wout] bf16, Hout = (Hin + 2 pad - 2 dil - 1)/stride + 1.
+ *   mask  NULL: out = bf16(relu(conv + bias)) (forward; bias is [32] FP32).
+ *         else [B][32][Hout][Wout] bf16: out = bf16(conv * (mask > 0)), bias
+ *         unused (input gradient through a ReLU: pass dZ of the next layer as
+ *         `in`, the packed transposed weights as `w`, and that layer's input
+ *         activation as `mask`).
+ * Cin*9 must not exceed 1024.
+ */
+int ih_lp_conv(const uint16_t *in, int32_t B, int32_t Cin, int32_t Hin,
+               int32_t Win, const uint16_t *w, const float *bias,
+               int32_t stride, int32_t dil, int32_t pad, const uint16_t *mask,
+               uint16_t *out, void *stream);
+
+/*
+ * Bytes of FP32 workspace ih_lp_wgrad needs: one 32 x Cin*9 partial sum per
+ * chunk of `chunk` output pixels (0 for invalid shapes).
+ */
+size_t ih_lp_wgrad_workspace(int32_t B, int32_t Cin, int32_t Hin, int32_t Win,
+                             int32_t stride, int32_t dil, int32_t pad,
+                             int64_t chunk);
+
+/*
+ * ih_lp_wgrad - weight and bias gradients of a 3x3 convolution.
+ *   in  [B][Cin][Hin][Win] bf16 (the layer input), dz [B][32][Hout][Wout] bf16
+ *   (gradient of the pre-activation).
+ *   dw  out: [32][Cin][3][3] FP32 = sum over batch and pixels of dz * im2col(in)
+ *   db  out: [32] FP32 = sum of dz per channel.
+ *   chunk  output pixels per partial sum (positive multiple of 8); partials
+ *          are added in chunk order.
+ */
+int ih_lp_wgrad(const uint16_t *in, const uint16_t *dz, int32_t B, int32_t Cin,
+                int32_t Hin, int32_t Win, int32_t stride, int32_t dil,
+                int32_t pad, int64_t chunk, float *ws, size_t ws_bytes,
+                float *dw, float *db, void *stream);
+
+/*
+ * ih_lp_head - score map and offset logits.
+ *   a3 [B][32][64][64] bf16, wh [32], bh [1] FP32; logits out [B][65][65] FP32,
+ *   logits[b][dy+32][dx+32] = bilinear(s_b, 32 + dy/2, 32 + dx/2).
+ */
+int ih_lp_head(const uint16_t *a3, const float *wh, const float *bh, int32_t B,
+               float *logits, void *stream);
+
+/*
+ * ih_lp_softmax_ce - per-sample loss and logit gradient.
+ *   labels [B] in [0, 4225) (index (dy+32)*65 + dx+32 of the true offset).
+ *   loss out [B] = -log softmax(logits_b)[label_b];
+ *   dlogits out [B][4225] = (softmax - onehot) / B  (gradient of the mean).
+ */
+int ih_lp_softmax_ce(const float *logits, const int32_t *labels, int32_t B,
+                     float *loss, float *dlogits, void *stream);
+
+/*
+ * ih_lp_head_bwd - backward of the head and the bilinear sampling.
+ *   ds  out [B][64][64] FP32 gradient of the score map.
+ *   dz3 out [B][32][64][64] bf16 = bf16(ds * wh[c] * (a3 > 0)).
+ *   dwh out [32], dbh out [1] FP32.
+ */
+int ih_lp_head_bwd(const float *dlogits, const uint16_t *a3, const float *wh,
+                   int32_t B, float *ds, uint16_t *dz3, float *dwh, float *dbh,
+                   void *stream);
+
+/*
+ * ih_lp_crop - network inputs from a stack of planar u8 feature frames.
+ *   feat [F][C][H][W] u8; frames [B] int32 frame index per crop (NULL: all
+ *   from frame 0); centers [B][2] (row, column) int32;
+ *   x out [B][C][side][side] bf16 with x[b][c][i][j] =
+ *   feat[frames[b]][c][row_b - side/2 + i][col_b - side/2 + j] / 255, and 0
+ *   outside the frame or for a frame index outside [0, F).  side must be even.
+ */
+int ih_lp_crop(const uint8_t *feat, int32_t F, int32_t C, int32_t H, int32_t W,
+               const int32_t *frames, const int32_t *centers, int32_t B,
+               int32_t side, uint16_t *x, void *stream);
+
+/*
+ * ih_lp_origins - candidate window origins from offset indices.
+ *   idx   [B][k] int32 offset indices (as from ih_lp_topk), or NULL for all
+ *         (2 radius + 1)^2 offsets in index order (then k must equal that).
+ *   base  [B][2] int32 window origin of the previous position.
+ *   origins out [B][k][2] = base + (o / n - radius, o % n - radius), n = 2 radius + 1;
+ *   an index outside [0, n^2) gives an origin far outside every frame, which
+ *   ih_match_candidates scores as +inf.
+ */
+int ih_lp_origins(const int32_t *idx, int32_t B, int32_t k,
+                  const int32_t *base, int32_t radius, int32_t *origins,
+                  void *stream);
+
+/*
+ * ih_lp_pack - BF16 operands from the FP32 parameter array:
+ *   w1 [32][64] (K = 63 padded with a zero column), w2, w3 [32][288], and the
+ *   transposed, tap-flipped w2t, w3t [32][288] used for input gradients:
+ *   wt[ci][co*9 + kh*3 + kw] = W[co][ci][2-kh][2-kw].
+ */
+int ih_lp_pack(const float *params, uint16_t *w1, uint16_t *w2, uint16_t *w3,
+               uint16_t *w2t, uint16_t *w3t, void *stream);
+
+/*
+ * ih_lp_sgd - SGD with momentum and L2 weight decay on n FP32 values:
+ *   v <- momentum v + (g + weight_decay p);  p <- p - lr v.
+ */
+int ih_lp_sgd(float *params, const float *grads, float *mom, int32_t n,
+              float lr, float momentum, float weight_decay, void *stream);
+
+/*
+ * ih_lp_topk - per sample, the indices of the k largest of n logits (n <= 8192),
+ * best first, ties to the lower index.  idx out [B][k] int32.
+ */
+int ih_lp_topk(const float *logits, int32_t B, int32_t n, int32_t k,
+               int32_t *idx, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IH_LP_H */

@@ -47,6 +47,18 @@ SIGNATURES = {
     "ih_batch_plan_bytes": (_SZ, [_I32]),
     "ih_batch_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _SZ, ctypes.POINTER(_SZ)]),
     "ih_build_batch": (ctypes.c_int, [_P, _P, _P, _SZ, _I32, _P]),
+    # learned proposal (include/ih_lp.h)
+    "ih_lp_conv": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P, _I32, _I32, _I32, _P, _P, _P]),
+    "ih_lp_wgrad_workspace": (_SZ, [_I32, _I32, _I32, _I32, _I32, _I32, _I32, _I64]),
+    "ih_lp_wgrad": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I64, _P, _SZ, _P, _P, _P]),
+    "ih_lp_head": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P]),
+    "ih_lp_softmax_ce": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P]),
+    "ih_lp_head_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _P, _P, _P]),
+    "ih_lp_crop": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P, _I32, _I32, _P, _P]),
+    "ih_lp_origins": (ctypes.c_int, [_P, _I32, _I32, _P, _I32, _P, _P]),
+    "ih_lp_pack": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "ih_lp_sgd": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "ih_lp_topk": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P]),
 }
 
 

@@ -1,0 +1,244 @@
+"""Pyramid-histogram tracking with exhaustive and learned candidate search.
+
+Per frame the integral histogram of the feature channels is built (Chapter 2);
+candidate windows around the previous target position are scored by their
+spatial-pyramid distance to the frame-0 template (Eqs. 2.23-2.24) and the best
+one becomes the new position, the sliding-window search of the thesis's
+tracker.  Two searches:
+
+* exhaustive: all 65 x 65 window offsets (-32..32 px per axis);
+* learned: the proposal network ranks the offsets from a crop centred on the
+  previous position, only the top k are scored exactly, and the exhaustive
+  search runs instead whenever the best of them scores worse than the margin
+  (1 + tau) d*, where d* is the distance accepted at the previous frame.
+
+All scoring, network and index work runs in libih.so; the host reads back
+one index and one distance per search.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import proposal as lp
+from .ih import (IHError, TileCfg, cells, ih_build, ih_match_candidates, ih_pyramid_desc, shape_of,
+                 workspace_size)
+
+RADIUS = lp.RADIUS
+N_OFF = lp.N_OFFSETS
+
+
+class PyramidTracker:
+    """Exhaustive pyramid-distance search over one frame size."""
+
+    def __init__(self, H: int, W: int, C: int = 7, bins: int = 16, levels: int = 3, metric: str = "chi2",
+                 layout: str = "hwb", cfg: Optional[TileCfg] = None, device="cuda"):
+        self.H, self.W, self.C, self.bins, self.levels = H, W, C, bins, levels
+        self.metric, self.layout, self.cfg = metric, layout, cfg
+        self.P = C * bins
+        dev = torch.device(device)
+        self.device = dev
+        self.ih = torch.empty(shape_of(self.P, H, W, layout), dtype=torch.int32, device=dev)
+        self.ws = torch.empty(max(1, workspace_size(H, W, C, bins, False, cfg, layout)), dtype=torch.uint8,
+                              device=dev)
+        self.origins = torch.empty((N_OFF, 2), dtype=torch.int32, device=dev)
+        self.dist = torch.empty(N_OFF, dtype=torch.float32, device=dev)
+        self.best = torch.empty(1, dtype=torch.int32, device=dev)
+        self.base = torch.empty((1, 2), dtype=torch.int32, device=dev)
+        self.tmpl = None
+        self.win = None
+
+    def build(self, feat: torch.Tensor):
+        ih_build(feat, self.bins, out=self.ih, ws=self.ws, cfg=self.cfg, layout=self.layout)
+
+    def set_template(self, feat0: torch.Tensor, box: Sequence[int]):
+        """Template = pyramid descriptor of window box = (row, col, h, w) in feat0."""
+        self.build(feat0)
+        wins = torch.tensor([list(box)], dtype=torch.int32, device=self.device)
+        self.tmpl = ih_pyramid_desc(self.ih, wins, self.levels, layout=self.layout).reshape(-1).clone()
+        self.win = (int(box[2]), int(box[3]))
+
+    def set_base(self, origin):
+        self.base.copy_(torch.tensor([[int(origin[0]), int(origin[1])]], dtype=torch.int32))
+
+    def score(self, origins: torch.Tensor, dist: torch.Tensor, best: torch.Tensor):
+        return ih_match_candidates(self.ih, self.tmpl, self.win[0], self.win[1], origins, self.levels,
+                                   self.metric, dist, best, self.layout)
+
+    def exhaustive(self, origin):
+        """Best window origin among all offsets around origin, and its distance
+        (origin unchanged and +inf when no candidate lies inside the frame)."""
+        self.set_base(origin)
+        lp.lp_origins(self.base, RADIUS, out=self.origins)
+        self.score(self.origins, self.dist, self.best)
+        b = int(self.best.item())
+        if b < 0:
+            return (int(origin[0]), int(origin[1])), math.inf
+        dy, dx = lp.offset_of(b)
+        return (int(origin[0]) + int(dy), int(origin[1]) + int(dx)), float(self.dist[b].item())
+
+
+class LearnedTracker:
+    """Top-k proposals from the network, exact scoring, exhaustive fallback."""
+
+    def __init__(self, tracker: PyramidTracker, net: Optional[lp.ProposalNet], k: int = 64, tau: float = 0.25,
+                 prior_logits: Optional[torch.Tensor] = None):
+        """net=None with prior_logits ranks the offsets by a fixed score instead
+        of the network (the no-network baseline)."""
+        if net is None and prior_logits is None:
+            raise IHError("need a network or fixed prior logits")
+        self.tr, self.net, self.k, self.tau = tracker, net, k, tau
+        dev = tracker.device
+        self.prior = prior_logits
+        self.idx = torch.empty((1, k), dtype=torch.int32, device=dev)
+        self.korig = torch.empty((k, 2), dtype=torch.int32, device=dev)
+        self.kdist = torch.empty(k, dtype=torch.float32, device=dev)
+        self.kbest = torch.empty(1, dtype=torch.int32, device=dev)
+        self.center = torch.empty((1, 2), dtype=torch.int32, device=dev)
+
+    def propose(self, feat: torch.Tensor, origin):
+        """Enqueue the ranking for a search around origin; fills self.idx."""
+        if self.net is None:
+            lp.lp_topk(self.prior.view(1, -1), self.k, self.idx)
+            return
+        h, w = self.tr.win
+        self.center.copy_(torch.tensor([[int(origin[0]) + h // 2, int(origin[1]) + w // 2]], dtype=torch.int32))
+        x = self.net.crop(feat, self.center)
+        logits = self.net.forward(x)
+        lp.lp_topk(logits.view(1, -1), self.k, self.idx)
+
+    def step(self, feat: torch.Tensor, origin, d_prev: float):
+        """(new origin, distance, fell_back, proposed offset indices on the host)."""
+        tr = self.tr
+        tr.set_base(origin)
+        self.propose(feat, origin)
+        lp.lp_origins(tr.base, RADIUS, idx=self.idx, out=self.korig)
+        tr.score(self.korig, self.kdist, self.kbest)
+        b = int(self.kbest.item())
+        d = float(self.kdist[b].item()) if b >= 0 else math.inf
+        if b < 0 or not d <= (1.0 + self.tau) * d_prev:
+            o, d = tr.exhaustive(origin)
+            return o, d, True
+        dy, dx = lp.offset_of(int(self.idx[0, b].item()))
+        return (int(origin[0]) + int(dy), int(origin[1]) + int(dx)), d, False
+
+
+@dataclass
+class Track:
+    origins: np.ndarray       # T x 2 window origins
+    dists: np.ndarray         # T accepted distances
+    fallback: np.ndarray      # T bool (learned search only)
+
+
+def track(frames, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker] = None,
+          teacher: Optional[Track] = None) -> Track:
+    """Track through frames (sequence of C x H x W uint8 device tensors, or a
+    stacked tensor).  With `teacher`, every search starts from the teacher's
+    previous position and distance (per-frame agreement)."""
+    T = len(frames)
+    tracker.set_template(frames[0], box0)
+    org = np.zeros((T, 2), np.int64)
+    dist = np.zeros(T)
+    fb = np.zeros(T, bool)
+    org[0] = box0[:2]
+    for t in range(1, T):
+        prev, dprev = (teacher.origins[t - 1], teacher.dists[t - 1]) if teacher is not None else (org[t - 1],
+                                                                                                 dist[t - 1])
+        tracker.build(frames[t])
+        if learned is None:
+            o, d = tracker.exhaustive(prev)
+        else:
+            o, d, fb[t] = learned.step(frames[t], prev, dprev)
+        org[t], dist[t] = o, d
+    return Track(org, dist, fb)
+
+
+def distance_prior() -> torch.Tensor:
+    """Fixed ranking of the offsets by distance from the previous position
+    (-(dy^2 + dx^2)): the search without a network."""
+    d = np.arange(-RADIUS, RADIUS + 1)
+    return torch.tensor(-(d[:, None] ** 2 + d[None, :] ** 2).astype(np.float32).reshape(1, -1))
+
+
+# ---------------------------------------------------------------- training --
+@dataclass
+class Samples:
+    frame: np.ndarray          # n, index into the frame stack
+    center: np.ndarray         # n x 2, crop centre of the previous window
+    offset: np.ndarray         # n x 2, displacement chosen by the exhaustive search
+
+
+def samples_from_track(trk: Track, win, frame0: int = 0) -> Samples:
+    """Frame t of a track gives one sample: crop of frame t centred on the
+    window at t-1, labelled with the exhaustive search's displacement."""
+    h, w = win
+    prev = trk.origins[:-1]
+    off = trk.origins[1:] - prev
+    ok = np.all(np.abs(off) <= RADIUS, axis=1) & np.isfinite(trk.dists[1:])
+    t = np.arange(1, len(trk.origins))[ok]
+    center = prev[ok] + np.array([h // 2, w // 2])
+    return Samples(frame0 + t, center, off[ok])
+
+
+def concat(samples: List[Samples]) -> Samples:
+    return Samples(np.concatenate([s.frame for s in samples]), np.concatenate([s.center for s in samples]),
+                   np.concatenate([s.offset for s in samples]))
+
+
+def train(net: lp.ProposalNet, stack: torch.Tensor, samples: Samples, steps: int, batch: int = 64,
+          lr: float = 0.02, momentum: float = 0.9, weight_decay: float = 1e-4, jitter: int = 12,
+          seed: int = 0, log_every: int = 0) -> List[float]:
+    """SGD on random batches of samples.  Each draw shifts the crop centre by a
+    random jitter j (|j| <= jitter per axis) and the label by -j, so the
+    network sees the target at many positions; labels stay inside the
+    search range.  Returns the mean loss of every step (read back every
+    `log_every` steps, or at the end)."""
+    rng = np.random.default_rng(seed)
+    dev = net.device
+    n = len(samples.frame)
+    losses = []
+    pending = []
+    fr_d = torch.empty(batch, dtype=torch.int32, device=dev)
+    ce_d = torch.empty((batch, 2), dtype=torch.int32, device=dev)
+    lb_d = torch.empty(batch, dtype=torch.int32, device=dev)
+    for s in range(steps):
+        pick = rng.integers(0, n, batch)
+        j = rng.integers(-jitter, jitter + 1, (batch, 2))
+        off = samples.offset[pick]
+        j = np.clip(j, off - RADIUS, off + RADIUS)
+        lab = lp.label_of(off[:, 0] - j[:, 0], off[:, 1] - j[:, 1])
+        fr_d.copy_(torch.from_numpy(samples.frame[pick].astype(np.int32)))
+        ce_d.copy_(torch.from_numpy((samples.center[pick] + j).astype(np.int32)))
+        lb_d.copy_(torch.from_numpy(lab.astype(np.int32)))
+        x = net.crop(stack, ce_d, frames=fr_d)
+        loss = net.train_step(x, lb_d, lr, momentum, weight_decay)
+        pending.append(loss.mean())
+        if (log_every and (s + 1) % log_every == 0) or s == steps - 1:
+            losses.extend(float(v) for v in torch.stack(pending).cpu())
+            pending = []
+            if log_every:
+                print("step %d loss %.4f" % (s + 1, losses[-1]), flush=True)
+    return losses
+
+
+def recall(net_or_prior, stack: torch.Tensor, samples: Samples, k: int = 64, batch: int = 64) -> float:
+    """Fraction of samples whose exhaustive displacement is among the top k."""
+    hits = 0
+    n = len(samples.frame)
+    for s in range(0, n, batch):
+        e = min(n, s + batch)
+        if isinstance(net_or_prior, lp.ProposalNet):
+            net = net_or_prior
+            x = net.crop(stack, torch.from_numpy(samples.center[s:e].astype(np.int32)).to(net.device),
+                         frames=torch.from_numpy(samples.frame[s:e].astype(np.int32)).to(net.device))
+            idx = lp.lp_topk(net.forward(x).view(e - s, -1), k).cpu().numpy()
+        else:
+            prior = net_or_prior.view(1, -1)
+            idx = np.repeat(lp.lp_topk(prior, k).cpu().numpy(), e - s, 0)
+        lab = lp.label_of(samples.offset[s:e, 0], samples.offset[s:e, 1])
+        hits += int(np.sum(np.any(idx == lab[:, None], axis=1)))
+    return hits / max(1, n)

@@ -77,7 +77,14 @@ def feature_channels(seed_base: int, H: int, W: int) -> np.ndarray:
         rng = np.random.default_rng(seed_base + k)
         f = 0.5 * smooth(rng, H, W, 64) + 0.3 * smooth(rng, H, W, 16) + 0.2 * smooth(rng, H, W, 4)
         chans.append(np.clip(255.0 * f, 0, 255).astype(np.uint8))
-    R, G, B = chans
+    return rgb_features(*chans)
+
+
+def rgb_features(R: np.ndarray, G: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """The seven uint8 channels R, G, B, I, GO, GM, Edge of an RGB image: the
+    intensity is the rounded mean; orientation, magnitude and a binary edge
+    map (top 20% of magnitudes) come from a 3x3 Sobel filter on the intensity
+    with replicated borders."""
     I = np.rint((R.astype(np.float64) + G + B) / 3.0).astype(np.uint8)
     gx, gy = _sobel(I)
     mag = np.sqrt(gx * gx + gy * gy)

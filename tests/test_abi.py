@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every symbol include/ih.h declares;
+"""The C-ABI library loads and exports every symbol include/*.h declares;
 host-side argument checks return error codes without touching a GPU."""
 import ctypes
 import os
@@ -10,7 +10,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "ih.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(ih_[a-z_]+)\s*\(", src)))
 

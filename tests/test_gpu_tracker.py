@@ -1,0 +1,135 @@
+"""Tracker with exhaustive and learned candidate search on a synthetic video.
+
+The exhaustive search is the judge: its per-frame result is checked against
+the oracle's candidate search, and the learned search is measured by how
+often it reaches the same window.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import cnn
+from synth.video import Video, render, training_videos
+
+pytestmark = pytest.mark.gpu
+
+H, W, T = 360, 640, 40
+BINS = 16
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_01656_amd import proposal, tracker
+    v = Video(77, H, W, T, n_objects=3)
+    feats = render(v)
+    stack = torch.from_numpy(feats).cuda()
+    tr = tracker.PyramidTracker(H, W, bins=BINS)
+    box0 = v.target_box(0)
+    ex = tracker.track(stack, box0, tr)
+    return dict(tracker=tracker, lp=proposal, video=v, feats=feats, stack=stack, tr=tr, box0=box0, ex=ex)
+
+
+def test_exhaustive_search_matches_oracle(env):
+    tr, feats, box0, ex = env["tr"], env["feats"], env["box0"], env["ex"]
+    h, w = box0[2], box0[3]
+    tmpl = oracle.pyramid_desc_direct(feats[0], BINS, 8, np.array([box0], np.int32), 3)[0]
+    d = np.arange(-32, 33)
+    for t in (1, 7, T - 1):
+        prev = ex.origins[t - 1]
+        origins = np.stack(np.meshgrid(prev[0] + d, prev[1] + d, indexing="ij"), -1).reshape(-1, 2)
+        dist, best = oracle.match_direct(feats[t], BINS, 8, tmpl, h, w, 3, origins)
+        got = ex.origins[t]
+        gi = (got[0] - prev[0] + 32) * 65 + (got[1] - prev[1] + 32)
+        # tie-tolerant: the GPU's pick is a minimum of the oracle's distances
+        assert dist[gi] <= dist[best] * (1 + 1e-5) + 1e-12, (t, dist[gi], dist[best])
+        assert abs(ex.dists[t] - dist[gi]) <= 1e-5 * dist[gi] + 1e-9
+
+
+def test_exhaustive_follows_the_target(env):
+    v, ex = env["video"], env["ex"]
+    truth = np.array([v.target_box(t)[:2] for t in range(T)])
+    err = np.abs(ex.origins - truth).max(1)
+    assert np.median(err) <= 2 and np.mean(err <= 8) >= 0.9
+
+
+def test_margin_minus_inf_is_always_exhaustive(env):
+    trk, lp = env["tracker"], env["lp"]
+    lt = trk.LearnedTracker(env["tr"], None, k=64, tau=-math.inf, prior_logits=trk.distance_prior().cuda())
+    res = trk.track(env["stack"], env["box0"], env["tr"], lt)
+    assert res.fallback[1:].all()
+    np.testing.assert_array_equal(res.origins, env["ex"].origins)
+
+
+def test_margin_plus_inf_agrees_when_proposals_hold_the_argmin(env):
+    trk, lp, ex = env["tracker"], env["lp"], env["ex"]
+    prior = trk.distance_prior().cuda()
+    lt = trk.LearnedTracker(env["tr"], None, k=64, tau=math.inf, prior_logits=prior)
+    res = trk.track(env["stack"], env["box0"], env["tr"], lt, teacher=ex)
+    top = set(lp.lp_topk(prior, 64).cpu().numpy()[0].tolist())
+    off = ex.origins[1:] - ex.origins[:-1]
+    inside = np.array([int(lp.label_of(a, b)) in top for a, b in off])
+    assert inside.any()
+    t = np.arange(1, T)
+    # from frame 2 on the margin is +inf (frame 1 compares with the template's own distance, 0)
+    sel = t[inside & (t >= 2)]
+    assert not res.fallback[sel].any()
+    np.testing.assert_array_equal(res.dists[sel], ex.dists[sel])
+
+
+def test_zero_network_falls_back_on_every_frame(env):
+    trk, lp = env["tracker"], env["lp"]
+    zero = {k: np.zeros_like(v) for k, v in cnn.init_params(0).items()}
+    net = lp.ProposalNet(zero, max_batch=1)
+    lt = trk.LearnedTracker(env["tr"], net, k=64, tau=0.25)
+    res = trk.track(env["stack"], env["box0"], env["tr"], lt, teacher=env["ex"])
+    assert res.fallback[1:].all()
+    np.testing.assert_array_equal(res.origins, env["ex"].origins)
+
+
+def test_trained_network_beats_the_search_without_it(env):
+    """Train on independent sequences (labels from the exhaustive search), then
+    compare on four held-out sequences with the no-network ranking (nearest
+    offsets first) at the same budget of 64 exactly scored candidates."""
+    trk, lp, tr = env["tracker"], env["lp"], env["tr"]
+    vids = training_videos(200, 16, H, W)
+    stack, parts = [], []
+    for i, v in enumerate(vids):
+        f = torch.from_numpy(render(v)).cuda()
+        box = v.target_box(0)
+        parts.append(trk.samples_from_track(trk.track(f, box, tr), box[2:], frame0=i * v.n_frames))
+        stack.append(f)
+    stack = torch.cat(stack)
+    net = lp.ProposalNet(lp.init_params(1), max_batch=64)
+    losses = trk.train(net, stack, trk.concat(parts), steps=2000, batch=64, lr=0.01, seed=3)
+    assert np.mean(losses[-50:]) < np.mean(losses[:50])
+    del stack
+    prior = trk.distance_prior().cuda()
+    tot = {"n": 0, "r_net": 0.0, "r_pr": 0.0, "fb_net": 0, "fb_pr": 0, "ag_net": 0, "ag_pr": 0}
+    held_out = [(env["stack"], env["box0"], env["ex"])]
+    for seed in (78, 79, 80):
+        v = Video(seed, H, W, T)
+        f = torch.from_numpy(render(v)).cuda()
+        held_out.append((f, v.target_box(0), trk.track(f, v.target_box(0), tr)))
+    for f, box, ex in held_out:
+        held = trk.samples_from_track(ex, box[2:])
+        n = len(held.frame)
+        tot["n"] += n
+        tot["r_net"] += trk.recall(net, f, held) * n
+        tot["r_pr"] += trk.recall(prior, f, held) * n
+        for tag, lt in (("net", trk.LearnedTracker(tr, net, k=64, tau=0.25)),
+                        ("pr", trk.LearnedTracker(tr, None, k=64, tau=0.25, prior_logits=prior))):
+            res = trk.track(f, box, tr, lt, teacher=ex)
+            tot["fb_" + tag] += int(res.fallback[1:].sum())
+            tot["ag_" + tag] += int(np.all(res.origins[1:] == ex.origins[1:], axis=1).sum())
+    m = tot["n"]
+    frames = len(held_out) * (T - 1)
+    r = {k: tot[k] / (m if k.startswith("r_") else frames) for k in tot if k != "n"}
+    print(" ".join("%s %.3f" % kv for kv in r.items()))
+    assert r["r_net"] > r["r_pr"] + 0.1
+    assert r["fb_net"] < r["fb_pr"]
+    assert r["ag_net"] >= r["ag_pr"]
