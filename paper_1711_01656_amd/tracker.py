@@ -191,12 +191,13 @@ def concat(samples: List[Samples]) -> Samples:
 
 def train(net: lp.ProposalNet, stack: torch.Tensor, samples: Samples, steps: int, batch: int = 64,
           lr: float = 0.02, momentum: float = 0.9, weight_decay: float = 1e-4, jitter: int = 12,
-          seed: int = 0, log_every: int = 0) -> List[float]:
+          seed: int = 0, log_every: int = 0, cosine: bool = True) -> List[float]:
     """SGD on random batches of samples.  Each draw shifts the crop centre by a
     random jitter j (|j| <= jitter per axis) and the label by -j, so the
     network sees the target at many positions; labels stay inside the
-    search range.  Returns the mean loss of every step (read back every
-    `log_every` steps, or at the end)."""
+    search range.  With `cosine` the learning rate decays as
+    lr (1 + cos(pi s / steps)) / 2.  Returns the mean loss of every step
+    (read back every `log_every` steps, or at the end)."""
     rng = np.random.default_rng(seed)
     dev = net.device
     n = len(samples.frame)
@@ -215,7 +216,8 @@ def train(net: lp.ProposalNet, stack: torch.Tensor, samples: Samples, steps: int
         ce_d.copy_(torch.from_numpy((samples.center[pick] + j).astype(np.int32)))
         lb_d.copy_(torch.from_numpy(lab.astype(np.int32)))
         x = net.crop(stack, ce_d, frames=fr_d)
-        loss = net.train_step(x, lb_d, lr, momentum, weight_decay)
+        lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps)) if cosine else lr
+        loss = net.train_step(x, lb_d, lr_s, momentum, weight_decay)
         pending.append(loss.mean())
         if (log_every and (s + 1) % log_every == 0) or s == steps - 1:
             losses.extend(float(v) for v in torch.stack(pending).cpu())
