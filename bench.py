@@ -9,6 +9,12 @@ One step = one pass of the whole path over one synthetic 1920x1080 frame with
   4. a 3-level pyramid descriptor of a 32x32 template and the pyramid
      chi-square search over a 129 x 129 grid of candidate origins.
 Inputs are resident in HBM before timing.  Prints one JSON line.
+
+The line also carries the tracker workload ("tracker"): a 1280x720, 300-frame
+synthetic video (7 feature channels x 16 bins), the exhaustive 65x65
+pyramid-distance search against the learned proposal (BF16 network trained
+here on exhaustive-search labels of independent sequences, top 64 scored
+exactly, exhaustive fallback), reported as frames per second and agreement.
 """
 from __future__ import annotations
 
@@ -39,6 +45,9 @@ def parse():
     ap.add_argument("--no-other", action="store_true", help="skip timing the other layout")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run one device fill and one copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-tracker", action="store_true", help="skip the tracker workload")
+    ap.add_argument("--train-videos", type=int, default=400)
+    ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--tile", type=str, default="",
                     help="tile_h,tile_w,planes_per_wave (default: autotuned at start-up)")
     return ap.parse_args()
@@ -135,6 +144,97 @@ def time_calls(torch, fn, n):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / n
+
+
+def tracker_leg(torch, args):
+    """Learned vs exhaustive tracking on the 1280x720, 300-frame video."""
+    from paper_1711_01656_amd import proposal as lp
+    from paper_1711_01656_amd import tracker as trk
+    from paper_1711_01656_amd import tune
+    from synth.video import config5, render, training_videos
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    # training data: independent 640x360 sequences labelled by the exhaustive search
+    th, tw, tf = 360, 640, 16
+    ttr = trk.PyramidTracker(th, tw)
+    stack, parts = [], []
+    for i, v in enumerate(training_videos(args.train_videos, tf, th, tw)):
+        f = torch.from_numpy(render(v, threads=16)).to(dev)
+        box = v.target_box(0)
+        parts.append(trk.samples_from_track(trk.track(f, box, ttr), box[2:], frame0=i * tf))
+        stack.append(f)
+    stack = torch.cat(stack)
+    samples = trk.concat(parts)
+    t_data = time.perf_counter() - t0
+    batch = 64
+    net = lp.ProposalNet(lp.init_params(1), max_batch=batch)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = trk.train(net, stack, samples, steps=args.train_steps, batch=batch, lr=0.01, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del stack, ttr
+    print("tracker: data %.1fs (%d samples), training %.1fs" % (t_data, len(samples.frame), t_train),
+          file=sys.stderr, flush=True)
+
+    video = config5()
+    frames = torch.from_numpy(render(video, threads=16)).to(dev)
+    box0 = video.target_box(0)
+    cfg, _ = tune.tune(frames[0], 16, moments=False, layout="hwb", reps=3)
+    tr = trk.PyramidTracker(video.H, video.W, cfg=cfg)
+    prior = trk.distance_prior().to(dev)
+    tau = 0.25
+
+    def timed(learned=None):
+        """Free-running track enqueued on the device; frames per second of wall time."""
+        trk.track_device(frames[:8], box0, tr, learned)          # warm-up
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        res = trk.track_device(frames, box0, tr, learned)
+        torch.cuda.synchronize()
+        return res, (len(frames) - 1) / (time.perf_counter() - a)
+
+    ex, fps_ex = timed()
+    learned = trk.LearnedTracker(tr, net, k=64, tau=tau)
+    free, fps_l = timed(learned)
+    base = trk.LearnedTracker(tr, None, k=64, tau=tau, prior_logits=prior)
+    free_b, fps_b = timed(base)
+    # per-frame agreement: every search starts from the exhaustive trajectory
+    forced = trk.track(frames, box0, tr, learned, teacher=ex)
+    forced_b = trk.track(frames, box0, tr, base, teacher=ex)
+    held = trk.samples_from_track(ex, box0[2:])
+
+    def agree(a, b, px=0):
+        return float(np.mean(np.all(np.abs(a.origins[1:] - b.origins[1:]) <= px, axis=1)))
+
+    # network forward alone (B = 1), timed on the device
+    x = net.crop(frames[1], torch.tensor([[box0[0] + box0[2] // 2, box0[1] + box0[3] // 2]], dtype=torch.int32,
+                                         device=dev))
+    fwd_ms = time_calls(torch, lambda: net.forward(x), 50)
+    return {
+        "workload": "1280x720 synthetic video, 300 frames, 7 channels x 16 bins; 65x65 offsets; top-64 learned",
+        "fps_exhaustive": round(fps_ex, 1),
+        "fps_learned": round(fps_l, 1),
+        "fps_no_network": round(fps_b, 1),
+        "tau": tau,
+        "agreement_per_frame": agree(forced, ex),
+        "agreement_per_frame_no_network": agree(forced_b, ex),
+        "fallback_rate": float(forced.fallback[1:].mean()),
+        "fallback_rate_no_network": float(forced_b.fallback[1:].mean()),
+        "recall_top64": round(trk.recall(net, frames, held), 4),
+        "recall_top64_no_network": round(trk.recall(prior, frames, held), 4),
+        "free_running_within_1px": agree(free, ex, 1),
+        "free_running_within_1px_no_network": agree(free_b, ex, 1),
+        "free_running_fallback_rate": float(free.fallback[1:].mean()),
+        "free_running_fallback_rate_no_network": float(free_b.fallback[1:].mean()),
+        "network_forward_ms": round(fwd_ms, 4),
+        "training": {"samples": int(len(samples.frame)), "steps": args.train_steps, "batch": batch,
+                     "seconds": round(t_train, 2), "ms_per_step": round(t_train / args.train_steps * 1e3, 3),
+                     "loss_first": round(float(np.mean(losses[:20])), 4),
+                     "loss_last": round(float(np.mean(losses[-100:])), 4)},
+        "ih_tile": repr(cfg),
+    }
 
 
 def main():
@@ -259,6 +359,9 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
         },
     }
+    if not args.no_tracker:
+        print("tracker ...", file=sys.stderr, flush=True)
+        res["tracker"] = tracker_leg(torch, args)
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, origins_np, (tr, tc, 32, 32))

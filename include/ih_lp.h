@@ -47,15 +47,15 @@ extern "C" {
 /*
  * ih_lp_conv - 3x3 convolution with 32 output channels.
  *   in    [B][Cin][Hin][Win] bf16.
- *   w     [32][Kpad] bf16, Kpad = Cin*9 rounded up to a multiple of 8, zero
- *         padded; column k = ci*9 + kh*3 + kw.
+ *   w     [32][9*Cpad] bf16, Cpad = Cin rounded up to a multiple of 8, tap-major:
+ *         column k = (kh*3 + kw)*Cpad + ci, zero for ci >= Cin; 8-byte aligned.
  *   out   [B][32][Hout][Wout] bf16, Hout = (Hin + 2 pad - 2 dil - 1)/stride + 1.
  *   mask  NULL: out = bf16(relu(conv + bias)) (forward; bias is [32] FP32).
  *         else [B][32][Hout][Wout] bf16: out = bf16(conv * (mask > 0)), bias
  *         unused (input gradient through a ReLU: pass dZ of the next layer as
  *         `in`, the packed transposed weights as `w`, and that layer's input
  *         activation as `mask`).
- * Cin*9 must not exceed 1024.
+ * Cin must not exceed 512.
  */
 int ih_lp_conv(const uint16_t *in, int32_t B, int32_t Cin, int32_t Hin,
                int32_t Win, const uint16_t *w, const float *bias,
@@ -137,10 +137,10 @@ int ih_lp_origins(const int32_t *idx, int32_t B, int32_t k,
                   void *stream);
 
 /*
- * ih_lp_pack - BF16 operands from the FP32 parameter array:
- *   w1 [32][64] (K = 63 padded with a zero column), w2, w3 [32][288], and the
- *   transposed, tap-flipped w2t, w3t [32][288] used for input gradients:
- *   wt[ci][co*9 + kh*3 + kw] = W[co][ci][2-kh][2-kw].
+ * ih_lp_pack - BF16 operands from the FP32 parameter array, in the tap-major
+ *   layout of ih_lp_conv: w1 [32][72] (Cpad = 8, channel 7 zero), w2, w3
+ *   [32][288], and the transposed, tap-flipped w2t, w3t [32][288] used for
+ *   input gradients: wt[ci][(kh*3 + kw)*32 + co] = W[co][ci][2-kh][2-kw].
  */
 int ih_lp_pack(const float *params, uint16_t *w1, uint16_t *w2, uint16_t *w3,
                uint16_t *w2t, uint16_t *w3t, void *stream);
@@ -158,6 +158,46 @@ int ih_lp_sgd(float *params, const float *grads, float *mom, int32_t n,
  */
 int ih_lp_topk(const float *logits, int32_t B, int32_t n, int32_t k,
                int32_t *idx, void *stream);
+
+/*
+ * Device-resident tracking.  The state of one target lives in device memory,
+ * so a sequence of frames is enqueued without host round trips.  Per frame:
+ *   ih_track_prepare                 base = previous origin, crop centre
+ *   (learned) crop, network, ih_lp_topk, ih_lp_origins, ih_match_candidates
+ *   over the k proposals, then ih_track_gate
+ *   (exhaustive only) ih_lp_origins over all offsets
+ *   ih_match_candidates over the exhaustive list, ih_track_commit
+ * The gate implements the fallback rule: the best proposal is accepted when
+ * its distance d satisfies d <= (1 + tau) * dist (evaluated in double);
+ * then the exhaustive list is filled with origins outside every frame, so the
+ * exhaustive scoring returns best = -1 without reading the histogram.
+ */
+typedef struct {
+  int32_t origin[2]; /* window origin (row, column) accepted at the previous frame */
+  float dist;        /* its distance d*                                           */
+  int32_t decision;  /* accepted offset index, or -1 (written by prepare / gate)  */
+} ih_track_state;
+
+/* base [2] = st->origin; center [2] (may be NULL) = origin + (win_h/2, win_w/2);
+   st->decision = -1. */
+int ih_track_prepare(ih_track_state *st, int32_t win_h, int32_t win_w,
+                     int32_t *base, int32_t *center, void *stream);
+
+/* Reads the k-proposal search (idx [k] offset indices, kdist [k], kbest [1]
+   from ih_match_candidates); sets st->decision and writes exh_origins
+   [(2 radius + 1)^2][2]. */
+int ih_track_gate(ih_track_state *st, const int32_t *idx, const float *kdist,
+                  const int32_t *kbest, int32_t radius, double tau,
+                  const int32_t *base, int32_t *exh_origins, void *stream);
+
+/* New state from the accepted proposal (kdist, kbest) or the exhaustive
+   search (exh_dist, exh_best; +inf and the old origin when no candidate was
+   inside); rec [4] receives origin row, origin column, the distance's FP32
+   bits and 1 when the exhaustive result was used. */
+int ih_track_commit(ih_track_state *st, const float *kdist,
+                    const int32_t *kbest, const float *exh_dist,
+                    const int32_t *exh_best, int32_t radius, int32_t *rec,
+                    void *stream);
 
 #ifdef __cplusplus
 }

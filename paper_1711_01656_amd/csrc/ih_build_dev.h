@@ -3,6 +3,8 @@
 // (ih_batch.hip).  Each body processes one work unit given by index.
 #pragma once
 
+#include <type_traits>
+
 #include "ih_internal.h"
 
 namespace ih {
@@ -329,6 +331,17 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 //     (the column prefix) and walks each row left to right keeping the row
 //     prefix; every (row, column) step stores 64 consecutive planes.
 // --------------------------------------------------------------------------
+#ifndef IH_HWB_NONTEMPORAL
+#define IH_HWB_NONTEMPORAL 1
+#endif
+__device__ __forceinline__ void hwb_store(int v, int32_t *dst) {
+#if IH_HWB_NONTEMPORAL
+  __builtin_nontemporal_store(v, dst);
+#else
+  *dst = v;
+#endif
+}
+
 template <typename T, int TW, bool MOM>
 __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g, int64_t unit) {
   const int lane = threadIdx.x & 63;
@@ -337,10 +350,12 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
   const int chunk = (int)(unit % nchunk);
   const int64_t tile = unit / nchunk;
   const int j = (int)(tile % g.nTC), I = (int)(tile / g.nTC);
-  const int p = chunk * 64 + lane;
-  const bool live = p < g.P;
-  const int ch = live ? p / g.bins : 0;
-  const int k = live ? p - ch * g.bins : 0;
+  // Lanes past the last plane repeat the last plane: they compute the same
+  // values and store them to the same addresses, so no store needs a guard.
+  const int p = min(chunk * 64 + lane, g.P - 1);
+  constexpr bool live = true;
+  const int ch = p / g.bins;
+  const int k = p - ch * g.bins;
   const int R0 = I * g.TH, C0 = j * TW;
   const int cols = min(TW, g.W - C0), rows = min(g.TH, g.H - R0);
   // pixel values of bin k are those in [lo, hi): floor(v * bins / 2^bits) = k
@@ -377,34 +392,57 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
   }
   const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
   const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
-  for (int rr = 0; rr < rows; ++rr) {
+  // A full tile row can be read as 32-bit words when every row of the tile
+  // starts on a 4-byte boundary.
+  const bool full = cols == TW;
+  const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
+                     ((int64_t)C0 * sizeof(T)) % 4 == 0;
+  constexpr int PER = 4 / (int)sizeof(T);  // pixels per 32-bit word
+  auto row_step = [&](auto FULL, int rr) {
+    constexpr bool F = decltype(FULL)::value;
     const int r = R0 + rr;
     const T *row = img + (int64_t)r * g.W + C0;
-    uint32_t v[TW];
-#pragma unroll
-    for (int c = 0; c < TW; ++c) v[c] = c < cols ? (uint32_t)row[c] : 0u;
     uint32_t rc = live ? lc[(int64_t)r * g.bins] : 0u;
     uint32_t ry = 0;
     if constexpr (MOM) ry = live ? lcy[(int64_t)r * g.bins] : 0u;
-    const int64_t base = ((int64_t)r * g.W + C0) * P + p;
-#pragma unroll
-    for (int c = 0; c < TW; ++c) {
-      if (c < cols) {
-        const uint32_t hit = (v[c] - lo) < width ? 1u : 0u;
-        rc += hit;
-        col[c] += rc;
-        if (live) __builtin_nontemporal_store((int)col[c], a.ih + base + c * P);
-        if constexpr (MOM) {
-          colx[c] += (uint32_t)r * rc;
-          ry += hit * (uint32_t)(C0 + c);
-          coly[c] += ry;
-          if (live) {
-            __builtin_nontemporal_store(colx[c], a.mx + base + c * P);
-            __builtin_nontemporal_store(coly[c], a.my + base + c * P);
-          }
-        }
+    // uniform row base and a 32-bit per-lane offset (TW * P words at most)
+    const int64_t rbase = ((int64_t)r * g.W + C0) * P;
+    // per-lane row pointers; column c adds the uniform c * P words
+    int32_t *dih = a.ih + rbase + p;
+    int32_t *dmx = reinterpret_cast<int32_t *>(a.mx) + rbase + p;
+    int32_t *dmy = reinterpret_cast<int32_t *>(a.my) + rbase + p;
+    auto pixel = [&](int c, uint32_t val) {
+      const uint32_t hit = (val - lo) < width ? 1u : 0u;
+      const int64_t cw = (int64_t)c * P;
+      rc += hit;
+      col[c] += rc;
+      hwb_store((int)col[c], dih + cw);
+      if constexpr (MOM) {
+        colx[c] += (uint32_t)r * rc;
+        ry += hit * (uint32_t)(C0 + c);
+        coly[c] += ry;
+        hwb_store((int)colx[c], dmx + cw);
+        hwb_store((int)coly[c], dmy + cw);
       }
+    };
+    if (F && words) {
+      uint32_t wv[TW / PER];
+      const uint32_t *wp = reinterpret_cast<const uint32_t *>(row);
+#pragma unroll
+      for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
+#pragma unroll
+      for (int c = 0; c < TW; ++c)
+        pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u));
+    } else {
+#pragma unroll
+      for (int c = 0; c < TW; ++c)
+        if (F || c < cols) pixel(c, (uint32_t)row[c]);
     }
+  };
+  if (full) {
+    for (int rr = 0; rr < rows; ++rr) row_step(std::true_type{}, rr);
+  } else {
+    for (int rr = 0; rr < rows; ++rr) row_step(std::false_type{}, rr);
   }
 }
 

@@ -6,7 +6,7 @@
 //
 // Convolutions, their input gradients and their weight gradients are implicit
 // GEMMs on the 32x32x8 BF16 matrix cores with FP32 accumulation:
-//   forward  out[co][pix] = sum_k W[co][k] X[k][pix]      (M=32, N=pixels, K=Cin*9)
+//   forward  out[co][pix] = sum_k W[co][k] X[k][pix]      (M=32, N=pixels, K=9*Cpad)
 //   dgrad    the forward of dZ with W transposed and its taps flipped
 //   wgrad    dW[co][k]     = sum_pix dZ[co][pix] X[k][pix] (M=32, N=K, K=pixels)
 // X is the im2col view of the layer input, gathered on the fly.  Reductions
@@ -32,7 +32,9 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 struct ConvShape {
-  int B, Cin, Hin, Win, Hout, Wout, stride, dil, pad, K, Kpad;
+  int B, Cin, Hin, Win, Hout, Wout, stride, dil, pad;
+  int K, Kpad;   // weight gradients: K = Cin*9 (channel-major), Kpad = K rounded up to 8
+  int Cpad, Kt;  // convolutions: channels padded to 8, Kt = 9*Cpad (tap-major)
 };
 
 // Value of the im2col matrix X[k][pixel] for the pixel (b, y, x).
@@ -45,42 +47,55 @@ __device__ __forceinline__ short im2col(const uint16_t *__restrict__ in, const C
   return (short)in[(((int64_t)b * s.Cin + ci) * s.Hin + r) * s.Win + c];
 }
 
-// Forward convolution (also used for input gradients).  Block: 4 waves, each
-// a tile of 32 output channels x 32 consecutive output pixels.
+// Forward convolution (also used for input gradients).  A block owns one
+// tile of 32 consecutive output pixels x 32 output channels; its 4 waves split
+// the K = 9*Cpad reduction (taps outer, 8 channels of one tap per matrix
+// instruction, so each lane computes its source pixel once per instruction
+// and needs no division), and the four partial tiles are added in a fixed
+// order through LDS.
 //   mask == nullptr: out = bf16(relu(acc + bias))
 //   mask != nullptr: out = bf16(acc * (mask > 0))   (input gradient through a ReLU)
 __global__ __launch_bounds__(256) void k_lp_conv(const uint16_t *__restrict__ in, const uint16_t *__restrict__ w,
                                                  const float *__restrict__ bias, const uint16_t *__restrict__ mask,
                                                  uint16_t *__restrict__ out, ConvShape s) {
-  extern __shared__ uint16_t wl[];  // LP_CO x Kpad weights
-  for (int i = threadIdx.x; i < LP_CO * s.Kpad; i += blockDim.x) wl[i] = w[i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ float red[4][LP_CO * 32];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
   const int64_t npix = (int64_t)s.B * s.Hout * s.Wout;
-  const int64_t p = ((int64_t)blockIdx.x * 4 + wave) * 32 + (lane & 31);
+  const int64_t p = (int64_t)blockIdx.x * 32 + (lane & 31);
   const bool live = p < npix;
   const int64_t pc = live ? p : 0;
   const int x = (int)(pc % s.Wout), y = (int)((pc / s.Wout) % s.Hout), b = (int)(pc / ((int64_t)s.Wout * s.Hout));
-  const int half = lane >> 5;
+  const int64_t plane = (int64_t)s.Hin * s.Win;
+  const uint16_t *inb = in + (int64_t)b * s.Cin * plane;
+  const uint16_t *wrow = w + (int64_t)(lane & 31) * s.Kt + 4 * half;
+  const int groups = s.Cpad >> 3, nslice = s.Kt >> 3;
+  const int per = (nslice + 3) >> 2;
+  const int s0 = wave * per, s1 = min(nslice, s0 + per);
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = 0; k0 < s.Kpad; k0 += 8) {
-    bf16x4 a, bv;
+  for (int sl = s0; sl < s1; ++sl) {
+    const int t = sl / groups, ci0 = (sl - t * groups) * 8 + 4 * half;
+    const int kh = t / 3, kw = t - kh * 3;
+    const int r = y * s.stride + kh * s.dil - s.pad, c = x * s.stride + kw * s.dil - s.pad;
+    const bool inside = live && r >= 0 && c >= 0 && r < s.Hin && c < s.Win;
+    const bf16x4 a = *reinterpret_cast<const bf16x4 *>(wrow + sl * 8);
+    bf16x4 bv;
+    const int64_t off = (int64_t)ci0 * plane + (int64_t)r * s.Win + c;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + 4 * half + j;
-      a[j] = (short)wl[(lane & 31) * s.Kpad + k];
-      bv[j] = live ? im2col(in, s, k, b, y, x) : (short)0;
-    }
+    for (int j = 0; j < 4; ++j) bv[j] = inside && ci0 + j < s.Cin ? (short)inb[off + j * plane] : (short)0;
     acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
   }
-  if (!live) return;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int co = 8 * (r >> 2) + 4 * half + (r & 3);
-    const int64_t o = (((int64_t)b * LP_CO + co) * s.Hout + y) * s.Wout + x;
-    float v = acc[r];
+  for (int r = 0; r < 16; ++r) red[wave][(8 * (r >> 2) + 4 * half + (r & 3)) * 32 + (lane & 31)] = acc[r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < LP_CO * 32; e += 256) {
+    const int co = e >> 5;
+    const int64_t q = (int64_t)blockIdx.x * 32 + (e & 31);
+    if (q >= npix) continue;
+    float v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    const int xq = (int)(q % s.Wout), yq = (int)((q / s.Wout) % s.Hout), bq = (int)(q / ((int64_t)s.Wout * s.Hout));
+    const int64_t o = (((int64_t)bq * LP_CO + co) * s.Hout + yq) * s.Wout + xq;
     if (mask) {
       v = bf2f(mask[o]) > 0.0f ? v : 0.0f;
     } else {
@@ -321,23 +336,24 @@ __global__ void k_lp_origins(const int32_t *__restrict__ idx, int B, int k, cons
 }
 
 // Parameter packing.  params (FP32): W1[32][7][3][3] b1[32] W2[32][32][3][3]
-// b2[32] W3 b3 wh[32] bh[1].  Writes the BF16 GEMM operands: W1 as [32][64]
-// (K padded with zeros), W2, W3 as [32][288], and for the input gradients the
-// transposed, tap-flipped W2t, W3t: Wt[ci][co*9 + kh*3 + kw] = W[co][ci][2-kh][2-kw].
+// b2[32] W3 b3 wh[32] bh[1].  Writes the BF16 operands of the convolutions in
+// tap-major order, column k = (kh*3 + kw)*Cpad + ci: W1 as [32][72] (Cpad = 8,
+// channel 7 zero), W2, W3 as [32][288], and for the input gradients the
+// transposed, tap-flipped W2t, W3t: Wt[ci][(kh*3 + kw)*32 + co] = W[co][ci][2-kh][2-kw].
 __global__ void k_lp_pack(const float *__restrict__ params, uint16_t *__restrict__ w1, uint16_t *__restrict__ w2,
                           uint16_t *__restrict__ w3, uint16_t *__restrict__ w2t, uint16_t *__restrict__ w3t) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n1 = 32 * 63, n2 = 32 * 288;
   const float *W1 = params, *W2 = params + n1 + 32, *W3 = W2 + n2 + 32;
-  if (i < 32 * 64) {
-    const int co = i / 64, k = i - co * 64;
-    w1[i] = k < 63 ? f2bf(W1[co * 63 + k]) : (uint16_t)0;
+  if (i < 32 * 72) {
+    const int co = i / 72, k = i - co * 72, t = k >> 3, ci = k & 7;
+    w1[i] = ci < 7 ? f2bf(W1[(co * 7 + ci) * 9 + t]) : (uint16_t)0;
   }
   if (i < n2) {
-    w2[i] = f2bf(W2[i]);
-    w3[i] = f2bf(W3[i]);
-    const int ci = i / 288, r = i - ci * 288, co = r / 9, t = r - co * 9, kh = t / 3, kw = t - kh * 3;
-    const int src = ((co * 32 + ci) * 3 + (2 - kh)) * 3 + (2 - kw);
+    const int row = i / 288, k = i - row * 288, t = k >> 5, col = k & 31;
+    w2[i] = f2bf(W2[(row * 32 + col) * 9 + t]);  // row = co, col = ci
+    w3[i] = f2bf(W3[(row * 32 + col) * 9 + t]);
+    const int src = (col * 32 + row) * 9 + (8 - t);   // row = ci, col = co; tap flipped
     w2t[i] = f2bf(W2[src]);
     w3t[i] = f2bf(W3[src]);
   }
@@ -394,9 +410,11 @@ static int conv_shape(int B, int Cin, int Hin, int Win, int stride, int dil, int
   s->Hout = (Hin + 2 * pad - 2 * dil - 1) / stride + 1;
   s->Wout = (Win + 2 * pad - 2 * dil - 1) / stride + 1;
   if (s->Hout < 1 || s->Wout < 1) return set_error(IH_ERR_INVALID_ARG, "convolution output is empty");
+  if (Cin > 512) return set_error(IH_ERR_UNSUPPORTED, "Cin > 512");
   s->K = Cin * 9;
   s->Kpad = (s->K + 7) & ~7;
-  if (s->Kpad > 1024) return set_error(IH_ERR_UNSUPPORTED, "Cin*9 > 1024");
+  s->Cpad = (Cin + 7) & ~7;
+  s->Kt = 9 * s->Cpad;
   return IH_OK;
 }
 
@@ -411,10 +429,11 @@ extern "C" int ih_lp_conv(const uint16_t *in, int32_t B, int32_t Cin, int32_t Hi
   int e = conv_shape(B, Cin, Hin, Win, stride, dil, pad, &s);
   if (e) return e;
   if (!in || !w || !out || (!mask && !bias)) return set_error(IH_ERR_INVALID_ARG, "NULL pointer");
+  if ((uintptr_t)w & 7) return set_error(IH_ERR_INVALID_ARG, "weights must be 8-byte aligned");
   const int64_t npix = (int64_t)B * s.Hout * s.Wout;
-  const int64_t blocks = (npix + 127) / 128;
-  hipLaunchKernelGGL(k_lp_conv, dim3((unsigned)blocks), dim3(256), (size_t)LP_CO * s.Kpad * 2, as_stream(stream), in,
-                     w, bias, mask, out, s);
+  const int64_t blocks = (npix + 31) / 32;
+  if (blocks >= ((int64_t)1 << 31)) return set_error(IH_ERR_RANGE, "too many output pixels");
+  hipLaunchKernelGGL(k_lp_conv, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), in, w, bias, mask, out, s);
   return hip_check(hipGetLastError(), "lp conv launch");
 }
 

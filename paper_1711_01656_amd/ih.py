@@ -59,6 +59,9 @@ SIGNATURES = {
     "ih_lp_pack": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "ih_lp_sgd": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
     "ih_lp_topk": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P]),
+    "ih_track_prepare": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P]),
+    "ih_track_gate": (ctypes.c_int, [_P, _P, _P, _P, _I32, ctypes.c_double, _P, _P, _P]),
+    "ih_track_commit": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P]),
 }
 
 

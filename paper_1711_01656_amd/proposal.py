@@ -106,8 +106,8 @@ def lp_conv(inp: torch.Tensor, w: torch.Tensor, bias: Optional[torch.Tensor], st
     B, Cin, Hin, Win = inp.shape
     Ho = (Hin + 2 * pad - 2 * dil - 1) // stride + 1
     Wo = (Win + 2 * pad - 2 * dil - 1) // stride + 1
-    kpad = (Cin * 9 + 7) // 8 * 8
-    if tuple(out.shape) != (B, C_MID, Ho, Wo) or w.numel() != C_MID * kpad:
+    kt = 9 * ((Cin + 7) // 8 * 8)
+    if tuple(out.shape) != (B, C_MID, Ho, Wo) or w.numel() != C_MID * kt:
         raise IHError("lp_conv: output or weight shape mismatch")
     if mask is not None:
         _dev(mask, "mask", torch.bfloat16)
@@ -180,7 +180,7 @@ def lp_pack(params: torch.Tensor, w1, w2, w3, w2t, w3t):
     _dev(params, "params", torch.float32)
     if params.numel() != N_PARAMS:
         raise IHError("lp_pack: params must hold %d floats" % N_PARAMS)
-    for t, n, name in ((w1, C_MID * 64, "w1"), (w2, C_MID * 288, "w2"), (w3, C_MID * 288, "w3"),
+    for t, n, name in ((w1, C_MID * 72, "w1"), (w2, C_MID * 288, "w2"), (w3, C_MID * 288, "w3"),
                        (w2t, C_MID * 288, "w2t"), (w3t, C_MID * 288, "w3t")):
         _dev(t, name, torch.bfloat16)
         if t.numel() != n:
@@ -236,7 +236,7 @@ class ProposalNet:
         self.mom = torch.zeros_like(self.params)
         self.set_params(params)
         bf = dict(dtype=torch.bfloat16, device=self.device)
-        self.w1 = torch.empty(C_MID * 64, **bf)
+        self.w1 = torch.empty(C_MID * 72, **bf)
         self.w2, self.w3, self.w2t, self.w3t = (torch.empty(C_MID * 288, **bf) for _ in range(4))
         B = max_batch
         self.x = torch.empty((B, C_IN, CROP, CROP), **bf)

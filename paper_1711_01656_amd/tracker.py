@@ -25,8 +25,8 @@ import numpy as np
 import torch
 
 from . import proposal as lp
-from .ih import (IHError, TileCfg, cells, ih_build, ih_match_candidates, ih_pyramid_desc, shape_of,
-                 workspace_size)
+from .ih import (IHError, TileCfg, _check, _p, _stream, ih_build, ih_match_candidates, ih_pyramid_desc, lib,
+                 shape_of, workspace_size)
 
 RADIUS = lp.RADIUS
 N_OFF = lp.N_OFFSETS
@@ -100,13 +100,17 @@ class LearnedTracker:
         self.kbest = torch.empty(1, dtype=torch.int32, device=dev)
         self.center = torch.empty((1, 2), dtype=torch.int32, device=dev)
 
-    def propose(self, feat: torch.Tensor, origin):
-        """Enqueue the ranking for a search around origin; fills self.idx."""
+    def propose(self, feat: torch.Tensor, origin=None):
+        """Enqueue the ranking of the offsets; fills self.idx.  The crop is
+        centred on the window at origin, or at self.center as already set on
+        the device when origin is None."""
         if self.net is None:
             lp.lp_topk(self.prior.view(1, -1), self.k, self.idx)
             return
-        h, w = self.tr.win
-        self.center.copy_(torch.tensor([[int(origin[0]) + h // 2, int(origin[1]) + w // 2]], dtype=torch.int32))
+        if origin is not None:
+            h, w = self.tr.win
+            self.center.copy_(torch.tensor([[int(origin[0]) + h // 2, int(origin[1]) + w // 2]],
+                                           dtype=torch.int32))
         x = self.net.crop(feat, self.center)
         logits = self.net.forward(x)
         lp.lp_topk(logits.view(1, -1), self.k, self.idx)
@@ -155,6 +159,45 @@ def track(frames, box0, tracker: PyramidTracker, learned: Optional[LearnedTracke
             o, d, fb[t] = learned.step(frames[t], prev, dprev)
         org[t], dist[t] = o, d
     return Track(org, dist, fb)
+
+
+def track_device(frames, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker] = None) -> Track:
+    """The free-running track() with the state kept on the device: every
+    frame's work is enqueued without a host round trip (the fallback rule
+    runs in ih_track_gate) and the results are read back once at the end.
+    Returns the same track as track(frames, box0, tracker, learned)."""
+    L = lib()
+    T = len(frames)
+    dev = tracker.device
+    tracker.set_template(frames[0], box0)
+    h, w = tracker.win
+    state = torch.from_numpy(np.array([box0[0], box0[1], 0, -1], np.int32)).to(dev)   # dist 0.0
+    exh = torch.empty((N_OFF, 2), dtype=torch.int32, device=dev)
+    rec = torch.zeros((T, 4), dtype=torch.int32, device=dev)
+    rec[0, 0], rec[0, 1] = int(box0[0]), int(box0[1])
+    use_net = learned is not None and learned.net is not None
+    if use_net and not learned.net.packed:
+        learned.net.pack()
+    s = _stream(state)
+    for t in range(1, T):
+        tracker.build(frames[t])
+        _check(L.ih_track_prepare(_p(state), h, w, _p(tracker.base), _p(learned.center) if use_net else None, s),
+               "ih_track_prepare")
+        if learned is not None:
+            learned.propose(frames[t])
+            lp.lp_origins(tracker.base, RADIUS, idx=learned.idx, out=learned.korig)
+            tracker.score(learned.korig, learned.kdist, learned.kbest)
+            _check(L.ih_track_gate(_p(state), _p(learned.idx), _p(learned.kdist), _p(learned.kbest), RADIUS,
+                                   float(learned.tau), _p(tracker.base), _p(exh), s), "ih_track_gate")
+        else:
+            lp.lp_origins(tracker.base, RADIUS, out=exh)
+        tracker.score(exh, tracker.dist, tracker.best)
+        _check(L.ih_track_commit(_p(state), _p(learned.kdist) if learned is not None else None,
+                                 _p(learned.kbest) if learned is not None else None, _p(tracker.dist),
+                                 _p(tracker.best), RADIUS, _p(rec[t]), s), "ih_track_commit")
+    r = rec.cpu().numpy()
+    fb = r[:, 3].astype(bool) if learned is not None else np.zeros(T, bool)
+    return Track(r[:, :2].astype(np.int64), r[:, 2].copy().view(np.float32).astype(np.float64), fb)
 
 
 def distance_prior() -> torch.Tensor:

@@ -55,13 +55,12 @@ def rand_act(rng, shape, frac_zero=0.4):
 
 
 def pack_w(w):
-    """[32][Cin][3][3] -> [32][Kpad] with zero padding (test-side layout)."""
+    """[32][Cin][3][3] -> [32][9][Cpad] tap-major, channels zero-padded to 8."""
     co, ci = w.shape[:2]
-    K = ci * 9
-    kpad = (K + 7) // 8 * 8
-    out = np.zeros((co, kpad))
-    out[:, :K] = w.reshape(co, K)
-    return out
+    cpad = (ci + 7) // 8 * 8
+    out = np.zeros((co, 9, cpad))
+    out[:, :, :ci] = w.reshape(co, ci, 9).transpose(0, 2, 1)
+    return out.reshape(co, 9 * cpad)
 
 
 def flip_t(w):
@@ -276,11 +275,11 @@ def test_pack_layout(P):
     net.pack()
     torch.cuda.synchronize()
     W1, W2, W3 = (cnn.bf16(p[k]) for k in ("W1", "W2", "W3"))
-    np.testing.assert_array_equal(host(net.w1).reshape(32, 64), pack_w(W1))
-    np.testing.assert_array_equal(host(net.w2).reshape(32, 288), W2.reshape(32, 288))
-    np.testing.assert_array_equal(host(net.w3).reshape(32, 288), W3.reshape(32, 288))
-    np.testing.assert_array_equal(host(net.w2t).reshape(32, 288), flip_t(W2).reshape(32, 288))
-    np.testing.assert_array_equal(host(net.w3t).reshape(32, 288), flip_t(W3).reshape(32, 288))
+    np.testing.assert_array_equal(host(net.w1).reshape(32, 72), pack_w(W1))
+    np.testing.assert_array_equal(host(net.w2).reshape(32, 288), pack_w(W2))
+    np.testing.assert_array_equal(host(net.w3).reshape(32, 288), pack_w(W3))
+    np.testing.assert_array_equal(host(net.w2t).reshape(32, 288), pack_w(flip_t(W2)))
+    np.testing.assert_array_equal(host(net.w3t).reshape(32, 288), pack_w(flip_t(W3)))
     got = net.get_params()
     for k in p:
         np.testing.assert_array_equal(got[k], p[k])
