@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run one device fill and one copy of this many MiB (counter calibration)")
     ap.add_argument("--no-tracker", action="store_true", help="skip the tracker workload")
-    ap.add_argument("--train-videos", type=int, default=400)
+    ap.add_argument("--train-videos", type=int, default=800)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--tile", type=str, default="",
                     help="tile_h,tile_w,planes_per_wave (default: autotuned at start-up)")
@@ -167,11 +167,11 @@ def tracker_leg(torch, args):
     stack = torch.cat(stack)
     samples = trk.concat(parts)
     t_data = time.perf_counter() - t0
-    batch = 64
+    batch, lr, jitter = 128, 0.02, 20
     net = lp.ProposalNet(lp.init_params(1), max_batch=batch)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    losses = trk.train(net, stack, samples, steps=args.train_steps, batch=batch, lr=0.01, seed=3)
+    losses = trk.train(net, stack, samples, steps=args.train_steps, batch=batch, lr=lr, jitter=jitter, seed=3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     del stack, ttr
@@ -186,12 +186,13 @@ def tracker_leg(torch, args):
     prior = trk.distance_prior().to(dev)
     tau = 0.25
 
-    def timed(learned=None):
-        """Free-running track enqueued on the device; frames per second of wall time."""
-        trk.track_device(frames[:8], box0, tr, learned)          # warm-up
+    def timed(learned=None, graph=True):
+        """Free-running track on the device (one captured step replayed per
+        frame); frames per second of wall time, template set-up excluded."""
+        trk.track_device(frames[:8], box0, tr, learned, graph=graph)          # warm-up
         torch.cuda.synchronize()
         a = time.perf_counter()
-        res = trk.track_device(frames, box0, tr, learned)
+        res = trk.track_device(frames, box0, tr, learned, graph=graph)
         torch.cuda.synchronize()
         return res, (len(frames) - 1) / (time.perf_counter() - a)
 
@@ -200,6 +201,8 @@ def tracker_leg(torch, args):
     free, fps_l = timed(learned)
     base = trk.LearnedTracker(tr, None, k=64, tau=tau, prior_logits=prior)
     free_b, fps_b = timed(base)
+    _, fps_ex_eager = timed(None, graph=False)
+    _, fps_l_eager = timed(learned, graph=False)
     # per-frame agreement: every search starts from the exhaustive trajectory
     forced = trk.track(frames, box0, tr, learned, teacher=ex)
     forced_b = trk.track(frames, box0, tr, base, teacher=ex)
@@ -217,6 +220,8 @@ def tracker_leg(torch, args):
         "fps_exhaustive": round(fps_ex, 1),
         "fps_learned": round(fps_l, 1),
         "fps_no_network": round(fps_b, 1),
+        "fps_exhaustive_eager": round(fps_ex_eager, 1),
+        "fps_learned_eager": round(fps_l_eager, 1),
         "tau": tau,
         "agreement_per_frame": agree(forced, ex),
         "agreement_per_frame_no_network": agree(forced_b, ex),
@@ -230,6 +235,7 @@ def tracker_leg(torch, args):
         "free_running_fallback_rate_no_network": float(free_b.fallback[1:].mean()),
         "network_forward_ms": round(fwd_ms, 4),
         "training": {"samples": int(len(samples.frame)), "steps": args.train_steps, "batch": batch,
+                     "lr": lr, "jitter": jitter,
                      "seconds": round(t_train, 2), "ms_per_step": round(t_train / args.train_steps * 1e3, 3),
                      "loss_first": round(float(np.mean(losses[:20])), 4),
                      "loss_last": round(float(np.mean(losses[-100:])), 4)},

@@ -153,15 +153,20 @@ int ih_lp_sgd(float *params, const float *grads, float *mom, int32_t n,
               float lr, float momentum, float weight_decay, void *stream);
 
 /*
- * ih_lp_topk - per sample, the indices of the k largest of n logits (n <= 8192),
- * best first, ties to the lower index.  idx out [B][k] int32.
+ * ih_lp_topk - per sample, the indices of the k largest of n logits
+ * (n <= 8192, k <= min(n, 1024)), best first, ties to the lower index, -0
+ * equal to +0, NaN below every number.  idx out [B][k] int32.
  */
 int ih_lp_topk(const float *logits, int32_t B, int32_t n, int32_t k,
                int32_t *idx, void *stream);
 
 /*
  * Device-resident tracking.  The state of one target lives in device memory,
- * so a sequence of frames is enqueued without host round trips.  Per frame:
+ * so a sequence of frames is enqueued without host round trips, and the
+ * per-frame step can be captured once in a HIP graph and replayed.  Per frame:
+ *   ih_track_fetch                   copy frame st->frame of a resident stack
+ *                                    into the buffer the build reads
+ *   ih_build                         integral histogram of that buffer
  *   ih_track_prepare                 base = previous origin, crop centre
  *   (learned) crop, network, ih_lp_topk, ih_lp_origins, ih_match_candidates
  *   over the k proposals, then ih_track_gate
@@ -176,7 +181,14 @@ typedef struct {
   int32_t origin[2]; /* window origin (row, column) accepted at the previous frame */
   float dist;        /* its distance d*                                           */
   int32_t decision;  /* accepted offset index, or -1 (written by prepare / gate)  */
+  int32_t frame;     /* frame being processed; ih_track_commit advances it        */
 } ih_track_state;
+
+/* dst [frame_bytes] = stack [st->frame * frame_bytes ...]; nothing is copied
+   when st->frame is outside [0, n_frames).  stack, dst and frame_bytes must be
+   multiples of 16 bytes. */
+int ih_track_fetch(const void *stack, int64_t frame_bytes, int32_t n_frames,
+                   const ih_track_state *st, void *dst, void *stream);
 
 /* base [2] = st->origin; center [2] (may be NULL) = origin + (win_h/2, win_w/2);
    st->decision = -1. */
@@ -192,12 +204,13 @@ int ih_track_gate(ih_track_state *st, const int32_t *idx, const float *kdist,
 
 /* New state from the accepted proposal (kdist, kbest) or the exhaustive
    search (exh_dist, exh_best; +inf and the old origin when no candidate was
-   inside); rec [4] receives origin row, origin column, the distance's FP32
-   bits and 1 when the exhaustive result was used. */
+   inside).  Record f = st->frame of rec [n_rec][4] (when f < n_rec) receives
+   origin row, origin column, the distance's FP32 bits and 1 when the
+   exhaustive result was used; then st->frame = f + 1. */
 int ih_track_commit(ih_track_state *st, const float *kdist,
                     const int32_t *kbest, const float *exh_dist,
                     const int32_t *exh_best, int32_t radius, int32_t *rec,
-                    void *stream);
+                    int32_t n_rec, void *stream);
 
 #ifdef __cplusplus
 }

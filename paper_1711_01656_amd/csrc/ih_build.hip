@@ -86,10 +86,13 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
     else { TH = 64; TW = 64; PG = 1; }
     while (PG > 1 && PG > bins) PG >>= 1;
   } else {
+    // defaults from device sweeps of the staged write-out: 16-column tiles
+    // with moments, 32-column tiles without; short tiles for small outputs
     PG = 64;
     const int64_t out_bytes = (int64_t)g->P * H * W * 4 * (g->mom ? 3 : 1);
     if (out_bytes < ((int64_t)128 << 20)) { TH = 8; TW = 16; }
-    else { TH = 64; TW = 32; }
+    else if (g->mom) { TH = 128; TW = 16; }
+    else { TH = 32; TW = 32; }
   }
   g->TH = TH; g->TW = TW; g->PG = PG;
   g->CPL = layout == IH_BHW ? TW / 64 : 1;
@@ -138,6 +141,24 @@ __global__ __launch_bounds__(256) void k_final_hwb(FinalArgs a, Geom g) {
   final_hwb_body<T, TW, MOM>(a, g, (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform(threadIdx.x >> 6));
 }
 
+template <typename T, int TW, bool MOM>
+__global__ __launch_bounds__(512) void k_final_hwb_staged(FinalArgs a, Geom g) {
+  extern __shared__ uint32_t seg[];
+  final_hwb_staged_body<T, TW, MOM>(a, g, blockIdx.x, seg);
+}
+
+// LDS bytes of one staged row segment (all arrays), or 0 when staging does not apply.
+#ifndef IH_HWB_STAGED
+#define IH_HWB_STAGED 1
+#endif
+static size_t staged_lds(const Geom &g) {
+  if (!IH_HWB_STAGED || g.layout != IH_HWB) return 0;
+  const int nchunk = (g.P + 63) / 64;
+  const size_t bytes = (size_t)(g.mom ? 3 : 1) * g.TW * g.P * 4;
+  // with moments a tile wider than 16 columns would spill registers
+  return (nchunk <= 8 && bytes <= 64 * 1024 && !(g.mom && g.TW > 16)) ? bytes : 0;
+}
+
 // ------------------------------------------------------------------ host --
 struct ProfileHook {
   hipEvent_t start = nullptr, stop = nullptr;
@@ -164,7 +185,15 @@ static final_fn pick_final_t(int CPL, int PG) {
 }
 
 template <typename T, bool MOM>
-static final_fn pick_hwb_t(int TW) {
+static final_fn pick_hwb_t(int TW, bool staged) {
+  if (staged) {
+    if (TW == 16) return &k_final_hwb_staged<T, 16, MOM>;
+    if constexpr (!MOM) {
+      if (TW == 32) return &k_final_hwb_staged<T, 32, MOM>;
+      if (TW == 64) return &k_final_hwb_staged<T, 64, MOM>;
+    }
+    return nullptr;
+  }
   if (TW == 16) return &k_final_hwb<T, 16, MOM>;
   if (TW == 32) return &k_final_hwb<T, 32, MOM>;
   if constexpr (!MOM) {
@@ -176,8 +205,9 @@ static final_fn pick_hwb_t(int TW) {
 static final_fn pick_final(int dtype, const Geom &g) {
   const bool u8 = dtype == IH_U8;
   if (g.layout == IH_HWB) {
-    if (u8) return g.mom ? pick_hwb_t<uint8_t, true>(g.TW) : pick_hwb_t<uint8_t, false>(g.TW);
-    return g.mom ? pick_hwb_t<uint16_t, true>(g.TW) : pick_hwb_t<uint16_t, false>(g.TW);
+    const bool st = staged_lds(g) > 0;
+    if (u8) return g.mom ? pick_hwb_t<uint8_t, true>(g.TW, st) : pick_hwb_t<uint8_t, false>(g.TW, st);
+    return g.mom ? pick_hwb_t<uint16_t, true>(g.TW, st) : pick_hwb_t<uint16_t, false>(g.TW, st);
   }
   if (u8) return g.mom ? pick_final_t<uint8_t, true>(g.CPL, g.PG) : pick_final_t<uint8_t, false>(g.CPL, g.PG);
   return g.mom ? pick_final_t<uint16_t, true>(g.CPL, g.PG) : pick_final_t<uint16_t, false>(g.CPL, g.PG);
@@ -252,13 +282,16 @@ extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, in
     const int wpb = groups < 4 ? groups : 4;
     grid = dim3(tiles, (unsigned)((groups + wpb - 1) / wpb));
     block = dim3(64 * wpb);
+  } else if (staged_lds(g)) {
+    grid = dim3((unsigned)((int64_t)g.nTR * g.nTC));
+    block = dim3(64 * ((g.P + 63) / 64));
   } else {
     const int64_t units = (int64_t)g.nTR * g.nTC * ((g.P + 63) / 64);
     grid = dim3((unsigned)((units + 3) / 4));
     block = dim3(256);
   }
   if (g_hook.start && (e = hip_check(hipEventRecord(g_hook.start, s), "profile start"))) return e;
-  hipLaunchKernelGGL(fin, grid, block, 0, s, fa, g);
+  hipLaunchKernelGGL(fin, grid, block, staged_lds(g), s, fa, g);
   if ((e = hip_check(hipGetLastError(), "final launch"))) return e;
   if (g_hook.stop && (e = hip_check(hipEventRecord(g_hook.stop, s), "profile stop"))) return e;
   return IH_OK;

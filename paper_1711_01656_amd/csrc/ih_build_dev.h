@@ -447,4 +447,124 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
 }
 
 
+// --------------------------------------------------------------------------
+// 3c. Planes-innermost write-out staged through LDS.  One block per tile with
+//     one wavefront per chunk of 64 planes (lane = plane, as in 3b).  For each
+//     row the waves put their prefix values for the whole row segment
+//     (cols x P words, contiguous in the output) into LDS, and then the block
+//     stores the segment with consecutive 16-byte (or 4-byte) stores, so every
+//     output line is written whole by one instruction whatever P is.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void copy_out(int32_t *__restrict__ dst, const uint32_t *__restrict__ src, int n,
+                                         bool vec) {
+  if (vec) {
+    const v4i *s4 = reinterpret_cast<const v4i *>(src);
+    v4i *d4 = reinterpret_cast<v4i *>(dst);
+    for (int i = threadIdx.x; i < (n >> 2); i += blockDim.x) __builtin_nontemporal_store(s4[i], d4 + i);
+  } else {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) __builtin_nontemporal_store((int)src[i], dst + i);
+  }
+}
+
+template <typename T, int TW, bool MOM>
+__device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const Geom &g, int64_t tile,
+                                                      uint32_t *lds) {
+  const int lane = threadIdx.x & 63;
+  const int chunk = uniform((int)(threadIdx.x >> 6));
+  const int j = (int)(tile % g.nTC), I = (int)(tile / g.nTC);
+  // lanes past the last plane repeat it (same values, same LDS words)
+  const int p = min(chunk * 64 + lane, g.P - 1);
+  const int ch = p / g.bins;
+  const int k = p - ch * g.bins;
+  const int R0 = I * g.TH, C0 = j * TW;
+  const int cols = min(TW, g.W - C0), rows = min(g.TH, g.H - R0);
+  const uint32_t lo = (uint32_t)((((uint64_t)k << a.bits) + g.bins - 1) / g.bins);
+  const uint32_t width = (uint32_t)((((uint64_t)(k + 1) << a.bits) + g.bins - 1) / g.bins) - lo;
+  const T *img = reinterpret_cast<const T *>(a.img) + (int64_t)ch * g.H * g.W;
+  const int64_t P = g.P;
+
+  uint32_t col[TW];
+  uint32_t colx[MOM ? TW : 1], coly[MOM ? TW : 1];
+  {
+    const int64_t cidx = ((int64_t)p * g.nTR + I) * g.nTC + j;
+    uint32_t run = a.ws[g.off_tt + cidx];
+    uint32_t runx = 0, runy = 0;
+    if constexpr (MOM) {
+      runx = a.ws[g.off_ttx + cidx];
+      runy = a.ws[g.off_tty + cidx];
+    }
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        const int64_t o = ((int64_t)I * g.W + C0 + c) * P + p;
+        const uint32_t v = a.ws[g.off_cc + o];
+        run += v;
+        col[c] = run;
+        if constexpr (MOM) {
+          runx += a.ws[g.off_ccx + o];
+          runy += v * (uint32_t)(C0 + c);
+          colx[c] = runx;
+          coly[c] = runy;
+        }
+      }
+    }
+  }
+  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const bool full = cols == TW;
+  const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
+                     ((int64_t)C0 * sizeof(T)) % 4 == 0;
+  const bool vec = (g.P & 3) == 0 && (((uintptr_t)a.ih | (uintptr_t)a.mx | (uintptr_t)a.my) & 15) == 0;
+  const int nseg = cols * g.P;
+  uint32_t *s0 = lds, *s1 = lds + TW * g.P, *s2 = lds + 2 * TW * g.P;
+  constexpr int PER = 4 / (int)sizeof(T);
+  auto row_step = [&](auto FULL, int rr) {
+    constexpr bool F = decltype(FULL)::value;
+    const int r = R0 + rr;
+    const T *row = img + (int64_t)r * g.W + C0;
+    uint32_t rc = lc[(int64_t)r * g.bins];
+    uint32_t ry = 0;
+    if constexpr (MOM) ry = lcy[(int64_t)r * g.bins];
+    auto pixel = [&](int c, uint32_t val) {
+      const uint32_t hit = (val - lo) < width ? 1u : 0u;
+      rc += hit;
+      col[c] += rc;
+      s0[c * g.P + p] = col[c];
+      if constexpr (MOM) {
+        colx[c] += (uint32_t)r * rc;
+        ry += hit * (uint32_t)(C0 + c);
+        coly[c] += ry;
+        s1[c * g.P + p] = colx[c];
+        s2[c * g.P + p] = coly[c];
+      }
+    };
+    if (F && words) {
+      uint32_t wv[TW / PER];
+      const uint32_t *wp = reinterpret_cast<const uint32_t *>(row);
+#pragma unroll
+      for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
+#pragma unroll
+      for (int c = 0; c < TW; ++c)
+        pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u));
+    } else {
+#pragma unroll
+      for (int c = 0; c < TW; ++c)
+        if (F || c < cols) pixel(c, (uint32_t)row[c]);
+    }
+    __syncthreads();
+    const int64_t rbase = ((int64_t)r * g.W + C0) * P;
+    copy_out(a.ih + rbase, s0, nseg, vec);
+    if constexpr (MOM) {
+      copy_out(reinterpret_cast<int32_t *>(a.mx) + rbase, s1, nseg, vec);
+      copy_out(reinterpret_cast<int32_t *>(a.my) + rbase, s2, nseg, vec);
+    }
+    __syncthreads();
+  };
+  if (full) {
+    for (int rr = 0; rr < rows; ++rr) row_step(std::true_type{}, rr);
+  } else {
+    for (int rr = 0; rr < rows; ++rr) row_step(std::false_type{}, rr);
+  }
+}
+
 }  // namespace ih

@@ -369,37 +369,151 @@ __global__ void k_lp_sgd(float *__restrict__ p, const float *__restrict__ g, flo
   p[i] = p[i] - lr * vi;
 }
 
-// Top-k offsets per sample by a bitonic sort of (logit desc, index asc) pairs
-// in LDS; n <= 8192.
-__global__ __launch_bounds__(1024) void k_lp_topk(const float *__restrict__ logits, int n, int k,
-                                                  int32_t *__restrict__ idx) {
-  __shared__ float sv[8192];
-  __shared__ int32_t si[8192];
-  const int b = blockIdx.x;
-  for (int i = threadIdx.x; i < 8192; i += 1024) {
-    sv[i] = i < n ? logits[(int64_t)b * n + i] : -INFINITY;
-    si[i] = i < n ? i : 0x7fffffff;
+// Exclusive prefix sum over the block in thread order (one value per thread);
+// *total receives the block sum.  sh holds one slot per wave.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+  for (int w2 = 0; w2 < nw; ++w2) {
+    const uint32_t x = sh[w2];
+    before += w2 < wave ? x : 0u;
+    tot += x;
   }
   __syncthreads();
-  for (int size = 2; size <= 8192; size <<= 1) {
+  *total = tot;
+  return before + inc - v;
+}
+
+// Monotone map of a logit to an unsigned key: a larger float gives a larger
+// key, -0 and +0 are equal, NaN is below everything.
+__device__ __forceinline__ uint32_t order_key(float f) {
+  if (f != f) return 0u;
+  uint32_t u = __float_as_uint(f);
+  if (u == 0x80000000u) u = 0u;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+constexpr int TK_THREADS = 1024, TK_PER = 8;  // n <= 8192
+
+// Top-k offsets per sample (best first, ties to the lower index, NaN last).
+// Radix select on the order keys: four 8-bit passes, each a histogram of the
+// next digit among the keys that share the digits chosen so far, find the key
+// T of the k-th best; the keys above T and the first (lowest-index) keys equal
+// to T are compacted in index order, and only those k are sorted.
+__global__ __launch_bounds__(1024) void k_lp_topk(const float *__restrict__ logits, int n, int k,
+                                                  int32_t *__restrict__ idx) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sh[TK_THREADS / 64];
+  __shared__ uint32_t s_prefix, s_need;
+  __shared__ uint32_t skey[TK_THREADS];
+  __shared__ int32_t sidx[TK_THREADS];
+  const int t = threadIdx.x;
+  const float *l = logits + (int64_t)blockIdx.x * n;
+  uint32_t key[TK_PER];
+  const int e0 = t * TK_PER;
+#pragma unroll
+  for (int j = 0; j < TK_PER; ++j) key[j] = e0 + j < n ? order_key(l[e0 + j]) : 0u;
+  const int nv = min(TK_PER, max(0, n - e0));  // valid elements of this thread
+  uint32_t prefix = 0, mask = 0, need = (uint32_t)k;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    if (t < 256) hist[t] = 0;
+    __syncthreads();
+    // one atomic per run of equal digits
+    int run_bin = -1;
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < TK_PER; ++j) {
+      if (j < nv && (key[j] & mask) == prefix) {
+        const int bin = (int)((key[j] >> shift) & 255u);
+        if (bin != run_bin) {
+          if (run) atomicAdd(&hist[run_bin], run);
+          run_bin = bin;
+          run = 0;
+        }
+        ++run;
+      }
+    }
+    if (run) atomicAdd(&hist[run_bin], run);
+    __syncthreads();
+    if (t < 64) {
+      uint32_t c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) c[q] = hist[4 * t + q];
+      const uint32_t lsum = c[0] + c[1] + c[2] + c[3];
+      const uint32_t incl = wave_incl_scan(lsum);
+      const uint32_t total = read_lane(incl, 63);
+      uint32_t above = total - incl;  // keys in bins above this lane's four
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        if (above < need && need <= above + c[q]) {
+          s_prefix = prefix | ((uint32_t)(4 * t + q) << shift);
+          s_need = need - above;
+        }
+        above += c[q];
+      }
+    }
+    __syncthreads();
+    prefix = s_prefix;
+    need = s_need;
+    mask |= 255u << shift;
+  }
+  // keys > prefix: exactly k - need of them; then `need` keys == prefix, lowest indices first
+  uint32_t ngt = 0, neq = 0;
+#pragma unroll
+  for (int j = 0; j < TK_PER; ++j)
+    if (j < nv) {
+      ngt += key[j] > prefix ? 1u : 0u;
+      neq += key[j] == prefix ? 1u : 0u;
+    }
+  uint32_t tot;
+  uint32_t gt_off = block_excl_scan(ngt, sh, &tot);
+  uint32_t eq_off = block_excl_scan(neq, sh, &tot);
+  const uint32_t cgt = (uint32_t)k - need;
+#pragma unroll
+  for (int j = 0; j < TK_PER; ++j) {
+    if (j >= nv) continue;
+    if (key[j] > prefix) {
+      skey[gt_off] = key[j];
+      sidx[gt_off] = e0 + j;
+      ++gt_off;
+    } else if (key[j] == prefix) {
+      if (eq_off < need) {
+        skey[cgt + eq_off] = key[j];
+        sidx[cgt + eq_off] = e0 + j;
+      }
+      ++eq_off;
+    }
+  }
+  int S = 1;
+  while (S < k) S <<= 1;
+  if (t >= k && t < S) {
+    skey[t] = 0u;
+    sidx[t] = 0x7fffffff;
+  }
+  __syncthreads();
+  // bitonic sort of the S <= 1024 selected pairs: larger key first, then lower index
+  for (int size = 2; size <= S; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < 8192; i += 1024) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool up = (i & size) == 0;  // this pair sorts "better first"
-          const float a = sv[i], c = sv[j];
-          const int ia = si[i], ic = si[j];
-          const bool j_better = c > a || (c == a && ic < ia);
-          if (j_better == up) {
-            sv[i] = c; sv[j] = a;
-            si[i] = ic; si[j] = ia;
-          }
+      const int j = t ^ stride;
+      if (t < S && j > t) {
+        const bool up = (t & size) == 0;
+        const uint32_t a = skey[t], c = skey[j];
+        const int32_t ia = sidx[t], ic = sidx[j];
+        const bool j_better = c > a || (c == a && ic < ia);
+        if (j_better == up) {
+          skey[t] = c;
+          skey[j] = a;
+          sidx[t] = ic;
+          sidx[j] = ia;
         }
       }
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < k; i += 1024) idx[(int64_t)b * k + i] = si[i];
+  if (t < k) idx[(int64_t)blockIdx.x * k + t] = sidx[t];
 }
 
 static int conv_shape(int B, int Cin, int Hin, int Win, int stride, int dil, int pad, ConvShape *s) {
@@ -538,8 +652,8 @@ extern "C" int ih_lp_sgd(float *params, const float *grads, float *mom, int32_t 
 }
 
 extern "C" int ih_lp_topk(const float *logits, int32_t B, int32_t n, int32_t k, int32_t *idx, void *stream) {
-  if (B < 1 || n < 1 || n > 8192 || k < 1 || k > n || !logits || !idx)
-    return set_error(IH_ERR_INVALID_ARG, "bad top-k arguments");
+  if (B < 1 || n < 1 || n > TK_THREADS * TK_PER || k < 1 || k > n || k > TK_THREADS || !logits || !idx)
+    return set_error(IH_ERR_INVALID_ARG, "bad top-k arguments (n <= 8192, 1 <= k <= min(n, 1024))");
   hipLaunchKernelGGL(k_lp_topk, dim3(B), dim3(1024), 0, as_stream(stream), logits, n, k, idx);
   return hip_check(hipGetLastError(), "lp top-k launch");
 }

@@ -161,30 +161,39 @@ def track(frames, box0, tracker: PyramidTracker, learned: Optional[LearnedTracke
     return Track(org, dist, fb)
 
 
-def track_device(frames, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker] = None) -> Track:
-    """The free-running track() with the state kept on the device: every
-    frame's work is enqueued without a host round trip (the fallback rule
-    runs in ih_track_gate) and the results are read back once at the end.
-    Returns the same track as track(frames, box0, tracker, learned)."""
+def track_device(frames: torch.Tensor, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker] = None,
+                 graph: bool = False) -> Track:
+    """The free-running track() with the state kept on the device.  frames is
+    a resident T x C x H x W uint8 stack; every frame's step (fetch the frame
+    into a fixed buffer, build, search, fallback rule, commit) is enqueued
+    without a host round trip, and the records are read back once at the end.
+    With `graph`, the step is captured once in a HIP graph and replayed per
+    frame.  Returns the same track as track(frames, box0, tracker, learned)."""
     L = lib()
-    T = len(frames)
+    if frames.dim() != 4 or frames.dtype != torch.uint8 or not frames.is_contiguous():
+        raise IHError("frames must be a contiguous T x C x H x W uint8 tensor")
+    T = frames.shape[0]
     dev = tracker.device
     tracker.set_template(frames[0], box0)
     h, w = tracker.win
-    state = torch.from_numpy(np.array([box0[0], box0[1], 0, -1], np.int32)).to(dev)   # dist 0.0
+    state = torch.from_numpy(np.array([box0[0], box0[1], 0, -1, 1], np.int32)).to(dev)   # dist 0.0, frame 1
     exh = torch.empty((N_OFF, 2), dtype=torch.int32, device=dev)
     rec = torch.zeros((T, 4), dtype=torch.int32, device=dev)
     rec[0, 0], rec[0, 1] = int(box0[0]), int(box0[1])
+    cur = torch.empty(frames.shape[1:], dtype=torch.uint8, device=dev)
+    fbytes = cur.numel()
     use_net = learned is not None and learned.net is not None
     if use_net and not learned.net.packed:
         learned.net.pack()
-    s = _stream(state)
-    for t in range(1, T):
-        tracker.build(frames[t])
+
+    def step():
+        s = _stream(state)
+        _check(L.ih_track_fetch(_p(frames), fbytes, T, _p(state), _p(cur), s), "ih_track_fetch")
+        tracker.build(cur)
         _check(L.ih_track_prepare(_p(state), h, w, _p(tracker.base), _p(learned.center) if use_net else None, s),
                "ih_track_prepare")
         if learned is not None:
-            learned.propose(frames[t])
+            learned.propose(cur)
             lp.lp_origins(tracker.base, RADIUS, idx=learned.idx, out=learned.korig)
             tracker.score(learned.korig, learned.kdist, learned.kbest)
             _check(L.ih_track_gate(_p(state), _p(learned.idx), _p(learned.kdist), _p(learned.kbest), RADIUS,
@@ -194,7 +203,18 @@ def track_device(frames, box0, tracker: PyramidTracker, learned: Optional[Learne
         tracker.score(exh, tracker.dist, tracker.best)
         _check(L.ih_track_commit(_p(state), _p(learned.kdist) if learned is not None else None,
                                  _p(learned.kbest) if learned is not None else None, _p(tracker.dist),
-                                 _p(tracker.best), RADIUS, _p(rec[t]), s), "ih_track_commit")
+                                 _p(tracker.best), RADIUS, _p(rec), T, s), "ih_track_commit")
+
+    if graph and T > 1:
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(1, T):
+            g.replay()
+    else:
+        for _ in range(1, T):
+            step()
     r = rec.cpu().numpy()
     fb = r[:, 3].astype(bool) if learned is not None else np.zeros(T, bool)
     return Track(r[:, :2].astype(np.int64), r[:, 2].copy().view(np.float32).astype(np.float64), fb)

@@ -62,7 +62,7 @@ def candidates(H, W, C, bins, moments, layout) -> List[ih.TileCfg]:
                 continue
             out.append(ih.TileCfg(th, tw, pg))
     else:
-        for th, tw in itertools.product((4, 8, 16, 32, 64), (16, 32, 64)):
+        for th, tw in itertools.product((4, 8, 16, 32, 64, 128), (16, 32, 64)):
             if moments and tw > 32:
                 continue
             if th > 2 * H or tw > 2 * max(W, 16):

@@ -285,14 +285,24 @@ def test_pack_layout(P):
         np.testing.assert_array_equal(got[k], p[k])
 
 
-def test_topk(P):
-    rng = np.random.default_rng(12)
-    L = cnn.to_f32(rng.standard_normal((3, 4225))).astype(np.float64)
-    L[1, 100:300] = 5.0                  # 200-way tie at the top: lower indices first
-    L[2, :] = 0.0                        # everything tied
-    idx = P.lp_topk(torch.tensor(L, dtype=torch.float32, device="cuda"), 64)
+@pytest.mark.parametrize("n,k", [(4225, 64), (4225, 1), (8192, 1024), (37, 37), (1000, 200)])
+def test_topk(P, n, k):
+    rng = np.random.default_rng(12 + n + k)
+    L = cnn.to_f32(rng.standard_normal((5, n))).astype(np.float64)
+    L[1, n // 10: n // 10 + n // 5] = 5.0      # a wide tie at the top: lower indices first
+    L[2, :] = 0.0                              # everything tied
+    L[2, ::3] = -0.0                           # -0 ranks with +0
+    L[3] = np.round(L[3], 1)                   # many small ties across the threshold
+    L[4, :] = 1e-30 * np.arange(n)[::-1]       # tiny distinct values
+    idx = P.lp_topk(torch.tensor(L, dtype=torch.float32, device="cuda"), k)
     torch.cuda.synchronize()
-    np.testing.assert_array_equal(idx.cpu().numpy(), cnn.topk(L, 64))
+    np.testing.assert_array_equal(idx.cpu().numpy(), cnn.topk(L, k))
+
+
+def test_topk_nan_last(P):
+    L = np.array([[1.0, np.nan, 3.0, np.nan, 2.0]])
+    idx = P.lp_topk(torch.tensor(L, dtype=torch.float32, device="cuda"), 5)
+    assert idx.cpu().numpy().tolist() == [[2, 4, 0, 1, 3]]
 
 
 def test_sgd(P):
