@@ -31,6 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the write-out kernel measured with rocprofv3 PMC
+# counters (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy)
+# for this workload and tile; see profiles/k_final_hwb_staged_1920x1080x112_moments.md.
+# Reported only when the benchmark runs the same kernel and tile.
+PROFILED_TRAFFIC = {("hwb", "TileCfg(128, 16, 64)"): 3048972697}
 METRIC = "integral-hist Gpx·bins/s (% HBM peak); queries/s; tracker fps learned vs exhaustive"
 
 
@@ -46,6 +51,8 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run one device fill and one copy of this many MiB (counter calibration)")
     ap.add_argument("--no-tracker", action="store_true", help="skip the tracker workload")
+    ap.add_argument("--tracker-only", action="store_true",
+                    help="run only the tracker workload and print its JSON object (for profiling)")
     ap.add_argument("--train-videos", type=int, default=800)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--tile", type=str, default="",
@@ -254,6 +261,10 @@ def main():
     import synth
     import paper_1711_01656_amd as ih
 
+    if args.tracker_only:
+        print(json.dumps(tracker_leg(torch, args)), flush=True)
+        return
+
     dev = torch.device("cuda:0")
     w = synth.config2()
     rng_win = np.random.default_rng(205)
@@ -361,7 +372,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": PROFILED_TRAFFIC.get((args.layout, repr(cfg))),
             "alg_bytes_per_launch": alg_bytes,
         },
     }
