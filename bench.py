@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--tracker-only", action="store_true",
                     help="run only the tracker workload and print its JSON object (for profiling)")
     ap.add_argument("--train-videos", type=int, default=800)
-    ap.add_argument("--train-steps", type=int, default=4000)
+    ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--tile", type=str, default="",
                     help="tile_h,tile_w,planes_per_wave (default: autotuned at start-up)")
     return ap.parse_args()
@@ -153,6 +153,47 @@ def time_calls(torch, fn, n):
     return a.elapsed_time(b) / n
 
 
+def search_cost_vs_targets(torch, trk, lp, tr, net, frame, box0, counts=(1, 4, 16, 64, 256)):
+    """Device time of one frame's search step for N targets at once (the
+    integral histogram already built): exhaustive = the pyramid distance of
+    N x 4,225 candidate windows; learned = network on N crops, top 64 per
+    target, pyramid distance of N x 64 candidates.  Targets sit on a grid
+    around the benchmark target so every window lies inside the frame."""
+    dev = frame.device
+    tr.set_template(frame, box0)
+    h, w = tr.win
+    out = {}
+    big = lp.ProposalNet(net.get_params(), max_batch=max(counts))
+    big.pack()
+    for n in counts:
+        g = int(np.ceil(np.sqrt(n)))
+        ys = np.linspace(40, frame.shape[1] - h - 40, g).astype(int)
+        xs = np.linspace(40, frame.shape[2] - w - 40, g).astype(int)
+        base = np.array([(y, x) for y in ys for x in xs][:n], np.int32)
+        base_d = torch.from_numpy(base).to(dev)
+        centers = torch.from_numpy(base + np.array([h // 2, w // 2], np.int32)).to(dev)
+        ex_orig = lp.lp_origins(base_d, lp.RADIUS)
+        ex_dist = torch.empty(n * lp.N_OFFSETS, dtype=torch.float32, device=dev)
+        best = torch.empty(1, dtype=torch.int32, device=dev)
+        idx = torch.empty((n, 64), dtype=torch.int32, device=dev)
+        k_orig = torch.empty((n * 64, 2), dtype=torch.int32, device=dev)
+        k_dist = torch.empty(n * 64, dtype=torch.float32, device=dev)
+
+        def exhaustive():
+            tr.score(ex_orig, ex_dist, best)
+
+        def learned():
+            x = big.crop(frame, centers)
+            logits = big.forward(x)
+            lp.lp_topk(logits.view(n, -1), 64, idx)
+            lp.lp_origins(base_d, lp.RADIUS, idx=idx, out=k_orig)
+            tr.score(k_orig, k_dist, best)
+
+        out[str(n)] = {"exhaustive": round(time_calls(torch, exhaustive, 20), 4),
+                       "learned": round(time_calls(torch, learned, 20), 4)}
+    return out
+
+
 def tracker_leg(torch, args):
     """Learned vs exhaustive tracking on the 1280x720, 300-frame video."""
     from paper_1711_01656_amd import proposal as lp
@@ -174,7 +215,8 @@ def tracker_leg(torch, args):
     stack = torch.cat(stack)
     samples = trk.concat(parts)
     t_data = time.perf_counter() - t0
-    batch, lr, jitter = 128, 0.02, 20
+    # chosen on validation sequences (seeds 600-607) disjoint from this video
+    batch, lr, jitter = 64, 0.01, 20
     net = lp.ProposalNet(lp.init_params(1), max_batch=batch)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -222,6 +264,7 @@ def tracker_leg(torch, args):
     x = net.crop(frames[1], torch.tensor([[box0[0] + box0[2] // 2, box0[1] + box0[3] // 2]], dtype=torch.int32,
                                          device=dev))
     fwd_ms = time_calls(torch, lambda: net.forward(x), 50)
+    scaling = search_cost_vs_targets(torch, trk, lp, tr, net, frames[1], box0)
     return {
         "workload": "1280x720 synthetic video, 300 frames, 7 channels x 16 bins; 65x65 offsets; top-64 learned",
         "fps_exhaustive": round(fps_ex, 1),
@@ -241,6 +284,7 @@ def tracker_leg(torch, args):
         "free_running_fallback_rate": float(free.fallback[1:].mean()),
         "free_running_fallback_rate_no_network": float(free_b.fallback[1:].mean()),
         "network_forward_ms": round(fwd_ms, 4),
+        "search_ms_vs_targets": scaling,
         "training": {"samples": int(len(samples.frame)), "steps": args.train_steps, "batch": batch,
                      "lr": lr, "jitter": jitter,
                      "seconds": round(t_train, 2), "ms_per_step": round(t_train / args.train_steps * 1e3, 3),

@@ -63,8 +63,8 @@ int ih_lp_conv(const uint16_t *in, int32_t B, int32_t Cin, int32_t Hin,
                uint16_t *out, void *stream);
 
 /*
- * Bytes of FP32 workspace ih_lp_wgrad needs: one 32 x Cin*9 partial sum per
- * chunk of `chunk` output pixels (0 for invalid shapes).
+ * Bytes of FP32 workspace ih_lp_wgrad needs: one 32 x (Cin*9 + 1) partial sum
+ * per chunk of `chunk` output pixels (0 for invalid shapes).
  */
 size_t ih_lp_wgrad_workspace(int32_t B, int32_t Cin, int32_t Hin, int32_t Win,
                              int32_t stride, int32_t dil, int32_t pad,
@@ -75,9 +75,11 @@ size_t ih_lp_wgrad_workspace(int32_t B, int32_t Cin, int32_t Hin, int32_t Win,
  *   in  [B][Cin][Hin][Win] bf16 (the layer input), dz [B][32][Hout][Wout] bf16
  *   (gradient of the pre-activation).
  *   dw  out: [32][Cin][3][3] FP32 = sum over batch and pixels of dz * im2col(in)
- *   db  out: [32] FP32 = sum of dz per channel.
- *   chunk  output pixels per partial sum (positive multiple of 8); partials
- *          are added in chunk order.
+ *   db  out: [32] FP32 = sum of dz per channel (the product of dz with an
+ *       extra column of ones, computed with the weights).
+ *   chunk  output pixels per partial sum (positive multiple of 8, at most
+ *          65,535 chunks); partials are added in chunk order, so results are
+ *          bit-reproducible for a given chunk.
  */
 int ih_lp_wgrad(const uint16_t *in, const uint16_t *dz, int32_t B, int32_t Cin,
                 int32_t Hin, int32_t Win, int32_t stride, int32_t dil,
@@ -106,10 +108,12 @@ int ih_lp_softmax_ce(const float *logits, const int32_t *labels, int32_t B,
  *   ds  out [B][64][64] FP32 gradient of the score map.
  *   dz3 out [B][32][64][64] bf16 = bf16(ds * wh[c] * (a3 > 0)).
  *   dwh out [32], dbh out [1] FP32.
+ *   ws  FP32 workspace of B * 33 floats (per-sample partial sums, added in
+ *       sample order).
  */
 int ih_lp_head_bwd(const float *dlogits, const uint16_t *a3, const float *wh,
                    int32_t B, float *ds, uint16_t *dz3, float *dwh, float *dbh,
-                   void *stream);
+                   float *ws, void *stream);
 
 /*
  * ih_lp_crop - network inputs from a stack of planar u8 feature frames.

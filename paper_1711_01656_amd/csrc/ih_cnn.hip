@@ -37,10 +37,11 @@ struct ConvShape {
   int Cpad, Kt;  // convolutions: channels padded to 8, Kt = 9*Cpad (tap-major)
 };
 
-// Value of the im2col matrix X[k][pixel] for the pixel (b, y, x).
+// Value of the im2col matrix X[k][pixel] for the pixel (b, y, x), extended by
+// a column of ones at k = K (its product with dZ is the bias gradient).
 __device__ __forceinline__ short im2col(const uint16_t *__restrict__ in, const ConvShape &s, int k, int b, int y,
                                         int x) {
-  if (k >= s.K) return 0;
+  if (k >= s.K) return k == s.K ? (short)0x3f80 : (short)0;  // bf16 1.0
   const int ci = k / 9, t = k - ci * 9, kh = t / 3, kw = t - kh * 3;
   const int r = y * s.stride + kh * s.dil - s.pad, c = x * s.stride + kw * s.dil - s.pad;
   if (r < 0 || c < 0 || r >= s.Hin || c >= s.Win) return 0;
@@ -108,7 +109,8 @@ __global__ __launch_bounds__(256) void k_lp_conv(const uint16_t *__restrict__ in
 
 // Weight-gradient partial sums.  Block (kt, chunk): 4 waves, each summing a
 // quarter of the chunk's output pixels for a 32 (co) x 32 (k) tile; the waves'
-// tiles are added in a fixed order and written to part[chunk][co][k].
+// tiles are added in a fixed order and written to part[chunk][co][k],
+// k = 0..K (k = K: the bias gradient).
 __global__ __launch_bounds__(256) void k_lp_wgrad(const uint16_t *__restrict__ in, const uint16_t *__restrict__ dz,
                                                   float *__restrict__ part, ConvShape s, int64_t chunk) {
   __shared__ float red[4][LP_CO * 32];
@@ -145,20 +147,24 @@ __global__ __launch_bounds__(256) void k_lp_wgrad(const uint16_t *__restrict__ i
   __syncthreads();
   for (int i = threadIdx.x; i < LP_CO * 32; i += blockDim.x) {
     const int co = i / 32, kk = i - co * 32;
-    if (kt + kk < s.K) {
+    if (kt + kk <= s.K) {
       const float v = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
-      part[((int64_t)blockIdx.y * LP_CO + co) * s.K + kt + kk] = v;
+      part[((int64_t)blockIdx.y * LP_CO + co) * (s.K + 1) + kt + kk] = v;
     }
   }
 }
 
-// out[j] = sum over rows r of part[r][j], in row order.
-__global__ void k_lp_sum_rows(const float *__restrict__ part, int64_t rows, int64_t cols, float *__restrict__ out) {
+// Sum of the partial rows in row order: dw[co][k] (k < K) and db[co] (k = K).
+__global__ void k_lp_sum_rows(const float *__restrict__ part, int64_t rows, int K, float *__restrict__ dw,
+                              float *__restrict__ db) {
+  const int64_t cols = (int64_t)LP_CO * (K + 1);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cols) return;
   float s = 0.0f;
   for (int64_t r = 0; r < rows; ++r) s += part[r * cols + j];
-  out[j] = s;
+  const int co = (int)(j / (K + 1)), k = (int)(j - (int64_t)co * (K + 1));
+  if (k < K) dw[co * K + k] = s;
+  else db[co] = s;
 }
 
 // Block reduction in a fixed tree order; returns the sum in thread 0.
@@ -172,18 +178,6 @@ __device__ __forceinline__ float block_sum(float v, float *sh) {
   const float r = sh[0];
   __syncthreads();
   return r;
-}
-
-// Per output channel, the sum of dZ over batch and pixels (bias gradient).
-__global__ __launch_bounds__(256) void k_lp_bias_grad(const uint16_t *__restrict__ dz, int B, int HW,
-                                                      float *__restrict__ db) {
-  __shared__ float sh[256];
-  const int co = blockIdx.x;
-  float v = 0.0f;
-  for (int b = 0; b < B; ++b)
-    for (int i = threadIdx.x; i < HW; i += 256) v += bf2f(dz[((int64_t)b * LP_CO + co) * HW + i]);
-  const float t = block_sum(v, sh);
-  if (threadIdx.x == 0) db[co] = t;
 }
 
 // Score-map value s(u, v) = wh . a3[:, u, v] + bh.
@@ -277,23 +271,42 @@ __global__ __launch_bounds__(256) void k_lp_head_bwd(const float *__restrict__ d
   }
 }
 
-// Head parameter gradients: block c < 32 sums dS * a3[c]; block 32 sums dS.
+// Head parameter gradients, stage 1: block b sums dS * a3[c] (c < 32) and dS
+// (c = 32) over the pixels of sample b; each thread keeps 33 running sums over
+// its pixels, and the 256 threads' sums are added in thread order.
 __global__ __launch_bounds__(256) void k_lp_head_wgrad(const float *__restrict__ ds, const uint16_t *__restrict__ a3,
-                                                       int B, float *__restrict__ dwh, float *__restrict__ dbh) {
-  __shared__ float sh[256];
-  const int c = blockIdx.x;
+                                                       float *__restrict__ part) {
+  __shared__ float red[LP_CO + 1][256];
+  const int b = blockIdx.x;
   const int HW = LP_SMAP * LP_SMAP;
-  float v = 0.0f;
-  for (int b = 0; b < B; ++b)
-    for (int i = threadIdx.x; i < HW; i += 256) {
-      const float d = ds[(int64_t)b * HW + i];
-      v += c < LP_CO ? d * bf2f(a3[((int64_t)b * LP_CO + c) * HW + i]) : d;
-    }
-  const float t = block_sum(v, sh);
-  if (threadIdx.x == 0) {
-    if (c < LP_CO) dwh[c] = t;
-    else dbh[0] = t;
+  float acc[LP_CO + 1];
+#pragma unroll
+  for (int c = 0; c <= LP_CO; ++c) acc[c] = 0.0f;
+  for (int i = threadIdx.x; i < HW; i += 256) {
+    const float d = ds[(int64_t)b * HW + i];
+#pragma unroll
+    for (int c = 0; c < LP_CO; ++c) acc[c] += d * bf2f(a3[((int64_t)b * LP_CO + c) * HW + i]);
+    acc[LP_CO] += d;
   }
+#pragma unroll
+  for (int c = 0; c <= LP_CO; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  if (threadIdx.x <= LP_CO) {
+    float v = 0.0f;
+    for (int t = 0; t < 256; ++t) v += red[threadIdx.x][t];
+    part[(int64_t)b * (LP_CO + 1) + threadIdx.x] = v;
+  }
+}
+
+// Stage 2: sum over the samples in order.
+__global__ void k_lp_head_wgrad_sum(const float *__restrict__ part, int B, float *__restrict__ dwh,
+                                    float *__restrict__ dbh) {
+  const int c = threadIdx.x;
+  if (c > LP_CO) return;
+  float v = 0.0f;
+  for (int b = 0; b < B; ++b) v += part[(int64_t)b * (LP_CO + 1) + c];
+  if (c < LP_CO) dwh[c] = v;
+  else dbh[0] = v;
 }
 
 // Crops: x[b][c][i][j] = bf16(feat[f_b][c][cy - side/2 + i][cx - side/2 + j] / 255),
@@ -557,7 +570,7 @@ extern "C" size_t ih_lp_wgrad_workspace(int32_t B, int32_t Cin, int32_t Hin, int
   if (conv_shape(B, Cin, Hin, Win, stride, dil, pad, &s) || chunk < 8) return 0;
   const int64_t npix = (int64_t)B * s.Hout * s.Wout;
   const int64_t nchunk = (npix + chunk - 1) / chunk;
-  return (size_t)nchunk * LP_CO * s.K * 4;
+  return (size_t)nchunk * LP_CO * (s.K + 1) * 4;
 }
 
 extern "C" int ih_lp_wgrad(const uint16_t *in, const uint16_t *dz, int32_t B, int32_t Cin, int32_t Hin, int32_t Win,
@@ -573,14 +586,13 @@ extern "C" int ih_lp_wgrad(const uint16_t *in, const uint16_t *dz, int32_t B, in
   const int64_t npix = (int64_t)B * s.Hout * s.Wout;
   const int64_t nchunk = (npix + chunk - 1) / chunk;
   hipStream_t st = as_stream(stream);
-  hipLaunchKernelGGL(k_lp_wgrad, dim3((unsigned)((s.K + 31) / 32), (unsigned)nchunk), dim3(256), 0, st, in, dz, ws,
-                     s, chunk);
+  if (nchunk >= 65536) return set_error(IH_ERR_RANGE, "too many pixel chunks; use a larger chunk");
+  hipLaunchKernelGGL(k_lp_wgrad, dim3((unsigned)((s.K + 1 + 31) / 32), (unsigned)nchunk), dim3(256), 0, st, in, dz,
+                     ws, s, chunk);
   if ((e = hip_check(hipGetLastError(), "lp wgrad launch"))) return e;
-  const int64_t cols = (int64_t)LP_CO * s.K;
-  hipLaunchKernelGGL(k_lp_sum_rows, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st, ws, nchunk, cols, dw);
-  if ((e = hip_check(hipGetLastError(), "lp row-sum launch"))) return e;
-  hipLaunchKernelGGL(k_lp_bias_grad, dim3(LP_CO), dim3(256), 0, st, dz, B, s.Hout * s.Wout, db);
-  return hip_check(hipGetLastError(), "lp bias-grad launch");
+  const int64_t cols = (int64_t)LP_CO * (s.K + 1);
+  hipLaunchKernelGGL(k_lp_sum_rows, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st, ws, nchunk, s.K, dw, db);
+  return hip_check(hipGetLastError(), "lp row-sum launch");
 }
 
 extern "C" int ih_lp_head(const uint16_t *a3, const float *wh, const float *bh, int32_t B, float *logits,
@@ -600,16 +612,18 @@ extern "C" int ih_lp_softmax_ce(const float *logits, const int32_t *labels, int3
 }
 
 extern "C" int ih_lp_head_bwd(const float *dlogits, const uint16_t *a3, const float *wh, int32_t B, float *ds,
-                              uint16_t *dz3, float *dwh, float *dbh, void *stream) {
-  if (B < 1 || !dlogits || !a3 || !wh || !ds || !dz3 || !dwh || !dbh)
+                              uint16_t *dz3, float *dwh, float *dbh, float *ws, void *stream) {
+  if (B < 1 || !dlogits || !a3 || !wh || !ds || !dz3 || !dwh || !dbh || !ws)
     return set_error(IH_ERR_INVALID_ARG, "bad head-backward arguments");
   hipStream_t st = as_stream(stream);
   const int64_t n = (int64_t)B * LP_SMAP * LP_SMAP;
   hipLaunchKernelGGL(k_lp_head_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dlogits, a3, wh, B, ds, dz3);
   int e = hip_check(hipGetLastError(), "lp head-backward launch");
   if (e) return e;
-  hipLaunchKernelGGL(k_lp_head_wgrad, dim3(LP_CO + 1), dim3(256), 0, st, ds, a3, B, dwh, dbh);
-  return hip_check(hipGetLastError(), "lp head-wgrad launch");
+  hipLaunchKernelGGL(k_lp_head_wgrad, dim3(B), dim3(256), 0, st, ds, a3, ws);
+  if ((e = hip_check(hipGetLastError(), "lp head-wgrad launch"))) return e;
+  hipLaunchKernelGGL(k_lp_head_wgrad_sum, dim3(1), dim3(64), 0, st, ws, B, dwh, dbh);
+  return hip_check(hipGetLastError(), "lp head-wgrad sum launch");
 }
 
 extern "C" int ih_lp_crop(const uint8_t *feat, int32_t F, int32_t C, int32_t H, int32_t W,

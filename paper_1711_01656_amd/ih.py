@@ -53,7 +53,7 @@ SIGNATURES = {
     "ih_lp_wgrad": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I64, _P, _SZ, _P, _P, _P]),
     "ih_lp_head": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P]),
     "ih_lp_softmax_ce": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P]),
-    "ih_lp_head_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _P, _P, _P]),
+    "ih_lp_head_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
     "ih_lp_crop": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P, _I32, _I32, _P, _P]),
     "ih_lp_origins": (ctypes.c_int, [_P, _I32, _I32, _P, _I32, _P, _P]),
     "ih_lp_pack": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),

@@ -28,7 +28,11 @@ PARAM_LAYOUT = (("W1", (C_MID, C_IN, 3, 3)), ("b1", (C_MID,)),
 # 3 + 2*3*2 + 2*9*2 = 51 input pixels, wide enough to see the outline of
 # targets up to about 50 px from their centre
 LAYERS = ((C_IN, 2, 1, 1), (C_MID, 1, 3, 3), (C_MID, 1, 9, 9))
-WGRAD_CHUNK = 1024
+def wgrad_chunk(npix: int) -> int:
+    """Pixels per weight-gradient partial sum: at least 1024, and at most
+    about 64 partial rows to add (the summation order depends only on npix)."""
+    per = -(-npix // 64)
+    return max(1024, (per + 7) // 8 * 8)
 
 
 def _offsets():
@@ -122,12 +126,14 @@ def lp_conv(inp: torch.Tensor, w: torch.Tensor, bias: Optional[torch.Tensor], st
 
 
 def lp_wgrad(inp: torch.Tensor, dz: torch.Tensor, stride: int, dil: int, pad: int, dw: torch.Tensor,
-             db: torch.Tensor, ws: Optional[torch.Tensor] = None, chunk: int = WGRAD_CHUNK):
+             db: torch.Tensor, ws: Optional[torch.Tensor] = None, chunk: Optional[int] = None):
     _dev(inp, "in", torch.bfloat16)
     _dev(dz, "dz", torch.bfloat16)
     _dev(dw, "dw", torch.float32)
     _dev(db, "db", torch.float32)
     B, Cin, Hin, Win = inp.shape
+    if chunk is None:
+        chunk = wgrad_chunk(dz.numel() // C_MID)
     need = lib().ih_lp_wgrad_workspace(B, Cin, Hin, Win, stride, dil, pad, chunk)
     if need == 0:
         raise IHError("lp_wgrad: invalid shape")
@@ -162,7 +168,7 @@ def lp_softmax_ce(logits: torch.Tensor, labels: torch.Tensor, loss: torch.Tensor
     _check(lib().ih_lp_softmax_ce(_p(logits), _p(labels), B, _p(loss), _p(dlogits), _s(loss)), "ih_lp_softmax_ce")
 
 
-def lp_head_bwd(dlogits, a3, wh, ds, dz3, dwh, dbh):
+def lp_head_bwd(dlogits, a3, wh, ds, dz3, dwh, dbh, ws: Optional[torch.Tensor] = None):
     B = a3.shape[0]
     for t, n in ((dlogits, "dlogits"), (wh, "wh"), (ds, "ds"), (dwh, "dwh"), (dbh, "dbh")):
         _dev(t, n, torch.float32)
@@ -172,7 +178,10 @@ def lp_head_bwd(dlogits, a3, wh, ds, dz3, dwh, dbh):
     if ds.numel() != B * SMAP * SMAP or dz3.shape != a3.shape or dwh.numel() != C_MID or dbh.numel() != 1:
         raise IHError("lp_head_bwd: shape mismatch")
     _dev(dz3, "dz3", torch.bfloat16)
-    _check(lib().ih_lp_head_bwd(_p(dlogits), _p(a3), _p(wh), B, _p(ds), _p(dz3), _p(dwh), _p(dbh), _s(ds)),
+    if ws is None or ws.numel() < B * (C_MID + 1):
+        ws = torch.empty(B * (C_MID + 1), dtype=torch.float32, device=a3.device)
+    _dev(ws, "ws", torch.float32)
+    _check(lib().ih_lp_head_bwd(_p(dlogits), _p(a3), _p(wh), B, _p(ds), _p(dz3), _p(dwh), _p(dbh), _p(ws), _s(ds)),
            "ih_lp_head_bwd")
 
 
@@ -248,9 +257,10 @@ class ProposalNet:
         self.loss = torch.empty(B, **f32)
         self.ds = torch.empty((B, SMAP, SMAP), **f32)
         self.labels = torch.empty(B, dtype=torch.int32, device=self.device)
-        ws = max(lib().ih_lp_wgrad_workspace(B, cin, SMAP * st, SMAP * st, st, d, pd, WGRAD_CHUNK)
-                 for cin, st, d, pd in LAYERS)
+        ws = max(lib().ih_lp_wgrad_workspace(b, cin, SMAP * st, SMAP * st, st, d, pd, wgrad_chunk(b * SMAP * SMAP))
+                 for cin, st, d, pd in LAYERS for b in range(1, B + 1))
         self.ws = torch.empty(ws // 4, **f32)
+        self.ws_head = torch.empty(B * (C_MID + 1), **f32)
         self.packed = False
 
     # parameters ------------------------------------------------------------
@@ -316,7 +326,7 @@ class ProposalNet:
         lp_softmax_ce(self.logits[:B], labels, self.loss[:B], self.dlogits[:B])
         g = self.grads
         lp_head_bwd(self.dlogits[:B], self.a[3][:B], self.view("wh"), self.ds[:B], self.dz[3][:B],
-                    self.view("wh", g), self.view("bh", g))
+                    self.view("wh", g), self.view("bh", g), self.ws_head)
         wt = {2: self.w2t, 3: self.w3t}
         for i in (3, 2, 1):
             cin, st, d, pd = LAYERS[i - 1]
