@@ -42,8 +42,9 @@ METRIC = "integral-hist Gpx·bins/s (% HBM peak); queries/s; tracker fps learned
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--trials", type=int, default=5, help="graph-replay trials of --steps steps; median reported")
     ap.add_argument("--layout", choices=["hwb", "bhw"], default="hwb",
                     help="memory layout of the integral histograms for the headline step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
@@ -60,9 +61,11 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, origins, tmpl_win, min_seconds=10.0):
-    """The oracle, as it stands, on the same workload, repeated for >= min_seconds."""
+def cpu_baseline(w, origins, tmpl_win, min_seconds=10.0, threads=0):
+    """The oracle, as it stands, on the same workload, repeated for >= min_seconds
+    (threads: OpenMP threads, 0 = all host cores)."""
     import oracle
+    oracle.set_threads(threads)
     reps, t_build, t_wq, t_rq, t_m = 0, 0.0, 0.0, 0.0, 0.0
     t_start = time.perf_counter()
     while reps == 0 or time.perf_counter() - t_start < min_seconds:
@@ -84,10 +87,12 @@ def cpu_baseline(w, origins, tmpl_win, min_seconds=10.0):
         t_rq += t3 - t2
         t_m += t4 - t3
     t_step = (t_build + t_wq + t_rq + t_m) / reps
+    cores = oracle.num_threads()
+    oracle.set_threads(0)
     return {
         "value": round(w.H * w.W * w.P / t_step / 1e9, 4),
         "unit": "Gpx·bins/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": ("the full step (count + moment IHs by the Alg. 5 recurrence, 100k SWIH queries, 100k "
                    "rect queries, 129x129 pyramid chi2 search) repeated %d times in %.1f s; per step: "
@@ -353,9 +358,45 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ih.ih_profile_events(None, None)
-    ms = t0.elapsed_time(t1) / args.steps
+    eager_ms = t0.elapsed_time(t1) / args.steps
     k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_k]))
-    print("timed %d steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
+    print("eager: %d steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
+
+    # the same step captured once as a HIP graph and replayed: each trial times
+    # exactly --steps replays between synchronisations; the median trial is
+    # reported, and every replayed result is checked against the eager one
+    ref = [t.clone() for t in (step.out, step.mx, step.my, step.wq, step.rq, step.dist, step.best)]
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        step()
+    for _ in range(args.warmup):
+        graph.replay()
+    trials = []
+    for _ in range(max(1, args.trials)):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(args.steps):
+            graph.replay()
+        b.record()
+        torch.cuda.synchronize()
+        trials.append(a.elapsed_time(b) / args.steps)
+    same = all(torch.equal(x, y) for x, y in zip(ref, (step.out, step.mx, step.my, step.wq, step.rq, step.dist,
+                                                       step.best)))
+    if not same:
+        raise SystemExit("graph replay results differ from the eager step")
+    del ref
+    ms = float(np.median(trials))
+    print("graph: %d trials of %d replays, median %.4f ms/step" % (len(trials), args.steps, ms), file=sys.stderr,
+          flush=True)
+
+    # measured stream-write ceiling: a 2 GiB device fill, best of 5
+    fill = torch.empty(1 << 29, dtype=torch.int32, device=dev)
+    fill_ms = min(time_calls(torch, lambda: fill.fill_(1), 3) for _ in range(5))
+    write_peak = fill.numel() * 4 / (fill_ms * 1e-3) / 1e9
+    del fill
 
     stages = {s: round(time_calls(torch, getattr(step, s), 5), 4) for s in ("build", "weighted", "rect", "match")}
     stages["final_kernel"] = round(k_ms, 4)
@@ -392,6 +433,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "timing": {"graph_trials_ms": [round(t, 4) for t in trials], "eager_ms_per_step": round(eager_ms, 4),
+                   "graph_replays_match_eager": same},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -416,6 +459,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "measured_write_peak": round(write_peak, 1),
+            "frac_of_measured_write_peak": round(achieved / write_peak, 4),
             "traffic": PROFILED_TRAFFIC.get((args.layout, repr(cfg))),
             "alg_bytes_per_launch": alg_bytes,
         },
@@ -426,6 +471,7 @@ def main():
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, origins_np, (tr, tc, 32, 32))
+        res["cpu_baseline_1thread"] = cpu_baseline(w, origins_np, (tr, tc, 32, 32), min_seconds=1.0, threads=1)
     print(json.dumps(res), flush=True)
 
 

@@ -67,6 +67,7 @@ def _load():
                 "or_match_direct": [P, I, I, I, I, I, I, P, I, I, I, P, I64, I, P, P],
                 "or_level_weight": [I, I],
                 "or_num_threads": [],
+                "or_set_threads": [I],
             }
             for name, args in sig.items():
                 f = getattr(lib, name)
@@ -104,6 +105,11 @@ def _img(img: np.ndarray):
 
 def num_threads() -> int:
     return _load().or_num_threads()
+
+
+def set_threads(n: int) -> int:
+    """Threads for later oracle calls (n < 1 restores the default); returns the count."""
+    return _load().or_set_threads(int(n))
 
 
 def cells(levels: int) -> int:

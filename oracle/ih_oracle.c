@@ -561,3 +561,15 @@ int or_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads for later parallel regions (n < 1: the runtime's default). */
+int or_set_threads(int n) {
+#ifdef _OPENMP
+  static int dflt = 0;
+  if (!dflt) dflt = omp_get_max_threads();
+  omp_set_num_threads(n >= 1 ? n : dflt);
+#else
+  (void)n;
+#endif
+  return or_num_threads();
+}
