@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run one device fill and one copy of this many MiB (counter calibration)")
     ap.add_argument("--no-tracker", action="store_true", help="skip the tracker workload")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (640x480, 8192^2 u16, 64-frame batch)")
     ap.add_argument("--tracker-only", action="store_true",
                     help="run only the tracker workload and print its JSON object (for profiling)")
     ap.add_argument("--train-videos", type=int, default=800)
@@ -156,6 +158,126 @@ def time_calls(torch, fn, n):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / n
+
+
+def config_legs(torch, ih, synth):
+    """The other benchmark workloads, each timed on the device (median of
+    repeated calls): 640x480 u8 with 32 bins and 10,000 rectangles; the
+    8192x8192 u16 frame with 64 bins (17 GB integral histogram), 1M rectangles
+    and a 129x129 pyramid search; 64 uneven frames built and searched as one
+    batch (phased launches replayed from a HIP graph, and one cooperative
+    launch; the batch's tile shape chosen by timing the whole batch) against
+    the same frames built and searched one call at a time (each frame with
+    its own autotuned tile)."""
+    from paper_1711_01656_amd import tune
+    dev = torch.device("cuda:0")
+    res = {}
+
+    def med(fn, n=10, trials=3):
+        return float(np.median([time_calls(torch, fn, n) for _ in range(trials)]))
+
+    # 640x480, 32 bins, 10k rectangles
+    w = synth.config1()
+    img = torch.from_numpy(w.img).to(dev)
+    cfg, _ = tune.tune(img, w.bins, w.bits, layout="hwb", reps=3)
+    out = torch.empty(ih.shape_of(w.P, w.H, w.W, "hwb"), dtype=torch.int32, device=dev)
+    ws = torch.empty(ih.workspace_size(w.H, w.W, w.C, w.bins, False, cfg, "hwb"), dtype=torch.uint8, device=dev)
+    rects = torch.from_numpy(w.rects).to(dev)
+    q = torch.empty((rects.shape[0], w.P), dtype=torch.int32, device=dev)
+    tb = med(lambda: ih.ih_build(img, w.bins, w.bits, cfg=cfg, out=out, ws=ws, layout="hwb"), 50)
+    tq = med(lambda: ih.ih_query_rect(out, rects, out=q, layout="hwb"), 50)
+    alg = w.P * w.H * w.W * 4 + w.H * w.W
+    res["640x480_u8_32bins"] = {"build_ms": round(tb, 4), "gpxbins_per_s": round(w.H * w.W * w.P / tb / 1e6, 2),
+                                "build_hbm_gbs": round(alg / tb / 1e6, 1), "rect_queries": int(rects.shape[0]),
+                                "rect_ms": round(tq, 4), "rect_queries_per_s": round(rects.shape[0] / tq * 1e3, 1),
+                                "tile": repr(cfg)}
+    del out, ws, q
+
+    # 8192x8192 u16, 64 bins, 1M rectangles, 129x129 search
+    w = synth.config3()
+    img = torch.from_numpy(w.img).to(dev)
+    cfg, _ = tune.tune(img, w.bins, w.bits, layout="hwb", reps=1)
+    out = torch.empty(ih.shape_of(w.P, w.H, w.W, "hwb"), dtype=torch.int32, device=dev)
+    ws = torch.empty(ih.workspace_size(w.H, w.W, w.C, w.bins, False, cfg, "hwb"), dtype=torch.uint8, device=dev)
+    rects = torch.from_numpy(w.rects).to(dev)
+    q = torch.empty((rects.shape[0], w.P), dtype=torch.int32, device=dev)
+    origins = torch.from_numpy(w.origins).to(dev)
+    tw = torch.tensor([list(w.tmpl_win)], dtype=torch.int32, device=dev)
+    desc = torch.empty((1, 21, w.P), dtype=torch.int32, device=dev)
+    dist = torch.empty(origins.shape[0], dtype=torch.float32, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+    tb = med(lambda: ih.ih_build(img, w.bins, w.bits, cfg=cfg, out=out, ws=ws, layout="hwb"), 5)
+    tq = med(lambda: ih.ih_query_rect(out, rects, out=q, layout="hwb"), 5)
+
+    def search():
+        ih.ih_pyramid_desc(out, tw, 3, out=desc, layout="hwb")
+        ih.ih_match_candidates(out, desc, 32, 32, origins, 3, "chi2", dist=dist, best=best, layout="hwb")
+
+    tm = med(search, 10)
+    alg = w.P * w.H * w.W * 4 + w.H * w.W * 2
+    res["8192x8192_u16_64bins"] = {"ih_bytes": out.numel() * 4, "build_ms": round(tb, 3),
+                                   "gpxbins_per_s": round(w.H * w.W * w.P / tb / 1e6, 2),
+                                   "build_hbm_gbs": round(alg / tb / 1e6, 1),
+                                   "build_frac_of_peak": round(alg / tb / 1e6 / HBM_PEAK_GBS, 4),
+                                   "rect_queries": int(rects.shape[0]), "rect_ms": round(tq, 3),
+                                   "rect_queries_per_s": round(rects.shape[0] / tq * 1e3, 1),
+                                   "search_candidates": int(origins.shape[0]), "search_ms": round(tm, 4),
+                                   "tile": repr(cfg)}
+    del out, ws, q, img
+
+    # 64 uneven frames as one batch
+    frames = []
+    total = 0
+    for f in synth.config4():
+        g = torch.from_numpy(f.img).to(dev)
+        frames.append(dict(img=g, bins=f.bins, value_bits=f.bits, tile=None,
+                           origins=torch.from_numpy(f.origins).to(dev), win=(32, 32), tmpl_win=f.tmpl_win))
+        total += f.img.shape[1] * f.img.shape[2] * f.bins
+    per_layout = {}
+    for lay in ("hwb", "bhw"):
+        tile, _ = tune.tune_batch(frames, "chi2", layout=lay, reps=2)
+        for fr in frames:
+            fr["tile"] = tile
+        batch = ih.Batch(frames, "chi2", layout=lay)
+        batch.run("phased")
+        torch.cuda.synchronize()
+        ref = [b.clone() for b in batch.best]
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            batch.run("phased")
+        t_graph = med(graph.replay, 5)
+        t_coop = med(lambda: batch.run("cooperative"), 5)
+        same = all(torch.equal(a, b) for a, b in zip(ref, batch.best))
+        per_layout[lay] = {"tile": repr(tile), "graph_phased_ms": round(t_graph, 3),
+                           "cooperative_ms": round(t_coop, 3),
+                           "gpxbins_per_s_graph": round(total / t_graph / 1e6, 2),
+                           "ih_write_gbs_graph": round(total * 4 / t_graph / 1e6, 1), "modes_agree": same}
+        del batch, graph, ref
+        torch.cuda.empty_cache()
+    seq = []
+    for fr in frames:
+        fr["tile"] = tune.tune(fr["img"], fr["bins"], fr["value_bits"], layout="bhw", reps=2)[0]
+        C, H, W = fr["img"].shape
+        P = C * fr["bins"]
+        o = torch.empty((P, H, W), dtype=torch.int32, device=dev)
+        s_ws = torch.empty(ih.workspace_size(H, W, C, fr["bins"], False, fr["tile"], "bhw"), dtype=torch.uint8,
+                           device=dev)
+        d = torch.empty((1, 21, P), dtype=torch.int32, device=dev)
+        di = torch.empty(fr["origins"].shape[0], dtype=torch.float32, device=dev)
+        bb = torch.empty(1, dtype=torch.int32, device=dev)
+        tww = torch.tensor([list(fr["tmpl_win"])], dtype=torch.int32, device=dev)
+        seq.append((fr, o, s_ws, d, di, bb, tww))
+
+    def one_by_one():
+        for fr, o, s_ws, d, di, bb, tww in seq:
+            ih.ih_build(fr["img"], fr["bins"], fr["value_bits"], cfg=fr["tile"], out=o, ws=s_ws, layout="bhw")
+            ih.ih_pyramid_desc(o, tww, 3, out=d, layout="bhw")
+            ih.ih_match_candidates(o, d, 32, 32, fr["origins"], 3, "chi2", dist=di, best=bb, layout="bhw")
+
+    t_seq = med(one_by_one, 3)
+    res["batch_64_uneven_frames"] = {"frames": len(frames), "ih_bytes": total * 4, "candidates_per_frame": 4096,
+                                     "layouts": per_layout, "one_call_per_frame_bhw_ms": round(t_seq, 3)}
+    return res
 
 
 def search_cost_vs_targets(torch, trk, lp, tr, net, frame, box0, counts=(1, 4, 16, 64, 256)):
@@ -465,6 +587,11 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
         },
     }
+    if not args.no_configs:
+        print("other workloads ...", file=sys.stderr, flush=True)
+        del step, graph
+        torch.cuda.empty_cache()
+        res["workloads"] = config_legs(torch, ih, synth)
     if not args.no_tracker:
         print("tracker ...", file=sys.stderr, flush=True)
         res["tracker"] = tracker_leg(torch, args)

@@ -227,7 +227,7 @@ int ih_match_candidates(const int32_t *ih, int32_t P, int32_t H, int32_t W,
 /*
  * Batched build and search over many frames of uneven size and bin count
  * (the device-resident analogue of the thesis's dual-buffered frame
- * pipeline, Alg. 10): every frame's integral histogram (bin-major),
+ * pipeline, Alg. 10): every frame's integral histogram (in its layout),
  * optionally its template descriptor and its candidate search (3-level
  * pyramid, as ih_pyramid_desc / ih_match_candidates), over all frames at
  * once.  The calls allocate nothing and do not synchronise; the phased mode
@@ -235,10 +235,11 @@ int ih_match_candidates(const int32_t *ih, int32_t P, int32_t H, int32_t W,
  */
 typedef struct {
   const void *img;          /* device, C x H x W values of the batch dtype   */
-  int32_t *ih;              /* device, out: P x H x W int32 (bin-major)      */
+  int32_t *ih;              /* device, out: P x H x W (IH_BHW) or H x W x P
+                               (IH_HWB) int32                               */
   int32_t H, W, C, bins, value_bits;
   ih_tile_cfg tile;         /* tile shape; tile_h == 0 selects the heuristic.
-                               planes_per_wave must be 1, 2, 4 or 8          */
+                               IH_BHW: planes_per_wave 1, 2, 4 or 8         */
   /* candidate search; n_cand == 0 skips it for this frame                   */
   const int32_t *tmpl_desc; /* device, 21 x P template descriptor, or NULL to
                                compute it from tmpl_win of this frame       */
@@ -249,6 +250,7 @@ typedef struct {
   int64_t n_cand;
   float *dist;              /* device, out: n_cand distances                 */
   int32_t *best;            /* device, out: best candidate index or -1       */
+  int32_t layout;           /* ih_layout of this frame's histogram           */
 } ih_frame;
 
 /* Bytes of the plan for n frames (0 when n < 1). */

@@ -20,6 +20,12 @@ namespace ih {
 
 constexpr int NPH = 6;
 constexpr int kBatchLds = 32 * 1024;  // LDS budget of the tile-histogram phase
+#ifndef IH_BATCH_BHW_TH
+#define IH_BATCH_BHW_TH 64
+#define IH_BATCH_BHW_TW 64
+#define IH_BATCH_HWB_TH 64
+#define IH_BATCH_HWB_TW 32
+#endif
 
 struct FramePlan {
   Geom g;
@@ -42,7 +48,9 @@ struct FramePlan {
 };
 
 struct BatchHeader {
-  int32_t n, dtype, metric, lds;  // lds: dynamic LDS bytes of the batch kernels
+  int32_t n, dtype, metric, lds;  // lds: dynamic LDS bytes of the cooperative kernel (all phases)
+  int32_t lds_ph[NPH];            // dynamic LDS bytes of each phase's own kernel (phased mode)
+  int32_t layouts;                // bit l set: some frame uses layout l
   int64_t phase_start[NPH + 1];   // unit numbering: phase-major, frame-minor
   int64_t ws_words;
 };
@@ -68,8 +76,25 @@ __device__ __forceinline__ void final_dispatch(const FinalArgs &a, const Geom &g
 #undef IH_B
 }
 
+// Planes-innermost write-out in a batch: four wave units per workgroup unit;
+// frames of at most 64 planes stage each tile row in the wave's LDS slice.
+template <typename T>
+__device__ __forceinline__ void final_hwb_batch(const FinalArgs &a, const Geom &g, int64_t u, uint32_t *lds) {
+  const int wave = uniform((int)(threadIdx.x >> 6));
+  const int64_t wu = u * 4 + wave;
+  if (g.P <= 64 && g.TW <= 32) {
+    uint32_t *slice = lds + wave * g.TW * 64;
+    if (g.TW == 16) final_hwb_wave_staged_body<T, 16>(a, g, wu, slice);
+    else final_hwb_wave_staged_body<T, 32>(a, g, wu, slice);
+  } else {
+    if (g.TW == 16) final_hwb_body<T, 16, false>(a, g, wu);
+    else if (g.TW == 32) final_hwb_body<T, 32, false>(a, g, wu);
+    else final_hwb_body<T, 64, false>(a, g, wu);
+  }
+}
+
 // One unit of phase ph: the u-th unit of frame F.
-template <typename T, int METRIC>
+template <typename T, int METRIC, int LAY = -1>
 __device__ __forceinline__ void run_unit(const FramePlan &F, int ph, int64_t u, uint32_t *ws, uint32_t *lds) {
   uint32_t *fws = ws + F.ws_off;
   const Geom &g = F.g;
@@ -82,17 +107,28 @@ __device__ __forceinline__ void run_unit(const FramePlan &F, int ph, int64_t u, 
       break;
     case 2: {
       const FinalArgs a{F.img, F.ih, nullptr, nullptr, fws, F.bits, F.vec_ok};
-      final_dispatch<T>(a, g, (int)(u % F.tiles), (int)(u / F.tiles));
+      if constexpr (LAY != IH_BHW) {
+        if (g.layout == IH_HWB) { final_hwb_batch<T>(a, g, u, lds); break; }
+      }
+      if constexpr (LAY != IH_HWB) final_dispatch<T>(a, g, (int)(u % F.tiles), (int)(u / F.tiles));
       break;
     }
     case 3:
       for (int p = threadIdx.x; p < g.P; p += blockDim.x)
-        pyramid_cells<3>(F.ih, g.P, g.H, g.W, IH_BHW, F.tmpl_win, p, F.tmpl_out + p);
+        pyramid_cells<3>(F.ih, g.P, g.H, g.W, g.layout, F.tmpl_win, p, F.tmpl_out + p);
       break;
     case 4: {
       const int32_t *tm = F.tmpl_desc ? F.tmpl_desc : F.tmpl_out;
-      match_body<3, METRIC>(F.ih, g.P, g.H, g.W, tm, F.win_h, F.win_w, F.origins, F.n_cand, F.dist, u,
-                            reinterpret_cast<double *>(lds), reinterpret_cast<long long *>(lds) + 64 * kMatchWaves);
+      if constexpr (LAY != IH_BHW) {
+        if (g.layout == IH_HWB) {
+          match_hwb_body<3, METRIC>(F.ih, g.P, g.H, g.W, tm, F.win_h, F.win_w, F.origins, F.n_cand, F.dist,
+                                    u * 4 + uniform((int)(threadIdx.x >> 6)));
+          break;
+        }
+      }
+      if constexpr (LAY != IH_HWB)
+        match_body<3, METRIC>(F.ih, g.P, g.H, g.W, tm, F.win_h, F.win_w, F.origins, F.n_cand, F.dist, u,
+                              reinterpret_cast<double *>(lds), reinterpret_cast<long long *>(lds) + 64 * kMatchWaves);
       break;
     }
     default:
@@ -104,24 +140,28 @@ __device__ __forceinline__ void run_unit(const FramePlan &F, int ph, int64_t u, 
 
 // All units of phase ph, grid-stride.  The unit of a workgroup iteration is
 // uniform across the workgroup, so the bodies' barriers are reached by all.
-template <typename T, int METRIC>
+// LAY >= 0 restricts the phase to frames of that layout (the others' units
+// are skipped, uniformly per workgroup).
+template <typename T, int METRIC, int LAY = -1>
 __device__ __forceinline__ void run_phase(const BatchHeader *__restrict__ hdr, const FramePlan *__restrict__ fr,
                                           uint32_t *__restrict__ ws, int ph, uint32_t *lds) {
   const int n = hdr->n;
   const int64_t end = hdr->phase_start[ph + 1];
   for (int64_t t = hdr->phase_start[ph] + blockIdx.x; t < end; t += gridDim.x) {
     const int f = find_frame(fr, n, ph, t);
-    run_unit<T, METRIC>(fr[f], ph, t - fr[f].start[ph], ws, lds);
+    if (LAY >= 0 && fr[f].g.layout != LAY) continue;
+    run_unit<T, METRIC, LAY>(fr[f], ph, t - fr[f].start[ph], ws, lds);
     __syncthreads();
   }
 }
 
-template <typename T, int METRIC>
+// Phased mode: one kernel per phase, so that each phase is compiled alone
+// (its own register count and LDS request, hence its own occupancy).
+template <typename T, int METRIC, int PH, int LAY>
 __global__ __launch_bounds__(256) void k_batch_phase(const BatchHeader *__restrict__ hdr,
-                                                     const FramePlan *__restrict__ fr, uint32_t *__restrict__ ws,
-                                                     int ph) {
+                                                     const FramePlan *__restrict__ fr, uint32_t *__restrict__ ws) {
   extern __shared__ uint32_t lds[];
-  run_phase<T, METRIC>(hdr, fr, ws, ph, lds);
+  run_phase<T, METRIC, LAY>(hdr, fr, ws, PH, lds);
 }
 
 template <typename T, int METRIC>
@@ -136,14 +176,29 @@ __global__ __launch_bounds__(256) void k_batch_coop(const BatchHeader *__restric
   }
 }
 
-typedef void (*phase_fn)(const BatchHeader *, const FramePlan *, uint32_t *, int);
+typedef void (*phase_fn)(const BatchHeader *, const FramePlan *, uint32_t *);
 typedef void (*coop_fn)(const BatchHeader *, const FramePlan *, uint32_t *);
 
+// pf[ph][l]: the phase-ph kernel for frames of layout l (phases 2 and 4 have
+// one kernel per layout; the others serve both layouts, entry [ph][0]).
+template <typename T, int METRIC>
+static void pick_m(phase_fn (*pf)[2], coop_fn *cf) {
+  pf[0][0] = &k_batch_phase<T, METRIC, 0, -1>;
+  pf[1][0] = &k_batch_phase<T, METRIC, 1, -1>;
+  pf[2][0] = &k_batch_phase<T, METRIC, 2, IH_BHW>;
+  pf[2][1] = &k_batch_phase<T, METRIC, 2, IH_HWB>;
+  pf[3][0] = &k_batch_phase<T, METRIC, 3, -1>;
+  pf[4][0] = &k_batch_phase<T, METRIC, 4, IH_BHW>;
+  pf[4][1] = &k_batch_phase<T, METRIC, 4, IH_HWB>;
+  pf[5][0] = &k_batch_phase<T, METRIC, 5, -1>;
+  *cf = &k_batch_coop<T, METRIC>;
+}
+
 template <typename T>
-static void pick_t(int metric, phase_fn *pf, coop_fn *cf) {
-  if (metric == IH_CHI2) { *pf = &k_batch_phase<T, IH_CHI2>; *cf = &k_batch_coop<T, IH_CHI2>; }
-  else if (metric == IH_L1) { *pf = &k_batch_phase<T, IH_L1>; *cf = &k_batch_coop<T, IH_L1>; }
-  else { *pf = &k_batch_phase<T, IH_PMK>; *cf = &k_batch_coop<T, IH_PMK>; }
+static void pick_t(int metric, phase_fn (*pf)[2], coop_fn *cf) {
+  if (metric == IH_CHI2) pick_m<T, IH_CHI2>(pf, cf);
+  else if (metric == IH_L1) pick_m<T, IH_L1>(pf, cf);
+  else pick_m<T, IH_PMK>(pf, cf);
 }
 
 static size_t a64(size_t w) { return (w + 63) & ~(size_t)63; }
@@ -168,6 +223,7 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
   const int maxbits = dtype == IH_U8 ? 8 : 16;
   size_t carry = 0, lds = (size_t)kMatchWaves * 64 * 16;  // match partials: waves x 64 x (8 + 8) bytes
   if (lds < 256 * 16) lds = 256 * 16;                     // best-candidate reduction: 256 x (4 + 8), 8-aligned
+  size_t lph[NPH] = {0, 0, 0, 0, 0, 256 * 16};
   for (int f = 0; f < n; ++f) {
     const ih_frame &F = frames[f];
     FramePlan &P = fp[f];
@@ -176,16 +232,32 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
     if (F.value_bits < 1 || F.value_bits > maxbits)
       return set_error(IH_ERR_INVALID_ARG, "frame %d: value_bits %d outside 1..%d", f, F.value_bits, maxbits);
     if (F.bins > (1 << F.value_bits)) return set_error(IH_ERR_INVALID_ARG, "frame %d: bins exceed 2^value_bits", f);
-    int e = make_geom(F.H, F.W, F.C, F.bins, 0, IH_BHW, F.tile.tile_h ? &F.tile : nullptr, &P.g);
+    if (F.layout != IH_BHW && F.layout != IH_HWB)
+      return set_error(IH_ERR_INVALID_ARG, "frame %d: layout %d unknown", f, F.layout);
+    const bool hwb = F.layout == IH_HWB;
+    // without a tile shape, batch defaults: many frames already fill the GPU,
+    // so tiles are taller than the single-frame heuristic's (fewer, longer units)
+    ih_tile_cfg dflt;
+    if (hwb) dflt = ih_tile_cfg{IH_BATCH_HWB_TH, IH_BATCH_HWB_TW, 64};
+    else dflt = ih_tile_cfg{IH_BATCH_BHW_TH, IH_BATCH_BHW_TW, F.bins >= 2 ? 2 : 1};
+    int e = make_geom(F.H, F.W, F.C, F.bins, 0, F.layout, F.tile.tile_h ? &F.tile : &dflt, &P.g);
     if (e) return set_error(e, "frame %d: %s", f, ih_last_error());
-    if (P.g.PG > 8) return set_error(IH_ERR_UNSUPPORTED, "frame %d: planes_per_wave %d > 8 in a batch", f, P.g.PG);
+    if (!hwb && P.g.PG > 8)
+      return set_error(IH_ERR_UNSUPPORTED, "frame %d: planes_per_wave %d > 8 in a batch", f, P.g.PG);
     size_t l;
     if ((e = pick_bc(P.g, kBatchLds, &P.bc, &l))) return set_error(e, "frame %d: %s", f, ih_last_error());
     if (l > lds) lds = l;
+    if (l > lph[0]) lph[0] = l;
     P.img = F.img;
     P.ih = F.ih;
     P.bits = F.value_bits;
     P.vec_ok = ((uintptr_t)F.ih % 16 == 0 && F.W % P.g.CPL == 0) ? 1 : 0;
+    if (hwb && P.g.P <= 64 && P.g.TW <= 32) {
+      const size_t slices = (size_t)4 * P.g.TW * 64 * 4;  // four waves' staged row segments
+      if (slices > lds) lds = slices;
+      if (slices > lph[2]) lph[2] = slices;
+    }
+    if (!hwb && F.n_cand > 0 && lph[4] < (size_t)kMatchWaves * 64 * 16) lph[4] = (size_t)kMatchWaves * 64 * 16;
     P.tiles = (int64_t)P.g.nTR * P.g.nTC * F.C;
     P.ws_off = (int64_t)carry;
     carry += a64(P.g.words);
@@ -195,7 +267,7 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
     P.gy = (groups + 3) / 4;
     P.cnt[0] = P.tiles;
     P.cnt[1] = P.nA + P.nB + P.g.P;
-    P.cnt[2] = P.tiles * P.gy;
+    P.cnt[2] = hwb ? ((int64_t)P.g.nTR * P.g.nTC * ((P.g.P + 63) / 64) + 3) / 4 : P.tiles * P.gy;
     if (F.n_cand < 0) return set_error(IH_ERR_INVALID_ARG, "frame %d: n_cand < 0", f);
     if (F.n_cand > 0) {
       if (!F.origins || !F.dist || !F.best) return set_error(IH_ERR_INVALID_ARG, "frame %d: NULL search buffer", f);
@@ -213,7 +285,7 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
       P.dist = F.dist;
       P.best = F.best;
       P.cnt[3] = F.tmpl_desc ? 0 : 1;
-      P.cnt[4] = (F.n_cand + 63) / 64;
+      P.cnt[4] = hwb ? (F.n_cand + 3) / 4 : (F.n_cand + 63) / 64;
       P.cnt[5] = 1;
     }
   }
@@ -231,6 +303,9 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
   h->dtype = dtype;
   h->metric = metric;
   h->lds = (int32_t)lds;
+  for (int ph = 0; ph < NPH; ++ph) h->lds_ph[ph] = (int32_t)lph[ph];
+  h->layouts = 0;
+  for (int f = 0; f < n; ++f) h->layouts |= 1 << fp[f].g.layout;
   h->ws_words = carry > 0 ? (int64_t)carry : 64;
   *ws_bytes = (size_t)h->ws_words * 4;
   return IH_OK;
@@ -247,35 +322,42 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
   if (!ws || ws_bytes < (size_t)h->ws_words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)h->ws_words * 4);
   hipStream_t s = as_stream(stream);
-  phase_fn pf;
+  phase_fn pf[NPH][2] = {};
   coop_fn cf;
-  if (h->dtype == IH_U8) pick_t<uint8_t>(h->metric, &pf, &cf);
-  else pick_t<uint16_t>(h->metric, &pf, &cf);
+  if (h->dtype == IH_U8) pick_t<uint8_t>(h->metric, pf, &cf);
+  else pick_t<uint16_t>(h->metric, pf, &cf);
   int dev = 0, e;
   if ((e = hip_check(hipGetDevice(&dev), "hipGetDevice"))) return e;
   int cus = 0;
   if ((e = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count"))) return e;
-  int per_cu = 0;
-  if (mode == IH_BATCH_PHASED)
-    e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pf, 256, h->lds), "occupancy");
-  else
-    e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cf, 256, h->lds), "occupancy");
-  if (e) return e;
-  if (per_cu < 1) return set_error(IH_ERR_UNSUPPORTED, "batch kernel cannot be resident (LDS %d)", h->lds);
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(plan_dev);
   const FramePlan *fd = reinterpret_cast<const FramePlan *>(hd + 1);
   uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
-  const int64_t resident = (int64_t)per_cu * cus;
+  int per_cu = 0;
   if (mode == IH_BATCH_PHASED) {
     for (int ph = 0; ph < NPH; ++ph) {
       const int64_t units = h->phase_start[ph + 1] - h->phase_start[ph];
       if (units == 0) continue;
-      const int64_t blocks = units < 4 * resident ? units : 4 * resident;
-      hipLaunchKernelGGL(pf, dim3((unsigned)blocks), dim3(256), h->lds, s, hd, fd, w32, ph);
-      if ((e = hip_check(hipGetLastError(), "batch phase launch"))) return e;
+      for (int l = 0; l < 2; ++l) {
+        const bool split = pf[ph][1] != nullptr;
+        if (!split && l == 1) break;
+        if (split && !(h->layouts & (1 << l))) continue;
+        phase_fn k = pf[ph][l];
+        if ((e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, h->lds_ph[ph]),
+                           "occupancy")))
+          return e;
+        if (per_cu < 1) return set_error(IH_ERR_UNSUPPORTED, "batch phase %d cannot be resident", ph);
+        const int64_t resident = (int64_t)per_cu * cus;
+        const int64_t blocks = units < 4 * resident ? units : 4 * resident;
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), h->lds_ph[ph], s, hd, fd, w32);
+        if ((e = hip_check(hipGetLastError(), "batch phase launch"))) return e;
+      }
     }
     return IH_OK;
   }
+  if ((e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cf, 256, h->lds), "occupancy"))) return e;
+  if (per_cu < 1) return set_error(IH_ERR_UNSUPPORTED, "batch kernel cannot be resident (LDS %d)", h->lds);
+  const int64_t resident = (int64_t)per_cu * cus;
   void *args[] = {(void *)&hd, (void *)&fd, (void *)&w32};
   return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(cf), dim3((unsigned)resident), dim3(256),
                                               args, (unsigned)h->lds, s),

@@ -277,21 +277,41 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
   uint32_t *mx_base = MOM ? a.mx + ((int64_t)ch * g.bins + kb) * HW + cf : nullptr;
   uint32_t *my_base = MOM ? a.my + ((int64_t)ch * g.bins + kb) * HW + cf : nullptr;
 
+  // the next row's pixels and row carries are loaded while this row is
+  // written (software pipelining hides their latency)
+  uint32_t px[CPL], lcv[PG], lcyv[MOM ? PG : 1];
+  auto fetch = [&](int r) {
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) px[e] = cf + e < g.W ? (uint32_t)img[(int64_t)r * g.W + cf + e] : 0u;
+    const uint32_t *lc = lc_base + (int64_t)r * g.bins;
+#pragma unroll
+    for (int k = 0; k < PG; ++k) lcv[k] = k < nk ? lc[k] : 0u;
+    if constexpr (MOM) {
+      const uint32_t *lcy = lcy_base + (int64_t)r * g.bins;
+#pragma unroll
+      for (int k = 0; k < PG; ++k) lcyv[k] = k < nk ? lcy[k] : 0u;
+    }
+  };
+  if (rows > 0) fetch(R0);
   for (int rr = 0; rr < rows; ++rr) {
     const int r = R0 + rr;
     int b[CPL];
 #pragma unroll
-    for (int e = 0; e < CPL; ++e) {
-      const int c = cf + e;
-      b[e] = c < g.W ? (int)(((uint64_t)img[(int64_t)r * g.W + c] * g.bins) >> a.bits) - kb : -1;
+    for (int e = 0; e < CPL; ++e)
+      b[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
+    uint32_t lcur[PG], lycur[MOM ? PG : 1];
+#pragma unroll
+    for (int k = 0; k < PG; ++k) lcur[k] = lcv[k];
+    if constexpr (MOM) {
+#pragma unroll
+      for (int k = 0; k < PG; ++k) lycur[k] = lcyv[k];
     }
-    const uint32_t *lc = lc_base + (int64_t)r * g.bins;
-    const uint32_t *lcy = lcy_base + (int64_t)r * g.bins;
+    if (rr + 1 < rows) fetch(r + 1);
     const int64_t orow = (int64_t)r * g.W;
 #pragma unroll
     for (int k = 0; k < PG; ++k) {
       if (k < nk) {
-        uint32_t t = lc[k];
+        uint32_t t = lcur[k];
         uint64_t m[CPL];
 #pragma unroll
         for (int e = 0; e < CPL; ++e) m[e] = ballot(b[e] == k);
@@ -314,7 +334,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
           }
 #pragma unroll
           for (int e = 1; e < CPL; ++e) y[e] += y[e - 1];
-          const uint32_t ey = wave_incl_scan(y[CPL - 1]) - y[CPL - 1] + lcy[k];
+          const uint32_t ey = wave_incl_scan(y[CPL - 1]) - y[CPL - 1] + lycur[k];
 #pragma unroll
           for (int e = 0; e < CPL; ++e) coly[k][e] += ey + y[e];
           put<CPL>(reinterpret_cast<int32_t *>(mx_base) + k * HW + orow, colx[k], cf, g.W, vec_ok);
@@ -456,13 +476,88 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
 //     output line is written whole by one instruction whatever P is.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void copy_out(int32_t *__restrict__ dst, const uint32_t *__restrict__ src, int n,
-                                         bool vec) {
+                                         bool vec, int tid, int nthreads) {
   if (vec) {
     const v4i *s4 = reinterpret_cast<const v4i *>(src);
     v4i *d4 = reinterpret_cast<v4i *>(dst);
-    for (int i = threadIdx.x; i < (n >> 2); i += blockDim.x) __builtin_nontemporal_store(s4[i], d4 + i);
+    for (int i = tid; i < (n >> 2); i += nthreads) __builtin_nontemporal_store(s4[i], d4 + i);
   } else {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) __builtin_nontemporal_store((int)src[i], dst + i);
+    for (int i = tid; i < n; i += nthreads) __builtin_nontemporal_store((int)src[i], dst + i);
+  }
+}
+
+__device__ __forceinline__ void copy_out(int32_t *__restrict__ dst, const uint32_t *__restrict__ src, int n,
+                                         bool vec) {
+  copy_out(dst, src, n, vec, threadIdx.x, blockDim.x);
+}
+
+// Completes this wavefront's LDS writes before any of its lanes reads them.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 3d. The staged write-out for P <= 64 done by one wavefront per tile (no
+//     block barrier), with its own LDS slice of TW x P words; used by the
+//     batched build, whose workgroups run four such units side by side.
+template <typename T, int TW>
+__device__ __forceinline__ void final_hwb_wave_staged_body(const FinalArgs &a, const Geom &g, int64_t tile,
+                                                           uint32_t *lds) {
+  const int lane = threadIdx.x & 63;
+  if (tile >= (int64_t)g.nTR * g.nTC) return;
+  const int j = (int)(tile % g.nTC), I = (int)(tile / g.nTC);
+  const int p = min(lane, g.P - 1);  // lanes past the last plane repeat it
+  const int ch = p / g.bins;
+  const int k = p - ch * g.bins;
+  const int R0 = I * g.TH, C0 = j * TW;
+  const int cols = min(TW, g.W - C0), rows = min(g.TH, g.H - R0);
+  const uint32_t lo = (uint32_t)((((uint64_t)k << a.bits) + g.bins - 1) / g.bins);
+  const uint32_t width = (uint32_t)((((uint64_t)(k + 1) << a.bits) + g.bins - 1) / g.bins) - lo;
+  const T *img = reinterpret_cast<const T *>(a.img) + (int64_t)ch * g.H * g.W;
+  const int64_t P = g.P;
+  uint32_t col[TW];
+  {
+    const int64_t cidx = ((int64_t)p * g.nTR + I) * g.nTC + j;
+    uint32_t run = a.ws[g.off_tt + cidx];
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        run += a.ws[g.off_cc + ((int64_t)I * g.W + C0 + c) * P + p];
+        col[c] = run;
+      }
+    }
+  }
+  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const bool vec = (g.P & 3) == 0 && ((uintptr_t)a.ih & 15) == 0;
+  const int nseg = cols * g.P;
+  uint32_t pxn[TW], rcn = 0;
+  auto fetch = [&](int r) {
+    const T *row = img + (int64_t)r * g.W + C0;
+#pragma unroll
+    for (int c = 0; c < TW; ++c) pxn[c] = c < cols ? (uint32_t)row[c] : 0u;
+    rcn = lc[(int64_t)r * g.bins];
+  };
+  if (rows > 0) fetch(R0);
+  for (int rr = 0; rr < rows; ++rr) {
+    const int r = R0 + rr;
+    uint32_t px[TW];
+#pragma unroll
+    for (int c = 0; c < TW; ++c) px[c] = pxn[c];
+    uint32_t rc = rcn;
+    if (rr + 1 < rows) fetch(r + 1);
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        const uint32_t hit = (px[c] - lo) < width ? 1u : 0u;
+        rc += hit;
+        col[c] += rc;
+        lds[c * g.P + p] = col[c];
+      }
+    }
+    wave_sync();
+    copy_out(a.ih + ((int64_t)r * g.W + C0) * P, lds, nseg, vec, lane, 64);
+    wave_sync();
   }
 }
 
@@ -560,11 +655,56 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
     }
     __syncthreads();
   };
-  if (full) {
+  if (TW <= 32 && full && words) {
+    // prefetched path: the next row's image words and row carries are loaded
+    // while this row is computed and stored
+    const int64_t rbase0 = ((int64_t)R0 * g.W + C0) * P;
+    uint32_t wv[TW / PER], rcn = 0, ryn = 0;
+    auto fetch = [&](int r) {
+      const uint32_t *wp = reinterpret_cast<const uint32_t *>(img + (int64_t)r * g.W + C0);
+#pragma unroll
+      for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
+      rcn = lc[(int64_t)r * g.bins];
+      if constexpr (MOM) ryn = lcy[(int64_t)r * g.bins];
+    };
+    if (rows > 0) fetch(R0);
+    for (int rr = 0; rr < rows; ++rr) {
+      const int r = R0 + rr;
+      uint32_t cur[TW / PER];
+#pragma unroll
+      for (int q = 0; q < TW / PER; ++q) cur[q] = wv[q];
+      uint32_t rc = rcn, ry = ryn;
+      if (rr + 1 < rows) fetch(r + 1);
+#pragma unroll
+      for (int c = 0; c < TW; ++c) {
+        const uint32_t val = (cur[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u);
+        const uint32_t hit = (val - lo) < width ? 1u : 0u;
+        rc += hit;
+        col[c] += rc;
+        s0[c * g.P + p] = col[c];
+        if constexpr (MOM) {
+          colx[c] += (uint32_t)r * rc;
+          ry += hit * (uint32_t)(C0 + c);
+          coly[c] += ry;
+          s1[c * g.P + p] = colx[c];
+          s2[c * g.P + p] = coly[c];
+        }
+      }
+      __syncthreads();
+      const int64_t rbase = rbase0 + (int64_t)rr * g.W * P;
+      copy_out(a.ih + rbase, s0, nseg, vec);
+      if constexpr (MOM) {
+        copy_out(reinterpret_cast<int32_t *>(a.mx) + rbase, s1, nseg, vec);
+        copy_out(reinterpret_cast<int32_t *>(a.my) + rbase, s2, nseg, vec);
+      }
+      __syncthreads();
+    }
+  } else if (full) {
     for (int rr = 0; rr < rows; ++rr) row_step(std::true_type{}, rr);
   } else {
     for (int rr = 0; rr < rows; ++rr) row_step(std::false_type{}, rr);
   }
 }
+
 
 }  // namespace ih

@@ -166,14 +166,14 @@ __device__ __forceinline__ void match_body(const int32_t *__restrict__ ih, int P
   }
 }
 
+// Planes-innermost search: one wavefront per candidate q, lanes over planes.
 template <int LEVELS, int METRIC>
-__global__ __launch_bounds__(256) void k_match_hwb(const int32_t *__restrict__ ih, int P, int H, int W,
-                                                  const int32_t *__restrict__ tmpl, int win_h, int win_w,
-                                                  const int32_t *__restrict__ origins, int64_t n,
-                                                  float *__restrict__ dist) {
+__device__ __forceinline__ void match_hwb_body(const int32_t *__restrict__ ih, int P, int H, int W,
+                                               const int32_t *__restrict__ tmpl, int win_h, int win_w,
+                                               const int32_t *__restrict__ origins, int64_t n,
+                                               float *__restrict__ dist, int64_t q) {
   constexpr int G = 1 << (LEVELS - 1);
   const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform(threadIdx.x >> 6);
   if (q >= n) return;
   const int r = origins[2 * q], c = origins[2 * q + 1];
   if (!(r >= 0 && c >= 0 && (int64_t)r + win_h <= H && (int64_t)c + win_w <= W)) {
@@ -211,6 +211,15 @@ __global__ __launch_bounds__(256) void k_match_hwb(const int32_t *__restrict__ i
     ti += __shfl_xor((long long)ti, m, 64);
   }
   if (lane == 0) dist[q] = finish<LEVELS, METRIC>(tf, ti);
+}
+
+template <int LEVELS, int METRIC>
+__global__ __launch_bounds__(256) void k_match_hwb(const int32_t *__restrict__ ih, int P, int H, int W,
+                                                  const int32_t *__restrict__ tmpl, int win_h, int win_w,
+                                                  const int32_t *__restrict__ origins, int64_t n,
+                                                  float *__restrict__ dist) {
+  match_hwb_body<LEVELS, METRIC>(ih, P, H, W, tmpl, win_h, win_w, origins, n, dist,
+                                 (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform(threadIdx.x >> 6));
 }
 
 // Best candidate: smallest distance (largest for PMK), lowest index on ties;

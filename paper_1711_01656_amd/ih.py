@@ -91,7 +91,7 @@ class Frame(ctypes.Structure):
                 ("tmpl_desc", ctypes.c_void_p), ("tmpl_win", ctypes.c_int32 * 4), ("tmpl_out", ctypes.c_void_p),
                 ("win_h", ctypes.c_int32), ("win_w", ctypes.c_int32),
                 ("origins", ctypes.c_void_p), ("n_cand", ctypes.c_int64),
-                ("dist", ctypes.c_void_p), ("best", ctypes.c_void_p)]
+                ("dist", ctypes.c_void_p), ("best", ctypes.c_void_p), ("layout", ctypes.c_int32)]
 
 
 def lib_path() -> str:
@@ -323,12 +323,13 @@ class Batch:
     CUDA tensor), ``bins``, optional ``value_bits``, ``tile`` (TileCfg),
     and, for the candidate search, ``origins`` (n x 2 int32 tensor),
     ``win`` ((h, w)) and either ``tmpl_desc`` (21 x P int32 tensor) or
-    ``tmpl_win`` ((r, c, h, w) in this frame).  Output tensors are allocated
+    ``tmpl_win`` ((r, c, h, w) in this frame), and optionally ``layout``
+    (default: the batch's ``layout``).  Output tensors are allocated
     once; ``run()`` enqueues the batch on the current stream and may be
     captured in a CUDA (HIP) graph (phased mode).
     """
 
-    def __init__(self, frames, metric: str = "chi2"):
+    def __init__(self, frames, metric: str = "chi2", layout: str = "bhw"):
         if not frames:
             raise IHError("empty batch")
         dt = frames[0]["img"].dtype
@@ -348,10 +349,12 @@ class Batch:
             C, H, W = img.shape
             bins = int(fr["bins"])
             bits = int(fr.get("value_bits", 8 if dt == torch.uint8 else 16))
-            out = torch.empty((C * bins, H, W), dtype=torch.int32, device=img.device)
+            lay = fr.get("layout", layout)
+            out = torch.empty(shape_of(C * bins, H, W, lay), dtype=torch.int32, device=img.device)
             a = arr[i]
             a.img, a.ih = img.data_ptr(), out.data_ptr()
             a.H, a.W, a.C, a.bins, a.value_bits = H, W, C, bins, bits
+            a.layout = _layout(lay)
             if fr.get("tile") is not None:
                 a.tile = fr["tile"]
             keep = [img, out]

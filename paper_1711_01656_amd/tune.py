@@ -117,3 +117,39 @@ def tune(img: torch.Tensor, bins: int, value_bits: Optional[int] = None, moments
         cache[k] = list(best.key())
         _save()
     return best, times
+
+
+def batch_candidates(layout: str) -> List[ih.TileCfg]:
+    """Uniform tile shapes tried for a whole batch (every frame gets the same one)."""
+    if layout == "hwb":
+        return [ih.TileCfg(th, tw, 64) for th, tw in itertools.product((32, 64, 128), (16, 32))]
+    return [ih.TileCfg(th, tw, pg) for th, tw, pg in itertools.product((32, 64, 128), (64, 128), (1, 2))]
+
+
+def tune_batch(frames, metric: str = "chi2", layout: str = "bhw", reps: int = 3,
+               verbose: bool = False) -> Tuple[ih.TileCfg, Dict[str, float]]:
+    """Tile shape for a batch, chosen by timing the whole batch (all phases, one
+    launch per phase) with each candidate shape applied to every frame.  In a
+    batch the parallelism comes from many frames at once, so the best shape
+    differs from the best shape of each frame built alone.  Frames are dicts as
+    for ih.Batch; their own "tile" entries are ignored."""
+    times: Dict[str, float] = {}
+    best, best_t = None, float("inf")
+    for cfg in batch_candidates(layout):
+        if layout == "bhw" and any(cfg.planes_per_wave > max(1, int(f["bins"])) for f in frames):
+            continue
+        fr = [dict(f, tile=cfg, layout=layout) for f in frames]
+        try:
+            b = ih.Batch(fr, metric, layout=layout)
+        except ih.IHError:
+            continue
+        t = _time(lambda: b.run("phased"), reps)
+        del b
+        times[repr(cfg)] = t
+        if verbose:
+            print("tune batch %s: %.4f ms" % (cfg, t), flush=True)
+        if t < best_t:
+            best, best_t = cfg, t
+    if best is None:
+        raise ih.IHError("no tile shape fits every frame of the batch")
+    return best, times

@@ -50,10 +50,15 @@ def make_frames(seed, dtype=np.uint8, n=12, search=True):
     return out
 
 
-def check(batch, frames, metric):
+def bin_major(batch, i, frames, layout):
+    t = batch.ih[i].cpu().numpy()
+    return t.transpose(2, 0, 1) if frames[i].get("layout", layout) == "hwb" else t
+
+
+def check(batch, frames, metric, layout="bhw"):
     for i, fr in enumerate(frames):
         img, bins, bits = fr["np_img"], fr["bins"], fr["value_bits"]
-        assert np.array_equal(batch.ih[i].cpu().numpy(), oracle.ih(img, bins, bits)), i
+        assert np.array_equal(bin_major(batch, i, frames, layout), oracle.ih(img, bins, bits)), i
         if "origins" not in fr:
             continue
         tr, tc, th, tw = fr["tmpl_win"]
@@ -74,15 +79,35 @@ def check(batch, frames, metric):
             assert b == ob, i
 
 
+@pytest.mark.parametrize("layout", ["bhw", "hwb"])
 @pytest.mark.parametrize("dtype,metric", [(np.uint8, "chi2"), (np.uint16, "l1"), (np.uint8, "pmk")])
-def test_batch_matches_oracle(dtype, metric):
+def test_batch_matches_oracle(dtype, metric, layout):
     ih = ihlib()
-    say("batch", dtype.__name__, metric)
+    say("batch", dtype.__name__, metric, layout)
     frames = make_frames(11, dtype)
-    batch = ih.Batch(frames, metric)
+    batch = ih.Batch(frames, metric, layout=layout)
     batch.run()
     torch.cuda.synchronize()
-    check(batch, frames, metric)
+    check(batch, frames, metric, layout)
+
+
+def test_batch_mixed_layouts_and_hwb_tiles():
+    ih = ihlib()
+    frames = make_frames(14, np.uint8, n=12)
+    tiles = [ih.TileCfg(16, 16, 64), ih.TileCfg(7, 32, 64), ih.TileCfg(64, 64, 64), ih.TileCfg(1, 16, 64)]
+    for i, fr in enumerate(frames):
+        if i % 2:
+            fr["layout"] = "hwb"
+            fr["tile"] = tiles[(i // 2) % len(tiles)]
+    batch = ih.Batch(frames, "chi2", layout="bhw")
+    batch.run()
+    first = [t.clone() for t in batch.ih]
+    for rep in range(5):
+        batch.run()
+    torch.cuda.synchronize()
+    for a, b in zip(first, batch.ih):
+        assert torch.equal(a, b)
+    check(batch, frames, "chi2", "bhw")
 
 
 def test_batch_tile_shapes_and_repeat():
@@ -102,10 +127,11 @@ def test_batch_tile_shapes_and_repeat():
     check(batch, frames, "chi2")
 
 
-def test_batch_graph_replays():
+@pytest.mark.parametrize("layout", ["bhw", "hwb"])
+def test_batch_graph_replays(layout):
     ih = ihlib()
     frames = make_frames(13, np.uint8, n=10)
-    batch = ih.Batch(frames, "chi2")
+    batch = ih.Batch(frames, "chi2", layout=layout)
     batch.run()
     torch.cuda.synchronize()
     ref_ih = [t.clone() for t in batch.ih]
@@ -136,15 +162,16 @@ def test_batch_graph_replays():
                 assert torch.equal(batch.best[i], ref_b[i]), (rep, i)
 
 
-def test_batch_64_uneven_frames():
+@pytest.mark.parametrize("layout", ["bhw", "hwb"])
+def test_batch_64_uneven_frames(layout):
     ih = ihlib()
-    say("64 uneven frames, 4096 candidates each")
+    say("64 uneven frames, 4096 candidates each", layout)
     fr4 = synth.config4()
     frames = []
     for f in fr4:
         frames.append(dict(np_img=f.img, img=gpu(f.img), bins=f.bins, value_bits=f.bits,
                            np_origins=f.origins, origins=gpu(f.origins), win=(32, 32), tmpl_win=f.tmpl_win))
-    batch = ih.Batch(frames, "chi2")
+    batch = ih.Batch(frames, "chi2", layout=layout)
     batch.run()
     torch.cuda.synchronize()
     for i, f in enumerate(fr4):
@@ -154,7 +181,7 @@ def test_batch_64_uneven_frames():
     for i in (0, 7, 31, 63):
         say("frame", i, fr4[i].img.shape, fr4[i].bins)
         f = fr4[i]
-        assert np.array_equal(batch.ih[i].cpu().numpy(), oracle.ih(f.img, f.bins, f.bits)), i
+        assert np.array_equal(bin_major(batch, i, frames, layout), oracle.ih(f.img, f.bins, f.bits)), i
         tmpl = oracle.pyramid_desc_direct(f.img, f.bins, f.bits, [f.tmpl_win], 3)[0]
         od, ob = oracle.match_direct(f.img, f.bins, f.bits, tmpl, 32, 32, 3, f.origins, "chi2")
         d = batch.dist[i].cpu().numpy().astype(np.float64)
