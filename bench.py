@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-tracker", action="store_true", help="skip the tracker workload")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (640x480, 8192^2 u16, 64-frame batch)")
+    ap.add_argument("--fixed-tiles", action="store_true",
+                    help="other workloads: use the tile shapes the autotuners chose on an MI355X instead of tuning")
+    ap.add_argument("--workloads-only", action="store_true",
+                    help="run only the other workloads and print their JSON object (for profiling)")
     ap.add_argument("--tracker-only", action="store_true",
                     help="run only the tracker workload and print its JSON object (for profiling)")
     ap.add_argument("--train-videos", type=int, default=800)
@@ -160,7 +164,12 @@ def time_calls(torch, fn, n):
     return a.elapsed_time(b) / n
 
 
-def config_legs(torch, ih, synth):
+# tile shapes the autotuners chose for the other workloads on one MI355X
+FIXED_TILES = {"640x480": (16, 16, 64), "8192x8192": (128, 64, 64), "batch_hwb": (128, 32, 64),
+               "batch_bhw": (64, 128, 1)}
+
+
+def config_legs(torch, ih, synth, fixed=False):
     """The other benchmark workloads, each timed on the device (median of
     repeated calls): 640x480 u8 with 32 bins and 10,000 rectangles; the
     8192x8192 u16 frame with 64 bins (17 GB integral histogram), 1M rectangles
@@ -173,19 +182,27 @@ def config_legs(torch, ih, synth):
     dev = torch.device("cuda:0")
     res = {}
 
-    def med(fn, n=10, trials=3):
-        return float(np.median([time_calls(torch, fn, n) for _ in range(trials)]))
+    def med(fn, n=10, trials=3, per=1):
+        """Median over trials of the device time per call: `per` calls captured
+        in one HIP graph, replayed n times per trial (no host launch cost)."""
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(per):
+                fn()
+        return float(np.median([time_calls(torch, g.replay, n) for _ in range(trials)])) / per
 
     # 640x480, 32 bins, 10k rectangles
     w = synth.config1()
     img = torch.from_numpy(w.img).to(dev)
-    cfg, _ = tune.tune(img, w.bins, w.bits, layout="hwb", reps=3)
+    cfg = ih.TileCfg(*FIXED_TILES["640x480"]) if fixed else tune.tune(img, w.bins, w.bits, layout="hwb", reps=3)[0]
     out = torch.empty(ih.shape_of(w.P, w.H, w.W, "hwb"), dtype=torch.int32, device=dev)
     ws = torch.empty(ih.workspace_size(w.H, w.W, w.C, w.bins, False, cfg, "hwb"), dtype=torch.uint8, device=dev)
     rects = torch.from_numpy(w.rects).to(dev)
     q = torch.empty((rects.shape[0], w.P), dtype=torch.int32, device=dev)
-    tb = med(lambda: ih.ih_build(img, w.bins, w.bits, cfg=cfg, out=out, ws=ws, layout="hwb"), 50)
-    tq = med(lambda: ih.ih_query_rect(out, rects, out=q, layout="hwb"), 50)
+    tb = med(lambda: ih.ih_build(img, w.bins, w.bits, cfg=cfg, out=out, ws=ws, layout="hwb"), 10, per=20)
+    tq = med(lambda: ih.ih_query_rect(out, rects, out=q, layout="hwb"), 10, per=20)
     alg = w.P * w.H * w.W * 4 + w.H * w.W
     res["640x480_u8_32bins"] = {"build_ms": round(tb, 4), "gpxbins_per_s": round(w.H * w.W * w.P / tb / 1e6, 2),
                                 "build_hbm_gbs": round(alg / tb / 1e6, 1), "rect_queries": int(rects.shape[0]),
@@ -196,7 +213,7 @@ def config_legs(torch, ih, synth):
     # 8192x8192 u16, 64 bins, 1M rectangles, 129x129 search
     w = synth.config3()
     img = torch.from_numpy(w.img).to(dev)
-    cfg, _ = tune.tune(img, w.bins, w.bits, layout="hwb", reps=1)
+    cfg = ih.TileCfg(*FIXED_TILES["8192x8192"]) if fixed else tune.tune(img, w.bins, w.bits, layout="hwb", reps=1)[0]
     out = torch.empty(ih.shape_of(w.P, w.H, w.W, "hwb"), dtype=torch.int32, device=dev)
     ws = torch.empty(ih.workspace_size(w.H, w.W, w.C, w.bins, False, cfg, "hwb"), dtype=torch.uint8, device=dev)
     rects = torch.from_numpy(w.rects).to(dev)
@@ -235,28 +252,27 @@ def config_legs(torch, ih, synth):
         total += f.img.shape[1] * f.img.shape[2] * f.bins
     per_layout = {}
     for lay in ("hwb", "bhw"):
-        tile, _ = tune.tune_batch(frames, "chi2", layout=lay, reps=2)
+        tile = (ih.TileCfg(*FIXED_TILES["batch_" + lay]) if fixed
+                else tune.tune_batch(frames, "chi2", layout=lay, reps=2)[0])
         for fr in frames:
             fr["tile"] = tile
         batch = ih.Batch(frames, "chi2", layout=lay)
         batch.run("phased")
         torch.cuda.synchronize()
         ref = [b.clone() for b in batch.best]
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            batch.run("phased")
-        t_graph = med(graph.replay, 5)
-        t_coop = med(lambda: batch.run("cooperative"), 5)
+        t_graph = med(lambda: batch.run("phased"), 5)
+        t_coop = float(np.median([time_calls(torch, lambda: batch.run("cooperative"), 5) for _ in range(3)]))
         same = all(torch.equal(a, b) for a, b in zip(ref, batch.best))
         per_layout[lay] = {"tile": repr(tile), "graph_phased_ms": round(t_graph, 3),
                            "cooperative_ms": round(t_coop, 3),
                            "gpxbins_per_s_graph": round(total / t_graph / 1e6, 2),
                            "ih_write_gbs_graph": round(total * 4 / t_graph / 1e6, 1), "modes_agree": same}
-        del batch, graph, ref
+        del batch, ref
         torch.cuda.empty_cache()
     seq = []
     for fr in frames:
-        fr["tile"] = tune.tune(fr["img"], fr["bins"], fr["value_bits"], layout="bhw", reps=2)[0]
+        fr["tile"] = (ih.TileCfg(*FIXED_TILES["batch_bhw"]) if fixed
+                      else tune.tune(fr["img"], fr["bins"], fr["value_bits"], layout="bhw", reps=2)[0])
         C, H, W = fr["img"].shape
         P = C * fr["bins"]
         o = torch.empty((P, H, W), dtype=torch.int32, device=dev)
@@ -435,6 +451,9 @@ def main():
     if args.tracker_only:
         print(json.dumps(tracker_leg(torch, args)), flush=True)
         return
+    if args.workloads_only:
+        print(json.dumps(config_legs(torch, ih, synth, args.fixed_tiles)), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     w = synth.config2()
@@ -591,7 +610,7 @@ def main():
         print("other workloads ...", file=sys.stderr, flush=True)
         del step, graph
         torch.cuda.empty_cache()
-        res["workloads"] = config_legs(torch, ih, synth)
+        res["workloads"] = config_legs(torch, ih, synth, args.fixed_tiles)
     if not args.no_tracker:
         print("tracker ...", file=sys.stderr, flush=True)
         res["tracker"] = tracker_leg(torch, args)
