@@ -120,6 +120,27 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
 //       columns
 //    C: for every plane, 2-D exclusive scan of TT (and TTX, TTY)
 // --------------------------------------------------------------------------
+// In-place exclusive scan of the n values a[0], a[step], a[2 step], ...  The
+// values are loaded CH at a time before any of them is stored, so the loads of
+// a chunk are in flight together instead of each waiting behind the previous
+// store (the compiler cannot prove the strided addresses distinct).
+template <int CH>
+__device__ __forceinline__ void excl_scan_strided(uint32_t *__restrict__ a, int64_t step, int n) {
+  uint32_t run = 0;
+  for (int j0 = 0; j0 < n; j0 += CH) {
+    uint32_t v[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) v[q] = j0 + q < n ? a[(int64_t)(j0 + q) * step] : 0u;
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      if (j0 + q < n) {
+        a[(int64_t)(j0 + q) * step] = run;
+        run += v[q];
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void carry_scan_body(const Geom &g, int64_t nblk_a, int64_t nblk_b,
                                                 uint32_t *__restrict__ ws, int64_t blk) {
   if (blk < nblk_a) {
@@ -129,60 +150,24 @@ __device__ __forceinline__ void carry_scan_body(const Geom &g, int64_t nblk_a, i
     if (g.layout == IH_BHW) { p = idx / g.W; c = idx - p * g.W; }
     else { c = idx / g.P; p = idx - c * g.P; }
     const int64_t step = cc_index(g, p, 1, c) - cc_index(g, p, 0, c);
-    uint32_t *a = ws + g.off_cc + cc_index(g, p, 0, c);
-    uint32_t *ax = ws + g.off_ccx + cc_index(g, p, 0, c);
-    uint32_t run = 0, runx = 0;
-    for (int I = 0; I < g.nTR; ++I) {
-      const uint32_t v = a[I * step];
-      a[I * step] = run;
-      run += v;
-      if (g.mom) {
-        const uint32_t vx = ax[I * step];
-        ax[I * step] = runx;
-        runx += vx;
-      }
-    }
+    excl_scan_strided<16>(ws + g.off_cc + cc_index(g, p, 0, c), step, g.nTR);
+    if (g.mom) excl_scan_strided<16>(ws + g.off_ccx + cc_index(g, p, 0, c), step, g.nTR);
   } else if (blk < nblk_a + nblk_b) {
     const int64_t idx = (blk - nblk_a) * 256 + threadIdx.x;
     const int64_t per_ch = (int64_t)g.H * g.bins;
     if (idx >= per_ch * g.C) return;
     const int64_t ch = idx / per_ch, rk = idx - ch * per_ch;
-    uint32_t *a = ws + g.off_rc + ch * g.nTC * per_ch + rk;
-    uint32_t *ay = ws + g.off_rcy + ch * g.nTC * per_ch + rk;
-    uint32_t run = 0, runy = 0;
-    for (int j = 0; j < g.nTC; ++j) {
-      const uint32_t v = a[j * per_ch];
-      a[j * per_ch] = run;
-      run += v;
-      if (g.mom) {
-        const uint32_t vy = ay[j * per_ch];
-        ay[j * per_ch] = runy;
-        runy += vy;
-      }
-    }
+    excl_scan_strided<16>(ws + g.off_rc + ch * g.nTC * per_ch + rk, per_ch, g.nTC);
+    if (g.mom) excl_scan_strided<16>(ws + g.off_rcy + ch * g.nTC * per_ch + rk, per_ch, g.nTC);
   } else {
     const int64_t p = blk - nblk_a - nblk_b;
     const int arrays = g.mom ? 3 : 1;
     for (int a = 0; a < arrays; ++a) {
       const size_t off = a == 0 ? g.off_tt : a == 1 ? g.off_ttx : g.off_tty;
       uint32_t *t = ws + off + p * g.nTR * (int64_t)g.nTC;
-      for (int I = threadIdx.x; I < g.nTR; I += 256) {
-        uint32_t run = 0;
-        for (int j = 0; j < g.nTC; ++j) {
-          const uint32_t v = t[I * g.nTC + j];
-          t[I * g.nTC + j] = run;
-          run += v;
-        }
-      }
+      for (int I = threadIdx.x; I < g.nTR; I += 256) excl_scan_strided<16>(t + (int64_t)I * g.nTC, 1, g.nTC);
       __syncthreads();
-      for (int j = threadIdx.x; j < g.nTC; j += 256) {
-        uint32_t run = 0;
-        for (int I = 0; I < g.nTR; ++I) {
-          const uint32_t v = t[I * g.nTC + j];
-          t[I * g.nTC + j] = run;
-          run += v;
-        }
-      }
+      for (int j = threadIdx.x; j < g.nTC; j += 256) excl_scan_strided<16>(t + j, g.nTC, g.nTR);
       __syncthreads();
     }
   }
