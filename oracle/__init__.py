@@ -67,6 +67,8 @@ def _load():
                 "or_match_direct": [P, I, I, I, I, I, I, P, I, I, I, P, I64, I, P, P],
                 "or_level_weight": [I, I],
                 "or_num_threads": [],
+                "or_ih_weighted": [P, I, P, P, I, I, I, I, I, P],
+                "or_ih_weighted_bruteforce": [P, I, P, P, I, I, I, I, I, P],
                 "or_set_threads": [I],
             }
             for name, args in sig.items():
@@ -133,6 +135,26 @@ def ih(img, bins, bits):
     a, dt, C, H, W = _img(img)
     out = np.empty((C * bins, H, W), np.int32)
     _check(_load().or_ih(_ptr(a), dt, H, W, C, bins, bits, _ptr(out)), "ih")
+    return out
+
+
+def _u8(a, shape, name):
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    if a.shape != shape:
+        raise ValueError("%s must have shape %s" % (name, shape))
+    return a
+
+
+def ih_weighted(img, bins, bits, weight, mask=None, brute=False):
+    """Weighted integral histogram (Alg. 2 step 4): plane k accumulates the
+    pixel's weight where its bin is k and its mask is set.  P x H x W int32."""
+    a, dt, C, H, W = _img(img)
+    w = _u8(weight, (C, H, W), "weight")
+    m = None if mask is None else _u8(mask, (C, H, W), "mask")
+    out = np.empty((C * bins, H, W), np.int32)
+    fn = _load().or_ih_weighted_bruteforce if brute else _load().or_ih_weighted
+    _check(fn(_ptr(a), dt, _ptr(w), _ptr(m) if m is not None else None, H, W, C, bins, bits, _ptr(out)),
+           "ih_weighted")
     return out
 
 

@@ -554,6 +554,77 @@ int or_match_direct(const void *img, int dtype, int H, int W, int C, int bins,
   return OR_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Weighted integral histogram (Alg. 2, step 4: the gradient-magnitude        */
+/* weighted integral histogram of gradient orientation over edges).  The      */
+/* indicator Q of Eq. 2.15 is replaced by the pixel's weight when its bin is  */
+/* k and its mask is set:                                                    */
+/*   G(k,x,y) = G(k,x-1,y) + G(k,x,y-1) - G(k,x-1,y-1)                        */
+/*              + wt(x,y) * [mask(x,y) != 0] * Q(k, I(x,y)),                  */
+/* with the weight and mask of the plane's channel (u8, C x H x W; mask NULL  */
+/* means every pixel).  int64 accumulation, range-checked into int32.        */
+/* ------------------------------------------------------------------------ */
+static int64_t or_wq(const void *img, int dtype, const uint8_t *wt, const uint8_t *mask,
+                     int H, int W, int bins, int bits, int p, int r, int c) {
+  int ch = p / bins;
+  int64_t i = ((int64_t)ch * H + r) * W + c;
+  if (mask && mask[i] == 0) return 0;
+  return or_Q(img, dtype, H, W, bins, bits, p, r, c) ? (int64_t)wt[i] : 0;
+}
+
+int or_ih_weighted(const void *img, int dtype, const uint8_t *wt, const uint8_t *mask,
+                   int H, int W, int C, int bins, int bits, int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (!wt) return OR_ERR_ARG;
+  int P = C * bins, rc = OR_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int p = 0; p < P; p++) {
+    int64_t *prev = (int64_t *)calloc((size_t)W, sizeof(int64_t));
+    int64_t *cur = (int64_t *)calloc((size_t)W, sizeof(int64_t));
+    int32_t *o = out + (int64_t)p * H * W;
+    int r = OR_OK;
+    if (!prev || !cur) r = OR_ERR_ARG;
+    for (int x = 0; x < H && !r; x++) {
+      for (int y = 0; y < W; y++) {
+        int64_t up = prev[y];
+        int64_t left = (y > 0) ? cur[y - 1] : 0;
+        int64_t diag = (y > 0) ? prev[y - 1] : 0;
+        cur[y] = up + left - diag + or_wq(img, dtype, wt, mask, H, W, bins, bits, p, x, y);
+        if (cur[y] > INT32_MAX) r = OR_ERR_OVERFLOW;
+        o[(int64_t)x * W + y] = (int32_t)cur[y];
+      }
+      int64_t *t = prev; prev = cur; cur = t;
+    }
+    free(prev);
+    free(cur);
+    if (r) {
+#pragma omp critical
+      rc = r;
+    }
+  }
+  return rc;
+}
+
+/* The same by the defining double sum, O(H^2 W^2) per plane (tiny inputs). */
+int or_ih_weighted_bruteforce(const void *img, int dtype, const uint8_t *wt,
+                              const uint8_t *mask, int H, int W, int C, int bins,
+                              int bits, int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (!wt) return OR_ERR_ARG;
+  for (int p = 0; p < C * bins; p++)
+    for (int x = 0; x < H; x++)
+      for (int y = 0; y < W; y++) {
+        int64_t s = 0;
+        for (int a = 0; a <= x; a++)
+          for (int b = 0; b <= y; b++) s += or_wq(img, dtype, wt, mask, H, W, bins, bits, p, a, b);
+        if (s > INT32_MAX) return OR_ERR_OVERFLOW;
+        out[((int64_t)p * H + x) * W + y] = (int32_t)s;
+      }
+  return OR_OK;
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
