@@ -60,6 +60,8 @@ def parse():
                     help="run only the other workloads and print their JSON object (for profiling)")
     ap.add_argument("--tracker-only", action="store_true",
                     help="run only the tracker workload and print its JSON object (for profiling)")
+    ap.add_argument("--phog-only", action="store_true",
+                    help="run only the magnitude-weighted orientation histogram and print its JSON object")
     ap.add_argument("--train-videos", type=int, default=800)
     ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--tile", type=str, default="",
@@ -169,6 +171,82 @@ FIXED_TILES = {"640x480": (16, 16, 64), "8192x8192": (128, 64, 64), "batch_hwb":
                "batch_bhw": (64, 128, 1)}
 
 
+def phog_leg(torch, ih, synth):
+    """Magnitude-weighted orientation integral histogram (Alg. 2 step 4) of
+    the 1920x1080 scene: gradient orientation in 16 bins, gradient magnitude
+    as the weight, edge pixels only.  Whole build (graph-replayed, median of
+    trials) and the write-out kernel alone (library events around its
+    launch), both layouts with their default tiles, checked against the
+    count build for the same frame."""
+    dev = torch.device("cuda:0")
+    go, gm, edge = synth.phog_inputs()
+    img, wt, mask = (torch.from_numpy(a).to(dev) for a in (go, gm, edge))
+    H, W, bins = go.shape[1], go.shape[2], 16
+    P = bins
+    alg = P * H * W * 4 + 3 * H * W
+    res = {"workload": "1920x1080 gradient orientation, 16 bins, magnitude-weighted over edge pixels",
+           "edge_fraction": round(float((edge != 0).mean()), 4), "algorithmic_bytes": alg, "layouts": {}}
+    for layout in ("bhw", "hwb"):
+        out = torch.empty(ih.shape_of(P, H, W, layout), dtype=torch.int32, device=dev)
+        ws = torch.empty(ih.workspace_size(H, W, 1, bins, False, None, layout), dtype=torch.uint8, device=dev)
+
+        def wbuild():
+            ih.ih_build_weighted(img, bins, wt, mask, out=out, ws=ws, layout=layout)
+
+        def cbuild():
+            ih.ih_build(img, bins, out=out, ws=ws, layout=layout)
+
+        wbuild()
+        torch.cuda.synchronize()
+        ref = out.clone()
+        tw = graph_median(torch, wbuild, 20, per=20)
+        same = bool(torch.equal(out, ref))
+        tc = graph_median(torch, cbuild, 20, per=20)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+        for a, b in ev:
+            a.record()
+            b.record()
+        torch.cuda.synchronize()
+        for a, b in ev:
+            ih.ih_profile_events(a, b)
+            wbuild()
+        torch.cuda.synchronize()
+        ih.ih_profile_events(None, None)
+        k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        res["layouts"][layout] = {"build_ms": round(tw, 4), "build_gbs": round(alg / tw / 1e6, 1),
+                                  "writeout_ms": round(k_ms, 4),
+                                  "writeout_gbs": round(P * H * W * 4 / k_ms / 1e6, 1),
+                                  "writeout_frac_of_peak": round(P * H * W * 4 / k_ms / 1e6 / HBM_PEAK_GBS, 4),
+                                  "count_build_ms": round(tc, 4), "replays_match_eager": same}
+        del out, ws
+    return res
+
+
+def copy_calibration(torch, mib):
+    """One device fill and one device-to-device copy of `mib` MiB: the copy
+    kernel's FETCH_SIZE and WRITE_SIZE against its known bytes give the
+    counters' scale."""
+    n = mib << 20
+    a = torch.empty(n // 4, dtype=torch.int32, device="cuda:0")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def graph_median(torch, fn, n=10, trials=3, per=1):
+    """Median over trials of the device time per call: `per` calls captured in
+    one HIP graph, replayed n times per trial (no host launch cost)."""
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(per):
+            fn()
+    return float(np.median([time_calls(torch, g.replay, n) for _ in range(trials)])) / per
+
+
 def config_legs(torch, ih, synth, fixed=False):
     """The other benchmark workloads, each timed on the device (median of
     repeated calls): 640x480 u8 with 32 bins and 10,000 rectangles; the
@@ -183,15 +261,7 @@ def config_legs(torch, ih, synth, fixed=False):
     res = {}
 
     def med(fn, n=10, trials=3, per=1):
-        """Median over trials of the device time per call: `per` calls captured
-        in one HIP graph, replayed n times per trial (no host launch cost)."""
-        fn()
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            for _ in range(per):
-                fn()
-        return float(np.median([time_calls(torch, g.replay, n) for _ in range(trials)])) / per
+        return graph_median(torch, fn, n, trials, per)
 
     # 640x480, 32 bins, 10k rectangles
     w = synth.config1()
@@ -209,6 +279,9 @@ def config_legs(torch, ih, synth, fixed=False):
                                 "rect_ms": round(tq, 4), "rect_queries_per_s": round(rects.shape[0] / tq * 1e3, 1),
                                 "tile": repr(cfg)}
     del out, ws, q
+
+    # magnitude-weighted orientation histogram of the 1920x1080 scene
+    res["phog_1920x1080_16bins"] = phog_leg(torch, ih, synth)
 
     # 8192x8192 u16, 64 bins, 1M rectangles, 129x129 search
     w = synth.config3()
@@ -454,6 +527,12 @@ def main():
     if args.workloads_only:
         print(json.dumps(config_legs(torch, ih, synth, args.fixed_tiles)), flush=True)
         return
+    if args.phog_only:
+        res = phog_leg(torch, ih, synth)
+        if args.copy_calib:
+            copy_calibration(torch, args.copy_calib)
+        print(json.dumps(res), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     w = synth.config2()
@@ -554,13 +633,7 @@ def main():
         del so
 
     if args.copy_calib:
-        n = args.copy_calib << 20
-        a = torch.empty(n // 4, dtype=torch.int32, device=dev)
-        a.fill_(1)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
+        copy_calibration(torch, args.copy_calib)
 
     alg_bytes = 3 * P * H * W * 4 + C * H * W   # three int32 tensors written, u8 image read
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9

@@ -135,6 +135,32 @@ int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C,
              void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * ih_build_weighted - weighted integral histogram: the plane-p entry sums a
+ * per-pixel weight instead of counting (Alg. 2 step 4, the PHoG building
+ * block: gradient orientation binned, gradient magnitude as the weight, edge
+ * pixels only):
+ *   G(p,r,c) = sum over r' <= r, c' <= c of
+ *              wt(ch,r',c') * [mask(ch,r',c') != 0] * [bin(ch,r',c') = p]
+ * with ch = p / bins.  Same tiles, passes and layouts as ih_build.
+ *
+ *   img, dtype, H, W, C, bins, value_bits, layout, cfg, ws, ws_bytes,
+ *   stream      as for ih_build (the workspace size is that of ih_build
+ *               without moments: ih_build_workspace_size(..., 0, ...)).
+ *   weight      device, C x H x W uint8 weights (not NULL).
+ *   mask        device, C x H x W uint8, or NULL: a pixel whose mask byte is
+ *               0 contributes nothing; NULL means every pixel contributes.
+ *   ih          device, out: P x H x W int32 (in layout).
+ * Needs H * W * 255 <= 2^31 - 1 (IH_ERR_OVERFLOW otherwise), so no sum can
+ * overflow.  Returns IH_OK or IH_ERR_*.  Outputs must not overlap the inputs
+ * or ws.
+ */
+int ih_build_weighted(const void *img, int32_t dtype, const uint8_t *weight,
+                      const uint8_t *mask, int32_t H, int32_t W, int32_t C,
+                      int32_t bins, int32_t value_bits, int32_t layout,
+                      int32_t *ih, const ih_tile_cfg *cfg, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/*
  * ih_query_rect - region histograms by four corner lookups (Eq. 2.16):
  *   h(R, p) = H(r1-1, c1-1) - H(r0-1, c1-1) - H(r1-1, c0-1) + H(r0-1, c0-1)
  * with H(-1, .) = H(., -1) = 0.

@@ -11,6 +11,7 @@ from .ih import (  # noqa: F401
     TileCfg,
     cells,
     ih_build,
+    ih_build_weighted,
     ih_match_candidates,
     ih_profile_events,
     ih_pyramid_desc,

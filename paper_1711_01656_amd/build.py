@@ -33,10 +33,7 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source (always, even when a library exists)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] + sources()
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -45,6 +42,26 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed (%d):\n%s" % (res.returncode, "\n".join(msgs)))
     if verbose and msgs:
         print("\n".join(msgs))
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every HIP source (always, even when a library exists): one
+    object per source, compiled in parallel, then linked into libih.so."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
+    tmp = LIB + ".tmp%d" % os.getpid()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    cflags = [f for f in FLAGS if f != "-shared"]
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
+    with tempfile.TemporaryDirectory(prefix="ihbuild") as d:
+        objs = [os.path.join(d, os.path.basename(s) + ".o") for s in srcs]
+        with ThreadPoolExecutor(jobs) as ex:
+            for f in [ex.submit(_run, [HIPCC] + cflags + inc + ["-c", s, "-o", o], verbose)
+                      for s, o in zip(srcs, objs)]:
+                f.result()
+        _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -25,6 +25,6 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace ih
 
-extern "C" int ih_version(void) { return 101; }
+extern "C" int ih_version(void) { return 102; }
 
 extern "C" const char *ih_last_error(void) { return ih::g_err; }

@@ -35,7 +35,7 @@ static size_t align64(size_t w) { return (w + 63) & ~(size_t)63; }
 
 int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds) {
   const int twp = g.TW + 4;
-  const size_t stage = ((size_t)g.TH * twp + 3) & ~(size_t)3;
+  const size_t stage = ((size_t)g.TH * twp * (g.wgt ? 2 : 1) + 3) & ~(size_t)3;
   const int span = g.TH > g.TW ? g.TH : g.TW;
   const int arrays = g.mom ? 2 : 1;
   long words = ((long)lds_budget - (long)stage) / 4;
@@ -48,7 +48,7 @@ int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds) {
 }
 
 int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, int32_t layout,
-              const ih_tile_cfg *cfg, Geom *g) {
+              const ih_tile_cfg *cfg, Geom *g, int32_t weighted) {
   if (H < 1 || W < 1 || C < 1)
     return set_error(IH_ERR_INVALID_ARG, "image shape %dx%dx%d must be positive", C, H, W);
   if ((int64_t)H * W >= ((int64_t)1 << 31))
@@ -59,6 +59,8 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
   if (layout != IH_BHW && layout != IH_HWB) return set_error(IH_ERR_INVALID_ARG, "layout %d unknown", layout);
   g->H = H; g->W = W; g->C = C; g->bins = bins; g->P = C * bins;
   g->mom = moments != 0;
+  g->wgt = weighted != 0;
+  if (g->mom && g->wgt) return set_error(IH_ERR_UNSUPPORTED, "moments of a weighted histogram are not built");
   g->layout = layout;
   int TH, TW, PG;
   if (cfg) {
@@ -81,7 +83,9 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
     // defaults from device sweeps: small outputs favour short tiles (more
     // waves), wide frames favour 256-column tiles with 16-byte stores
     const int64_t out_bytes = (int64_t)g->P * H * W * 4 * (g->mom ? 3 : 1);
-    if (out_bytes < ((int64_t)128 << 20)) { TH = 16; TW = 64; PG = 2; }
+    if (out_bytes < ((int64_t)64 << 20)) { TH = 16; TW = 64; PG = 2; }
+    else if (g->P <= 32 && out_bytes < ((int64_t)1 << 30)) { TH = 32; TW = 64; PG = 2; }
+    else if (out_bytes < ((int64_t)128 << 20)) { TH = 16; TW = 64; PG = 2; }
     else if (W >= 4096) { TH = 128; TW = 256; PG = g->mom ? 8 : 8; }
     else { TH = 64; TW = 64; PG = 1; }
     while (PG > 1 && PG > bins) PG >>= 1;
@@ -121,9 +125,10 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
 // ------------------------------------------------------ stand-alone kernels --
 template <typename T>
 __global__ __launch_bounds__(256) void k_tile_hist(const T *__restrict__ img, Geom g, int bits, int bc,
-                                                   uint32_t *__restrict__ ws) {
+                                                   uint32_t *__restrict__ ws, const uint8_t *__restrict__ wt,
+                                                   const uint8_t *__restrict__ mask) {
   extern __shared__ uint32_t lds[];
-  tile_hist_body<T>(img, g, bits, bc, ws, blockIdx.x, lds);
+  tile_hist_body<T>(img, g, bits, bc, ws, blockIdx.x, lds, wt, mask);
 }
 
 __global__ __launch_bounds__(256) void k_carry_scan(Geom g, int64_t nblk_a, int64_t nblk_b,
@@ -131,20 +136,20 @@ __global__ __launch_bounds__(256) void k_carry_scan(Geom g, int64_t nblk_a, int6
   carry_scan_body(g, nblk_a, nblk_b, ws, blockIdx.x);
 }
 
-template <typename T, int CPL, int PG, bool MOM>
+template <typename T, int CPL, int PG, bool MOM, bool WGT>
 __global__ __launch_bounds__(256) void k_final(FinalArgs a, Geom g) {
-  final_body<T, CPL, PG, MOM>(a, g, blockIdx.x, blockIdx.y, uniform(threadIdx.x >> 6), blockDim.x >> 6);
+  final_body<T, CPL, PG, MOM, WGT>(a, g, blockIdx.x, blockIdx.y, uniform(threadIdx.x >> 6), blockDim.x >> 6);
 }
 
-template <typename T, int TW, bool MOM>
+template <typename T, int TW, bool MOM, bool WGT>
 __global__ __launch_bounds__(256) void k_final_hwb(FinalArgs a, Geom g) {
-  final_hwb_body<T, TW, MOM>(a, g, (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform(threadIdx.x >> 6));
+  final_hwb_body<T, TW, MOM, WGT>(a, g, (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform(threadIdx.x >> 6));
 }
 
-template <typename T, int TW, bool MOM>
+template <typename T, int TW, bool MOM, bool WGT>
 __global__ __launch_bounds__(512) void k_final_hwb_staged(FinalArgs a, Geom g) {
   extern __shared__ uint32_t seg[];
-  final_hwb_staged_body<T, TW, MOM>(a, g, blockIdx.x, seg);
+  final_hwb_staged_body<T, TW, MOM, WGT>(a, g, blockIdx.x, seg);
 }
 
 // LDS bytes of one staged row segment (all arrays), or 0 when staging does not apply.
@@ -167,10 +172,10 @@ static thread_local ProfileHook g_hook;
 
 typedef void (*final_fn)(FinalArgs, Geom);
 
-template <typename T, bool MOM>
+template <typename T, bool MOM, bool WGT = false>
 static final_fn pick_final_t(int CPL, int PG) {
 #define IH_F(C_, G_) \
-  if (CPL == C_ && PG == G_) return &k_final<T, C_, G_, MOM>;
+  if (CPL == C_ && PG == G_) return &k_final<T, C_, G_, MOM, WGT>;
   if constexpr (MOM) {
     IH_F(1, 1) IH_F(1, 2) IH_F(1, 4) IH_F(1, 8) IH_F(1, 16)
     IH_F(2, 1) IH_F(2, 2) IH_F(2, 4) IH_F(2, 8) IH_F(2, 16)
@@ -184,26 +189,33 @@ static final_fn pick_final_t(int CPL, int PG) {
   return nullptr;
 }
 
-template <typename T, bool MOM>
+template <typename T, bool MOM, bool WGT = false>
 static final_fn pick_hwb_t(int TW, bool staged) {
   if (staged) {
-    if (TW == 16) return &k_final_hwb_staged<T, 16, MOM>;
+    if (TW == 16) return &k_final_hwb_staged<T, 16, MOM, WGT>;
     if constexpr (!MOM) {
-      if (TW == 32) return &k_final_hwb_staged<T, 32, MOM>;
-      if (TW == 64) return &k_final_hwb_staged<T, 64, MOM>;
+      if (TW == 32) return &k_final_hwb_staged<T, 32, MOM, WGT>;
+      if (TW == 64) return &k_final_hwb_staged<T, 64, MOM, WGT>;
     }
     return nullptr;
   }
-  if (TW == 16) return &k_final_hwb<T, 16, MOM>;
-  if (TW == 32) return &k_final_hwb<T, 32, MOM>;
+  if (TW == 16) return &k_final_hwb<T, 16, MOM, WGT>;
+  if (TW == 32) return &k_final_hwb<T, 32, MOM, WGT>;
   if constexpr (!MOM) {
-    if (TW == 64) return &k_final_hwb<T, 64, MOM>;
+    if (TW == 64) return &k_final_hwb<T, 64, MOM, WGT>;
   }
   return nullptr;
 }
 
 static final_fn pick_final(int dtype, const Geom &g) {
   const bool u8 = dtype == IH_U8;
+  if (g.wgt) {
+    if (g.layout == IH_HWB) {
+      const bool st = staged_lds(g) > 0;
+      return u8 ? pick_hwb_t<uint8_t, false, true>(g.TW, st) : pick_hwb_t<uint16_t, false, true>(g.TW, st);
+    }
+    return u8 ? pick_final_t<uint8_t, false, true>(g.CPL, g.PG) : pick_final_t<uint16_t, false, true>(g.CPL, g.PG);
+  }
   if (g.layout == IH_HWB) {
     const bool st = staged_lds(g) > 0;
     if (u8) return g.mom ? pick_hwb_t<uint8_t, true>(g.TW, st) : pick_hwb_t<uint8_t, false>(g.TW, st);
@@ -232,9 +244,10 @@ extern "C" int ih_profile_events(void *start, void *stop) {
   return IH_OK;
 }
 
-extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C, int32_t bins,
-                        int32_t value_bits, int32_t layout, int32_t *ih, uint32_t *mom_x, uint32_t *mom_y,
-                        const ih_tile_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
+static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const uint8_t *mask, int32_t H,
+                      int32_t W, int32_t C, int32_t bins, int32_t value_bits, int32_t layout, int32_t *ih,
+                      uint32_t *mom_x, uint32_t *mom_y, const ih_tile_cfg *cfg, void *ws, size_t ws_bytes,
+                      void *stream) {
   if (!img || !ih) return set_error(IH_ERR_INVALID_ARG, "img and ih must be non-NULL");
   if ((mom_x == nullptr) != (mom_y == nullptr))
     return set_error(IH_ERR_INVALID_ARG, "mom_x and mom_y must be both NULL or both set");
@@ -245,7 +258,7 @@ extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, in
   if (bins > (1 << value_bits)) return set_error(IH_ERR_INVALID_ARG, "bins %d exceed 2^value_bits", bins);
   const bool mom = mom_x != nullptr;
   Geom g;
-  int e = make_geom(H, W, C, bins, mom, layout, cfg, &g);
+  int e = make_geom(H, W, C, bins, mom, layout, cfg, &g, wt != nullptr);
   if (e) return e;
   if (!ws || ws_bytes < g.words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.words * 4,
@@ -262,10 +275,10 @@ extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, in
   const unsigned tiles = (unsigned)((int64_t)g.nTR * g.nTC * C);
   if (dtype == IH_U8)
     hipLaunchKernelGGL(k_tile_hist<uint8_t>, dim3(tiles), dim3(256), lds, s,
-                       reinterpret_cast<const uint8_t *>(img), g, value_bits, bc, w32);
+                       reinterpret_cast<const uint8_t *>(img), g, value_bits, bc, w32, wt, mask);
   else
     hipLaunchKernelGGL(k_tile_hist<uint16_t>, dim3(tiles), dim3(256), lds, s,
-                       reinterpret_cast<const uint16_t *>(img), g, value_bits, bc, w32);
+                       reinterpret_cast<const uint16_t *>(img), g, value_bits, bc, w32, wt, mask);
   if ((e = hip_check(hipGetLastError(), "tile_hist launch"))) return e;
 
   const int64_t nA = ((int64_t)g.P * W + 255) / 256;
@@ -275,7 +288,7 @@ extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, in
   if ((e = hip_check(hipGetLastError(), "carry_scan launch"))) return e;
 
   const bool aligned = ((uintptr_t)ih % 16 == 0) && ((uintptr_t)mom_x % 16 == 0) && ((uintptr_t)mom_y % 16 == 0);
-  FinalArgs fa{img, ih, mom_x, mom_y, w32, value_bits, (W % g.CPL == 0 && aligned) ? 1 : 0};
+  FinalArgs fa{img, ih, mom_x, mom_y, w32, value_bits, (W % g.CPL == 0 && aligned) ? 1 : 0, wt, mask};
   dim3 grid, block;
   if (layout == IH_BHW) {
     const int groups = (bins + g.PG - 1) / g.PG;
@@ -295,4 +308,22 @@ extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, in
   if ((e = hip_check(hipGetLastError(), "final launch"))) return e;
   if (g_hook.stop && (e = hip_check(hipEventRecord(g_hook.stop, s), "profile stop"))) return e;
   return IH_OK;
+}
+
+extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C, int32_t bins,
+                        int32_t value_bits, int32_t layout, int32_t *ih, uint32_t *mom_x, uint32_t *mom_y,
+                        const ih_tile_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
+  return build_impl(img, dtype, nullptr, nullptr, H, W, C, bins, value_bits, layout, ih, mom_x, mom_y, cfg, ws,
+                    ws_bytes, stream);
+}
+
+extern "C" int ih_build_weighted(const void *img, int32_t dtype, const uint8_t *weight, const uint8_t *mask,
+                                 int32_t H, int32_t W, int32_t C, int32_t bins, int32_t value_bits,
+                                 int32_t layout, int32_t *ih, const ih_tile_cfg *cfg, void *ws, size_t ws_bytes,
+                                 void *stream) {
+  if (!weight) return set_error(IH_ERR_INVALID_ARG, "weight must be non-NULL");
+  if (H >= 1 && W >= 1 && (int64_t)H * W * 255 > (int64_t)INT32_MAX)
+    return set_error(IH_ERR_OVERFLOW, "H*W*255 = %lld may overflow int32 sums", (long long)H * W * 255);
+  return build_impl(img, dtype, weight, mask, H, W, C, bins, value_bits, layout, ih, nullptr, nullptr, cfg, ws,
+                    ws_bytes, stream);
 }

@@ -22,13 +22,18 @@ __host__ __device__ __forceinline__ int64_t cc_index(const Geom &g, int64_t p, i
 //    RC  [ch][j][r][bin]  plane count of row r over the tile's columns
 //    TT  [p][I][j]        tile totals
 //    CCX (sum of rows), RCY (sum of columns), TTX, TTY for the moments.
+//    With weights (g.wgt) every "count" above is the sum of the pixels'
+//    weights, wt where the mask is set (or there is no mask), else 0.
 // --------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const Geom &g, int bits, int bc,
-                                               uint32_t *__restrict__ ws, int blkid, uint32_t *lds) {
+                                               uint32_t *__restrict__ ws, int blkid, uint32_t *lds,
+                                               const uint8_t *__restrict__ wt = nullptr,
+                                               const uint8_t *__restrict__ mask = nullptr) {
   const int twp = g.TW + 4;
   uint8_t *bin_s = reinterpret_cast<uint8_t *>(lds);
-  uint32_t *hist = lds + (((size_t)g.TH * twp + 3) >> 2);
+  uint8_t *wt_s = bin_s + (size_t)g.TH * twp;  // weights (weighted build only)
+  uint32_t *hist = lds + (((size_t)g.TH * twp * (g.wgt ? 2 : 1) + 3) >> 2);
   const int tid = threadIdx.x;
   int blk = blkid;
   const int j = blk % g.nTC; blk /= g.nTC;
@@ -40,8 +45,13 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
 
   for (int idx = tid; idx < th * tw; idx += 256) {
     const int r = idx / tw, c = idx - r * tw;
-    const uint32_t v = src[(int64_t)(R0 + r) * g.W + C0 + c];
+    const int64_t i = (int64_t)(R0 + r) * g.W + C0 + c;
+    const uint32_t v = src[i];
     bin_s[r * twp + c] = (uint8_t)(((uint64_t)v * g.bins) >> bits);
+    if (g.wgt) {
+      const int64_t iw = (int64_t)ch * g.H * g.W + i;
+      wt_s[r * twp + c] = (mask && mask[iw] == 0) ? (uint8_t)0 : wt[iw];
+    }
   }
   uint32_t *CC = ws + g.off_cc, *RC = ws + g.off_rc, *TT = ws + g.off_tt;
   uint32_t *CCX = ws + g.off_ccx, *RCY = ws + g.off_rcy;
@@ -60,8 +70,9 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       const int cl = idx % tw, seg = idx / tw;
       for (int r = seg; r < th; r += nseg) {
         const int b = (int)bin_s[r * twp + cl] - b0;
-        if (b >= 0 && b < nb) {
-          atomicAdd(&hist[cl * stride + b], 1u);
+        const uint32_t w = g.wgt ? (uint32_t)wt_s[r * twp + cl] : 1u;
+        if (b >= 0 && b < nb && w) {
+          atomicAdd(&hist[cl * stride + b], w);
           if (g.mom) atomicAdd(&hist[colw + cl * stride + b], (uint32_t)(R0 + r));
         }
       }
@@ -75,17 +86,33 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       CC[o] = hist[cl * stride + k];
       if (g.mom) CCX[o] = hist[colw + cl * stride + k];
     }
-    for (int k = tid; k < nb; k += 256) {
+    // tile totals: 16 threads per bin sum every 16th column, then combine
+    // across those 16 lanes (the loop bound is uniform, so whole waves shuffle)
+    for (int base = 0; base < nb * 16; base += 256) {
+      const int i = base + tid;
+      const int k = i >> 4, part = i & 15;
       uint32_t s = 0, sx = 0, sy = 0;
-      for (int cl = 0; cl < tw; ++cl) {
-        const uint32_t n = hist[cl * stride + k];
-        s += n;
-        if (g.mom) { sx += hist[colw + cl * stride + k]; sy += n * (uint32_t)(C0 + cl); }
+      if (k < nb) {
+        for (int cl = part; cl < tw; cl += 16) {
+          const uint32_t n = hist[cl * stride + k];
+          s += n;
+          if (g.mom) { sx += hist[colw + cl * stride + k]; sy += n * (uint32_t)(C0 + cl); }
+        }
       }
-      const size_t p = (size_t)ch * g.bins + b0 + k;
-      const size_t o = (p * g.nTR + I) * (size_t)g.nTC + j;
-      TT[o] = s;
-      if (g.mom) { TTX[o] = sx; TTY[o] = sy; }
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        s += (uint32_t)__shfl_xor((int)s, off, 16);
+        if (g.mom) {
+          sx += (uint32_t)__shfl_xor((int)sx, off, 16);
+          sy += (uint32_t)__shfl_xor((int)sy, off, 16);
+        }
+      }
+      if (k < nb && part == 0) {
+        const size_t p = (size_t)ch * g.bins + b0 + k;
+        const size_t o = (p * g.nTR + I) * (size_t)g.nTC + j;
+        TT[o] = s;
+        if (g.mom) { TTX[o] = sx; TTY[o] = sy; }
+      }
     }
     // ---- rows: each thread owns a row, columns split over segments
     const int rseg = g.TH >= 256 ? 1 : 256 / g.TH;
@@ -97,8 +124,9 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       const int r = idx % th, seg = idx / th;
       for (int cl = seg; cl < tw; cl += rseg) {
         const int b = (int)bin_s[r * twp + cl] - b0;
-        if (b >= 0 && b < nb) {
-          atomicAdd(&hist[r * stride + b], 1u);
+        const uint32_t w = g.wgt ? (uint32_t)wt_s[r * twp + cl] : 1u;
+        if (b >= 0 && b < nb && w) {
+          atomicAdd(&hist[r * stride + b], w);
           if (g.mom) atomicAdd(&hist[roww + r * stride + b], (uint32_t)(C0 + cl));
         }
       }
@@ -184,7 +212,24 @@ struct FinalArgs {
   const uint32_t *ws;
   int bits;
   int vec_ok;  // bin-major: W divisible by CPL and the outputs 16-byte aligned
+  const uint8_t *wt, *mask;  // weighted build: C x H x W weights, optional mask
 };
+
+// Weight of pixel (r, c) of channel ch in the weighted build: wt where the
+// mask is set (or there is no mask), else 0.
+__device__ __forceinline__ uint32_t pixel_weight(const FinalArgs &a, const Geom &g, int ch, int r, int c) {
+  const int64_t i = ((int64_t)ch * g.H + r) * g.W + c;
+  return (a.mask && a.mask[i] == 0) ? 0u : (uint32_t)a.wt[i];
+}
+
+// Four weights packed in a word (byte q = column c0 + q) from the weight and
+// mask words of the same four pixels.
+__device__ __forceinline__ uint32_t masked_weights(uint32_t w, uint32_t m) {
+  uint32_t keep = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) keep |= ((m >> (8 * q)) & 0xffu) ? (0xffu << (8 * q)) : 0u;
+  return w & keep;
+}
 
 template <int CPL>
 __device__ __forceinline__ void put(int32_t *dst, const uint32_t (&v)[CPL], int cf, int W, bool vec_ok) {
@@ -200,7 +245,7 @@ __device__ __forceinline__ void put(int32_t *dst, const uint32_t (&v)[CPL], int 
   }
 }
 
-template <typename T, int CPL, int PG, bool MOM>
+template <typename T, int CPL, int PG, bool MOM, bool WGT = false>
 __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, int bx, int by, int wave, int wpb) {
   const int lane = threadIdx.x & 63;
   const int grp = by * wpb + wave;
@@ -264,10 +309,14 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 
   // the next row's pixels and row carries are loaded while this row is
   // written (software pipelining hides their latency)
-  uint32_t px[CPL], lcv[PG], lcyv[MOM ? PG : 1];
+  uint32_t px[CPL], lcv[PG], lcyv[MOM ? PG : 1], pw[WGT ? CPL : 1];
   auto fetch = [&](int r) {
 #pragma unroll
     for (int e = 0; e < CPL; ++e) px[e] = cf + e < g.W ? (uint32_t)img[(int64_t)r * g.W + cf + e] : 0u;
+    if constexpr (WGT) {
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) pw[e] = cf + e < g.W ? pixel_weight(a, g, ch, r, cf + e) : 0u;
+    }
     const uint32_t *lc = lc_base + (int64_t)r * g.bins;
 #pragma unroll
     for (int k = 0; k < PG; ++k) lcv[k] = k < nk ? lc[k] : 0u;
@@ -284,9 +333,13 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 #pragma unroll
     for (int e = 0; e < CPL; ++e)
       b[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
-    uint32_t lcur[PG], lycur[MOM ? PG : 1];
+    uint32_t lcur[PG], lycur[MOM ? PG : 1], wcur[WGT ? CPL : 1];
 #pragma unroll
     for (int k = 0; k < PG; ++k) lcur[k] = lcv[k];
+    if constexpr (WGT) {
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) wcur[e] = pw[e];
+    }
     if constexpr (MOM) {
 #pragma unroll
       for (int k = 0; k < PG; ++k) lycur[k] = lcyv[k];
@@ -295,7 +348,19 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
     const int64_t orow = (int64_t)r * g.W;
 #pragma unroll
     for (int k = 0; k < PG; ++k) {
-      if (k < nk) {
+      if constexpr (WGT) {
+        if (k < nk) {
+          // weighted row prefix: the lane's own running sum plus a wave scan
+          // of the lanes' totals
+          uint32_t sw[CPL];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) sw[e] = (e ? sw[e - 1] : 0u) + (b[e] == k ? wcur[e] : 0u);
+          const uint32_t t0 = wave_incl_scan(sw[CPL - 1]) - sw[CPL - 1] + lcur[k];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) col[k][e] += t0 + sw[e];
+          put<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec_ok);
+        }
+      } else if (k < nk) {
         uint32_t t = lcur[k];
         uint64_t m[CPL];
 #pragma unroll
@@ -347,7 +412,36 @@ __device__ __forceinline__ void hwb_store(int v, int32_t *dst) {
 #endif
 }
 
-template <typename T, int TW, bool MOM>
+// Whether the weight (and mask) row segment of a full tile can be read as
+// 32-bit words: 4 weights per word.
+__device__ __forceinline__ bool weight_words(const FinalArgs &a, const Geom &g, int C0) {
+  return ((((uintptr_t)a.wt | (uintptr_t)a.mask) & 3) == 0) && (g.W & 3) == 0 && (C0 & 3) == 0;
+}
+
+// Loads the TW/4 masked weight words of row r, columns C0 .. C0+TW-1.
+template <int TW>
+__device__ __forceinline__ void load_weight_words(const FinalArgs &a, const Geom &g, int ch, int r, int C0,
+                                                  uint32_t (&wq)[TW / 4]) {
+  const int64_t i = ((int64_t)ch * g.H + r) * g.W + C0;
+  const uint32_t *wp = reinterpret_cast<const uint32_t *>(a.wt + i);
+  if (a.mask) {
+    const uint32_t *mp = reinterpret_cast<const uint32_t *>(a.mask + i);
+#pragma unroll
+    for (int q = 0; q < TW / 4; ++q) wq[q] = masked_weights(wp[q], mp[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < TW / 4; ++q) wq[q] = wp[q];
+  }
+}
+
+// Weight of column c from the packed words (1 for the unweighted build).
+template <bool WGT, int N>
+__device__ __forceinline__ uint32_t weight_byte(const uint32_t (&wq)[N], int c) {
+  if constexpr (WGT) return (wq[c >> 2] >> (8 * (c & 3))) & 0xffu;
+  else return 1u;
+}
+
+template <typename T, int TW, bool MOM, bool WGT = false>
 __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g, int64_t unit) {
   const int lane = threadIdx.x & 63;
   const int nchunk = (g.P + 63) >> 6;
@@ -401,7 +495,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
   // starts on a 4-byte boundary.
   const bool full = cols == TW;
   const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
-                     ((int64_t)C0 * sizeof(T)) % 4 == 0;
+                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (!WGT || weight_words(a, g, C0));
   constexpr int PER = 4 / (int)sizeof(T);  // pixels per 32-bit word
   auto row_step = [&](auto FULL, int rr) {
     constexpr bool F = decltype(FULL)::value;
@@ -416,8 +510,8 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
     int32_t *dih = a.ih + rbase + p;
     int32_t *dmx = reinterpret_cast<int32_t *>(a.mx) + rbase + p;
     int32_t *dmy = reinterpret_cast<int32_t *>(a.my) + rbase + p;
-    auto pixel = [&](int c, uint32_t val) {
-      const uint32_t hit = (val - lo) < width ? 1u : 0u;
+    auto pixel = [&](int c, uint32_t val, uint32_t w) {
+      const uint32_t hit = (val - lo) < width ? w : 0u;
       const int64_t cw = (int64_t)c * P;
       rc += hit;
       col[c] += rc;
@@ -435,13 +529,16 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(row);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
+      uint32_t wq[WGT ? TW / 4 : 1];
+      if constexpr (WGT) load_weight_words<TW>(a, g, ch, r, C0, wq);
 #pragma unroll
       for (int c = 0; c < TW; ++c)
-        pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u));
+        pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u),
+              weight_byte<WGT>(wq, c));
     } else {
 #pragma unroll
       for (int c = 0; c < TW; ++c)
-        if (F || c < cols) pixel(c, (uint32_t)row[c]);
+        if (F || c < cols) pixel(c, (uint32_t)row[c], WGT ? pixel_weight(a, g, ch, r, C0 + c) : 1u);
     }
   };
   if (full) {
@@ -546,7 +643,7 @@ __device__ __forceinline__ void final_hwb_wave_staged_body(const FinalArgs &a, c
   }
 }
 
-template <typename T, int TW, bool MOM>
+template <typename T, int TW, bool MOM, bool WGT = false>
 __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const Geom &g, int64_t tile,
                                                       uint32_t *lds) {
   const int lane = threadIdx.x & 63;
@@ -593,7 +690,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
   const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
   const bool full = cols == TW;
   const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
-                     ((int64_t)C0 * sizeof(T)) % 4 == 0;
+                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (!WGT || weight_words(a, g, C0));
   const bool vec = (g.P & 3) == 0 && (((uintptr_t)a.ih | (uintptr_t)a.mx | (uintptr_t)a.my) & 15) == 0;
   const int nseg = cols * g.P;
   uint32_t *s0 = lds, *s1 = lds + TW * g.P, *s2 = lds + 2 * TW * g.P;
@@ -605,8 +702,8 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
     uint32_t rc = lc[(int64_t)r * g.bins];
     uint32_t ry = 0;
     if constexpr (MOM) ry = lcy[(int64_t)r * g.bins];
-    auto pixel = [&](int c, uint32_t val) {
-      const uint32_t hit = (val - lo) < width ? 1u : 0u;
+    auto pixel = [&](int c, uint32_t val, uint32_t w) {
+      const uint32_t hit = (val - lo) < width ? w : 0u;
       rc += hit;
       col[c] += rc;
       s0[c * g.P + p] = col[c];
@@ -623,13 +720,16 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(row);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
+      uint32_t wq[WGT ? TW / 4 : 1];
+      if constexpr (WGT) load_weight_words<TW>(a, g, ch, r, C0, wq);
 #pragma unroll
       for (int c = 0; c < TW; ++c)
-        pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u));
+        pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u),
+              weight_byte<WGT>(wq, c));
     } else {
 #pragma unroll
       for (int c = 0; c < TW; ++c)
-        if (F || c < cols) pixel(c, (uint32_t)row[c]);
+        if (F || c < cols) pixel(c, (uint32_t)row[c], WGT ? pixel_weight(a, g, ch, r, C0 + c) : 1u);
     }
     __syncthreads();
     const int64_t rbase = ((int64_t)r * g.W + C0) * P;
@@ -644,26 +744,32 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
     // prefetched path: the next row's image words and row carries are loaded
     // while this row is computed and stored
     const int64_t rbase0 = ((int64_t)R0 * g.W + C0) * P;
-    uint32_t wv[TW / PER], rcn = 0, ryn = 0;
+    uint32_t wv[TW / PER], rcn = 0, ryn = 0, wqn[WGT ? TW / 4 : 1];
     auto fetch = [&](int r) {
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(img + (int64_t)r * g.W + C0);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
+      if constexpr (WGT) load_weight_words<TW>(a, g, ch, r, C0, wqn);
       rcn = lc[(int64_t)r * g.bins];
       if constexpr (MOM) ryn = lcy[(int64_t)r * g.bins];
     };
     if (rows > 0) fetch(R0);
     for (int rr = 0; rr < rows; ++rr) {
       const int r = R0 + rr;
-      uint32_t cur[TW / PER];
+      uint32_t cur[TW / PER], wq[WGT ? TW / 4 : 1];
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) cur[q] = wv[q];
+      if constexpr (WGT) {
+#pragma unroll
+        for (int q = 0; q < TW / 4; ++q) wq[q] = wqn[q];
+      }
       uint32_t rc = rcn, ry = ryn;
       if (rr + 1 < rows) fetch(r + 1);
 #pragma unroll
       for (int c = 0; c < TW; ++c) {
         const uint32_t val = (cur[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u);
-        const uint32_t hit = (val - lo) < width ? 1u : 0u;
+        const uint32_t w = weight_byte<WGT>(wq, c);
+        const uint32_t hit = (val - lo) < width ? w : 0u;
         rc += hit;
         col[c] += rc;
         s0[c * g.P + p] = col[c];

@@ -95,13 +95,14 @@ struct Geom {
   int TH, CPL, TW, PG;  // tile rows, columns per lane (bin-major), tile columns, planes per wave
   int nTR, nTC;         // tile rows / columns of the grid
   bool mom;
+  bool wgt;             // per-pixel u8 weights replace the unit count
   int layout;           // IH_BHW or IH_HWB
   // workspace sections (in 4-byte words)
   size_t off_cc, off_rc, off_tt, off_ccx, off_rcy, off_ttx, off_tty, words;
 };
 
 int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, int32_t layout,
-              const ih_tile_cfg *cfg, Geom *g);
+              const ih_tile_cfg *cfg, Geom *g, int32_t weighted = 0);
 
 // LDS budget of the tile-histogram pass of the stand-alone build (bytes).
 constexpr int kLdsBudget = 64 * 1024;

@@ -38,6 +38,8 @@ SIGNATURES = {
     "ih_last_error": (ctypes.c_char_p, []),
     "ih_build_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I32, _I32, _P]),
     "ih_build": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "ih_build_weighted": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ,
+                                         _P]),
     "ih_query_rect": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I64, _P, _P]),
     "ih_query_weighted": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _I64, _I32, _I32, _P, _P]),
     "ih_pyramid_desc": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I64, _I32, _P, _P]),
@@ -217,6 +219,47 @@ def ih_build(img: torch.Tensor, bins: int, value_bits: Optional[int] = None, mom
                         ws.numel() * ws.element_size(), _stream(img))
     _check(rc, "ih_build")
     return (out, mx, my) if moments else out
+
+
+def ih_build_weighted(img: torch.Tensor, bins: int, weight: torch.Tensor, mask: Optional[torch.Tensor] = None,
+                      value_bits: Optional[int] = None, cfg: Optional[TileCfg] = None,
+                      out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                      layout: str = "bhw") -> torch.Tensor:
+    """Weighted integral histogram: plane p sums ``weight`` (uint8, same shape
+    as ``img``) over the pixels of bin p whose ``mask`` byte is non-zero (all
+    pixels when ``mask`` is None).  Shape follows ``layout``."""
+    _dev(img, "img")
+    if img.dim() == 2:
+        img = img.unsqueeze(0)
+    if img.dtype == torch.uint8:
+        dt, maxbits = IH_U8, 8
+    elif img.dtype == torch.uint16:
+        dt, maxbits = IH_U16, 16
+    else:
+        raise IHError("img must be uint8 or uint16")
+    C, H, W = img.shape
+    _dev(weight, "weight", torch.uint8)
+    if weight.numel() != C * H * W:
+        raise IHError("weight must have the image's C*H*W values")
+    if mask is not None:
+        _dev(mask, "mask", torch.uint8)
+        if mask.numel() != C * H * W:
+            raise IHError("mask must have the image's C*H*W values")
+    bits = maxbits if value_bits is None else value_bits
+    P = C * bins
+    if out is None:
+        out = torch.empty(shape_of(P, H, W, layout), dtype=torch.int32, device=img.device)
+    _dev(out, "out", torch.int32)
+    if out.numel() != P * H * W:
+        raise IHError("out must hold P*H*W values")
+    need = workspace_size(H, W, C, bins, False, cfg, layout)
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=img.device)
+    rc = lib().ih_build_weighted(_p(img), dt, _p(weight), _p(mask), H, W, C, bins, bits, _layout(layout), _p(out),
+                                 ctypes.byref(cfg) if cfg is not None else None, _p(ws),
+                                 ws.numel() * ws.element_size(), _stream(img))
+    _check(rc, "ih_build_weighted")
+    return out
 
 
 def _rects(rects: torch.Tensor, name="rects") -> torch.Tensor:

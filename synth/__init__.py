@@ -172,6 +172,16 @@ def config2(scale: float = 1.0, n_windows: int = 100_000) -> Workload:
                     windows=wins, moments=True)
 
 
+def phog_inputs(scale: float = 1.0, seed_base: int = 201):
+    """Inputs of the magnitude-weighted orientation histogram at 1920x1080 (the
+    config-2 scene): gradient orientation (the binned image), gradient
+    magnitude (the weight) and the binary edge map (the mask), each 1 x H x W
+    uint8."""
+    H, W = max(16, int(1080 * scale)), max(16, int(1920 * scale))
+    f = feature_channels(seed_base, H, W)
+    return f[4:5].copy(), f[5:6].copy(), f[6:7].copy()
+
+
 def config3(scale: float = 1.0, n_rects: int = 1_000_000, n_blobs: int = 2000,
             radius: int = 64, shifted: bool = False) -> Workload:
     """8192^2 uint16 aerial-style frame, 64 bins; 1M rects; 129x129 candidate grid."""
