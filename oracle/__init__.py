@@ -68,6 +68,8 @@ def _load():
                 "or_level_weight": [I, I],
                 "or_num_threads": [],
                 "or_ih_weighted": [P, I, P, P, I, I, I, I, I, P],
+                "or_jih": [P, I, I, I, I, I, I, I, P],
+                "or_st_median": [P, I, I, I, I, I, I, I, I, I, P],
                 "or_ih_weighted_bruteforce": [P, I, P, P, I, I, I, I, I, P],
                 "or_set_threads": [I],
             }
@@ -155,6 +157,42 @@ def ih_weighted(img, bins, bits, weight, mask=None, brute=False):
     fn = _load().or_ih_weighted_bruteforce if brute else _load().or_ih_weighted
     _check(fn(_ptr(a), dt, _ptr(w), _ptr(m) if m is not None else None, H, W, C, bins, bits, _ptr(out)),
            "ih_weighted")
+    return out
+
+
+def _frames(frames):
+    """F x C x H x W (or F x H x W) uint8/uint16 stack -> (array, dtype code, F, C, H, W)."""
+    a = np.ascontiguousarray(frames)
+    if a.ndim == 3:
+        a = a[:, None]
+    if a.ndim != 4:
+        raise ValueError("frames must be F x C x H x W")
+    if a.dtype == np.uint8:
+        dt = U8
+    elif a.dtype == np.uint16:
+        dt = U16
+    else:
+        raise TypeError("frames must be uint8 or uint16, got %s" % a.dtype)
+    F, C, H, W = a.shape
+    return a, dt, F, C, H, W
+
+
+def jih(frames, bins, bits):
+    """Joint integral histogram of a temporal window of frames (Alg. 4): the
+    integral histogram of all the window's pixels.  P x H x W int32."""
+    a, dt, F, C, H, W = _frames(frames)
+    out = np.empty((C * bins, H, W), np.int32)
+    _check(_load().or_jih(_ptr(a), dt, F, H, W, C, bins, bits, _ptr(out)), "jih")
+    return out
+
+
+def st_median(frames, bins, bits, win_h, win_w):
+    """Spatio-temporal median (Alg. 4, Sec. 4.1.1) by its definition: the lower
+    median of the binned samples of each pixel's clipped win_h x win_w window
+    over all frames.  C x H x W int32 bin indices."""
+    a, dt, F, C, H, W = _frames(frames)
+    out = np.empty((C, H, W), np.int32)
+    _check(_load().or_st_median(_ptr(a), dt, F, H, W, C, bins, bits, win_h, win_w, _ptr(out)), "st_median")
     return out
 
 

@@ -625,6 +625,101 @@ int or_ih_weighted_bruteforce(const void *img, int dtype, const uint8_t *wt,
   return OR_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Spatio-temporal median (Alg. 4, Sec. 4.1.1).                               */
+/*                                                                            */
+/* frames: F consecutive images, F x C x H x W (the temporal window of T+1    */
+/* frames).  The joint integral histogram is the integral histogram of the   */
+/* whole window: plane p at (r, c) counts the window's pixels of bin p in     */
+/* [0, r] x [0, c] over all F frames, which is what Alg. 4's running          */
+/* JIH + IH_head - IH_tail holds once the window is full.                     */
+/* ------------------------------------------------------------------------ */
+int or_jih(const void *frames, int dtype, int F, int H, int W, int C, int bins, int bits,
+           int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (F < 1) return OR_ERR_ARG;
+  if ((int64_t)F * H * W >= ((int64_t)1 << 31)) return OR_ERR_OVERFLOW;
+  const int64_t fsz = (int64_t)C * H * W * (dtype == OR_U8 ? 1 : 2);
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int p = 0; p < P; p++) {
+    int64_t *prev = (int64_t *)calloc((size_t)W, sizeof(int64_t));
+    int64_t *cur = (int64_t *)calloc((size_t)W, sizeof(int64_t));
+    int32_t *o = out + (int64_t)p * H * W;
+    for (int x = 0; x < H; x++) {
+      for (int y = 0; y < W; y++) {
+        int64_t q = 0;  /* frames whose pixel (x, y) falls in plane p */
+        for (int f = 0; f < F; f++)
+          q += or_Q((const char *)frames + f * fsz, dtype, H, W, bins, bits, p, x, y);
+        int64_t up = prev[y];
+        int64_t left = (y > 0) ? cur[y - 1] : 0;
+        int64_t diag = (y > 0) ? prev[y - 1] : 0;
+        cur[y] = up + left - diag + q;
+        o[(int64_t)x * W + y] = (int32_t)cur[y];
+      }
+      int64_t *t = prev; prev = cur; cur = t;
+    }
+    free(prev);
+    free(cur);
+  }
+  return OR_OK;
+}
+
+/* Window of pixel (r, c) for a win_h x win_w median: rows
+   r - (win_h-1)/2 .. r + win_h/2 and columns likewise, clipped to the image. */
+static void or_median_window(int r, int c, int H, int W, int win_h, int win_w, int *r0, int *r1, int *c0,
+                             int *c1) {
+  *r0 = r - (win_h - 1) / 2;
+  *r1 = r + win_h / 2;
+  *c0 = c - (win_w - 1) / 2;
+  *c1 = c + win_w / 2;
+  if (*r0 < 0) *r0 = 0;
+  if (*c0 < 0) *c0 = 0;
+  if (*r1 > H - 1) *r1 = H - 1;
+  if (*c1 > W - 1) *c1 = W - 1;
+}
+
+static int or_cmp_int(const void *a, const void *b) {
+  int x = *(const int *)a, y = *(const int *)b;
+  return (x > y) - (x < y);
+}
+
+/* The median of the samples, by its definition: every binned value of the
+   pixel's (clipped) win_h x win_w window in every one of the F frames is
+   collected and sorted; the median is the sample at position (N-1)/2 (the
+   lower median when N is even).  out: C x H x W bin indices. */
+int or_st_median(const void *frames, int dtype, int F, int H, int W, int C, int bins, int bits, int win_h,
+                 int win_w, int32_t *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (F < 1 || win_h < 1 || win_w < 1) return OR_ERR_ARG;
+  const int64_t fsz = (int64_t)C * H * W;
+  int rc = OR_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int row = 0; row < C * H; row++) {
+    const int ch = row / H, r = row % H;
+    int *smp = (int *)malloc(sizeof(int) * (size_t)F * win_h * win_w);
+    if (!smp) {
+#pragma omp critical
+      rc = OR_ERR_ARG;
+      continue;
+    }
+    for (int c = 0; c < W; c++) {
+      int r0, r1, c0, c1, n = 0;
+      or_median_window(r, c, H, W, win_h, win_w, &r0, &r1, &c0, &c1);
+      for (int f = 0; f < F; f++)
+        for (int a = r0; a <= r1; a++)
+          for (int b = c0; b <= c1; b++)
+            smp[n++] = or_bin_of(or_value(frames, dtype, f * fsz + ((int64_t)ch * H + a) * W + b), bins, bits);
+      qsort(smp, (size_t)n, sizeof(int), or_cmp_int);
+      out[((int64_t)ch * H + r) * W + c] = smp[(n - 1) / 2];
+    }
+    free(smp);
+  }
+  return rc;
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
