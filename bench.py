@@ -62,6 +62,8 @@ def parse():
                     help="run only the tracker workload and print its JSON object (for profiling)")
     ap.add_argument("--phog-only", action="store_true",
                     help="run only the magnitude-weighted orientation histogram and print its JSON object")
+    ap.add_argument("--median-only", action="store_true",
+                    help="run only the spatio-temporal median and print its JSON object")
     ap.add_argument("--train-videos", type=int, default=800)
     ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--tile", type=str, default="",
@@ -222,6 +224,59 @@ def phog_leg(torch, ih, synth):
     return res
 
 
+def median_leg(torch, ih, synth):
+    """Spatio-temporal median background model (Alg. 4) of a 768x576 grey
+    surveillance video: 256 bins, a window of T+1 = 17 frames, a 3x3 spatial
+    window.  Per layout: the joint-IH update (head in, tail out, in place)
+    and the local-median pass, each graph-replayed, and the whole per-frame
+    push (update, ring copy, median) timed over a stream of frames; the first
+    and last medians are checked against the graph-free result."""
+    from paper_1711_01656_amd.median import SpatioTemporalMedian
+    dev = torch.device("cuda:0")
+    F, T, bins, wh, ww = 48, 16, 256, 3, 3
+    v = synth.surveillance_video(600, F)
+    H, W = v.shape[1], v.shape[2]
+    frames = torch.from_numpy(v).to(dev)
+    P = bins
+    upd_bytes = 2 * P * H * W * 4 + 2 * H * W
+    med_bytes = P * H * W * 4 + H * W * 4
+    res = {"workload": "768x576 u8 grey video, 256 bins, 17-frame window, 3x3 spatial median",
+           "frames_streamed": F - (T + 1), "update_algorithmic_bytes": upd_bytes,
+           "median_algorithmic_bytes": med_bytes, "layouts": {}}
+    for layout in ("bhw", "hwb"):
+        model = SpatioTemporalMedian(1, H, W, bins, T, wh, ww, layout=layout)
+        for f in range(T + 1):
+            model.push(frames[f])
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for f in range(T + 1, F):
+            model.push(frames[f])
+        b.record()
+        torch.cuda.synchronize()
+        push_ms = a.elapsed_time(b) / (F - T - 1)
+        med_ref = model.median.clone()
+        jih_ref = model.jih.clone()
+        out = torch.empty_like(model.median)
+        tm = graph_median(torch, lambda: ih.ih_local_median(jih_ref, 1, bins, T + 1, wh, ww, out=out,
+                                                             layout=layout), 20, per=5)
+        same = bool(torch.equal(out, med_ref))
+        J = jih_ref.clone()
+        ws = model.ws
+        tu = graph_median(torch, lambda: ih.ih_jih_update(frames[F - 1], frames[F - 2], bins, J, ws=ws,
+                                                          layout=layout), 20, per=5)
+        res["layouts"][layout] = {"push_ms_per_frame": round(push_ms, 4),
+                                  "frames_per_s": round(1e3 / push_ms, 1),
+                                  "update_ms": round(tu, 4), "update_gbs": round(upd_bytes / tu / 1e6, 1),
+                                  "update_frac_of_peak": round(upd_bytes / tu / 1e6 / HBM_PEAK_GBS, 4),
+                                  "median_ms": round(tm, 4), "median_gbs": round(med_bytes / tm / 1e6, 1),
+                                  "median_replay_matches_stream": same}
+        del model, J, jih_ref, med_ref, out
+        torch.cuda.empty_cache()
+    return res
+
+
 def copy_calibration(torch, mib):
     """One device fill and one device-to-device copy of `mib` MiB: the copy
     kernel's FETCH_SIZE and WRITE_SIZE against its known bytes give the
@@ -282,6 +337,8 @@ def config_legs(torch, ih, synth, fixed=False):
 
     # magnitude-weighted orientation histogram of the 1920x1080 scene
     res["phog_1920x1080_16bins"] = phog_leg(torch, ih, synth)
+    # spatio-temporal median of a 768x576 video
+    res["median_768x576_256bins"] = median_leg(torch, ih, synth)
 
     # 8192x8192 u16, 64 bins, 1M rectangles, 129x129 search
     w = synth.config3()
@@ -526,6 +583,12 @@ def main():
         return
     if args.workloads_only:
         print(json.dumps(config_legs(torch, ih, synth, args.fixed_tiles)), flush=True)
+        return
+    if args.median_only:
+        res = median_leg(torch, ih, synth)
+        if args.copy_calib:
+            copy_calibration(torch, args.copy_calib)
+        print(json.dumps(res), flush=True)
         return
     if args.phog_only:
         res = phog_leg(torch, ih, synth)

@@ -315,6 +315,52 @@ int ih_build_batch(const void *plan_host, const void *plan_dev, void *ws,
                    size_t ws_bytes, int32_t mode, void *stream);
 
 /*
+ * ih_jih_update - joint integral histogram update of the spatio-temporal
+ * median (Alg. 4, Fig. 4.1): JIH = JIH + IH(head) - IH(tail), in place.
+ * The joint IH of a window of frames is the integral histogram of all their
+ * pixels; sliding the window by one frame adds the entering (head) frame and
+ * removes the leaving (tail) one.  Computed as one build of the integral
+ * histogram of the difference (head +1, tail -1 per pixel, modulo 2^32)
+ * whose write-out adds into jih, so each update reads and writes jih once.
+ *
+ *   head        device, C x H x W values of type dtype: the entering frame.
+ *   tail        device, same shape and dtype: the leaving frame, or NULL
+ *               while the window is filling (then JIH = JIH + IH(head)).
+ *   dtype, H, W, C, bins, value_bits, layout, cfg, ws, ws_bytes, stream
+ *               as for ih_build (workspace: ih_build_workspace_size with
+ *               moments = 0).  IH_HWB needs P <= 512 and tile_w * P <= 16384.
+ *   jih         device, in/out: P x H x W int32 (in layout).  Start from
+ *               zeros (or from ih_build of the first frame).  Every entry
+ *               stays exact while the window's frame count * H * W < 2^31.
+ * Returns IH_OK or IH_ERR_*.  jih must not overlap the frames or ws.
+ */
+int ih_jih_update(const void *head, const void *tail, int32_t dtype,
+                  int32_t H, int32_t W, int32_t C, int32_t bins,
+                  int32_t value_bits, int32_t layout, int32_t *jih,
+                  const ih_tile_cfg *cfg, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/*
+ * ih_local_median - per-pixel median of the spatio-temporal box from a joint
+ * integral histogram (Alg. 4, ComputeLocalMedian; Sec. 4.1.1).
+ *   jih         device, P x H x W int32 (in layout), P = C * bins, holding
+ *               exactly `frames` frames.
+ *   frames      number of frames in the window (T + 1), >= 1.
+ *   win_h, win_w  spatial window; pixel (r, c) uses rows
+ *               r - (win_h-1)/2 .. r + win_h/2 and columns likewise,
+ *               clipped to the image.
+ *   median      device, out: C x H x W int32 bin indices.  The median of the
+ *               N = frames * (window area) samples is the first bin whose
+ *               running count reaches ceil(N/2) (the lower median for even N).
+ * Needs bins <= 256 and frames * H * W < 2^31.  A jih that does not hold
+ * `frames` frames gives unspecified (in-bounds) bins.  Returns IH_OK or
+ * IH_ERR_*.
+ */
+int ih_local_median(const int32_t *jih, int32_t C, int32_t bins, int32_t H,
+                    int32_t W, int32_t layout, int32_t frames, int32_t win_h,
+                    int32_t win_w, int32_t *median, void *stream);
+
+/*
  * ih_profile_events - profiling hook.  When both are non-NULL (hipEvent_t),
  * every later ih_build on this thread records `start` on its stream just
  * before its final write-out kernel and `stop` just after it, so that the

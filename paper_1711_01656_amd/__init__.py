@@ -12,6 +12,8 @@ from .ih import (  # noqa: F401
     cells,
     ih_build,
     ih_build_weighted,
+    ih_jih_update,
+    ih_local_median,
     ih_match_candidates,
     ih_profile_events,
     ih_pyramid_desc,

@@ -35,7 +35,7 @@ static size_t align64(size_t w) { return (w + 63) & ~(size_t)63; }
 
 int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds) {
   const int twp = g.TW + 4;
-  const size_t stage = ((size_t)g.TH * twp * (g.wgt ? 2 : 1) + 3) & ~(size_t)3;
+  const size_t stage = ((size_t)g.TH * twp * (g.wgt || g.diff ? 2 : 1) + 3) & ~(size_t)3;
   const int span = g.TH > g.TW ? g.TH : g.TW;
   const int arrays = g.mom ? 2 : 1;
   long words = ((long)lds_budget - (long)stage) / 4;
@@ -60,6 +60,7 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
   g->H = H; g->W = W; g->C = C; g->bins = bins; g->P = C * bins;
   g->mom = moments != 0;
   g->wgt = weighted != 0;
+  g->diff = false;
   if (g->mom && g->wgt) return set_error(IH_ERR_UNSUPPORTED, "moments of a weighted histogram are not built");
   g->layout = layout;
   int TH, TW, PG;
@@ -152,17 +153,6 @@ __global__ __launch_bounds__(512) void k_final_hwb_staged(FinalArgs a, Geom g) {
   final_hwb_staged_body<T, TW, MOM, WGT>(a, g, blockIdx.x, seg);
 }
 
-// LDS bytes of one staged row segment (all arrays), or 0 when staging does not apply.
-#ifndef IH_HWB_STAGED
-#define IH_HWB_STAGED 1
-#endif
-static size_t staged_lds(const Geom &g) {
-  if (!IH_HWB_STAGED || g.layout != IH_HWB) return 0;
-  const int nchunk = (g.P + 63) / 64;
-  const size_t bytes = (size_t)(g.mom ? 3 : 1) * g.TW * g.P * 4;
-  // with moments a tile wider than 16 columns would spill registers
-  return (nchunk <= 8 && bytes <= 64 * 1024 && !(g.mom && g.TW > 16)) ? bytes : 0;
-}
 
 // ------------------------------------------------------------------ host --
 struct ProfileHook {

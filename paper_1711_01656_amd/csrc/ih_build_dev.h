@@ -25,15 +25,32 @@ __host__ __device__ __forceinline__ int64_t cc_index(const Geom &g, int64_t p, i
 //    With weights (g.wgt) every "count" above is the sum of the pixels'
 //    weights, wt where the mask is set (or there is no mask), else 0.
 // --------------------------------------------------------------------------
+// LDS bytes of one staged row segment of the planes-innermost write-out (all
+// arrays), or 0 when staging does not apply.
+#ifndef IH_HWB_STAGED
+#define IH_HWB_STAGED 1
+#endif
+inline size_t staged_lds(const Geom &g) {
+  if (!IH_HWB_STAGED || g.layout != IH_HWB) return 0;
+  const int nchunk = (g.P + 63) / 64;
+  const size_t bytes = (size_t)(g.mom ? 3 : 1) * g.TW * g.P * 4;
+  // with moments a tile wider than 16 columns would spill registers
+  return (nchunk <= 8 && bytes <= 64 * 1024 && !(g.mom && g.TW > 16)) ? bytes : 0;
+}
+
+//    In the joint-IH update (g.diff) a second image, the tail frame, counts
+//    -1 (modulo 2^32) in its pixels' bins; the carries then hold the counts
+//    of head minus tail, exact modulo 2^32.
 template <typename T>
 __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const Geom &g, int bits, int bc,
                                                uint32_t *__restrict__ ws, int blkid, uint32_t *lds,
                                                const uint8_t *__restrict__ wt = nullptr,
-                                               const uint8_t *__restrict__ mask = nullptr) {
+                                               const uint8_t *__restrict__ mask = nullptr,
+                                               const T *__restrict__ tail = nullptr) {
   const int twp = g.TW + 4;
   uint8_t *bin_s = reinterpret_cast<uint8_t *>(lds);
-  uint8_t *wt_s = bin_s + (size_t)g.TH * twp;  // weights (weighted build only)
-  uint32_t *hist = lds + (((size_t)g.TH * twp * (g.wgt ? 2 : 1) + 3) >> 2);
+  uint8_t *wt_s = bin_s + (size_t)g.TH * twp;  // weights (weighted build) or tail bins (update)
+  uint32_t *hist = lds + (((size_t)g.TH * twp * (g.wgt || g.diff ? 2 : 1) + 3) >> 2);
   const int tid = threadIdx.x;
   int blk = blkid;
   const int j = blk % g.nTC; blk /= g.nTC;
@@ -52,6 +69,7 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       const int64_t iw = (int64_t)ch * g.H * g.W + i;
       wt_s[r * twp + c] = (mask && mask[iw] == 0) ? (uint8_t)0 : wt[iw];
     }
+    if (g.diff) wt_s[r * twp + c] = (uint8_t)(((uint64_t)tail[(int64_t)ch * g.H * g.W + i] * g.bins) >> bits);
   }
   uint32_t *CC = ws + g.off_cc, *RC = ws + g.off_rc, *TT = ws + g.off_tt;
   uint32_t *CCX = ws + g.off_ccx, *RCY = ws + g.off_rcy;
@@ -70,6 +88,15 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       const int cl = idx % tw, seg = idx / tw;
       for (int r = seg; r < th; r += nseg) {
         const int b = (int)bin_s[r * twp + cl] - b0;
+        if (g.diff) {
+          // head +1, tail -1; a pixel whose bin did not change adds nothing
+          const int bt = (int)wt_s[r * twp + cl] - b0;
+          if (b != bt) {
+            if (b >= 0 && b < nb) atomicAdd(&hist[cl * stride + b], 1u);
+            if (bt >= 0 && bt < nb) atomicAdd(&hist[cl * stride + bt], 0xffffffffu);
+          }
+          continue;
+        }
         const uint32_t w = g.wgt ? (uint32_t)wt_s[r * twp + cl] : 1u;
         if (b >= 0 && b < nb && w) {
           atomicAdd(&hist[cl * stride + b], w);
@@ -124,6 +151,14 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       const int r = idx % th, seg = idx / th;
       for (int cl = seg; cl < tw; cl += rseg) {
         const int b = (int)bin_s[r * twp + cl] - b0;
+        if (g.diff) {
+          const int bt = (int)wt_s[r * twp + cl] - b0;
+          if (b != bt) {
+            if (b >= 0 && b < nb) atomicAdd(&hist[r * stride + b], 1u);
+            if (bt >= 0 && bt < nb) atomicAdd(&hist[r * stride + bt], 0xffffffffu);
+          }
+          continue;
+        }
         const uint32_t w = g.wgt ? (uint32_t)wt_s[r * twp + cl] : 1u;
         if (b >= 0 && b < nb && w) {
           atomicAdd(&hist[r * stride + b], w);
@@ -213,7 +248,30 @@ struct FinalArgs {
   int bits;
   int vec_ok;  // bin-major: W divisible by CPL and the outputs 16-byte aligned
   const uint8_t *wt, *mask;  // weighted build: C x H x W weights, optional mask
+  const void *tail;          // joint-IH update: the frame leaving the window (or NULL)
 };
+
+// Adds CPL consecutive values to the int32 output in place (the joint-IH
+// update's read-modify-write store).
+template <int CPL>
+__device__ __forceinline__ void put_add(int32_t *dst, const uint32_t (&v)[CPL], int cf, int W, bool vec_ok) {
+  if (vec_ok && cf + CPL <= W) {
+    typedef typename vec_of<CPL>::type VT;
+    VT old = *reinterpret_cast<const VT *>(dst);
+    int t[CPL];
+    if constexpr (CPL == 1) {
+      t[0] = old + (int)v[0];
+    } else {
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) t[e] = old[e] + (int)v[e];
+    }
+    store_stream<CPL>(dst, t);
+  } else {
+#pragma unroll
+    for (int e = 0; e < CPL; ++e)
+      if (cf + e < W) dst[e] = (int)((uint32_t)dst[e] + v[e]);
+  }
+}
 
 // Weight of pixel (r, c) of channel ch in the weighted build: wt where the
 // mask is set (or there is no mask), else 0.
@@ -245,7 +303,7 @@ __device__ __forceinline__ void put(int32_t *dst, const uint32_t (&v)[CPL], int 
   }
 }
 
-template <typename T, int CPL, int PG, bool MOM, bool WGT = false>
+template <typename T, int CPL, int PG, bool MOM, bool WGT = false, bool ACC = false>
 __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, int bx, int by, int wave, int wpb) {
   const int lane = threadIdx.x & 63;
   const int grp = by * wpb + wave;
@@ -309,10 +367,17 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 
   // the next row's pixels and row carries are loaded while this row is
   // written (software pipelining hides their latency)
-  uint32_t px[CPL], lcv[PG], lcyv[MOM ? PG : 1], pw[WGT ? CPL : 1];
+  const T *timg = ACC && a.tail ? reinterpret_cast<const T *>(a.tail) + ch * HW : nullptr;
+  uint32_t px[CPL], lcv[PG], lcyv[MOM ? PG : 1], pw[WGT ? CPL : 1], pt[ACC ? CPL : 1];
   auto fetch = [&](int r) {
 #pragma unroll
     for (int e = 0; e < CPL; ++e) px[e] = cf + e < g.W ? (uint32_t)img[(int64_t)r * g.W + cf + e] : 0u;
+    if constexpr (ACC) {
+      // a tail bin of -1 (value 2^bits) matches no plane
+#pragma unroll
+      for (int e = 0; e < CPL; ++e)
+        pt[e] = (timg && cf + e < g.W) ? (uint32_t)timg[(int64_t)r * g.W + cf + e] : (1u << a.bits);
+    }
     if constexpr (WGT) {
 #pragma unroll
       for (int e = 0; e < CPL; ++e) pw[e] = cf + e < g.W ? pixel_weight(a, g, ch, r, cf + e) : 0u;
@@ -334,6 +399,12 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
     for (int e = 0; e < CPL; ++e)
       b[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
     uint32_t lcur[PG], lycur[MOM ? PG : 1], wcur[WGT ? CPL : 1];
+    int bt[ACC ? CPL : 1];
+    if constexpr (ACC) {
+#pragma unroll
+      for (int e = 0; e < CPL; ++e)
+        bt[e] = cf + e < g.W && pt[e] < (1u << a.bits) ? (int)(((uint64_t)pt[e] * g.bins) >> a.bits) - kb : -1;
+    }
 #pragma unroll
     for (int k = 0; k < PG; ++k) lcur[k] = lcv[k];
     if constexpr (WGT) {
@@ -348,7 +419,27 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
     const int64_t orow = (int64_t)r * g.W;
 #pragma unroll
     for (int k = 0; k < PG; ++k) {
-      if constexpr (WGT) {
+      if constexpr (ACC) {
+        if (k < nk) {
+          // row prefix of head minus tail: ballots of both, difference of the
+          // lanes-below counts (modulo 2^32), added to the stored joint IH
+          uint32_t t = lcur[k];
+          uint64_t mh[CPL], mt[CPL];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            mh[e] = ballot(b[e] == k);
+            mt[e] = ballot(bt[e] == k);
+          }
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) t = lanes_below(mh[e], t) - lanes_below(mt[e], 0u);
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            t += (b[e] == k ? 1u : 0u) - (bt[e] == k ? 1u : 0u);
+            col[k][e] += t;
+          }
+          put_add<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec_ok);
+        }
+      } else if constexpr (WGT) {
         if (k < nk) {
           // weighted row prefix: the lane's own running sum plus a wave scan
           // of the lanes' totals
@@ -797,5 +888,74 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
   }
 }
 
+
+// 3e. The joint-IH update in the planes-innermost layout: the staged
+//     write-out (one block per tile, one wavefront per 64 planes, row segments
+//     staged in LDS) of the integral histogram of head minus tail, added to
+//     the stored joint IH with 16-byte (or 4-byte) read-modify-write copies.
+__device__ __forceinline__ void copy_out_add(int32_t *__restrict__ dst, const uint32_t *__restrict__ src, int n,
+                                             bool vec) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (vec) {
+    const v4i *s4 = reinterpret_cast<const v4i *>(src);
+    v4i *d4 = reinterpret_cast<v4i *>(dst);
+    for (int i = tid; i < (n >> 2); i += nt) __builtin_nontemporal_store(d4[i] + s4[i], d4 + i);
+  } else {
+    for (int i = tid; i < n; i += nt) dst[i] = (int)((uint32_t)dst[i] + src[i]);
+  }
+}
+
+template <typename T, int TW>
+__device__ __forceinline__ void final_hwb_acc_staged_body(const FinalArgs &a, const Geom &g, int64_t tile,
+                                                          uint32_t *lds) {
+  const int lane = threadIdx.x & 63;
+  const int chunk = uniform((int)(threadIdx.x >> 6));
+  const int j = (int)(tile % g.nTC), I = (int)(tile / g.nTC);
+  const int p = min(chunk * 64 + lane, g.P - 1);  // lanes past the last plane repeat it
+  const int ch = p / g.bins;
+  const int k = p - ch * g.bins;
+  const int R0 = I * g.TH, C0 = j * TW;
+  const int cols = min(TW, g.W - C0), rows = min(g.TH, g.H - R0);
+  const uint32_t lo = (uint32_t)((((uint64_t)k << a.bits) + g.bins - 1) / g.bins);
+  const uint32_t width = (uint32_t)((((uint64_t)(k + 1) << a.bits) + g.bins - 1) / g.bins) - lo;
+  const int64_t HW = (int64_t)g.H * g.W;
+  const T *img = reinterpret_cast<const T *>(a.img) + ch * HW;
+  const T *timg = a.tail ? reinterpret_cast<const T *>(a.tail) + ch * HW : nullptr;
+  const int64_t P = g.P;
+  uint32_t col[TW];
+  {
+    const int64_t cidx = ((int64_t)p * g.nTR + I) * g.nTC + j;
+    uint32_t run = a.ws[g.off_tt + cidx];
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        run += a.ws[g.off_cc + ((int64_t)I * g.W + C0 + c) * P + p];
+        col[c] = run;
+      }
+    }
+  }
+  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const bool vec = (g.P & 3) == 0 && ((uintptr_t)a.ih & 15) == 0;
+  const int nseg = cols * g.P;
+  for (int rr = 0; rr < rows; ++rr) {
+    const int r = R0 + rr;
+    const T *row = img + (int64_t)r * g.W + C0;
+    const T *trow = timg ? timg + (int64_t)r * g.W + C0 : nullptr;
+    uint32_t rc = lc[(int64_t)r * g.bins];
+#pragma unroll
+    for (int c = 0; c < TW; ++c) {
+      if (c < cols) {
+        uint32_t hit = ((uint32_t)row[c] - lo) < width ? 1u : 0u;
+        if (trow) hit -= ((uint32_t)trow[c] - lo) < width ? 1u : 0u;
+        rc += hit;
+        col[c] += rc;
+        lds[c * g.P + p] = col[c];
+      }
+    }
+    __syncthreads();
+    copy_out_add(a.ih + ((int64_t)r * g.W + C0) * P, lds, nseg, vec);
+    __syncthreads();
+  }
+}
 
 }  // namespace ih

@@ -1,0 +1,252 @@
+// Spatio-temporal median through a joint integral histogram (Alg. 4,
+// Sec. 4.1.1) for gfx950.
+//
+// The joint integral histogram (JIH) of a window of T+1 frames is the
+// integral histogram of all of its pixels.  Alg. 4 keeps it up to date as the
+// window slides by adding the head frame's integral histogram and subtracting
+// the tail frame's.  Here that update is one build of the integral histogram
+// of the signed difference image (head counts +1 in its bin, tail -1 in its
+// bin; all arithmetic modulo 2^32, exact because the result is in range),
+// with the write-out adding its values to the stored JIH in place: one read
+// and one write of the JIH per frame, and no per-frame histogram is kept.
+//
+// The median of a pixel's win_h x win_w x (T+1) box is then read from the
+// JIH: its local histogram by four corners per bin (Eq. 2.16) and the first
+// bin whose running count reaches ceil(N/2), N the box's sample count.
+#include "ih_build_dev.h"
+
+namespace ih {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_hist_upd(const T *__restrict__ head, Geom g, int bits, int bc,
+                                                       uint32_t *__restrict__ ws, const T *__restrict__ tail) {
+  extern __shared__ uint32_t lds[];
+  tile_hist_body<T>(head, g, bits, bc, ws, blockIdx.x, lds, nullptr, nullptr, tail);
+}
+
+__global__ __launch_bounds__(256) void k_carry_scan_upd(Geom g, int64_t nblk_a, int64_t nblk_b,
+                                                        uint32_t *__restrict__ ws) {
+  carry_scan_body(g, nblk_a, nblk_b, ws, blockIdx.x);
+}
+
+template <typename T, int CPL, int PG>
+__global__ __launch_bounds__(256) void k_final_acc(FinalArgs a, Geom g) {
+  final_body<T, CPL, PG, false, false, true>(a, g, blockIdx.x, blockIdx.y, uniform(threadIdx.x >> 6),
+                                             blockDim.x >> 6);
+}
+
+template <typename T, int TW>
+__global__ __launch_bounds__(512) void k_final_hwb_acc(FinalArgs a, Geom g) {
+  extern __shared__ uint32_t seg[];
+  final_hwb_acc_staged_body<T, TW>(a, g, blockIdx.x, seg);
+}
+
+// ------------------------------------------------------------- median --
+// Window of pixel (r, c): rows r - (win_h-1)/2 .. r + win_h/2, columns
+// likewise, clipped to the image; inclusive corners of the JIH.
+struct MedianWin {
+  int r0, r1, c0, c1;
+  __device__ __forceinline__ MedianWin(int r, int c, int H, int W, int wh, int ww) {
+    r0 = max(0, r - (wh - 1) / 2);
+    r1 = min(H - 1, r + wh / 2);
+    c0 = max(0, c - (ww - 1) / 2);
+    c1 = min(W - 1, c + ww / 2);
+  }
+};
+
+// Bin-major JIH: one thread per pixel (lanes along a row, so every corner
+// load of a plane is one contiguous run), bins walked four at a time with
+// their 16 corner loads in flight together, stopping at the median bin.
+__global__ __launch_bounds__(256) void k_median_bhw(const int32_t *__restrict__ J, int bins, int H, int W,
+                                                    int frames, int wh, int ww, int32_t *__restrict__ out) {
+  const int c = blockIdx.x * 64 + (int)(threadIdx.x & 63);
+  const int r = blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+  const int ch = blockIdx.z;
+  if (c >= W || r >= H) return;
+  const MedianWin w(r, c, H, W, wh, ww);
+  const int64_t HW = (int64_t)H * W;
+  const int32_t *base = J + (int64_t)ch * bins * HW;
+  const bool top = w.r0 > 0, left = w.c0 > 0;
+  const int64_t o11 = (int64_t)w.r1 * W + w.c1;
+  const int64_t o01 = top ? (int64_t)(w.r0 - 1) * W + w.c1 : 0;
+  const int64_t o10 = left ? (int64_t)w.r1 * W + w.c0 - 1 : 0;
+  const int64_t o00 = top && left ? (int64_t)(w.r0 - 1) * W + w.c0 - 1 : 0;
+  const uint32_t n = (uint32_t)frames * (uint32_t)((w.r1 - w.r0 + 1) * (w.c1 - w.c0 + 1));
+  const uint32_t target = (n + 1) / 2;
+  uint32_t cum = 0;
+  int med = bins - 1;
+  for (int k0 = 0; k0 < bins; k0 += 4) {
+    uint32_t h[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      h[u] = 0;
+      if (k0 + u < bins) {
+        const int32_t *pl = base + (int64_t)(k0 + u) * HW;
+        uint32_t v = (uint32_t)pl[o11];
+        if (top) v -= (uint32_t)pl[o01];
+        if (left) v -= (uint32_t)pl[o10];
+        if (top && left) v += (uint32_t)pl[o00];
+        h[u] = v;
+      }
+    }
+    bool done = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!done && k0 + u < bins) {
+        cum += h[u];
+        if (cum >= target) {
+          med = k0 + u;
+          done = true;
+        }
+      }
+    }
+    if (done) break;
+  }
+  out[(int64_t)ch * HW + (int64_t)r * W + c] = med;
+}
+
+// Planes-innermost JIH: one wavefront per pixel, lanes = 64 bins at a time;
+// each corner is one contiguous 256-byte load, the running count a wave scan,
+// the median the first lane whose count reaches the target.
+__global__ __launch_bounds__(256) void k_median_hwb(const int32_t *__restrict__ J, int C, int bins, int H, int W,
+                                                    int frames, int wh, int ww, int32_t *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t pix = (int64_t)blockIdx.x * 4 + uniform((int)(threadIdx.x >> 6));
+  if (pix >= (int64_t)C * HW) return;
+  const int ch = (int)(pix / HW);
+  const int64_t rem = pix - (int64_t)ch * HW;
+  const int r = (int)(rem / W), c = (int)(rem - (int64_t)r * W);
+  const MedianWin w(r, c, H, W, wh, ww);
+  const int64_t P = (int64_t)C * bins;
+  const bool top = w.r0 > 0, left = w.c0 > 0;
+  const int64_t o11 = ((int64_t)w.r1 * W + w.c1) * P;
+  const int64_t o01 = top ? ((int64_t)(w.r0 - 1) * W + w.c1) * P : 0;
+  const int64_t o10 = left ? ((int64_t)w.r1 * W + w.c0 - 1) * P : 0;
+  const int64_t o00 = top && left ? ((int64_t)(w.r0 - 1) * W + w.c0 - 1) * P : 0;
+  const uint32_t n = (uint32_t)frames * (uint32_t)((w.r1 - w.r0 + 1) * (w.c1 - w.c0 + 1));
+  const uint32_t target = (n + 1) / 2;
+  uint32_t carry = 0;
+  int med = bins - 1;
+  for (int k0 = 0; k0 < bins; k0 += 64) {
+    const int k = k0 + lane;
+    const bool valid = k < bins;
+    uint32_t h = 0;
+    if (valid) {
+      const int64_t p = (int64_t)ch * bins + k;
+      h = (uint32_t)J[o11 + p];
+      if (top) h -= (uint32_t)J[o01 + p];
+      if (left) h -= (uint32_t)J[o10 + p];
+      if (top && left) h += (uint32_t)J[o00 + p];
+    }
+    const uint32_t inc = wave_incl_scan(h) + carry;
+    const uint64_t m = ballot(valid && inc >= target);
+    if (m) {
+      med = k0 + (int)__builtin_ctzll(m);
+      break;
+    }
+    carry = read_lane(inc, 63);
+  }
+  if (lane == 0) out[pix] = med;
+}
+
+typedef void (*final_fn)(FinalArgs, Geom);
+
+template <typename T>
+static final_fn pick_acc_t(const Geom &g) {
+  if (g.layout == IH_HWB) {
+    if (g.TW == 16) return &k_final_hwb_acc<T, 16>;
+    if (g.TW == 32) return &k_final_hwb_acc<T, 32>;
+    if (g.TW == 64) return &k_final_hwb_acc<T, 64>;
+    return nullptr;
+  }
+#define IH_F(C_, G_) \
+  if (g.CPL == C_ && g.PG == G_) return &k_final_acc<T, C_, G_>;
+  IH_F(1, 1) IH_F(1, 2) IH_F(1, 4) IH_F(1, 8) IH_F(1, 16)
+  IH_F(2, 1) IH_F(2, 2) IH_F(2, 4) IH_F(2, 8) IH_F(2, 16)
+  IH_F(4, 1) IH_F(4, 2) IH_F(4, 4) IH_F(4, 8) IH_F(4, 16)
+#undef IH_F
+  return nullptr;
+}
+
+}  // namespace ih
+
+using namespace ih;
+
+extern "C" int ih_jih_update(const void *head, const void *tail, int32_t dtype, int32_t H, int32_t W, int32_t C,
+                             int32_t bins, int32_t value_bits, int32_t layout, int32_t *jih,
+                             const ih_tile_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
+  if (!head || !jih) return set_error(IH_ERR_INVALID_ARG, "head and jih must be non-NULL");
+  if (dtype != IH_U8 && dtype != IH_U16) return set_error(IH_ERR_INVALID_ARG, "dtype %d unknown", dtype);
+  const int maxbits = dtype == IH_U8 ? 8 : 16;
+  if (value_bits < 1 || value_bits > maxbits)
+    return set_error(IH_ERR_INVALID_ARG, "value_bits %d outside 1..%d", value_bits, maxbits);
+  if (bins > (1 << value_bits)) return set_error(IH_ERR_INVALID_ARG, "bins %d exceed 2^value_bits", bins);
+  Geom g;
+  int e = make_geom(H, W, C, bins, 0, layout, cfg, &g);
+  if (e) return e;
+  g.diff = tail != nullptr;
+  if (!ws || ws_bytes < g.words * 4)
+    return set_error(IH_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.words * 4,
+                     ws ? ws_bytes : (size_t)0);
+  if (layout == IH_HWB && staged_lds(g) == 0)
+    return set_error(IH_ERR_UNSUPPORTED, "planes-innermost update needs P <= 512 and tile_w * P <= 16384 (P = %d)",
+                     g.P);
+  final_fn fin = dtype == IH_U8 ? pick_acc_t<uint8_t>(g) : pick_acc_t<uint16_t>(g);
+  if (!fin)
+    return set_error(IH_ERR_UNSUPPORTED, "no update kernel for tile_w %d planes_per_wave %d", g.TW, g.PG);
+  int bc;
+  size_t lds;
+  if ((e = pick_bc(g, kLdsBudget, &bc, &lds))) return e;
+  hipStream_t s = as_stream(stream);
+  uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
+  const unsigned tiles = (unsigned)((int64_t)g.nTR * g.nTC * C);
+  if (dtype == IH_U8)
+    hipLaunchKernelGGL(k_tile_hist_upd<uint8_t>, dim3(tiles), dim3(256), lds, s,
+                       reinterpret_cast<const uint8_t *>(head), g, value_bits, bc, w32,
+                       reinterpret_cast<const uint8_t *>(tail));
+  else
+    hipLaunchKernelGGL(k_tile_hist_upd<uint16_t>, dim3(tiles), dim3(256), lds, s,
+                       reinterpret_cast<const uint16_t *>(head), g, value_bits, bc, w32,
+                       reinterpret_cast<const uint16_t *>(tail));
+  if ((e = hip_check(hipGetLastError(), "update tile_hist launch"))) return e;
+  const int64_t nA = ((int64_t)g.P * W + 255) / 256;
+  const int64_t nB = ((int64_t)C * H * bins + 255) / 256;
+  hipLaunchKernelGGL(k_carry_scan_upd, dim3((unsigned)(nA + nB + g.P)), dim3(256), 0, s, g, nA, nB, w32);
+  if ((e = hip_check(hipGetLastError(), "update carry_scan launch"))) return e;
+  FinalArgs fa{head, jih, nullptr, nullptr, w32, value_bits,
+               (W % g.CPL == 0 && (uintptr_t)jih % 16 == 0) ? 1 : 0, nullptr, nullptr, tail};
+  if (layout == IH_BHW) {
+    const int groups = (bins + g.PG - 1) / g.PG;
+    const int wpb = groups < 4 ? groups : 4;
+    hipLaunchKernelGGL(fin, dim3(tiles, (unsigned)((groups + wpb - 1) / wpb)), dim3(64 * wpb), 0, s, fa, g);
+  } else {
+    hipLaunchKernelGGL(fin, dim3((unsigned)((int64_t)g.nTR * g.nTC)), dim3(64 * ((g.P + 63) / 64)),
+                       staged_lds(g), s, fa, g);
+  }
+  return hip_check(hipGetLastError(), "update write-out launch");
+}
+
+extern "C" int ih_local_median(const int32_t *jih, int32_t C, int32_t bins, int32_t H, int32_t W, int32_t layout,
+                               int32_t frames, int32_t win_h, int32_t win_w, int32_t *median, void *stream) {
+  if (!jih || !median) return set_error(IH_ERR_INVALID_ARG, "jih and median must be non-NULL");
+  if (H < 1 || W < 1 || C < 1 || bins < 1 || bins > 256)
+    return set_error(IH_ERR_INVALID_ARG, "shape %dx%dx%d with %d bins invalid", C, H, W, bins);
+  if (layout != IH_BHW && layout != IH_HWB) return set_error(IH_ERR_INVALID_ARG, "layout %d unknown", layout);
+  if (frames < 1 || win_h < 1 || win_w < 1)
+    return set_error(IH_ERR_INVALID_ARG, "frames %d and window %dx%d must be positive", frames, win_h, win_w);
+  if ((int64_t)frames * H * W >= ((int64_t)1 << 31))
+    return set_error(IH_ERR_OVERFLOW, "frames*H*W = %lld does not fit int32 counts", (long long)frames * H * W);
+  hipStream_t s = as_stream(stream);
+  if (layout == IH_BHW) {
+    dim3 grid((unsigned)((W + 63) / 64), (unsigned)((H + 3) / 4), (unsigned)C);
+    if (grid.y > 65535 || grid.z > 65535) return set_error(IH_ERR_RANGE, "image too tall for the median grid");
+    hipLaunchKernelGGL(k_median_bhw, grid, dim3(256), 0, s, jih, bins, H, W, frames, win_h, win_w, median);
+  } else {
+    const int64_t blocks = ((int64_t)C * H * W + 3) / 4;
+    if (blocks >= ((int64_t)1 << 31)) return set_error(IH_ERR_RANGE, "too many pixels for the median grid");
+    hipLaunchKernelGGL(k_median_hwb, dim3((unsigned)blocks), dim3(256), 0, s, jih, C, bins, H, W, frames, win_h,
+                       win_w, median);
+  }
+  return hip_check(hipGetLastError(), "median launch");
+}

@@ -40,6 +40,8 @@ SIGNATURES = {
     "ih_build": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "ih_build_weighted": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ,
                                          _P]),
+    "ih_jih_update": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "ih_local_median": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P]),
     "ih_query_rect": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I64, _P, _P]),
     "ih_query_weighted": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _I64, _I32, _I32, _P, _P]),
     "ih_pyramid_desc": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I64, _I32, _P, _P]),
@@ -259,6 +261,60 @@ def ih_build_weighted(img: torch.Tensor, bins: int, weight: torch.Tensor, mask: 
                                  ctypes.byref(cfg) if cfg is not None else None, _p(ws),
                                  ws.numel() * ws.element_size(), _stream(img))
     _check(rc, "ih_build_weighted")
+    return out
+
+
+def _frame_dtype(img: torch.Tensor):
+    if img.dtype == torch.uint8:
+        return IH_U8, 8
+    if img.dtype == torch.uint16:
+        return IH_U16, 16
+    raise IHError("frames must be uint8 or uint16")
+
+
+def ih_jih_update(head: torch.Tensor, tail: Optional[torch.Tensor], bins: int, jih: torch.Tensor,
+                  value_bits: Optional[int] = None, cfg: Optional[TileCfg] = None,
+                  ws: Optional[torch.Tensor] = None, layout: str = "bhw") -> torch.Tensor:
+    """Joint integral histogram update (Alg. 4): jih += IH(head) - IH(tail), in
+    place (tail None while the window fills).  Returns jih."""
+    _dev(head, "head")
+    if head.dim() == 2:
+        head = head.unsqueeze(0)
+    dt, maxbits = _frame_dtype(head)
+    C, H, W = head.shape
+    if tail is not None:
+        _dev(tail, "tail", head.dtype)
+        if tail.numel() != head.numel():
+            raise IHError("tail must have the head's shape")
+    bits = maxbits if value_bits is None else value_bits
+    _dev(jih, "jih", torch.int32)
+    if jih.numel() != C * bins * H * W:
+        raise IHError("jih must hold P*H*W values")
+    need = workspace_size(H, W, C, bins, False, cfg, layout)
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=head.device)
+    rc = lib().ih_jih_update(_p(head), _p(tail), dt, H, W, C, bins, bits, _layout(layout), _p(jih),
+                             ctypes.byref(cfg) if cfg is not None else None, _p(ws),
+                             ws.numel() * ws.element_size(), _stream(head))
+    _check(rc, "ih_jih_update")
+    return jih
+
+
+def ih_local_median(jih: torch.Tensor, C: int, bins: int, frames: int, win_h: int, win_w: int,
+                    out: Optional[torch.Tensor] = None, layout: str = "bhw") -> torch.Tensor:
+    """Per-pixel median bin of each win_h x win_w x frames box of a joint
+    integral histogram (Alg. 4).  C x H x W int32."""
+    _dev(jih, "jih", torch.int32)
+    P, H, W = _phw(jih, layout)
+    if P != C * bins:
+        raise IHError("jih has %d planes, expected C*bins = %d" % (P, C * bins))
+    if out is None:
+        out = torch.empty((C, H, W), dtype=torch.int32, device=jih.device)
+    _dev(out, "out", torch.int32)
+    if out.numel() != C * H * W:
+        raise IHError("out must hold C*H*W values")
+    _check(lib().ih_local_median(_p(jih), C, bins, H, W, _layout(layout), frames, win_h, win_w, _p(out),
+                                 _stream(jih)), "ih_local_median")
     return out
 
 

@@ -182,6 +182,43 @@ def phog_inputs(scale: float = 1.0, seed_base: int = 201):
     return f[4:5].copy(), f[5:6].copy(), f[6:7].copy()
 
 
+def surveillance_video(seed: int, n_frames: int, H: int = 576, W: int = 768, n_movers: int = 12,
+                       noise: int = 6) -> np.ndarray:
+    """Grey surveillance-style video (n_frames x H x W uint8), the input of the
+    spatio-temporal median: a static textured background (200 smooth(cell 32)
+    + 40 smooth(cell 4)), n_movers rectangles 8-60 px a side with their own
+    grey level U{0..255} moving at a constant velocity of 0.5-4 px/frame
+    (reflected at the borders), and fresh per-frame noise U{-noise..noise}."""
+    rng = np.random.default_rng(seed)
+    bg = 200.0 * smooth(rng, H, W, 32) + 40.0 * smooth(rng, H, W, 4)
+    hs = rng.integers(8, 61, n_movers)
+    ws = rng.integers(8, 61, n_movers)
+    y = rng.uniform(0, H - hs)
+    x = rng.uniform(0, W - ws)
+    speed = rng.uniform(0.5, 4.0, n_movers)
+    ang = rng.uniform(0, 2 * np.pi, n_movers)
+    vy, vx = speed * np.sin(ang), speed * np.cos(ang)
+    level = rng.integers(0, 256, n_movers)
+    out = np.empty((n_frames, H, W), np.uint8)
+    for f in range(n_frames):
+        img = bg.copy()
+        for i in range(n_movers):
+            r0, c0 = int(y[i]), int(x[i])
+            img[r0:r0 + hs[i], c0:c0 + ws[i]] = level[i]
+        img += rng.integers(-noise, noise + 1, size=(H, W))
+        out[f] = np.clip(img, 0, 255).astype(np.uint8)
+        y += vy
+        x += vx
+        for i in range(n_movers):
+            if y[i] < 0 or y[i] > H - hs[i]:
+                vy[i] = -vy[i]
+                y[i] = min(max(y[i], 0), H - hs[i])
+            if x[i] < 0 or x[i] > W - ws[i]:
+                vx[i] = -vx[i]
+                x[i] = min(max(x[i], 0), W - ws[i])
+    return out
+
+
 def config3(scale: float = 1.0, n_rects: int = 1_000_000, n_blobs: int = 2000,
             radius: int = 64, shifted: bool = False) -> Workload:
     """8192^2 uint16 aerial-style frame, 64 bins; 1M rects; 129x129 candidate grid."""
