@@ -48,6 +48,7 @@ def _load():
             P = ctypes.c_void_p
             I = ctypes.c_int
             I64 = ctypes.c_int64
+            D = ctypes.c_double
             sig = {
                 "or_check_values": [P, I, I, I, I, I],
                 "or_plane_index": [P, I, I, I, I, I, I, P],
@@ -68,6 +69,13 @@ def _load():
                 "or_level_weight": [I, I],
                 "or_num_threads": [],
                 "or_ih_weighted": [P, I, P, P, I, I, I, I, I, P],
+                "or_kernel_bruteforce": [P, I, I, I, I, I, I, P, I64, I, D, I, P],
+                "or_moments2": [P, I, I, I, I, I, I, P, P],
+                "or_quadratic_numerator": [P, I, I, I, I, I, I, P, I64, P],
+                "or_quadratic_swih": [P, P, P, P, P, I, I, I, I, P, I64, I, P, P],
+                "or_ring_weights": [I, I, I, I, D, P],
+                "or_wedding": [P, I, I, I, P, I64, I, I, D, P],
+                "or_wedding_direct": [P, I, I, I, I, I, I, P, I64, I, I, D, P],
                 "or_jih": [P, I, I, I, I, I, I, I, P],
                 "or_st_median": [P, I, I, I, I, I, I, I, I, I, P],
                 "or_ih_weighted_bruteforce": [P, I, P, P, I, I, I, I, I, P],
@@ -284,6 +292,79 @@ def weighted_swih(ihist, mx, my, C, rects, l1norm=False):
     _check(_load().or_weighted_swih(_ptr(t), _ptr(mx), _ptr(my), P, H, W, C, _ptr(r), n,
                                     int(bool(l1norm)), _ptr(num), _ptr(out)), "weighted_swih")
     return num, out
+
+
+KERNELS = {"manhattan": 0, "quadratic": 1, "gaussian": 2}
+
+
+def kernel_bruteforce(img, bins, bits, rects, kernel="manhattan", sigma=0.5, l1norm=False):
+    """Eq. 3.1 by brute force in FP64 with the Manhattan, quadratic or Gaussian
+    kernel (normalised window coordinates); n x P float64."""
+    a, dt, C, H, W = _img(img)
+    r, n = _rects(rects)
+    out = np.empty((n, C * bins), np.float64)
+    _check(_load().or_kernel_bruteforce(_ptr(a), dt, H, W, C, bins, bits, _ptr(r), n, KERNELS[kernel],
+                                        float(sigma), int(bool(l1norm)), _ptr(out)), "kernel_bruteforce")
+    return out
+
+
+def moments2(img, bins, bits):
+    """Second coordinate-moment integral histograms (Mxx, Myy), P x H x W int64."""
+    a, dt, C, H, W = _img(img)
+    mxx = np.empty((C * bins, H, W), np.int64)
+    myy = np.empty((C * bins, H, W), np.int64)
+    _check(_load().or_moments2(_ptr(a), dt, H, W, C, bins, bits, _ptr(mxx), _ptr(myy)), "moments2")
+    return mxx, myy
+
+
+def quadratic_numerator(img, bins, bits, rects):
+    a, dt, C, H, W = _img(img)
+    r, n = _rects(rects)
+    out = np.empty((n, C * bins), np.int64)
+    _check(_load().or_quadratic_numerator(_ptr(a), dt, H, W, C, bins, bits, _ptr(r), n, _ptr(out)),
+           "quadratic_numerator")
+    return out
+
+
+def quadratic_swih(ihist, mx, my, mxx, myy, C, rects, l1norm=False):
+    """The quadratic kernel from five integral histograms: (int64 numerators, float32 values)."""
+    t = np.ascontiguousarray(ihist, dtype=np.int32)
+    arrs = [np.ascontiguousarray(m, dtype=np.int64) for m in (mx, my, mxx, myy)]
+    P, H, W = t.shape
+    r, n = _rects(rects)
+    num = np.empty((n, P), np.int64)
+    out = np.empty((n, P), np.float32)
+    _check(_load().or_quadratic_swih(_ptr(t), *[_ptr(m) for m in arrs], P, H, W, C, _ptr(r), n,
+                                     int(bool(l1norm)), _ptr(num), _ptr(out)), "quadratic_swih")
+    return num, out
+
+
+def ring_weights(h, w, layers, kernel="manhattan", sigma=0.5):
+    """The wedding cake's ring weights (Eq. 3.2) for an h x w window."""
+    out = np.empty(layers, np.float64)
+    _check(_load().or_ring_weights(h, w, layers, KERNELS[kernel], float(sigma), _ptr(out)), "ring_weights")
+    return out
+
+
+def wedding(ihist, rects, layers, kernel="manhattan", sigma=0.5):
+    """Wedding-cake approximation (Eq. 3.2) from the count IH; n x P float64."""
+    t = np.ascontiguousarray(ihist, dtype=np.int32)
+    P, H, W = t.shape
+    r, n = _rects(rects)
+    out = np.empty((n, P), np.float64)
+    _check(_load().or_wedding(_ptr(t), P, H, W, _ptr(r), n, layers, KERNELS[kernel], float(sigma), _ptr(out)),
+           "wedding")
+    return out
+
+
+def wedding_direct(img, bins, bits, rects, layers, kernel="manhattan", sigma=0.5):
+    """The wedding-cake approximation by direct per-pixel ring counting; n x P float64."""
+    a, dt, C, H, W = _img(img)
+    r, n = _rects(rects)
+    out = np.empty((n, C * bins), np.float64)
+    _check(_load().or_wedding_direct(_ptr(a), dt, H, W, C, bins, bits, _ptr(r), n, layers, KERNELS[kernel],
+                                     float(sigma), _ptr(out)), "wedding_direct")
+    return out
 
 
 def _wins(wins):

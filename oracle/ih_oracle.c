@@ -400,6 +400,266 @@ int or_weighted_swih(const int32_t *ih, const int64_t *mx, const int64_t *my,
 }
 
 /* ------------------------------------------------------------------------ */
+/* More spatial kernels for Eq. 3.1 (Fig. 3.1) and the wedding cake (Eq. 3.2) */
+/*                                                                            */
+/* Normalised window coordinates: for a window of h rows and w columns with   */
+/* centre xc = (r0+r1-1)/2, yc = (c0+c1-1)/2,                                  */
+/*   u = (x - xc) / (h/2),  v = (y - yc) / (w/2).                              */
+/* Kernels (weights, 1 at the centre):                                        */
+/*   0 Manhattan  K = 1 - (|u| + |v|) / 2          (Eq. 3.3)                  */
+/*   1 quadratic  K = 1 - (u^2 + v^2) / 2          (squared Euclidean         */
+/*                                                  distance)                 */
+/*   2 Gaussian   K = exp(-(u^2 + v^2) / (2 s^2))  (s relative to the         */
+/*                                                  half-sizes)               */
+/* The quadratic kernel's integer form: K = N2 / (2 h^2 w^2) with             */
+/*   N2 = 2 h^2 w^2 - w^2 (2x - X)^2 - h^2 (2y - Y)^2,  X = r0+r1-1, Y = c0+c1-1. */
+/* ------------------------------------------------------------------------ */
+static double or_kernel(int kernel, double u, double v, double sigma) {
+  if (kernel == 0) return 1.0 - 0.5 * (fabs(u) + fabs(v));
+  if (kernel == 1) return 1.0 - 0.5 * (u * u + v * v);
+  return exp(-(u * u + v * v) / (2.0 * sigma * sigma));
+}
+
+/* Eq. 3.1 by brute force in FP64 for any of the three kernels; with l1norm
+   each channel is divided by the window's total weight. */
+int or_kernel_bruteforce(const void *img, int dtype, int H, int W, int C, int bins, int bits,
+                         const int32_t *rects, int64_t n, int kernel, double sigma, int l1norm,
+                         double *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (kernel < 0 || kernel > 2 || (kernel == 2 && !(sigma > 0))) return OR_ERR_ARG;
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    double *o = out + i * P;
+    int ok = or_rect_ok(q, H, W);
+    for (int p = 0; p < P; p++) o[p] = ok ? 0.0 : NAN;
+    if (!ok || q[0] == q[2] || q[1] == q[3]) continue;
+    double h = q[2] - q[0], w = q[3] - q[1];
+    double xc = (q[0] + q[2] - 1) / 2.0, yc = (q[1] + q[3] - 1) / 2.0;
+    double wsum = 0.0;
+    for (int r = q[0]; r < q[2]; r++)
+      for (int c = q[1]; c < q[3]; c++) wsum += or_kernel(kernel, (r - xc) / (h / 2), (c - yc) / (w / 2), sigma);
+    for (int ch = 0; ch < C; ch++) {
+      for (int r = q[0]; r < q[2]; r++)
+        for (int c = q[1]; c < q[3]; c++) {
+          uint32_t v = or_value(img, dtype, ((int64_t)ch * H + r) * W + c);
+          o[ch * bins + or_bin_of(v, bins, bits)] += or_kernel(kernel, (r - xc) / (h / 2), (c - yc) / (w / 2), sigma);
+        }
+      if (l1norm)
+        for (int b = 0; b < bins; b++) o[ch * bins + b] /= wsum;
+    }
+  }
+  return OR_OK;
+}
+
+/* Second coordinate-moment integral histograms: sums of row^2 * [bin = p]
+   and column^2 * [bin = p] over [0, r] x [0, c] (the weighted integral
+   histograms of Eq. 3.4 for the weights x^2 and y^2), exact in int64. */
+int or_moments2(const void *img, int dtype, int H, int W, int C, int bins, int bits, int64_t *mxx,
+                int64_t *myy) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int p = 0; p < P; p++) {
+    int64_t *a = mxx + (int64_t)p * H * W, *b = myy + (int64_t)p * H * W;
+    for (int x = 0; x < H; x++)
+      for (int y = 0; y < W; y++) {
+        int64_t q = or_Q(img, dtype, H, W, bins, bits, p, x, y);
+        int64_t i = (int64_t)x * W + y;
+        int64_t up_a = x ? a[i - W] : 0, left_a = y ? a[i - 1] : 0, diag_a = (x && y) ? a[i - W - 1] : 0;
+        int64_t up_b = x ? b[i - W] : 0, left_b = y ? b[i - 1] : 0, diag_b = (x && y) ? b[i - W - 1] : 0;
+        a[i] = up_a + left_a - diag_a + q * x * x;
+        b[i] = up_b + left_b - diag_b + q * y * y;
+      }
+  }
+  return OR_OK;
+}
+
+/* Brute-force integer numerators of the quadratic kernel: sum of N2 over
+   the window's pixels of each plane. */
+int or_quadratic_numerator(const void *img, int dtype, int H, int W, int C, int bins, int bits,
+                           const int32_t *rects, int64_t n, int64_t *num) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    for (int p = 0; p < P; p++) num[i * P + p] = 0;
+    if (!or_rect_ok(q, H, W)) continue;
+    int64_t h = q[2] - q[0], w = q[3] - q[1];
+    int64_t X = q[0] + q[2] - 1, Y = q[1] + q[3] - 1;
+    for (int ch = 0; ch < C; ch++)
+      for (int64_t r = q[0]; r < q[2]; r++)
+        for (int64_t c = q[1]; c < q[3]; c++) {
+          int64_t N2 = 2 * h * h * w * w - w * w * (2 * r - X) * (2 * r - X) - h * h * (2 * c - Y) * (2 * c - Y);
+          uint32_t v = or_value(img, dtype, ((int64_t)ch * H + r) * W + c);
+          num[i * P + ch * bins + or_bin_of(v, bins, bits)] += N2;
+        }
+  }
+  return OR_OK;
+}
+
+/* The quadratic kernel in O(1) per window from five integral histograms,
+   after Sec. 3.1.3's steps: (1) the weight N2 is a combination of the
+   independent weights 1, x, x^2, y, y^2 (the quadratic kernel needs no
+   quadrant split); (2) their weighted integral histograms are the count,
+   moment and second-moment IHs (Eq. 3.4); (3) each is read over the window
+   with Eq. 2.16 and the combination is taken about the window centre:
+     sum N2 = 2h^2w^2 n - w^2 (4 Sxx - 4 X Sx + X^2 n) - h^2 (4 Syy - 4 Y Sy + Y^2 n);
+   (4) normalised by 2h^2w^2, or by the window's total weight with l1norm,
+   in FP64 and rounded to FP32.  The integer numerator is also returned. */
+int or_quadratic_swih(const int32_t *ih, const int64_t *mx, const int64_t *my, const int64_t *mxx,
+                      const int64_t *myy, int P, int H, int W, int C, const int32_t *rects, int64_t n,
+                      int l1norm, int64_t *num, float *out) {
+  if (C < 1 || P % C != 0) return OR_ERR_ARG;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    int ok = or_rect_ok(q, H, W);
+    int64_t h = q[2] - q[0], w = q[3] - q[1];
+    for (int p = 0; p < P; p++) {
+      num[i * P + p] = 0;
+      out[i * P + p] = ok ? 0.0f : NAN;
+    }
+    if (!ok || h == 0 || w == 0) continue;
+    int64_t X = q[0] + q[2] - 1, Y = q[1] + q[3] - 1;
+    int64_t total = 0;
+    for (int64_t r = q[0]; r < q[2]; r++)
+      for (int64_t c = q[1]; c < q[3]; c++)
+        total += 2 * h * h * w * w - w * w * (2 * r - X) * (2 * r - X) - h * h * (2 * c - Y) * (2 * c - Y);
+    for (int p = 0; p < P; p++) {
+      int64_t cnt = or_rect32(ih, H, W, p, q[0], q[1], q[2], q[3]);
+      int64_t Sx = or_rect64(mx, H, W, p, q[0], q[1], q[2], q[3]);
+      int64_t Sy = or_rect64(my, H, W, p, q[0], q[1], q[2], q[3]);
+      int64_t Sxx = or_rect64(mxx, H, W, p, q[0], q[1], q[2], q[3]);
+      int64_t Syy = or_rect64(myy, H, W, p, q[0], q[1], q[2], q[3]);
+      int64_t acc = 2 * h * h * w * w * cnt - w * w * (4 * Sxx - 4 * X * Sx + X * X * cnt) -
+                    h * h * (4 * Syy - 4 * Y * Sy + Y * Y * cnt);
+      num[i * P + p] = acc;
+      double den = l1norm ? (double)total : (double)(2 * h * h * w * w);
+      out[i * P + p] = (float)((double)acc / den);
+    }
+  }
+  return OR_OK;
+}
+
+/* Wedding cake (Eq. 3.2, Sec. 3.1.2).  Window R with h rows and w columns;
+   layers j = 1..L are the centred nested windows R_j with margins
+   m_j = floor((L-j) h / (2L)) rows and n_j = floor((L-j) w / (2L)) columns
+   on each side (R_L = R).  Ring j = R_j minus R_{j-1} (R_0 empty) gets one
+   weight: the mean of the kernel over the ring in the normalised window
+   coordinates, where R_j is the rectangle [-a_j, a_j] x [-b_j, b_j] with
+   a_j = 1 - 2 m_j / h and b_j = 1 - 2 n_j / w:
+     w_j = (I(a_j, b_j) - I(a_{j-1}, b_{j-1})) / (4 a_j b_j - 4 a_{j-1} b_{j-1}),
+   I(a, b) being the kernel's integral over [-a, a] x [-b, b]:
+     Manhattan  4ab - ab(a + b);   quadratic  4ab - (2/3) ab (a^2 + b^2);
+     Gaussian   F(a) F(b), F(t) = s sqrt(2 pi) erf(t / (s sqrt 2)).
+   SWLH(R) = sum_j w_j (H(R_j) - H(R_{j-1})), plane by plane. */
+static double or_kernel_integral(int kernel, double a, double b, double sigma) {
+  if (kernel == 0) return 4 * a * b - a * b * (a + b);
+  if (kernel == 1) return 4 * a * b - (2.0 / 3.0) * a * b * (a * a + b * b);
+  double fa = sigma * sqrt(2.0 * M_PI) * erf(a / (sigma * sqrt(2.0)));
+  double fb = sigma * sqrt(2.0 * M_PI) * erf(b / (sigma * sqrt(2.0)));
+  return fa * fb;
+}
+
+int or_ring_weights(int h, int w, int layers, int kernel, double sigma, double *wt) {
+  if (h < 1 || w < 1 || layers < 1 || kernel < 0 || kernel > 2 || (kernel == 2 && !(sigma > 0)))
+    return OR_ERR_ARG;
+  double a0 = 0.0, b0 = 0.0, i0 = 0.0;
+  for (int j = 1; j <= layers; j++) {
+    int64_t m = ((int64_t)(layers - j) * h) / (2 * layers), k = ((int64_t)(layers - j) * w) / (2 * layers);
+    double a = 1.0 - 2.0 * (double)m / h, b = 1.0 - 2.0 * (double)k / w;
+    double i1 = or_kernel_integral(kernel, a, b, sigma);
+    double area = 4 * a * b - 4 * a0 * b0;
+    /* a layer that adds no pixels has no ring; its weight is never used */
+    wt[j - 1] = area > 0 ? (i1 - i0) / area : 0.0;
+    a0 = a;
+    b0 = b;
+    i0 = i1;
+  }
+  return OR_OK;
+}
+
+static void or_layer_window(const int32_t *q, int layers, int j, int *r0, int *c0, int *r1, int *c1) {
+  int h = q[2] - q[0], w = q[3] - q[1];
+  int mr = (int)(((int64_t)(layers - j) * h) / (2 * layers));
+  int mc = (int)(((int64_t)(layers - j) * w) / (2 * layers));
+  *r0 = q[0] + mr;
+  *r1 = q[2] - mr;
+  *c0 = q[1] + mc;
+  *c1 = q[3] - mc;
+}
+
+int or_wedding(const int32_t *ih, int P, int H, int W, const int32_t *rects, int64_t n, int layers,
+               int kernel, double sigma, double *out) {
+  if (layers < 1 || layers > 64 || kernel < 0 || kernel > 2 || (kernel == 2 && !(sigma > 0))) return OR_ERR_ARG;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    int ok = or_rect_ok(q, H, W);
+    double wt[64];
+    if (ok && q[0] < q[2] && q[1] < q[3]) or_ring_weights(q[2] - q[0], q[3] - q[1], layers, kernel, sigma, wt);
+    for (int p = 0; p < P; p++) {
+      double acc = 0.0;
+      int64_t prev = 0;
+      if (ok && q[0] < q[2] && q[1] < q[3]) {
+        for (int j = 1; j <= layers; j++) {
+          int r0, c0, r1, c1;
+          or_layer_window(q, layers, j, &r0, &c0, &r1, &c1);
+          int64_t cur = or_rect32(ih, H, W, p, r0, c0, r1, c1);
+          acc += wt[j - 1] * (double)(cur - prev);
+          prev = cur;
+        }
+      }
+      out[i * P + p] = ok ? acc : NAN;
+    }
+  }
+  return OR_OK;
+}
+
+/* The same approximation by direct counting: each pixel of the window goes to
+   the innermost layer window that contains it and adds that ring's weight. */
+int or_wedding_direct(const void *img, int dtype, int H, int W, int C, int bins, int bits,
+                      const int32_t *rects, int64_t n, int layers, int kernel, double sigma, double *out) {
+  int e = or_check(dtype, H, W, C, bins, bits);
+  if (e) return e;
+  if (layers < 1 || layers > 64 || kernel < 0 || kernel > 2 || (kernel == 2 && !(sigma > 0))) return OR_ERR_ARG;
+  int P = C * bins;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t *q = rects + 4 * i;
+    double *o = out + i * P;
+    int ok = or_rect_ok(q, H, W);
+    for (int p = 0; p < P; p++) o[p] = ok ? 0.0 : NAN;
+    if (!ok || q[0] == q[2] || q[1] == q[3]) continue;
+    double wt[64];
+    or_ring_weights(q[2] - q[0], q[3] - q[1], layers, kernel, sigma, wt);
+    for (int r = q[0]; r < q[2]; r++)
+      for (int c = q[1]; c < q[3]; c++) {
+        int ring = layers;
+        for (int j = 1; j <= layers; j++) {
+          int r0, c0, r1, c1;
+          or_layer_window(q, layers, j, &r0, &c0, &r1, &c1);
+          if (r >= r0 && r < r1 && c >= c0 && c < c1) {
+            ring = j;
+            break;
+          }
+        }
+        for (int ch = 0; ch < C; ch++) {
+          uint32_t v = or_value(img, dtype, ((int64_t)ch * H + r) * W + c);
+          o[ch * bins + or_bin_of(v, bins, bits)] += wt[ring - 1];
+        }
+      }
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Spatial pyramid descriptor (Alg. 2; layout per Sec. 2.4.4).               */
 /* Level l has 2^l x 2^l cells; cell (i, j) of a window at (r, c) with h     */
 /* rows and w columns covers rows [r + floor(i*h/2^l), r + floor((i+1)*h/2^l))*/
