@@ -64,6 +64,8 @@ def parse():
                     help="run only the magnitude-weighted orientation histogram and print its JSON object")
     ap.add_argument("--median-only", action="store_true",
                     help="run only the spatio-temporal median and print its JSON object")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="run only the spatial-kernel accuracy/time comparison and print its JSON object")
     ap.add_argument("--train-videos", type=int, default=800)
     ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--tile", type=str, default="",
@@ -277,6 +279,58 @@ def median_leg(torch, ih, synth):
     return res
 
 
+def kernels_leg(torch, ih, synth, sample=400):
+    """Accuracy against time of the spatially weighted local histograms on the
+    1920x1080, 7-channel x 16-bin frame with 100,000 windows (sides 16-256):
+    exact SWIH with the Manhattan and quadratic kernels (O(1) from the count,
+    moment and second-moment integral histograms) and the wedding cake of
+    Eq. 3.2 with 1-8 layers for the Manhattan, quadratic and Gaussian
+    (sigma 0.5) kernels.  Each query batch is graph-replayed; its error is
+    the relative L1 distance to the oracle's FP64 brute force of the same
+    kernel on `sample` of the windows, whose CPU time is also reported."""
+    import oracle
+    dev = torch.device("cuda:0")
+    w = synth.config2()
+    img = torch.from_numpy(w.img).to(dev)
+    rects = torch.from_numpy(w.windows).to(dev)
+    n = rects.shape[0]
+    P = w.P
+    c, mx, my = ih.ih_build(img, w.bins, w.bits, moments=True, layout="hwb")
+    mxx, myy = ih.ih_build_moments2(img, w.bins, w.bits, layout="hwb")
+    t_build = graph_median(torch, lambda: ih.ih_build(img, w.bins, w.bits, moments=True, out=c, mom_out=(mx, my),
+                                                      layout="hwb"), 5)
+    t_m2 = graph_median(torch, lambda: ih.ih_build_moments2(img, w.bins, w.bits, out=(mxx, myy), layout="hwb"), 5)
+    out = torch.empty((n, P), dtype=torch.float32, device=dev)
+    samp = w.windows[:sample]
+    t0 = time.perf_counter()
+    bf = {k: oracle.kernel_bruteforce(w.img, w.bins, w.bits, samp, k, 0.5) for k in ("manhattan", "quadratic",
+                                                                                   "gaussian")}
+    cpu_s = time.perf_counter() - t0
+    methods = [("swih", "manhattan", 0, lambda: ih.ih_query_weighted(c, mx, my, w.C, rects, out=out, layout="hwb")),
+               ("swih", "quadratic", 0, lambda: ih.ih_query_quadratic(c, mx, my, mxx, myy, w.C, rects, out=out,
+                                                                      layout="hwb"))]
+    for kern in ("manhattan", "quadratic", "gaussian"):
+        for L in (1, 2, 3, 5, 8):
+            methods.append(("wedding", kern, L, (lambda k=kern, l=L: ih.ih_query_wedding(c, w.C, rects, l, k, 0.5,
+                                                                                      out=out, layout="hwb"))))
+    rows = []
+    for name, kern, L, fn in methods:
+        t = graph_median(torch, fn, 10)
+        fn()
+        torch.cuda.synchronize()
+        got = out[:sample].cpu().numpy().astype(np.float64)
+        ref = bf[kern]
+        err = float(np.abs(got - ref).sum() / np.abs(ref).sum())
+        rows.append({"method": name, "kernel": kern, "layers": L, "ms": round(t, 4),
+                     "windows_per_s": round(n / t * 1e3, 1), "rel_l1_err": float("%.3g" % err)})
+    return {"workload": "1920x1080 frame, 7 u8 channels x 16 bins, 100k windows 16-256 px (planes innermost)",
+            "windows": int(n), "build_count_and_moments_ms": round(t_build, 4), "build_second_moments_ms":
+            round(t_m2, 4), "methods": rows,
+            "cpu_bruteforce": {"windows": sample, "kernels": 3, "seconds": round(cpu_s, 3),
+                               "ms_per_window_per_kernel": round(cpu_s / sample / 3 * 1e3, 4),
+                               "threads": oracle.num_threads()}}
+
+
 def copy_calibration(torch, mib):
     """One device fill and one device-to-device copy of `mib` MiB: the copy
     kernel's FETCH_SIZE and WRITE_SIZE against its known bytes give the
@@ -339,6 +393,8 @@ def config_legs(torch, ih, synth, fixed=False):
     res["phog_1920x1080_16bins"] = phog_leg(torch, ih, synth)
     # spatio-temporal median of a 768x576 video
     res["median_768x576_256bins"] = median_leg(torch, ih, synth)
+    # spatial kernels: exact SWIH against the wedding cake
+    res["swih_kernels_1920x1080x112"] = kernels_leg(torch, ih, synth)
 
     # 8192x8192 u16, 64 bins, 1M rectangles, 129x129 search
     w = synth.config3()
@@ -583,6 +639,9 @@ def main():
         return
     if args.workloads_only:
         print(json.dumps(config_legs(torch, ih, synth, args.fixed_tiles)), flush=True)
+        return
+    if args.kernels_only:
+        print(json.dumps(kernels_leg(torch, ih, synth)), flush=True)
         return
     if args.median_only:
         res = median_leg(torch, ih, synth)

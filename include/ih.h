@@ -51,7 +51,7 @@ extern "C" {
 
 typedef enum { IH_U8 = 0, IH_U16 = 1 } ih_dtype;
 typedef enum { IH_CHI2 = 0, IH_L1 = 1, IH_PMK = 2 } ih_metric;
-typedef enum { IH_MANHATTAN = 0 } ih_kernel;
+typedef enum { IH_MANHATTAN = 0, IH_QUADRATIC = 1, IH_GAUSSIAN = 2 } ih_kernel;
 
 /*
  * Memory layout of integral-histogram tensors (and their moment tensors).
@@ -315,6 +315,77 @@ int ih_build_batch(const void *plan_host, const void *plan_dev, void *ws,
                    size_t ws_bytes, int32_t mode, void *stream);
 
 /*
+ * ih_build_moments2 - second coordinate-moment integral histograms (the
+ * weighted integral histograms of Eq. 3.4 for the weights x^2 and y^2):
+ *   Mxx(p,r,c) = sum over r' <= r, c' <= c of r'^2 * [bin(r',c') = p]
+ *   Myy(p,r,c) = sum over r' <= r, c' <= c of c'^2 * [bin(r',c') = p]
+ * stored modulo 2^32, by two builds with coordinate weights.  With the count
+ * and moment tensors of ih_build they give the quadratic kernel in O(1)
+ * (ih_query_quadratic).
+ *   img, dtype, H, W, C, bins, value_bits, layout, cfg, ws, ws_bytes, stream
+ *               as for ih_build (workspace: ih_build_workspace_size with
+ *               moments = 0).
+ *   mom_xx, mom_yy  device, out: P x H x W uint32 each (in layout).
+ * Returns IH_OK or IH_ERR_*.
+ */
+int ih_build_moments2(const void *img, int32_t dtype, int32_t H, int32_t W,
+                      int32_t C, int32_t bins, int32_t value_bits,
+                      int32_t layout, uint32_t *mom_xx, uint32_t *mom_yy,
+                      const ih_tile_cfg *cfg, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/*
+ * ih_query_quadratic - spatially weighted local histograms (Eq. 3.1) with the
+ * quadratic kernel of the squared Euclidean distance (Fig. 3.1), exact in
+ * O(1) per window: the weight is a combination of 1, x, x^2, y, y^2, each
+ * read over the window from its integral histogram (Eq. 3.4, Eq. 2.16) and
+ * combined about the window centre (the SWIH steps of Sec. 3.1.3; this
+ * kernel needs no quadrant split).
+ *
+ * Weight of pixel (x, y) in a window of h rows and w columns, in normalised
+ * coordinates u = (x - xc) / (h/2), v = (y - yc) / (w/2) with
+ * xc = (r0 + r1 - 1) / 2, yc = (c0 + c1 - 1) / 2:
+ *   K = 1 - (u^2 + v^2) / 2 = N2 / (2 h^2 w^2),
+ *   N2 = 2 h^2 w^2 - w^2 (2x - (r0+r1-1))^2 - h^2 (2y - (c0+c1-1))^2.
+ * out(q, p) = the sum of N2 over the window's pixels of plane p, an exact
+ * int64, divided in FP64 by 2 h^2 w^2 (or, with l1_normalize, by the sum of
+ * N2 over the whole window), rounded to FP32.
+ *
+ *   ih, mom_x, mom_y   device, from ih_build with moments, in `layout`.
+ *   mom_xx, mom_yy     device, from ih_build_moments2, in `layout`.
+ *   P, H, W, C, layout, rects, n, out, stream  as for ih_query_weighted.
+ * Empty windows give zeros; windows outside the frame, or so large that
+ * w (h-1) h (2h-1) / 6 or h (w-1) w (2w-1) / 6 reaches 2^32, give NaN.
+ */
+int ih_query_quadratic(const int32_t *ih, const uint32_t *mom_x,
+                       const uint32_t *mom_y, const uint32_t *mom_xx,
+                       const uint32_t *mom_yy, int32_t P, int32_t H,
+                       int32_t W, int32_t C, int32_t layout,
+                       const ih_rect *rects, int64_t n, int32_t l1_normalize,
+                       float *out, void *stream);
+
+/*
+ * ih_query_wedding - the wedding-cake approximation of a spatially weighted
+ * local histogram (Eq. 3.2, Sec. 3.1.2), from the count integral histogram.
+ * Layer j = 1..layers of a window with h rows and w columns is the centred
+ * window with margins floor((layers-j) h / (2 layers)) rows and
+ * floor((layers-j) w / (2 layers)) columns (layer `layers` is the window);
+ * ring j (layer j minus layer j-1) is weighted by the kernel's mean over the
+ * ring in normalised coordinates (the kernel as for ih_query_quadratic:
+ * IH_MANHATTAN 1 - (|u|+|v|)/2, IH_QUADRATIC 1 - (u^2+v^2)/2, IH_GAUSSIAN
+ * exp(-(u^2+v^2) / (2 sigma^2))).  The sum over rings of weight times ring
+ * count is taken in FP64 and rounded to FP32, on the same scale as the
+ * exact kernels' non-normalised output.
+ *   layers   1..16;  sigma  > 0 for IH_GAUSSIAN (relative to the half-sizes).
+ *   Other arguments as for ih_query_weighted; empty windows give zeros,
+ *   windows outside the frame NaN.
+ */
+int ih_query_wedding(const int32_t *ih, int32_t P, int32_t H, int32_t W,
+                     int32_t C, int32_t layout, const ih_rect *rects,
+                     int64_t n, int32_t layers, int32_t kernel, double sigma,
+                     float *out, void *stream);
+
+/*
  * ih_jih_update - joint integral histogram update of the spatio-temporal
  * median (Alg. 4, Fig. 4.1): JIH = JIH + IH(head) - IH(tail), in place.
  * The joint IH of a window of frames is the integral histogram of all their
@@ -362,7 +433,8 @@ int ih_local_median(const int32_t *jih, int32_t C, int32_t bins, int32_t H,
 
 /*
  * ih_profile_events - profiling hook.  When both are non-NULL (hipEvent_t),
- * every later ih_build on this thread records `start` on its stream just
+ * every later build on this thread (ih_build, ih_build_weighted,
+ * ih_build_moments2, ih_jih_update) records `start` on its stream just
  * before its final write-out kernel and `stop` just after it, so that the
  * caller can time that kernel alone.  Passing NULL, NULL turns it off.
  */

@@ -11,13 +11,16 @@ from .ih import (  # noqa: F401
     TileCfg,
     cells,
     ih_build,
+    ih_build_moments2,
     ih_build_weighted,
     ih_jih_update,
     ih_local_median,
     ih_match_candidates,
     ih_profile_events,
     ih_pyramid_desc,
+    ih_query_quadratic,
     ih_query_rect,
+    ih_query_wedding,
     ih_query_weighted,
     lib,
     lib_path,

@@ -61,6 +61,7 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
   g->mom = moments != 0;
   g->wgt = weighted != 0;
   g->diff = false;
+  g->coord = 0;
   if (g->mom && g->wgt) return set_error(IH_ERR_UNSUPPORTED, "moments of a weighted histogram are not built");
   g->layout = layout;
   int TH, TW, PG;
@@ -127,9 +128,9 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
 template <typename T>
 __global__ __launch_bounds__(256) void k_tile_hist(const T *__restrict__ img, Geom g, int bits, int bc,
                                                    uint32_t *__restrict__ ws, const uint8_t *__restrict__ wt,
-                                                   const uint8_t *__restrict__ mask) {
+                                                   const uint8_t *__restrict__ mask, const T *__restrict__ tail) {
   extern __shared__ uint32_t lds[];
-  tile_hist_body<T>(img, g, bits, bc, ws, blockIdx.x, lds, wt, mask);
+  tile_hist_body<T>(img, g, bits, bc, ws, blockIdx.x, lds, wt, mask, tail);
 }
 
 __global__ __launch_bounds__(256) void k_carry_scan(Geom g, int64_t nblk_a, int64_t nblk_b,
@@ -137,21 +138,7 @@ __global__ __launch_bounds__(256) void k_carry_scan(Geom g, int64_t nblk_a, int6
   carry_scan_body(g, nblk_a, nblk_b, ws, blockIdx.x);
 }
 
-template <typename T, int CPL, int PG, bool MOM, bool WGT>
-__global__ __launch_bounds__(256) void k_final(FinalArgs a, Geom g) {
-  final_body<T, CPL, PG, MOM, WGT>(a, g, blockIdx.x, blockIdx.y, uniform(threadIdx.x >> 6), blockDim.x >> 6);
-}
 
-template <typename T, int TW, bool MOM, bool WGT>
-__global__ __launch_bounds__(256) void k_final_hwb(FinalArgs a, Geom g) {
-  final_hwb_body<T, TW, MOM, WGT>(a, g, (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform(threadIdx.x >> 6));
-}
-
-template <typename T, int TW, bool MOM, bool WGT>
-__global__ __launch_bounds__(512) void k_final_hwb_staged(FinalArgs a, Geom g) {
-  extern __shared__ uint32_t seg[];
-  final_hwb_staged_body<T, TW, MOM, WGT>(a, g, blockIdx.x, seg);
-}
 
 
 // ------------------------------------------------------------------ host --
@@ -160,12 +147,10 @@ struct ProfileHook {
 };
 static thread_local ProfileHook g_hook;
 
-typedef void (*final_fn)(FinalArgs, Geom);
-
-template <typename T, bool MOM, bool WGT = false>
+template <typename T, bool MOM, int WK = 0>
 static final_fn pick_final_t(int CPL, int PG) {
 #define IH_F(C_, G_) \
-  if (CPL == C_ && PG == G_) return &k_final<T, C_, G_, MOM, WGT>;
+  if (CPL == C_ && PG == G_) return &k_final<T, C_, G_, MOM, WK>;
   if constexpr (MOM) {
     IH_F(1, 1) IH_F(1, 2) IH_F(1, 4) IH_F(1, 8) IH_F(1, 16)
     IH_F(2, 1) IH_F(2, 2) IH_F(2, 4) IH_F(2, 8) IH_F(2, 16)
@@ -179,20 +164,20 @@ static final_fn pick_final_t(int CPL, int PG) {
   return nullptr;
 }
 
-template <typename T, bool MOM, bool WGT = false>
+template <typename T, bool MOM, int WK = 0>
 static final_fn pick_hwb_t(int TW, bool staged) {
   if (staged) {
-    if (TW == 16) return &k_final_hwb_staged<T, 16, MOM, WGT>;
+    if (TW == 16) return &k_final_hwb_staged<T, 16, MOM, WK>;
     if constexpr (!MOM) {
-      if (TW == 32) return &k_final_hwb_staged<T, 32, MOM, WGT>;
-      if (TW == 64) return &k_final_hwb_staged<T, 64, MOM, WGT>;
+      if (TW == 32) return &k_final_hwb_staged<T, 32, MOM, WK>;
+      if (TW == 64) return &k_final_hwb_staged<T, 64, MOM, WK>;
     }
     return nullptr;
   }
-  if (TW == 16) return &k_final_hwb<T, 16, MOM, WGT>;
-  if (TW == 32) return &k_final_hwb<T, 32, MOM, WGT>;
+  if (TW == 16) return &k_final_hwb<T, 16, MOM, WK>;
+  if (TW == 32) return &k_final_hwb<T, 32, MOM, WK>;
   if constexpr (!MOM) {
-    if (TW == 64) return &k_final_hwb<T, 64, MOM, WGT>;
+    if (TW == 64) return &k_final_hwb<T, 64, MOM, WK>;
   }
   return nullptr;
 }
@@ -202,9 +187,9 @@ static final_fn pick_final(int dtype, const Geom &g) {
   if (g.wgt) {
     if (g.layout == IH_HWB) {
       const bool st = staged_lds(g) > 0;
-      return u8 ? pick_hwb_t<uint8_t, false, true>(g.TW, st) : pick_hwb_t<uint16_t, false, true>(g.TW, st);
+      return u8 ? pick_hwb_t<uint8_t, false, 1>(g.TW, st) : pick_hwb_t<uint16_t, false, 1>(g.TW, st);
     }
-    return u8 ? pick_final_t<uint8_t, false, true>(g.CPL, g.PG) : pick_final_t<uint16_t, false, true>(g.CPL, g.PG);
+    return u8 ? pick_final_t<uint8_t, false, 1>(g.CPL, g.PG) : pick_final_t<uint16_t, false, 1>(g.CPL, g.PG);
   }
   if (g.layout == IH_HWB) {
     const bool st = staged_lds(g) > 0;
@@ -234,6 +219,50 @@ extern "C" int ih_profile_events(void *start, void *stop) {
   return IH_OK;
 }
 
+int ih::launch_build(const Geom &g, int dtype, const void *img, const void *tail, const uint8_t *wt,
+                     const uint8_t *mask, int bits, void *ws, final_fn fin, const FinalArgs &fa, hipStream_t s) {
+  int bc, e;
+  size_t lds;
+  if ((e = pick_bc(g, kLdsBudget, &bc, &lds))) return e;
+  uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
+  const unsigned tiles = (unsigned)((int64_t)g.nTR * g.nTC * g.C);
+  if (dtype == IH_U8)
+    hipLaunchKernelGGL(k_tile_hist<uint8_t>, dim3(tiles), dim3(256), lds, s, reinterpret_cast<const uint8_t *>(img),
+                       g, bits, bc, w32, wt, mask, reinterpret_cast<const uint8_t *>(tail));
+  else
+    hipLaunchKernelGGL(k_tile_hist<uint16_t>, dim3(tiles), dim3(256), lds, s,
+                       reinterpret_cast<const uint16_t *>(img), g, bits, bc, w32, wt, mask,
+                       reinterpret_cast<const uint16_t *>(tail));
+  if ((e = hip_check(hipGetLastError(), "tile_hist launch"))) return e;
+
+  const int64_t nA = ((int64_t)g.P * g.W + 255) / 256;
+  const int64_t nB = ((int64_t)g.C * g.H * g.bins + 255) / 256;
+  const int64_t nC = g.P;
+  hipLaunchKernelGGL(k_carry_scan, dim3((unsigned)(nA + nB + nC)), dim3(256), 0, s, g, nA, nB, w32);
+  if ((e = hip_check(hipGetLastError(), "carry_scan launch"))) return e;
+
+  dim3 grid, block;
+  const size_t st = staged_lds(g);
+  if (g.layout == IH_BHW) {
+    const int groups = (g.bins + g.PG - 1) / g.PG;
+    const int wpb = groups < 4 ? groups : 4;
+    grid = dim3(tiles, (unsigned)((groups + wpb - 1) / wpb));
+    block = dim3(64 * wpb);
+  } else if (st) {
+    grid = dim3((unsigned)((int64_t)g.nTR * g.nTC));
+    block = dim3(64 * ((g.P + 63) / 64));
+  } else {
+    const int64_t units = (int64_t)g.nTR * g.nTC * ((g.P + 63) / 64);
+    grid = dim3((unsigned)((units + 3) / 4));
+    block = dim3(256);
+  }
+  if (g_hook.start && (e = hip_check(hipEventRecord(g_hook.start, s), "profile start"))) return e;
+  hipLaunchKernelGGL(fin, grid, block, g.layout == IH_BHW ? 0 : st, s, fa, g);
+  if ((e = hip_check(hipGetLastError(), "final launch"))) return e;
+  if (g_hook.stop && (e = hip_check(hipEventRecord(g_hook.stop, s), "profile stop"))) return e;
+  return IH_OK;
+}
+
 static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const uint8_t *mask, int32_t H,
                       int32_t W, int32_t C, int32_t bins, int32_t value_bits, int32_t layout, int32_t *ih,
                       uint32_t *mom_x, uint32_t *mom_y, const ih_tile_cfg *cfg, void *ws, size_t ws_bytes,
@@ -256,48 +285,10 @@ static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const u
   final_fn fin = pick_final(dtype, g);
   if (!fin)
     return set_error(IH_ERR_UNSUPPORTED, "no write-out kernel for tile_w %d planes_per_wave %d", g.TW, g.PG);
-  int bc;
-  size_t lds;
-  if ((e = pick_bc(g, kLdsBudget, &bc, &lds))) return e;
-  hipStream_t s = as_stream(stream);
-  uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
-
-  const unsigned tiles = (unsigned)((int64_t)g.nTR * g.nTC * C);
-  if (dtype == IH_U8)
-    hipLaunchKernelGGL(k_tile_hist<uint8_t>, dim3(tiles), dim3(256), lds, s,
-                       reinterpret_cast<const uint8_t *>(img), g, value_bits, bc, w32, wt, mask);
-  else
-    hipLaunchKernelGGL(k_tile_hist<uint16_t>, dim3(tiles), dim3(256), lds, s,
-                       reinterpret_cast<const uint16_t *>(img), g, value_bits, bc, w32, wt, mask);
-  if ((e = hip_check(hipGetLastError(), "tile_hist launch"))) return e;
-
-  const int64_t nA = ((int64_t)g.P * W + 255) / 256;
-  const int64_t nB = ((int64_t)C * H * bins + 255) / 256;
-  const int64_t nC = g.P;
-  hipLaunchKernelGGL(k_carry_scan, dim3((unsigned)(nA + nB + nC)), dim3(256), 0, s, g, nA, nB, w32);
-  if ((e = hip_check(hipGetLastError(), "carry_scan launch"))) return e;
-
   const bool aligned = ((uintptr_t)ih % 16 == 0) && ((uintptr_t)mom_x % 16 == 0) && ((uintptr_t)mom_y % 16 == 0);
-  FinalArgs fa{img, ih, mom_x, mom_y, w32, value_bits, (W % g.CPL == 0 && aligned) ? 1 : 0, wt, mask};
-  dim3 grid, block;
-  if (layout == IH_BHW) {
-    const int groups = (bins + g.PG - 1) / g.PG;
-    const int wpb = groups < 4 ? groups : 4;
-    grid = dim3(tiles, (unsigned)((groups + wpb - 1) / wpb));
-    block = dim3(64 * wpb);
-  } else if (staged_lds(g)) {
-    grid = dim3((unsigned)((int64_t)g.nTR * g.nTC));
-    block = dim3(64 * ((g.P + 63) / 64));
-  } else {
-    const int64_t units = (int64_t)g.nTR * g.nTC * ((g.P + 63) / 64);
-    grid = dim3((unsigned)((units + 3) / 4));
-    block = dim3(256);
-  }
-  if (g_hook.start && (e = hip_check(hipEventRecord(g_hook.start, s), "profile start"))) return e;
-  hipLaunchKernelGGL(fin, grid, block, staged_lds(g), s, fa, g);
-  if ((e = hip_check(hipGetLastError(), "final launch"))) return e;
-  if (g_hook.stop && (e = hip_check(hipEventRecord(g_hook.stop, s), "profile stop"))) return e;
-  return IH_OK;
+  FinalArgs fa{img, ih, mom_x, mom_y, reinterpret_cast<uint32_t *>(ws), value_bits,
+               (W % g.CPL == 0 && aligned) ? 1 : 0, wt, mask};
+  return launch_build(g, dtype, img, nullptr, wt, mask, value_bits, ws, fin, fa, as_stream(stream));
 }
 
 extern "C" int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C, int32_t bins,

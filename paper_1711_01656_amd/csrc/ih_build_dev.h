@@ -25,6 +25,9 @@ __host__ __device__ __forceinline__ int64_t cc_index(const Geom &g, int64_t p, i
 //    With weights (g.wgt) every "count" above is the sum of the pixels'
 //    weights, wt where the mask is set (or there is no mask), else 0.
 // --------------------------------------------------------------------------
+struct FinalArgs;
+typedef void (*final_fn)(FinalArgs, Geom);
+
 // LDS bytes of one staged row segment of the planes-innermost write-out (all
 // arrays), or 0 when staging does not apply.
 #ifndef IH_HWB_STAGED
@@ -97,7 +100,10 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
           }
           continue;
         }
-        const uint32_t w = g.wgt ? (uint32_t)wt_s[r * twp + cl] : 1u;
+        const uint32_t w = g.coord == 2   ? (uint32_t)(R0 + r) * (uint32_t)(R0 + r)
+                           : g.coord == 3 ? (uint32_t)(C0 + cl) * (uint32_t)(C0 + cl)
+                           : g.wgt        ? (uint32_t)wt_s[r * twp + cl]
+                                          : 1u;
         if (b >= 0 && b < nb && w) {
           atomicAdd(&hist[cl * stride + b], w);
           if (g.mom) atomicAdd(&hist[colw + cl * stride + b], (uint32_t)(R0 + r));
@@ -159,7 +165,10 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
           }
           continue;
         }
-        const uint32_t w = g.wgt ? (uint32_t)wt_s[r * twp + cl] : 1u;
+        const uint32_t w = g.coord == 2   ? (uint32_t)(R0 + r) * (uint32_t)(R0 + r)
+                           : g.coord == 3 ? (uint32_t)(C0 + cl) * (uint32_t)(C0 + cl)
+                           : g.wgt        ? (uint32_t)wt_s[r * twp + cl]
+                                          : 1u;
         if (b >= 0 && b < nb && w) {
           atomicAdd(&hist[r * stride + b], w);
           if (g.mom) atomicAdd(&hist[roww + r * stride + b], (uint32_t)(C0 + cl));
@@ -280,6 +289,23 @@ __device__ __forceinline__ uint32_t pixel_weight(const FinalArgs &a, const Geom 
   return (a.mask && a.mask[i] == 0) ? 0u : (uint32_t)a.wt[i];
 }
 
+// Coordinate weights of the second-moment integral histograms: row^2 (kind 2)
+// or column^2 (kind 3), modulo 2^32; kind 0 counts (weight 1).
+template <int WK>
+__device__ __forceinline__ uint32_t coord_weight(int r, int c) {
+  if constexpr (WK == 2) return (uint32_t)r * (uint32_t)r;
+  else if constexpr (WK == 3) return (uint32_t)c * (uint32_t)c;
+  else return 1u;
+}
+
+// Weight of pixel (r, c) for weight kind WK: 1 = the u8 weight plane (masked),
+// 2, 3 = coordinate weights, 0 = 1.
+template <int WK>
+__device__ __forceinline__ uint32_t pixel_weight_of(const FinalArgs &a, const Geom &g, int ch, int r, int c) {
+  if constexpr (WK == 1) return pixel_weight(a, g, ch, r, c);
+  else return coord_weight<WK>(r, c);
+}
+
 // Four weights packed in a word (byte q = column c0 + q) from the weight and
 // mask words of the same four pixels.
 __device__ __forceinline__ uint32_t masked_weights(uint32_t w, uint32_t m) {
@@ -303,7 +329,7 @@ __device__ __forceinline__ void put(int32_t *dst, const uint32_t (&v)[CPL], int 
   }
 }
 
-template <typename T, int CPL, int PG, bool MOM, bool WGT = false, bool ACC = false>
+template <typename T, int CPL, int PG, bool MOM, int WK = 0, bool ACC = false>
 __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, int bx, int by, int wave, int wpb) {
   const int lane = threadIdx.x & 63;
   const int grp = by * wpb + wave;
@@ -368,7 +394,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
   // the next row's pixels and row carries are loaded while this row is
   // written (software pipelining hides their latency)
   const T *timg = ACC && a.tail ? reinterpret_cast<const T *>(a.tail) + ch * HW : nullptr;
-  uint32_t px[CPL], lcv[PG], lcyv[MOM ? PG : 1], pw[WGT ? CPL : 1], pt[ACC ? CPL : 1];
+  uint32_t px[CPL], lcv[PG], lcyv[MOM ? PG : 1], pw[WK ? CPL : 1], pt[ACC ? CPL : 1];
   auto fetch = [&](int r) {
 #pragma unroll
     for (int e = 0; e < CPL; ++e) px[e] = cf + e < g.W ? (uint32_t)img[(int64_t)r * g.W + cf + e] : 0u;
@@ -378,9 +404,12 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
       for (int e = 0; e < CPL; ++e)
         pt[e] = (timg && cf + e < g.W) ? (uint32_t)timg[(int64_t)r * g.W + cf + e] : (1u << a.bits);
     }
-    if constexpr (WGT) {
+    if constexpr (WK == 1) {
 #pragma unroll
       for (int e = 0; e < CPL; ++e) pw[e] = cf + e < g.W ? pixel_weight(a, g, ch, r, cf + e) : 0u;
+    } else if constexpr (WK != 0) {
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) pw[e] = cf + e < g.W ? coord_weight<WK>(r, cf + e) : 0u;
     }
     const uint32_t *lc = lc_base + (int64_t)r * g.bins;
 #pragma unroll
@@ -398,7 +427,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 #pragma unroll
     for (int e = 0; e < CPL; ++e)
       b[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
-    uint32_t lcur[PG], lycur[MOM ? PG : 1], wcur[WGT ? CPL : 1];
+    uint32_t lcur[PG], lycur[MOM ? PG : 1], wcur[WK ? CPL : 1];
     int bt[ACC ? CPL : 1];
     if constexpr (ACC) {
 #pragma unroll
@@ -407,7 +436,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
     }
 #pragma unroll
     for (int k = 0; k < PG; ++k) lcur[k] = lcv[k];
-    if constexpr (WGT) {
+    if constexpr (WK != 0) {
 #pragma unroll
       for (int e = 0; e < CPL; ++e) wcur[e] = pw[e];
     }
@@ -439,7 +468,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
           }
           put_add<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec_ok);
         }
-      } else if constexpr (WGT) {
+      } else if constexpr (WK != 0) {
         if (k < nk) {
           // weighted row prefix: the lane's own running sum plus a wave scan
           // of the lanes' totals
@@ -526,13 +555,13 @@ __device__ __forceinline__ void load_weight_words(const FinalArgs &a, const Geom
 }
 
 // Weight of column c from the packed words (1 for the unweighted build).
-template <bool WGT, int N>
-__device__ __forceinline__ uint32_t weight_byte(const uint32_t (&wq)[N], int c) {
-  if constexpr (WGT) return (wq[c >> 2] >> (8 * (c & 3))) & 0xffu;
-  else return 1u;
+template <int WK, int N>
+__device__ __forceinline__ uint32_t weight_byte(const uint32_t (&wq)[N], int r, int c0, int c) {
+  if constexpr (WK == 1) return (wq[c >> 2] >> (8 * (c & 3))) & 0xffu;
+  else return coord_weight<WK>(r, c0 + c);
 }
 
-template <typename T, int TW, bool MOM, bool WGT = false>
+template <typename T, int TW, bool MOM, int WK = 0>
 __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g, int64_t unit) {
   const int lane = threadIdx.x & 63;
   const int nchunk = (g.P + 63) >> 6;
@@ -586,7 +615,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
   // starts on a 4-byte boundary.
   const bool full = cols == TW;
   const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
-                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (!WGT || weight_words(a, g, C0));
+                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (WK != 1 || weight_words(a, g, C0));
   constexpr int PER = 4 / (int)sizeof(T);  // pixels per 32-bit word
   auto row_step = [&](auto FULL, int rr) {
     constexpr bool F = decltype(FULL)::value;
@@ -620,16 +649,16 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(row);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
-      uint32_t wq[WGT ? TW / 4 : 1];
-      if constexpr (WGT) load_weight_words<TW>(a, g, ch, r, C0, wq);
+      uint32_t wq[WK == 1 ? TW / 4 : 1];
+      if constexpr (WK == 1) load_weight_words<TW>(a, g, ch, r, C0, wq);
 #pragma unroll
       for (int c = 0; c < TW; ++c)
         pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u),
-              weight_byte<WGT>(wq, c));
+              weight_byte<WK>(wq, r, C0, c));
     } else {
 #pragma unroll
       for (int c = 0; c < TW; ++c)
-        if (F || c < cols) pixel(c, (uint32_t)row[c], WGT ? pixel_weight(a, g, ch, r, C0 + c) : 1u);
+        if (F || c < cols) pixel(c, (uint32_t)row[c], pixel_weight_of<WK>(a, g, ch, r, C0 + c));
     }
   };
   if (full) {
@@ -734,7 +763,7 @@ __device__ __forceinline__ void final_hwb_wave_staged_body(const FinalArgs &a, c
   }
 }
 
-template <typename T, int TW, bool MOM, bool WGT = false>
+template <typename T, int TW, bool MOM, int WK = 0>
 __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const Geom &g, int64_t tile,
                                                       uint32_t *lds) {
   const int lane = threadIdx.x & 63;
@@ -781,7 +810,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
   const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
   const bool full = cols == TW;
   const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
-                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (!WGT || weight_words(a, g, C0));
+                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (WK != 1 || weight_words(a, g, C0));
   const bool vec = (g.P & 3) == 0 && (((uintptr_t)a.ih | (uintptr_t)a.mx | (uintptr_t)a.my) & 15) == 0;
   const int nseg = cols * g.P;
   uint32_t *s0 = lds, *s1 = lds + TW * g.P, *s2 = lds + 2 * TW * g.P;
@@ -811,16 +840,16 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(row);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
-      uint32_t wq[WGT ? TW / 4 : 1];
-      if constexpr (WGT) load_weight_words<TW>(a, g, ch, r, C0, wq);
+      uint32_t wq[WK == 1 ? TW / 4 : 1];
+      if constexpr (WK == 1) load_weight_words<TW>(a, g, ch, r, C0, wq);
 #pragma unroll
       for (int c = 0; c < TW; ++c)
         pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u),
-              weight_byte<WGT>(wq, c));
+              weight_byte<WK>(wq, r, C0, c));
     } else {
 #pragma unroll
       for (int c = 0; c < TW; ++c)
-        if (F || c < cols) pixel(c, (uint32_t)row[c], WGT ? pixel_weight(a, g, ch, r, C0 + c) : 1u);
+        if (F || c < cols) pixel(c, (uint32_t)row[c], pixel_weight_of<WK>(a, g, ch, r, C0 + c));
     }
     __syncthreads();
     const int64_t rbase = ((int64_t)r * g.W + C0) * P;
@@ -835,22 +864,22 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
     // prefetched path: the next row's image words and row carries are loaded
     // while this row is computed and stored
     const int64_t rbase0 = ((int64_t)R0 * g.W + C0) * P;
-    uint32_t wv[TW / PER], rcn = 0, ryn = 0, wqn[WGT ? TW / 4 : 1];
+    uint32_t wv[TW / PER], rcn = 0, ryn = 0, wqn[WK == 1 ? TW / 4 : 1];
     auto fetch = [&](int r) {
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(img + (int64_t)r * g.W + C0);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
-      if constexpr (WGT) load_weight_words<TW>(a, g, ch, r, C0, wqn);
+      if constexpr (WK == 1) load_weight_words<TW>(a, g, ch, r, C0, wqn);
       rcn = lc[(int64_t)r * g.bins];
       if constexpr (MOM) ryn = lcy[(int64_t)r * g.bins];
     };
     if (rows > 0) fetch(R0);
     for (int rr = 0; rr < rows; ++rr) {
       const int r = R0 + rr;
-      uint32_t cur[TW / PER], wq[WGT ? TW / 4 : 1];
+      uint32_t cur[TW / PER], wq[WK == 1 ? TW / 4 : 1];
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) cur[q] = wv[q];
-      if constexpr (WGT) {
+      if constexpr (WK == 1) {
 #pragma unroll
         for (int q = 0; q < TW / 4; ++q) wq[q] = wqn[q];
       }
@@ -859,7 +888,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
 #pragma unroll
       for (int c = 0; c < TW; ++c) {
         const uint32_t val = (cur[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u);
-        const uint32_t w = weight_byte<WGT>(wq, c);
+        const uint32_t w = weight_byte<WK>(wq, r, C0, c);
         const uint32_t hit = (val - lo) < width ? w : 0u;
         rc += hit;
         col[c] += rc;
@@ -888,6 +917,29 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
   }
 }
 
+
+// ------------------------------------------------ stand-alone kernels --
+template <typename T, int CPL, int PG, bool MOM, int WK>
+__global__ __launch_bounds__(256) void k_final(FinalArgs a, Geom g) {
+  final_body<T, CPL, PG, MOM, WK>(a, g, blockIdx.x, blockIdx.y, uniform(threadIdx.x >> 6), blockDim.x >> 6);
+}
+
+template <typename T, int TW, bool MOM, int WK>
+__global__ __launch_bounds__(256) void k_final_hwb(FinalArgs a, Geom g) {
+  final_hwb_body<T, TW, MOM, WK>(a, g, (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform(threadIdx.x >> 6));
+}
+
+template <typename T, int TW, bool MOM, int WK>
+__global__ __launch_bounds__(512) void k_final_hwb_staged(FinalArgs a, Geom g) {
+  extern __shared__ uint32_t seg[];
+  final_hwb_staged_body<T, TW, MOM, WK>(a, g, blockIdx.x, seg);
+}
+
+// Enqueues the three passes of a build (tile histograms, carry scans, the
+// given write-out kernel with its grid for g's layout) on stream s.  tail,
+// wt and mask as in the tile pass.  Defined in ih_build.hip.
+int launch_build(const Geom &g, int dtype, const void *img, const void *tail, const uint8_t *wt,
+                 const uint8_t *mask, int bits, void *ws, final_fn fin, const FinalArgs &fa, hipStream_t s);
 
 // 3e. The joint-IH update in the planes-innermost layout: the staged
 //     write-out (one block per tile, one wavefront per 64 planes, row segments

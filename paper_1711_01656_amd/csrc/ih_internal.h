@@ -97,6 +97,7 @@ struct Geom {
   bool mom;
   bool wgt;             // per-pixel u8 weights replace the unit count
   bool diff;            // a second (tail) image counts -1: joint-IH update
+  int coord;            // 2: weight row^2, 3: weight column^2 (second moments); 0: none
   int layout;           // IH_BHW or IH_HWB
   // workspace sections (in 4-byte words)
   size_t off_cc, off_rc, off_tt, off_ccx, off_rcy, off_ttx, off_tty, words;

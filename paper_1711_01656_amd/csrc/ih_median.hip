@@ -17,22 +17,10 @@
 
 namespace ih {
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_tile_hist_upd(const T *__restrict__ head, Geom g, int bits, int bc,
-                                                       uint32_t *__restrict__ ws, const T *__restrict__ tail) {
-  extern __shared__ uint32_t lds[];
-  tile_hist_body<T>(head, g, bits, bc, ws, blockIdx.x, lds, nullptr, nullptr, tail);
-}
-
-__global__ __launch_bounds__(256) void k_carry_scan_upd(Geom g, int64_t nblk_a, int64_t nblk_b,
-                                                        uint32_t *__restrict__ ws) {
-  carry_scan_body(g, nblk_a, nblk_b, ws, blockIdx.x);
-}
-
 template <typename T, int CPL, int PG>
 __global__ __launch_bounds__(256) void k_final_acc(FinalArgs a, Geom g) {
-  final_body<T, CPL, PG, false, false, true>(a, g, blockIdx.x, blockIdx.y, uniform(threadIdx.x >> 6),
-                                             blockDim.x >> 6);
+  final_body<T, CPL, PG, false, 0, true>(a, g, blockIdx.x, blockIdx.y, uniform(threadIdx.x >> 6),
+                                         blockDim.x >> 6);
 }
 
 template <typename T, int TW>
@@ -150,8 +138,6 @@ __global__ __launch_bounds__(256) void k_median_hwb(const int32_t *__restrict__ 
   if (lane == 0) out[pix] = med;
 }
 
-typedef void (*final_fn)(FinalArgs, Geom);
-
 template <typename T>
 static final_fn pick_acc_t(const Geom &g) {
   if (g.layout == IH_HWB) {
@@ -195,36 +181,9 @@ extern "C" int ih_jih_update(const void *head, const void *tail, int32_t dtype, 
   final_fn fin = dtype == IH_U8 ? pick_acc_t<uint8_t>(g) : pick_acc_t<uint16_t>(g);
   if (!fin)
     return set_error(IH_ERR_UNSUPPORTED, "no update kernel for tile_w %d planes_per_wave %d", g.TW, g.PG);
-  int bc;
-  size_t lds;
-  if ((e = pick_bc(g, kLdsBudget, &bc, &lds))) return e;
-  hipStream_t s = as_stream(stream);
-  uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
-  const unsigned tiles = (unsigned)((int64_t)g.nTR * g.nTC * C);
-  if (dtype == IH_U8)
-    hipLaunchKernelGGL(k_tile_hist_upd<uint8_t>, dim3(tiles), dim3(256), lds, s,
-                       reinterpret_cast<const uint8_t *>(head), g, value_bits, bc, w32,
-                       reinterpret_cast<const uint8_t *>(tail));
-  else
-    hipLaunchKernelGGL(k_tile_hist_upd<uint16_t>, dim3(tiles), dim3(256), lds, s,
-                       reinterpret_cast<const uint16_t *>(head), g, value_bits, bc, w32,
-                       reinterpret_cast<const uint16_t *>(tail));
-  if ((e = hip_check(hipGetLastError(), "update tile_hist launch"))) return e;
-  const int64_t nA = ((int64_t)g.P * W + 255) / 256;
-  const int64_t nB = ((int64_t)C * H * bins + 255) / 256;
-  hipLaunchKernelGGL(k_carry_scan_upd, dim3((unsigned)(nA + nB + g.P)), dim3(256), 0, s, g, nA, nB, w32);
-  if ((e = hip_check(hipGetLastError(), "update carry_scan launch"))) return e;
-  FinalArgs fa{head, jih, nullptr, nullptr, w32, value_bits,
+  FinalArgs fa{head, jih, nullptr, nullptr, reinterpret_cast<uint32_t *>(ws), value_bits,
                (W % g.CPL == 0 && (uintptr_t)jih % 16 == 0) ? 1 : 0, nullptr, nullptr, tail};
-  if (layout == IH_BHW) {
-    const int groups = (bins + g.PG - 1) / g.PG;
-    const int wpb = groups < 4 ? groups : 4;
-    hipLaunchKernelGGL(fin, dim3(tiles, (unsigned)((groups + wpb - 1) / wpb)), dim3(64 * wpb), 0, s, fa, g);
-  } else {
-    hipLaunchKernelGGL(fin, dim3((unsigned)((int64_t)g.nTR * g.nTC)), dim3(64 * ((g.P + 63) / 64)),
-                       staged_lds(g), s, fa, g);
-  }
-  return hip_check(hipGetLastError(), "update write-out launch");
+  return launch_build(g, dtype, head, tail, nullptr, nullptr, value_bits, ws, fin, fa, as_stream(stream));
 }
 
 extern "C" int ih_local_median(const int32_t *jih, int32_t C, int32_t bins, int32_t H, int32_t W, int32_t layout,

@@ -41,6 +41,11 @@ SIGNATURES = {
     "ih_build_weighted": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ,
                                          _P]),
     "ih_jih_update": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "ih_build_moments2": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
+    "ih_query_quadratic": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _I64, _I32, _P,
+                                          _P]),
+    "ih_query_wedding": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _P, _I64, _I32, _I32, ctypes.c_double,
+                                        _P, _P]),
     "ih_local_median": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P]),
     "ih_query_rect": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I64, _P, _P]),
     "ih_query_weighted": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _I64, _I32, _I32, _P, _P]),
@@ -315,6 +320,77 @@ def ih_local_median(jih: torch.Tensor, C: int, bins: int, frames: int, win_h: in
         raise IHError("out must hold C*H*W values")
     _check(lib().ih_local_median(_p(jih), C, bins, H, W, _layout(layout), frames, win_h, win_w, _p(out),
                                  _stream(jih)), "ih_local_median")
+    return out
+
+
+KERNELS = {"manhattan": 0, "quadratic": 1, "gaussian": 2}
+
+
+def ih_build_moments2(img: torch.Tensor, bins: int, value_bits: Optional[int] = None,
+                      cfg: Optional[TileCfg] = None, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                      ws: Optional[torch.Tensor] = None, layout: str = "bhw"):
+    """Second coordinate-moment integral histograms (row^2 and column^2 sums
+    per plane, modulo 2^32, as int32 views); shapes follow ``layout``."""
+    _dev(img, "img")
+    if img.dim() == 2:
+        img = img.unsqueeze(0)
+    dt, maxbits = _frame_dtype(img)
+    C, H, W = img.shape
+    bits = maxbits if value_bits is None else value_bits
+    P = C * bins
+    shp = shape_of(P, H, W, layout)
+    if out is None:
+        out = (torch.empty(shp, dtype=torch.int32, device=img.device),
+               torch.empty(shp, dtype=torch.int32, device=img.device))
+    mxx, myy = out
+    for t, name in ((mxx, "mom_xx"), (myy, "mom_yy")):
+        _dev(t, name, torch.int32)
+        if t.numel() != P * H * W:
+            raise IHError("%s must hold P*H*W values" % name)
+    need = workspace_size(H, W, C, bins, False, cfg, layout)
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=img.device)
+    rc = lib().ih_build_moments2(_p(img), dt, H, W, C, bins, bits, _layout(layout), _p(mxx), _p(myy),
+                                 ctypes.byref(cfg) if cfg is not None else None, _p(ws),
+                                 ws.numel() * ws.element_size(), _stream(img))
+    _check(rc, "ih_build_moments2")
+    return mxx, myy
+
+
+def ih_query_quadratic(ih: torch.Tensor, mom_x: torch.Tensor, mom_y: torch.Tensor, mom_xx: torch.Tensor,
+                       mom_yy: torch.Tensor, C: int, rects: torch.Tensor, l1_normalize: bool = False,
+                       out: Optional[torch.Tensor] = None, layout: str = "bhw") -> torch.Tensor:
+    """Quadratic-kernel (squared Euclidean distance) weighted local histograms
+    in O(1) per window; n x P float32."""
+    for t, name in ((ih, "ih"), (mom_x, "mom_x"), (mom_y, "mom_y"), (mom_xx, "mom_xx"), (mom_yy, "mom_yy")):
+        _dev(t, name, torch.int32)
+    P, H, W = _phw(ih, layout)
+    _rects(rects)
+    n = rects.shape[0]
+    if out is None:
+        out = torch.empty((n, P), dtype=torch.float32, device=ih.device)
+    _dev(out, "out", torch.float32)
+    _check(lib().ih_query_quadratic(_p(ih), _p(mom_x), _p(mom_y), _p(mom_xx), _p(mom_yy), P, H, W, C,
+                                    _layout(layout), _p(rects), n, int(bool(l1_normalize)), _p(out),
+                                    _stream(ih)), "ih_query_quadratic")
+    return out
+
+
+def ih_query_wedding(ih: torch.Tensor, C: int, rects: torch.Tensor, layers: int, kernel: str = "manhattan",
+                     sigma: float = 0.5, out: Optional[torch.Tensor] = None, layout: str = "bhw") -> torch.Tensor:
+    """Wedding-cake approximation (Eq. 3.2) of a kernel-weighted local
+    histogram from the count integral histogram; n x P float32."""
+    _dev(ih, "ih", torch.int32)
+    P, H, W = _phw(ih, layout)
+    _rects(rects)
+    n = rects.shape[0]
+    if kernel not in KERNELS:
+        raise IHError("kernel must be one of %s" % sorted(KERNELS))
+    if out is None:
+        out = torch.empty((n, P), dtype=torch.float32, device=ih.device)
+    _dev(out, "out", torch.float32)
+    _check(lib().ih_query_wedding(_p(ih), P, H, W, C, _layout(layout), _p(rects), n, layers, KERNELS[kernel],
+                                  float(sigma), _p(out), _stream(ih)), "ih_query_wedding")
     return out
 
 

@@ -13,7 +13,7 @@ def declared_functions():
     inc = os.path.join(ROOT, "include")
     src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ih_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(ih_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
