@@ -69,6 +69,9 @@ def _load():
                 "or_level_weight": [I, I],
                 "or_num_threads": [],
                 "or_ih_weighted": [P, I, P, P, I, I, I, I, I, P],
+                "or_color_likelihood": [P, I, I, P, P, P, P],
+                "or_moment_images": [P, I, I, P, P, P],
+                "or_camshift": [P, I, I, P, I64, I, I, D, I, P, P],
                 "or_kernel_bruteforce": [P, I, I, I, I, I, I, P, I64, I, D, I, P],
                 "or_moments2": [P, I, I, I, I, I, I, P, P],
                 "or_quadratic_numerator": [P, I, I, I, I, I, I, P, I64, P],
@@ -365,6 +368,43 @@ def wedding_direct(img, bins, bits, rects, layers, kernel="manhattan", sigma=0.5
     _check(_load().or_wedding_direct(_ptr(a), dt, H, W, C, bins, bits, _ptr(r), n, layers, KERNELS[kernel],
                                      float(sigma), _ptr(out)), "wedding_direct")
     return out
+
+
+def color_likelihood(rgb, fg, bg):
+    """FG/BG colour likelihood (Eq. 2.18-2.21) of a 3 x H x W uint8 image:
+    (q, L) with q the uint8 code round(255 L) taken in integers and L in FP64."""
+    a = np.ascontiguousarray(rgb, dtype=np.uint8)
+    if a.ndim != 3 or a.shape[0] != 3:
+        raise ValueError("rgb must be 3 x H x W")
+    _, H, W = a.shape
+    f = np.ascontiguousarray(fg, dtype=np.int32).reshape(4)
+    b = np.ascontiguousarray(bg, dtype=np.int32).reshape(4)
+    q = np.empty((H, W), np.uint8)
+    L = np.empty((H, W), np.float64)
+    _check(_load().or_color_likelihood(_ptr(a), H, W, _ptr(f), _ptr(b), _ptr(q), _ptr(L)), "color_likelihood")
+    return q, L
+
+
+def moment_images(q):
+    """Integral images of q, row*q and column*q (int64 H x W each)."""
+    a = np.ascontiguousarray(q, dtype=np.uint8)
+    H, W = a.shape
+    S, Sx, Sy = (np.empty((H, W), np.int64) for _ in range(3))
+    _check(_load().or_moment_images(_ptr(a), H, W, _ptr(S), _ptr(Sx), _ptr(Sy)), "moment_images")
+    return S, Sx, Sy
+
+
+def camshift(q, starts, win_h, win_w, delta=0.5, max_iter=20):
+    """CAMSHIFT (Alg. 1) with direct window sums: (n x 2 centres, n iterations)."""
+    a = np.ascontiguousarray(q, dtype=np.uint8)
+    H, W = a.shape
+    st = np.ascontiguousarray(starts, dtype=np.float64).reshape(-1, 2)
+    n = st.shape[0]
+    cen = np.empty((n, 2), np.float64)
+    it = np.empty(n, np.int32)
+    _check(_load().or_camshift(_ptr(a), H, W, _ptr(st), n, win_h, win_w, float(delta), max_iter, _ptr(cen),
+                               _ptr(it)), "camshift")
+    return cen, it
 
 
 def _wins(wins):

@@ -660,6 +660,106 @@ int or_wedding_direct(const void *img, int dtype, int H, int W, int C, int bins,
 }
 
 /* ------------------------------------------------------------------------ */
+/* FG/BG colour likelihood (Sec. 2.4.2, Eq. 2.18-2.21) and CAMSHIFT (Alg. 1). */
+/*                                                                            */
+/* rgb: 3 x H x W uint8 (R, G, B planes).  Joint colour bin of a pixel:       */
+/*   b = ((R >> 3) * 32 + (G >> 3)) * 32 + (B >> 3)   (32 x 32 x 32 bins).    */
+/* H_FG counts the pixels of the rectangle fg, H_BG those of the rectangle bg */
+/* outside fg (Eq. 2.18).  The likelihood of Eq. 2.21 is                      */
+/*   L = H_FG(b) / (H_FG(b) + H_BG(b)),  0 where both are 0,                  */
+/* and its 8-bit code is q = round-half-up(255 L), taken in integers:         */
+/*   q = (2 * 255 * H_FG(b) + (H_FG(b) + H_BG(b))) / (2 (H_FG(b) + H_BG(b))).  */
+/* ------------------------------------------------------------------------ */
+int or_color_likelihood(const uint8_t *rgb, int H, int W, const int32_t *fg, const int32_t *bg, uint8_t *q,
+                        double *L) {
+  if (H < 1 || W < 1 || !or_rect_ok(fg, H, W) || !or_rect_ok(bg, H, W)) return OR_ERR_ARG;
+  int64_t *hf = (int64_t *)calloc(32768, sizeof(int64_t));
+  int64_t *hb = (int64_t *)calloc(32768, sizeof(int64_t));
+  if (!hf || !hb) {
+    free(hf);
+    free(hb);
+    return OR_ERR_ARG;
+  }
+  const int64_t HW = (int64_t)H * W;
+#define OR_BIN(i) ((((int)(rgb[i] >> 3)) * 32 + (int)(rgb[HW + (i)] >> 3)) * 32 + (int)(rgb[2 * HW + (i)] >> 3))
+  for (int r = bg[0]; r < bg[2]; r++)
+    for (int c = bg[1]; c < bg[3]; c++) {
+      int in_fg = r >= fg[0] && r < fg[2] && c >= fg[1] && c < fg[3];
+      if (!in_fg) hb[OR_BIN((int64_t)r * W + c)]++;
+    }
+  for (int r = fg[0]; r < fg[2]; r++)
+    for (int c = fg[1]; c < fg[3]; c++) hf[OR_BIN((int64_t)r * W + c)]++;
+  for (int64_t i = 0; i < HW; i++) {
+    int b = OR_BIN(i);
+    int64_t f = hf[b], t = hf[b] + hb[b];
+    q[i] = t ? (uint8_t)((2 * 255 * f + t) / (2 * t)) : 0;
+    if (L) L[i] = t ? (double)f / (double)t : 0.0;
+  }
+#undef OR_BIN
+  free(hf);
+  free(hb);
+  return OR_OK;
+}
+
+/* Moment integral images of a u8 map q: the sums over [0, r] x [0, c] of q,
+   row * q and column * q (int64), by the recurrence of Alg. 5 with one plane. */
+int or_moment_images(const uint8_t *q, int H, int W, int64_t *S, int64_t *Sx, int64_t *Sy) {
+  if (H < 1 || W < 1) return OR_ERR_ARG;
+  for (int x = 0; x < H; x++)
+    for (int y = 0; y < W; y++) {
+      int64_t i = (int64_t)x * W + y, v = q[i];
+      S[i] = v + (x ? S[i - W] : 0) + (y ? S[i - 1] : 0) - ((x && y) ? S[i - W - 1] : 0);
+      Sx[i] = v * x + (x ? Sx[i - W] : 0) + (y ? Sx[i - 1] : 0) - ((x && y) ? Sx[i - W - 1] : 0);
+      Sy[i] = v * y + (x ? Sy[i - W] : 0) + (y ? Sy[i - 1] : 0) - ((x && y) ? Sy[i - W - 1] : 0);
+    }
+  return OR_OK;
+}
+
+/* CAMSHIFT (Alg. 1) on the map q with a fixed win_h x win_w search window,
+   from each start point (row, col).  Each step places the window at
+   r0 = floor(cr - (win_h-1)/2 + 0.5), c0 likewise, shifted inside the image,
+   takes its zero and first moments by summing q, row*q and col*q over the
+   window (M00, and the row and column moments), moves the centre to the
+   window's centroid, and stops when the squared move is below delta^2, when
+   M00 = 0 (the centre stays), or after max_iter steps.  Outputs the final
+   centres and the number of steps taken. */
+int or_camshift(const uint8_t *q, int H, int W, const double *starts, int64_t n, int win_h, int win_w,
+                double delta, int max_iter, double *centers, int32_t *iters) {
+  if (H < 1 || W < 1 || win_h < 1 || win_w < 1 || win_h > H || win_w > W || max_iter < 0) return OR_ERR_ARG;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; i++) {
+    double cr = starts[2 * i], cc = starts[2 * i + 1];
+    int it = 0;
+    while (it < max_iter) {
+      int r0 = (int)floor(cr - (win_h - 1) / 2.0 + 0.5), c0 = (int)floor(cc - (win_w - 1) / 2.0 + 0.5);
+      if (r0 < 0) r0 = 0;
+      if (c0 < 0) c0 = 0;
+      if (r0 > H - win_h) r0 = H - win_h;
+      if (c0 > W - win_w) c0 = W - win_w;
+      int64_t m00 = 0, mr = 0, mc = 0;
+      for (int r = r0; r < r0 + win_h; r++)
+        for (int c = c0; c < c0 + win_w; c++) {
+          int64_t v = q[(int64_t)r * W + c];
+          m00 += v;
+          mr += v * r;
+          mc += v * c;
+        }
+      it++;
+      if (m00 == 0) break;
+      double nr = (double)mr / (double)m00, nc = (double)mc / (double)m00;
+      double dr = nr - cr, dc = nc - cc;
+      cr = nr;
+      cc = nc;
+      if (dr * dr + dc * dc < delta * delta) break;
+    }
+    centers[2 * i] = cr;
+    centers[2 * i + 1] = cc;
+    iters[i] = it;
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Spatial pyramid descriptor (Alg. 2; layout per Sec. 2.4.4).               */
 /* Level l has 2^l x 2^l cells; cell (i, j) of a window at (r, c) with h     */
 /* rows and w columns covers rows [r + floor(i*h/2^l), r + floor((i+1)*h/2^l))*/
