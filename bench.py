@@ -64,6 +64,8 @@ def parse():
                     help="run only the magnitude-weighted orientation histogram and print its JSON object")
     ap.add_argument("--median-only", action="store_true",
                     help="run only the spatio-temporal median and print its JSON object")
+    ap.add_argument("--camshift-only", action="store_true",
+                    help="run only the colour likelihood + CAMSHIFT workload and print its JSON object")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run only the spatial-kernel accuracy/time comparison and print its JSON object")
     ap.add_argument("--train-videos", type=int, default=800)
@@ -331,6 +333,83 @@ def kernels_leg(torch, ih, synth, sample=400):
                                "threads": oracle.num_threads()}}
 
 
+def camshift_leg(torch, ih, synth, n_starts=4096):
+    """FG/BG colour likelihood and CAMSHIFT (Alg. 1) on frame 0 of the
+    1280x720 tracking video: the likelihood from the target box and the box
+    grown by its own size on every side (Eq. 2.18-2.21), the moment integral
+    images of its 8-bit code, and CAMSHIFT with the target-sized window from
+    one start and from `n_starts` starts scattered around the target.  Each
+    stage graph-replayed; the oracle's CAMSHIFT (direct window sums) timed
+    on the same starts."""
+    import oracle
+    from synth.video import config5
+    dev = torch.device("cuda:0")
+    v = config5(n_frames=1)
+    rgb_np = v.rgb(0)
+    r, c, h, w = v.target_box(0)
+    H, W = rgb_np.shape[1:]
+    fg = (r, c, r + h, c + w)
+    bg = (max(0, r - h), max(0, c - w), min(H, r + 2 * h), min(W, c + 2 * w))
+    rgb = torch.from_numpy(rgb_np).to(dev)
+    q = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    L = torch.empty((H, W), dtype=torch.float32, device=dev)
+    ws = torch.empty(ih.lib().ih_color_likelihood_workspace_size(), dtype=torch.uint8, device=dev)
+    moms = tuple(torch.empty((H, W), dtype=torch.int32, device=dev) for _ in range(3))
+    mws = torch.empty(ih.workspace_size(H, W, 1, 1, False, None, "bhw"), dtype=torch.uint8, device=dev)
+    rng = np.random.default_rng(5)
+    st_np = np.stack([r + h / 2 + rng.uniform(-h, h, n_starts), c + w / 2 + rng.uniform(-w, w, n_starts)], 1)
+    starts = torch.from_numpy(st_np).to(dev)
+    one = starts[:1].contiguous()
+    cen = torch.empty((n_starts, 2), dtype=torch.float64, device=dev)
+    its = torch.empty(n_starts, dtype=torch.int32, device=dev)
+    cen1, its1 = cen[:1], its[:1]
+
+    def like():
+        ih.ih_color_likelihood(rgb, fg, bg, q=q, L=L, ws=ws)
+
+    def mom():
+        ih.ih_moment_images(q, out=moms, ws=mws)
+
+    def cam(n):
+        if n == 1:
+            ih.ih_camshift(moms, one, h, w, 0.5, 20, centers=cen1, iters=its1)
+        else:
+            ih.ih_camshift(moms, starts, h, w, 0.5, 20, centers=cen, iters=its)
+
+    def frame():
+        like()
+        mom()
+        cam(1)
+
+    frame()
+    cam(n_starts)
+    torch.cuda.synchronize()
+    ref = cen.clone()
+    t_like = graph_median(torch, like, 20, per=10)
+    t_mom = graph_median(torch, mom, 20, per=10)
+    t_cam1 = graph_median(torch, lambda: cam(1), 20, per=10)
+    t_camn = graph_median(torch, lambda: cam(n_starts), 20, per=10)
+    t_frame = graph_median(torch, frame, 20, per=10)
+    cam(n_starts)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(cen, ref))
+    t0 = time.perf_counter()
+    oq, _ = oracle.color_likelihood(rgb_np, fg, bg)
+    t_olike = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ocen, oit = oracle.camshift(oq, st_np, h, w, 0.5, 20)
+    t_ocam = time.perf_counter() - t0
+    agree = bool(np.array_equal(ocen, cen.cpu().numpy()) and np.array_equal(oit, its.cpu().numpy()))
+    return {"workload": "1280x720 RGB tracking frame, 32^3-bin FG/BG likelihood, %dx%d CAMSHIFT window" % (h, w),
+            "likelihood_ms": round(t_like, 4), "moment_images_ms": round(t_mom, 4),
+            "camshift_1_start_ms": round(t_cam1, 4), "camshift_%d_starts_ms" % n_starts: round(t_camn, 4),
+            "frame_ms": round(t_frame, 4), "frames_per_s": round(1e3 / t_frame, 1),
+            "mean_steps": round(float(its.float().mean().item()), 2),
+            "replays_match_eager": same, "matches_oracle": agree,
+            "oracle_ms": {"likelihood": round(t_olike * 1e3, 2), "camshift_%d_starts" % n_starts:
+                          round(t_ocam * 1e3, 2), "threads": oracle.num_threads()}}
+
+
 def copy_calibration(torch, mib):
     """One device fill and one device-to-device copy of `mib` MiB: the copy
     kernel's FETCH_SIZE and WRITE_SIZE against its known bytes give the
@@ -395,6 +474,8 @@ def config_legs(torch, ih, synth, fixed=False):
     res["median_768x576_256bins"] = median_leg(torch, ih, synth)
     # spatial kernels: exact SWIH against the wedding cake
     res["swih_kernels_1920x1080x112"] = kernels_leg(torch, ih, synth)
+    # colour likelihood and CAMSHIFT on the tracking frame
+    res["camshift_1280x720"] = camshift_leg(torch, ih, synth)
 
     # 8192x8192 u16, 64 bins, 1M rectangles, 129x129 search
     w = synth.config3()
@@ -639,6 +720,9 @@ def main():
         return
     if args.workloads_only:
         print(json.dumps(config_legs(torch, ih, synth, args.fixed_tiles)), flush=True)
+        return
+    if args.camshift_only:
+        print(json.dumps(camshift_leg(torch, ih, synth)), flush=True)
         return
     if args.kernels_only:
         print(json.dumps(kernels_leg(torch, ih, synth)), flush=True)

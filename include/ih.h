@@ -386,6 +386,67 @@ int ih_query_wedding(const int32_t *ih, int32_t P, int32_t H, int32_t W,
                      float *out, void *stream);
 
 /*
+ * ih_color_likelihood - FG/BG colour likelihood map (Sec. 2.4.2,
+ * Eq. 2.18-2.21).  Joint RGB histograms with 32 x 32 x 32 bins (bin =
+ * ((R>>3)*32 + (G>>3))*32 + (B>>3)) of the foreground rectangle fg and of
+ * the background rectangle bg minus fg (Eq. 2.18); every pixel's likelihood
+ * of belonging to the foreground is
+ *   L = H_FG(b) / (H_FG(b) + H_BG(b))   (Eq. 2.21; 0 where both are 0),
+ * and its 8-bit code is q = round-half-up(255 L), computed in integers as
+ * (510 H_FG + T) / (2 T), T = H_FG + H_BG.
+ *   rgb      device, 3 x H x W uint8 (R, G, B planes), H * W < 2^31.
+ *   fg, bg   rectangles (by value, half-open) inside the image.
+ *   ws       device workspace of ws_bytes >= ih_color_likelihood_workspace_size().
+ *   q        device, out: H x W uint8 codes.
+ *   L        device, out: H x W float likelihoods (FP64 ratio rounded to
+ *            FP32), or NULL.
+ * Returns IH_OK or IH_ERR_*.
+ */
+size_t ih_color_likelihood_workspace_size(void);
+int ih_color_likelihood(const uint8_t *rgb, int32_t H, int32_t W, ih_rect fg,
+                        ih_rect bg, void *ws, size_t ws_bytes, uint8_t *q,
+                        float *L, void *stream);
+
+/*
+ * ih_moment_images - moment integral images of an 8-bit map q (the zero and
+ * first moments of Alg. 1 over any rectangle in O(1)):
+ *   S(r,c)  = sum over r' <= r, c' <= c of q(r',c')          (int32, exact)
+ *   Sx(r,c) = sum of r' * q(r',c'),  Sy(r,c) = sum of c' * q(r',c')
+ *             (uint32, modulo 2^32)
+ * built by the integral-histogram passes with one plane and the weights q,
+ * row * q and column * q.
+ *   q           device, H x W uint8; H * W * 255 <= 2^31 - 1.
+ *   S, Sx, Sy   device, out: H x W each.
+ *   cfg, ws, ws_bytes  as for ih_build with C = 1, bins = 1, IH_BHW
+ *               (workspace: ih_build_workspace_size(H, W, 1, 1, 0, IH_BHW, cfg)).
+ * Returns IH_OK or IH_ERR_*.
+ */
+int ih_moment_images(const uint8_t *q, int32_t H, int32_t W, int32_t *S,
+                     uint32_t *Sx, uint32_t *Sy, const ih_tile_cfg *cfg,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * ih_camshift - CAMSHIFT (Alg. 1) from many start points at once on moment
+ * integral images (one thread per start).  Each step places the fixed
+ * win_h x win_w search window at r0 = floor(cr - (win_h-1)/2 + 0.5),
+ * c0 = floor(cc - (win_w-1)/2 + 0.5), shifted inside the image, reads its
+ * M00 and first moments from S, Sx, Sy (four corners each), and moves the
+ * centre to the centroid (row moment / M00, column moment / M00, in FP64).
+ * It stops when the squared move is below delta^2, when M00 = 0 (the centre
+ * stays), or after max_iter steps.
+ *   S, Sx, Sy   device, from ih_moment_images.
+ *   starts      device, n x 2 double (row, column).
+ *   win_h, win_w  window, at most the image; 255 w h (h-1) / 2 and
+ *               255 h w (w-1) / 2 must be below 2^32 (IH_ERR_RANGE).
+ *   centers     device, out: n x 2 double;  iters  device, out: n int32.
+ * Returns IH_OK or IH_ERR_*; n may be 0.
+ */
+int ih_camshift(const int32_t *S, const uint32_t *Sx, const uint32_t *Sy,
+                int32_t H, int32_t W, const double *starts, int64_t n,
+                int32_t win_h, int32_t win_w, double delta, int32_t max_iter,
+                double *centers, int32_t *iters, void *stream);
+
+/*
  * ih_jih_update - joint integral histogram update of the spatio-temporal
  * median (Alg. 4, Fig. 4.1): JIH = JIH + IH(head) - IH(tail), in place.
  * The joint IH of a window of frames is the integral histogram of all their

@@ -11,11 +11,14 @@ from .ih import (  # noqa: F401
     TileCfg,
     cells,
     ih_build,
+    ih_camshift,
+    ih_color_likelihood,
     ih_build_moments2,
     ih_build_weighted,
     ih_jih_update,
     ih_local_median,
     ih_match_candidates,
+    ih_moment_images,
     ih_profile_events,
     ih_pyramid_desc,
     ih_query_quadratic,

@@ -102,6 +102,8 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
         }
         const uint32_t w = g.coord == 2   ? (uint32_t)(R0 + r) * (uint32_t)(R0 + r)
                            : g.coord == 3 ? (uint32_t)(C0 + cl) * (uint32_t)(C0 + cl)
+                           : g.coord == 4 ? (uint32_t)(R0 + r) * (uint32_t)wt_s[r * twp + cl]
+                           : g.coord == 5 ? (uint32_t)(C0 + cl) * (uint32_t)wt_s[r * twp + cl]
                            : g.wgt        ? (uint32_t)wt_s[r * twp + cl]
                                           : 1u;
         if (b >= 0 && b < nb && w) {
@@ -167,6 +169,8 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
         }
         const uint32_t w = g.coord == 2   ? (uint32_t)(R0 + r) * (uint32_t)(R0 + r)
                            : g.coord == 3 ? (uint32_t)(C0 + cl) * (uint32_t)(C0 + cl)
+                           : g.coord == 4 ? (uint32_t)(R0 + r) * (uint32_t)wt_s[r * twp + cl]
+                           : g.coord == 5 ? (uint32_t)(C0 + cl) * (uint32_t)wt_s[r * twp + cl]
                            : g.wgt        ? (uint32_t)wt_s[r * twp + cl]
                                           : 1u;
         if (b >= 0 && b < nb && w) {
@@ -289,21 +293,28 @@ __device__ __forceinline__ uint32_t pixel_weight(const FinalArgs &a, const Geom 
   return (a.mask && a.mask[i] == 0) ? 0u : (uint32_t)a.wt[i];
 }
 
-// Coordinate weights of the second-moment integral histograms: row^2 (kind 2)
-// or column^2 (kind 3), modulo 2^32; kind 0 counts (weight 1).
+// Weight kinds of the weighted write-outs: 0 counts (weight 1); 1 the u8
+// weight plane (masked); 2, 3 row^2 and column^2 (second-moment integral
+// histograms); 4, 5 row and column times the u8 weight plane (first-moment
+// integral images of a weight map).  All modulo 2^32.
 template <int WK>
-__device__ __forceinline__ uint32_t coord_weight(int r, int c) {
-  if constexpr (WK == 2) return (uint32_t)r * (uint32_t)r;
+constexpr bool loads_weights() { return WK == 1 || WK == 4 || WK == 5; }
+
+// The weight of pixel (r, c) given its u8 plane weight u.
+template <int WK>
+__device__ __forceinline__ uint32_t kind_weight(int r, int c, uint32_t u) {
+  if constexpr (WK == 1) return u;
+  else if constexpr (WK == 2) return (uint32_t)r * (uint32_t)r;
   else if constexpr (WK == 3) return (uint32_t)c * (uint32_t)c;
+  else if constexpr (WK == 4) return (uint32_t)r * u;
+  else if constexpr (WK == 5) return (uint32_t)c * u;
   else return 1u;
 }
 
-// Weight of pixel (r, c) for weight kind WK: 1 = the u8 weight plane (masked),
-// 2, 3 = coordinate weights, 0 = 1.
 template <int WK>
 __device__ __forceinline__ uint32_t pixel_weight_of(const FinalArgs &a, const Geom &g, int ch, int r, int c) {
-  if constexpr (WK == 1) return pixel_weight(a, g, ch, r, c);
-  else return coord_weight<WK>(r, c);
+  if constexpr (loads_weights<WK>()) return kind_weight<WK>(r, c, pixel_weight(a, g, ch, r, c));
+  else return kind_weight<WK>(r, c, 1u);
 }
 
 // Four weights packed in a word (byte q = column c0 + q) from the weight and
@@ -404,12 +415,9 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
       for (int e = 0; e < CPL; ++e)
         pt[e] = (timg && cf + e < g.W) ? (uint32_t)timg[(int64_t)r * g.W + cf + e] : (1u << a.bits);
     }
-    if constexpr (WK == 1) {
+    if constexpr (WK != 0) {
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) pw[e] = cf + e < g.W ? pixel_weight(a, g, ch, r, cf + e) : 0u;
-    } else if constexpr (WK != 0) {
-#pragma unroll
-      for (int e = 0; e < CPL; ++e) pw[e] = cf + e < g.W ? coord_weight<WK>(r, cf + e) : 0u;
+      for (int e = 0; e < CPL; ++e) pw[e] = cf + e < g.W ? pixel_weight_of<WK>(a, g, ch, r, cf + e) : 0u;
     }
     const uint32_t *lc = lc_base + (int64_t)r * g.bins;
 #pragma unroll
@@ -557,8 +565,8 @@ __device__ __forceinline__ void load_weight_words(const FinalArgs &a, const Geom
 // Weight of column c from the packed words (1 for the unweighted build).
 template <int WK, int N>
 __device__ __forceinline__ uint32_t weight_byte(const uint32_t (&wq)[N], int r, int c0, int c) {
-  if constexpr (WK == 1) return (wq[c >> 2] >> (8 * (c & 3))) & 0xffu;
-  else return coord_weight<WK>(r, c0 + c);
+  if constexpr (loads_weights<WK>()) return kind_weight<WK>(r, c0 + c, (wq[c >> 2] >> (8 * (c & 3))) & 0xffu);
+  else return kind_weight<WK>(r, c0 + c, 1u);
 }
 
 template <typename T, int TW, bool MOM, int WK = 0>
@@ -615,7 +623,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
   // starts on a 4-byte boundary.
   const bool full = cols == TW;
   const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
-                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (WK != 1 || weight_words(a, g, C0));
+                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (!loads_weights<WK>() || weight_words(a, g, C0));
   constexpr int PER = 4 / (int)sizeof(T);  // pixels per 32-bit word
   auto row_step = [&](auto FULL, int rr) {
     constexpr bool F = decltype(FULL)::value;
@@ -649,8 +657,8 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(row);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
-      uint32_t wq[WK == 1 ? TW / 4 : 1];
-      if constexpr (WK == 1) load_weight_words<TW>(a, g, ch, r, C0, wq);
+      uint32_t wq[loads_weights<WK>() ? TW / 4 : 1];
+      if constexpr (loads_weights<WK>()) load_weight_words<TW>(a, g, ch, r, C0, wq);
 #pragma unroll
       for (int c = 0; c < TW; ++c)
         pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u),
@@ -810,7 +818,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
   const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
   const bool full = cols == TW;
   const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
-                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (WK != 1 || weight_words(a, g, C0));
+                     ((int64_t)C0 * sizeof(T)) % 4 == 0 && (!loads_weights<WK>() || weight_words(a, g, C0));
   const bool vec = (g.P & 3) == 0 && (((uintptr_t)a.ih | (uintptr_t)a.mx | (uintptr_t)a.my) & 15) == 0;
   const int nseg = cols * g.P;
   uint32_t *s0 = lds, *s1 = lds + TW * g.P, *s2 = lds + 2 * TW * g.P;
@@ -840,8 +848,8 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(row);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
-      uint32_t wq[WK == 1 ? TW / 4 : 1];
-      if constexpr (WK == 1) load_weight_words<TW>(a, g, ch, r, C0, wq);
+      uint32_t wq[loads_weights<WK>() ? TW / 4 : 1];
+      if constexpr (loads_weights<WK>()) load_weight_words<TW>(a, g, ch, r, C0, wq);
 #pragma unroll
       for (int c = 0; c < TW; ++c)
         pixel(c, (wv[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u),
@@ -864,22 +872,22 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
     // prefetched path: the next row's image words and row carries are loaded
     // while this row is computed and stored
     const int64_t rbase0 = ((int64_t)R0 * g.W + C0) * P;
-    uint32_t wv[TW / PER], rcn = 0, ryn = 0, wqn[WK == 1 ? TW / 4 : 1];
+    uint32_t wv[TW / PER], rcn = 0, ryn = 0, wqn[loads_weights<WK>() ? TW / 4 : 1];
     auto fetch = [&](int r) {
       const uint32_t *wp = reinterpret_cast<const uint32_t *>(img + (int64_t)r * g.W + C0);
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
-      if constexpr (WK == 1) load_weight_words<TW>(a, g, ch, r, C0, wqn);
+      if constexpr (loads_weights<WK>()) load_weight_words<TW>(a, g, ch, r, C0, wqn);
       rcn = lc[(int64_t)r * g.bins];
       if constexpr (MOM) ryn = lcy[(int64_t)r * g.bins];
     };
     if (rows > 0) fetch(R0);
     for (int rr = 0; rr < rows; ++rr) {
       const int r = R0 + rr;
-      uint32_t cur[TW / PER], wq[WK == 1 ? TW / 4 : 1];
+      uint32_t cur[TW / PER], wq[loads_weights<WK>() ? TW / 4 : 1];
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) cur[q] = wv[q];
-      if constexpr (WK == 1) {
+      if constexpr (loads_weights<WK>()) {
 #pragma unroll
         for (int q = 0; q < TW / 4; ++q) wq[q] = wqn[q];
       }

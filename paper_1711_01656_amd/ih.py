@@ -33,6 +33,13 @@ _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
 _SZ = ctypes.c_size_t
+
+
+class Rect(ctypes.Structure):
+    """A half-open rectangle [r0, r1) x [c0, c1) (ih_rect in include/ih.h)."""
+    _fields_ = [("r0", ctypes.c_int32), ("c0", ctypes.c_int32), ("r1", ctypes.c_int32), ("c1", ctypes.c_int32)]
+
+
 SIGNATURES = {
     "ih_version": (ctypes.c_int, []),
     "ih_last_error": (ctypes.c_char_p, []),
@@ -41,6 +48,11 @@ SIGNATURES = {
     "ih_build_weighted": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ,
                                          _P]),
     "ih_jih_update": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "ih_color_likelihood_workspace_size": (_SZ, []),
+    "ih_color_likelihood": (ctypes.c_int, [_P, _I32, _I32, Rect, Rect, _P, _SZ, _P, _P, _P]),
+    "ih_moment_images": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "ih_camshift": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _P, _I64, _I32, _I32, ctypes.c_double, _I32, _P, _P,
+                                   _P]),
     "ih_build_moments2": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "ih_query_quadratic": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _I64, _I32, _P,
                                           _P]),
@@ -392,6 +404,80 @@ def ih_query_wedding(ih: torch.Tensor, C: int, rects: torch.Tensor, layers: int,
     _check(lib().ih_query_wedding(_p(ih), P, H, W, C, _layout(layout), _p(rects), n, layers, KERNELS[kernel],
                                   float(sigma), _p(out), _stream(ih)), "ih_query_wedding")
     return out
+
+
+def _rect(r) -> Rect:
+    r0, c0, r1, c1 = (int(v) for v in r)
+    return Rect(r0, c0, r1, c1)
+
+
+def ih_color_likelihood(rgb: torch.Tensor, fg, bg, q: Optional[torch.Tensor] = None,
+                        L: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                        want_L: bool = True):
+    """FG/BG colour likelihood (Eq. 2.18-2.21) of a 3 x H x W uint8 image with
+    foreground rectangle fg and background rectangle bg (minus fg), each
+    (r0, c0, r1, c1).  Returns (q uint8 codes, L float32 or None)."""
+    _dev(rgb, "rgb", torch.uint8)
+    if rgb.dim() != 3 or rgb.shape[0] != 3:
+        raise IHError("rgb must be 3 x H x W")
+    _, H, W = rgb.shape
+    if q is None:
+        q = torch.empty((H, W), dtype=torch.uint8, device=rgb.device)
+    _dev(q, "q", torch.uint8)
+    if want_L and L is None:
+        L = torch.empty((H, W), dtype=torch.float32, device=rgb.device)
+    if L is not None:
+        _dev(L, "L", torch.float32)
+    need = lib().ih_color_likelihood_workspace_size()
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=rgb.device)
+    _check(lib().ih_color_likelihood(_p(rgb), H, W, _rect(fg), _rect(bg), _p(ws), ws.numel() * ws.element_size(),
+                                     _p(q), _p(L), _stream(rgb)), "ih_color_likelihood")
+    return q, L
+
+
+def ih_moment_images(q: torch.Tensor, out=None, cfg: Optional[TileCfg] = None,
+                     ws: Optional[torch.Tensor] = None):
+    """Moment integral images (S, Sx, Sy) of an H x W uint8 map: int32 S, and
+    Sx, Sy as int32 views of values modulo 2^32."""
+    _dev(q, "q", torch.uint8)
+    H, W = q.shape
+    if out is None:
+        out = tuple(torch.empty((H, W), dtype=torch.int32, device=q.device) for _ in range(3))
+    for t, name in zip(out, ("S", "Sx", "Sy")):
+        _dev(t, name, torch.int32)
+        if t.numel() != H * W:
+            raise IHError("%s must hold H*W values" % name)
+    need = workspace_size(H, W, 1, 1, False, cfg, "bhw")
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=q.device)
+    _check(lib().ih_moment_images(_p(q), H, W, _p(out[0]), _p(out[1]), _p(out[2]),
+                                  ctypes.byref(cfg) if cfg is not None else None, _p(ws),
+                                  ws.numel() * ws.element_size(), _stream(q)), "ih_moment_images")
+    return out
+
+
+def ih_camshift(moments, starts: torch.Tensor, win_h: int, win_w: int, delta: float = 0.5, max_iter: int = 20,
+                centers: Optional[torch.Tensor] = None, iters: Optional[torch.Tensor] = None):
+    """CAMSHIFT (Alg. 1) from n start points (n x 2 float64 row, column) on the
+    moment images of ih_moment_images.  Returns (centres n x 2, steps n)."""
+    S, Sx, Sy = moments
+    for t, name in ((S, "S"), (Sx, "Sx"), (Sy, "Sy")):
+        _dev(t, name, torch.int32)
+    H, W = S.shape
+    _dev(starts, "starts", torch.float64)
+    if starts.dim() != 2 or starts.shape[1] != 2:
+        raise IHError("starts must be n x 2")
+    n = starts.shape[0]
+    if centers is None:
+        centers = torch.empty((n, 2), dtype=torch.float64, device=S.device)
+    if iters is None:
+        iters = torch.empty(n, dtype=torch.int32, device=S.device)
+    _dev(centers, "centers", torch.float64)
+    _dev(iters, "iters", torch.int32)
+    _check(lib().ih_camshift(_p(S), _p(Sx), _p(Sy), H, W, _p(starts), n, win_h, win_w, float(delta), max_iter,
+                             _p(centers), _p(iters), _stream(S)), "ih_camshift")
+    return centers, iters
 
 
 def _rects(rects: torch.Tensor, name="rects") -> torch.Tensor:
