@@ -454,18 +454,25 @@ int ih_camshift(const int32_t *S, const uint32_t *Sx, const uint32_t *Sy,
  * removes the leaving (tail) one.  Computed as one build of the integral
  * histogram of the difference (head +1, tail -1 per pixel, modulo 2^32)
  * whose write-out adds into jih, so each update reads and writes jih once.
+ * The planes are stored cumulative over each channel's bins: plane
+ * ch*bins + k holds the counts of bins 0..k (the plain count of bin k is the
+ * difference of planes k and k-1).
  *
  *   head        device, C x H x W values of type dtype: the entering frame.
  *   tail        device, same shape and dtype: the leaving frame, or NULL
  *               while the window is filling (then JIH = JIH + IH(head)).
  *   dtype, H, W, C, bins, value_bits, layout, cfg, ws, ws_bytes, stream
- *               as for ih_build (workspace: ih_build_workspace_size with
- *               moments = 0).  IH_HWB needs P <= 512 and tile_w * P <= 16384.
- *   jih         device, in/out: P x H x W int32 (in layout).  Start from
- *               zeros (or from ih_build of the first frame).  Every entry
- *               stays exact while the window's frame count * H * W < 2^31.
+ *               as for ih_build, except that cfg = NULL selects the update's
+ *               own default tile (workspace: ih_jih_update_workspace_size).
+ *               IH_HWB needs P <= 512 and tile_w * P <= 16384.
+ *   jih         device, in/out: P x H x W int32 (in layout), cumulative
+ *               planes.  Start from zeros.  Every entry stays exact while
+ *               the window's frame count * H * W < 2^31.
  * Returns IH_OK or IH_ERR_*.  jih must not overlap the frames or ws.
  */
+size_t ih_jih_update_workspace_size(int32_t H, int32_t W, int32_t C,
+                                    int32_t bins, int32_t layout,
+                                    const ih_tile_cfg *cfg);
 int ih_jih_update(const void *head, const void *tail, int32_t dtype,
                   int32_t H, int32_t W, int32_t C, int32_t bins,
                   int32_t value_bits, int32_t layout, int32_t *jih,
@@ -475,8 +482,11 @@ int ih_jih_update(const void *head, const void *tail, int32_t dtype,
 /*
  * ih_local_median - per-pixel median of the spatio-temporal box from a joint
  * integral histogram (Alg. 4, ComputeLocalMedian; Sec. 4.1.1).
- *   jih         device, P x H x W int32 (in layout), P = C * bins, holding
- *               exactly `frames` frames.
+ *   jih         device, P x H x W int32 (in layout), P = C * bins, the
+ *               cumulative planes of ih_jih_update holding exactly `frames`
+ *               frames.  The median is found by a binary search over the
+ *               cumulative counts (bin-major) or 64 bins at a time
+ *               (planes innermost).
  *   frames      number of frames in the window (T + 1), >= 1.
  *   win_h, win_w  spatial window; pixel (r, c) uses rows
  *               r - (win_h-1)/2 .. r + win_h/2 and columns likewise,

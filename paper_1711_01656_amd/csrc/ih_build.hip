@@ -38,12 +38,13 @@ int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds) {
   const size_t stage = ((size_t)g.TH * twp * (g.wgt || g.diff ? 2 : 1) + 3) & ~(size_t)3;
   const int span = g.TH > g.TW ? g.TH : g.TW;
   const int arrays = g.mom ? 2 : 1;
-  long words = ((long)lds_budget - (long)stage) / 4;
+  const long carries = g.cum ? (long)(g.TH + g.TW) : 0;  // per-row and per-column bin-prefix carries
+  long words = ((long)lds_budget - (long)stage) / 4 - carries;
   int b = (int)(words / ((long)span * arrays)) - 1;
   if (b > g.bins) b = g.bins;
   if (b < 1) return set_error(IH_ERR_UNSUPPORTED, "tile %dx%d leaves no LDS for histograms", g.TH, g.TW);
   *bc = b;
-  *lds = stage + (size_t)span * (b + 1) * arrays * 4;
+  *lds = stage + (size_t)span * (b + 1) * arrays * 4 + (size_t)carries * 4;
   return IH_OK;
 }
 
@@ -62,6 +63,7 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
   g->wgt = weighted != 0;
   g->diff = false;
   g->coord = 0;
+  g->cum = false;
   if (g->mom && g->wgt) return set_error(IH_ERR_UNSUPPORTED, "moments of a weighted histogram are not built");
   g->layout = layout;
   int TH, TW, PG;

@@ -43,7 +43,11 @@ inline size_t staged_lds(const Geom &g) {
 
 //    In the joint-IH update (g.diff) a second image, the tail frame, counts
 //    -1 (modulo 2^32) in its pixels' bins; the carries then hold the counts
-//    of head minus tail, exact modulo 2^32.
+//    of head minus tail, exact modulo 2^32.  With cumulative planes (g.cum)
+//    each column's and each row's counts are prefixed over the bins in LDS
+//    before they are written (running carries across bin passes), so every
+//    carry counts the bins <= k; the tile totals, sums of the column counts,
+//    follow.
 template <typename T>
 __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const Geom &g, int bits, int bc,
                                                uint32_t *__restrict__ ws, int blkid, uint32_t *lds,
@@ -54,6 +58,12 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
   uint8_t *bin_s = reinterpret_cast<uint8_t *>(lds);
   uint8_t *wt_s = bin_s + (size_t)g.TH * twp;  // weights (weighted build) or tail bins (update)
   uint32_t *hist = lds + (((size_t)g.TH * twp * (g.wgt || g.diff ? 2 : 1) + 3) >> 2);
+  // bin-prefix carries of the columns and rows (cumulative planes), after the
+  // histograms: hist holds (span) x (bc + 1) words per array
+  uint32_t *ccarry = hist + (size_t)(g.TH > g.TW ? g.TH : g.TW) * (bc + 1) * (g.mom ? 2 : 1);
+  uint32_t *rcarry = ccarry + g.TW;
+  if (g.cum)
+    for (int i = threadIdx.x; i < g.TW + g.TH; i += 256) ccarry[i] = 0u;
   const int tid = threadIdx.x;
   int blk = blkid;
   const int j = blk % g.nTC; blk /= g.nTC;
@@ -113,6 +123,17 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       }
     }
     __syncthreads();
+    if (g.cum) {
+      for (int cl = tid; cl < tw; cl += 256) {
+        uint32_t run = ccarry[cl];
+        for (int k = 0; k < nb; ++k) {
+          run += hist[cl * stride + k];
+          hist[cl * stride + k] = run;
+        }
+        ccarry[cl] = run;
+      }
+      __syncthreads();
+    }
     for (int i = tid; i < nb * tw; i += 256) {
       int k, cl;
       if (g.layout == IH_BHW) { k = i / tw; cl = i - k * tw; }     // unit stride along columns
@@ -180,6 +201,17 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       }
     }
     __syncthreads();
+    if (g.cum) {
+      for (int r = tid; r < th; r += 256) {
+        uint32_t run = rcarry[r];
+        for (int k = 0; k < nb; ++k) {
+          run += hist[r * stride + k];
+          hist[r * stride + k] = run;
+        }
+        rcarry[r] = run;
+      }
+      __syncthreads();
+    }
     for (int i = tid; i < th * nb; i += 256) {
       const int r = i / nb, k = i - r * nb;
       const size_t o = (((size_t)ch * g.nTC + j) * g.H + R0 + r) * g.bins + b0 + k;
@@ -434,13 +466,14 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
     int b[CPL];
 #pragma unroll
     for (int e = 0; e < CPL; ++e)
-      b[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
+      b[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : (ACC ? 1 << 30 : -1);
     uint32_t lcur[PG], lycur[MOM ? PG : 1], wcur[WK ? CPL : 1];
     int bt[ACC ? CPL : 1];
     if constexpr (ACC) {
+      // a tail bin past every plane (2^30) counts nowhere
 #pragma unroll
       for (int e = 0; e < CPL; ++e)
-        bt[e] = cf + e < g.W && pt[e] < (1u << a.bits) ? (int)(((uint64_t)pt[e] * g.bins) >> a.bits) - kb : -1;
+        bt[e] = cf + e < g.W && pt[e] < (1u << a.bits) ? (int)(((uint64_t)pt[e] * g.bins) >> a.bits) - kb : 1 << 30;
     }
 #pragma unroll
     for (int k = 0; k < PG; ++k) lcur[k] = lcv[k];
@@ -458,20 +491,21 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
     for (int k = 0; k < PG; ++k) {
       if constexpr (ACC) {
         if (k < nk) {
-          // row prefix of head minus tail: ballots of both, difference of the
-          // lanes-below counts (modulo 2^32), added to the stored joint IH
+          // cumulative planes: plane k counts the bins <= k.  Row prefix of
+          // head minus tail: ballots of both, difference of the lanes-below
+          // counts (modulo 2^32), added to the stored joint IH
           uint32_t t = lcur[k];
           uint64_t mh[CPL], mt[CPL];
 #pragma unroll
           for (int e = 0; e < CPL; ++e) {
-            mh[e] = ballot(b[e] == k);
-            mt[e] = ballot(bt[e] == k);
+            mh[e] = ballot(b[e] <= k);
+            mt[e] = ballot(bt[e] <= k);
           }
 #pragma unroll
           for (int e = 0; e < CPL; ++e) t = lanes_below(mh[e], t) - lanes_below(mt[e], 0u);
 #pragma unroll
           for (int e = 0; e < CPL; ++e) {
-            t += (b[e] == k ? 1u : 0u) - (bt[e] == k ? 1u : 0u);
+            t += (b[e] <= k ? 1u : 0u) - (bt[e] <= k ? 1u : 0u);
             col[k][e] += t;
           }
           put_add<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec_ok);
@@ -951,8 +985,9 @@ int launch_build(const Geom &g, int dtype, const void *img, const void *tail, co
 
 // 3e. The joint-IH update in the planes-innermost layout: the staged
 //     write-out (one block per tile, one wavefront per 64 planes, row segments
-//     staged in LDS) of the integral histogram of head minus tail, added to
-//     the stored joint IH with 16-byte (or 4-byte) read-modify-write copies.
+//     staged in LDS) of the integral histogram of head minus tail with
+//     cumulative planes (plane k counts bins <= k), added to the stored joint
+//     IH with 16-byte (or 4-byte) read-modify-write copies.
 __device__ __forceinline__ void copy_out_add(int32_t *__restrict__ dst, const uint32_t *__restrict__ src, int n,
                                              bool vec) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -976,8 +1011,9 @@ __device__ __forceinline__ void final_hwb_acc_staged_body(const FinalArgs &a, co
   const int k = p - ch * g.bins;
   const int R0 = I * g.TH, C0 = j * TW;
   const int cols = min(TW, g.W - C0), rows = min(g.TH, g.H - R0);
-  const uint32_t lo = (uint32_t)((((uint64_t)k << a.bits) + g.bins - 1) / g.bins);
-  const uint32_t width = (uint32_t)((((uint64_t)(k + 1) << a.bits) + g.bins - 1) / g.bins) - lo;
+  // values of bins <= k are those below the first value of bin k + 1
+  const uint32_t lo = 0;
+  const uint32_t width = (uint32_t)((((uint64_t)(k + 1) << a.bits) + g.bins - 1) / g.bins);
   const int64_t HW = (int64_t)g.H * g.W;
   const T *img = reinterpret_cast<const T *>(a.img) + ch * HW;
   const T *timg = a.tail ? reinterpret_cast<const T *>(a.tail) + ch * HW : nullptr;

@@ -97,7 +97,8 @@ struct Geom {
   bool mom;
   bool wgt;             // per-pixel u8 weights replace the unit count
   bool diff;            // a second (tail) image counts -1: joint-IH update
-  int coord;            // 2: weight row^2, 3: weight column^2 (second moments); 0: none
+  int coord;            // weight kind of the tile pass (2, 3: row^2, column^2; 4, 5: row, column x plane)
+  bool cum;             // cumulative planes: plane k counts bins <= k (joint-IH update)
   int layout;           // IH_BHW or IH_HWB
   // workspace sections (in 4-byte words)
   size_t off_cc, off_rc, off_tt, off_ccx, off_rcy, off_ttx, off_tty, words;

@@ -10,9 +10,13 @@
 // with the write-out adding its values to the stored JIH in place: one read
 // and one write of the JIH per frame, and no per-frame histogram is kept.
 //
-// The median of a pixel's win_h x win_w x (T+1) box is then read from the
-// JIH: its local histogram by four corners per bin (Eq. 2.16) and the first
-// bin whose running count reaches ceil(N/2), N the box's sample count.
+// The JIH is kept with cumulative planes: plane k of a channel counts the
+// samples of bins <= k (the plain local histogram of bin k is two planes
+// apart, still O(1)).  They cost the same to update (the tile pass prefixes
+// its per-tile counts over the bins in LDS, and the write-out counts
+// bins <= k), and they turn the median into a binary search: the median of a
+// pixel's win_h x win_w x (T+1) box is the first bin whose window count
+// (four corners, Eq. 2.16) reaches ceil(N/2), N the box's sample count.
 #include "ih_build_dev.h"
 
 namespace ih {
@@ -42,9 +46,29 @@ struct MedianWin {
   }
 };
 
-// Bin-major JIH: one thread per pixel (lanes along a row, so every corner
-// load of a plane is one contiguous run), bins walked four at a time with
-// their 16 corner loads in flight together, stopping at the median bin.
+// Window sum of cumulative plane k (bins <= k) of channel ch, modulo 2^32.
+struct CumWin {
+  const int32_t *J;
+  int64_t P, HW;
+  int layout;
+  int64_t o11, o01, o10, o00;  // pixel offsets of the corners (r*W + c)
+  bool top, left;
+  __device__ __forceinline__ uint32_t at(int64_t pix, int64_t p) const {
+    return (uint32_t)(layout == IH_BHW ? J[p * HW + pix] : J[pix * P + p]);
+  }
+  __device__ __forceinline__ uint32_t sum(int64_t p) const {
+    uint32_t v = at(o11, p);
+    if (top) v -= at(o01, p);
+    if (left) v -= at(o10, p);
+    if (top && left) v += at(o00, p);
+    return v;
+  }
+};
+
+// Bin-major JIH: one thread per pixel (a wavefront covers 64 columns of a
+// row, so each probe's corner loads are contiguous runs); the running counts
+// are the cumulative planes themselves, so the median is a binary search
+// for the first bin whose count reaches the target: ceil(log2 bins) probes.
 __global__ __launch_bounds__(256) void k_median_bhw(const int32_t *__restrict__ J, int bins, int H, int W,
                                                     int frames, int wh, int ww, int32_t *__restrict__ out) {
   const int c = blockIdx.x * 64 + (int)(threadIdx.x & 63);
@@ -52,50 +76,32 @@ __global__ __launch_bounds__(256) void k_median_bhw(const int32_t *__restrict__ 
   const int ch = blockIdx.z;
   if (c >= W || r >= H) return;
   const MedianWin w(r, c, H, W, wh, ww);
-  const int64_t HW = (int64_t)H * W;
-  const int32_t *base = J + (int64_t)ch * bins * HW;
-  const bool top = w.r0 > 0, left = w.c0 > 0;
-  const int64_t o11 = (int64_t)w.r1 * W + w.c1;
-  const int64_t o01 = top ? (int64_t)(w.r0 - 1) * W + w.c1 : 0;
-  const int64_t o10 = left ? (int64_t)w.r1 * W + w.c0 - 1 : 0;
-  const int64_t o00 = top && left ? (int64_t)(w.r0 - 1) * W + w.c0 - 1 : 0;
+  CumWin cw;
+  cw.J = J;
+  cw.P = 0;
+  cw.HW = (int64_t)H * W;
+  cw.layout = IH_BHW;
+  cw.top = w.r0 > 0;
+  cw.left = w.c0 > 0;
+  cw.o11 = (int64_t)w.r1 * W + w.c1;
+  cw.o01 = cw.top ? (int64_t)(w.r0 - 1) * W + w.c1 : 0;
+  cw.o10 = cw.left ? (int64_t)w.r1 * W + w.c0 - 1 : 0;
+  cw.o00 = cw.top && cw.left ? (int64_t)(w.r0 - 1) * W + w.c0 - 1 : 0;
   const uint32_t n = (uint32_t)frames * (uint32_t)((w.r1 - w.r0 + 1) * (w.c1 - w.c0 + 1));
   const uint32_t target = (n + 1) / 2;
-  uint32_t cum = 0;
-  int med = bins - 1;
-  for (int k0 = 0; k0 < bins; k0 += 4) {
-    uint32_t h[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      h[u] = 0;
-      if (k0 + u < bins) {
-        const int32_t *pl = base + (int64_t)(k0 + u) * HW;
-        uint32_t v = (uint32_t)pl[o11];
-        if (top) v -= (uint32_t)pl[o01];
-        if (left) v -= (uint32_t)pl[o10];
-        if (top && left) v += (uint32_t)pl[o00];
-        h[u] = v;
-      }
-    }
-    bool done = false;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (!done && k0 + u < bins) {
-        cum += h[u];
-        if (cum >= target) {
-          med = k0 + u;
-          done = true;
-        }
-      }
-    }
-    if (done) break;
+  const int64_t p0 = (int64_t)ch * bins;
+  int lo = 0, hi = bins - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cw.sum(p0 + mid) >= target) hi = mid;
+    else lo = mid + 1;
   }
-  out[(int64_t)ch * HW + (int64_t)r * W + c] = med;
+  out[(int64_t)ch * cw.HW + (int64_t)r * W + c] = lo;
 }
 
-// Planes-innermost JIH: one wavefront per pixel, lanes = 64 bins at a time;
-// each corner is one contiguous 256-byte load, the running count a wave scan,
-// the median the first lane whose count reaches the target.
+// Planes-innermost JIH: one wavefront per pixel, lanes = 64 bins at a time
+// (each corner one contiguous 256-byte load); the first lane whose
+// cumulative count reaches the target is the median.
 __global__ __launch_bounds__(256) void k_median_hwb(const int32_t *__restrict__ J, int C, int bins, int H, int W,
                                                     int frames, int wh, int ww, int32_t *__restrict__ out) {
   const int lane = threadIdx.x & 63;
@@ -106,34 +112,29 @@ __global__ __launch_bounds__(256) void k_median_hwb(const int32_t *__restrict__ 
   const int64_t rem = pix - (int64_t)ch * HW;
   const int r = (int)(rem / W), c = (int)(rem - (int64_t)r * W);
   const MedianWin w(r, c, H, W, wh, ww);
-  const int64_t P = (int64_t)C * bins;
-  const bool top = w.r0 > 0, left = w.c0 > 0;
-  const int64_t o11 = ((int64_t)w.r1 * W + w.c1) * P;
-  const int64_t o01 = top ? ((int64_t)(w.r0 - 1) * W + w.c1) * P : 0;
-  const int64_t o10 = left ? ((int64_t)w.r1 * W + w.c0 - 1) * P : 0;
-  const int64_t o00 = top && left ? ((int64_t)(w.r0 - 1) * W + w.c0 - 1) * P : 0;
+  CumWin cw;
+  cw.J = J;
+  cw.P = (int64_t)C * bins;
+  cw.HW = HW;
+  cw.layout = IH_HWB;
+  cw.top = w.r0 > 0;
+  cw.left = w.c0 > 0;
+  cw.o11 = (int64_t)w.r1 * W + w.c1;
+  cw.o01 = cw.top ? (int64_t)(w.r0 - 1) * W + w.c1 : 0;
+  cw.o10 = cw.left ? (int64_t)w.r1 * W + w.c0 - 1 : 0;
+  cw.o00 = cw.top && cw.left ? (int64_t)(w.r0 - 1) * W + w.c0 - 1 : 0;
   const uint32_t n = (uint32_t)frames * (uint32_t)((w.r1 - w.r0 + 1) * (w.c1 - w.c0 + 1));
   const uint32_t target = (n + 1) / 2;
-  uint32_t carry = 0;
   int med = bins - 1;
   for (int k0 = 0; k0 < bins; k0 += 64) {
     const int k = k0 + lane;
     const bool valid = k < bins;
-    uint32_t h = 0;
-    if (valid) {
-      const int64_t p = (int64_t)ch * bins + k;
-      h = (uint32_t)J[o11 + p];
-      if (top) h -= (uint32_t)J[o01 + p];
-      if (left) h -= (uint32_t)J[o10 + p];
-      if (top && left) h += (uint32_t)J[o00 + p];
-    }
-    const uint32_t inc = wave_incl_scan(h) + carry;
-    const uint64_t m = ballot(valid && inc >= target);
+    const uint32_t cum = valid ? cw.sum((int64_t)ch * bins + k) : 0u;
+    const uint64_t m = ballot(valid && cum >= target);
     if (m) {
       med = k0 + (int)__builtin_ctzll(m);
       break;
     }
-    carry = read_lane(inc, 63);
   }
   if (lane == 0) out[pix] = med;
 }
@@ -159,6 +160,21 @@ static final_fn pick_acc_t(const Geom &g) {
 
 using namespace ih;
 
+// Default tile of the update (device sweeps at 768x576 x 256 bins): short,
+// 128-column bin-major tiles with up to 8 planes per wave.
+static const ih_tile_cfg *update_tile(const ih_tile_cfg *cfg, int32_t layout, int32_t bins, ih_tile_cfg *dflt) {
+  if (cfg || layout != IH_BHW) return cfg;
+  *dflt = {16, 128, 8};
+  while (dflt->planes_per_wave > 1 && dflt->planes_per_wave > bins) dflt->planes_per_wave >>= 1;
+  return dflt;
+}
+
+extern "C" size_t ih_jih_update_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t layout,
+                                               const ih_tile_cfg *cfg) {
+  ih_tile_cfg dflt;
+  return ih_build_workspace_size(H, W, C, bins, 0, layout, update_tile(cfg, layout, bins, &dflt));
+}
+
 extern "C" int ih_jih_update(const void *head, const void *tail, int32_t dtype, int32_t H, int32_t W, int32_t C,
                              int32_t bins, int32_t value_bits, int32_t layout, int32_t *jih,
                              const ih_tile_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
@@ -168,10 +184,13 @@ extern "C" int ih_jih_update(const void *head, const void *tail, int32_t dtype, 
   if (value_bits < 1 || value_bits > maxbits)
     return set_error(IH_ERR_INVALID_ARG, "value_bits %d outside 1..%d", value_bits, maxbits);
   if (bins > (1 << value_bits)) return set_error(IH_ERR_INVALID_ARG, "bins %d exceed 2^value_bits", bins);
+  ih_tile_cfg dflt;
+  cfg = update_tile(cfg, layout, bins, &dflt);
   Geom g;
   int e = make_geom(H, W, C, bins, 0, layout, cfg, &g);
   if (e) return e;
   g.diff = tail != nullptr;
+  g.cum = true;
   if (!ws || ws_bytes < g.words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.words * 4,
                      ws ? ws_bytes : (size_t)0);

@@ -47,6 +47,7 @@ SIGNATURES = {
     "ih_build": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "ih_build_weighted": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ,
                                          _P]),
+    "ih_jih_update_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I32, _P]),
     "ih_jih_update": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "ih_color_likelihood_workspace_size": (_SZ, []),
     "ih_color_likelihood": (ctypes.c_int, [_P, _I32, _I32, Rect, Rect, _P, _SZ, _P, _P, _P]),
@@ -289,6 +290,14 @@ def _frame_dtype(img: torch.Tensor):
     raise IHError("frames must be uint8 or uint16")
 
 
+def jih_update_workspace_size(H, W, C, bins, cfg: Optional[TileCfg] = None, layout: str = "bhw") -> int:
+    n = lib().ih_jih_update_workspace_size(H, W, C, bins, _layout(layout),
+                                           ctypes.byref(cfg) if cfg is not None else None)
+    if n == 0:
+        raise IHError("ih_jih_update_workspace_size: %s" % lib().ih_last_error().decode())
+    return n
+
+
 def ih_jih_update(head: torch.Tensor, tail: Optional[torch.Tensor], bins: int, jih: torch.Tensor,
                   value_bits: Optional[int] = None, cfg: Optional[TileCfg] = None,
                   ws: Optional[torch.Tensor] = None, layout: str = "bhw") -> torch.Tensor:
@@ -307,7 +316,7 @@ def ih_jih_update(head: torch.Tensor, tail: Optional[torch.Tensor], bins: int, j
     _dev(jih, "jih", torch.int32)
     if jih.numel() != C * bins * H * W:
         raise IHError("jih must hold P*H*W values")
-    need = workspace_size(H, W, C, bins, False, cfg, layout)
+    need = jih_update_workspace_size(H, W, C, bins, cfg, layout)
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=head.device)
     rc = lib().ih_jih_update(_p(head), _p(tail), dt, H, W, C, bins, bits, _layout(layout), _p(jih),

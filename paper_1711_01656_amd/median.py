@@ -29,7 +29,7 @@ class SpatioTemporalMedian:
         P = C * bins
         self.ring = torch.empty((T + 1, C, H, W), dtype=dtype, device=device)
         self.jih = torch.zeros(ih.shape_of(P, H, W, layout), dtype=torch.int32, device=device)
-        self.ws = torch.empty(ih.workspace_size(H, W, C, bins, False, cfg, layout), dtype=torch.uint8,
+        self.ws = torch.empty(ih.jih_update_workspace_size(H, W, C, bins, cfg, layout), dtype=torch.uint8,
                               device=device)
         self.median = torch.empty((C, H, W), dtype=torch.int32, device=device)
         self.count = 0

@@ -1,8 +1,8 @@
 """GPU parity of the spatio-temporal median path (Alg. 4): the in-place joint
 integral histogram update (bit-exact against the oracle's joint IH of the
-window after every push), the local median from a joint IH (bit-exact
-against the oracle's median of the samples) and the streaming model end to
-end, both layouts."""
+window after every push, in the cumulative-plane form the GPU stores), the
+local median from a joint IH (bit-exact against the oracle's median of the
+samples) and the streaming model end to end, both layouts."""
 import itertools
 
 import numpy as np
@@ -39,6 +39,13 @@ def to_layout(a, layout):
     return a if layout == "bhw" else np.ascontiguousarray(a.transpose(1, 2, 0))
 
 
+def cum(J, C, bins):
+    """Joint IH with cumulative planes (plane k counts bins <= k), as the GPU
+    stores it, from the oracle's plain joint IH."""
+    P, H, W = J.shape
+    return J.reshape(C, bins, H, W).cumsum(axis=1, dtype=np.int64).reshape(P, H, W).astype(np.int32)
+
+
 def video(seed, F, C, H, W, bits):
     rng = np.random.default_rng(seed)
     dt = np.uint8 if bits <= 8 else np.uint16
@@ -72,15 +79,15 @@ def test_jih_update_tracks_window(C, H, W, bins, bits, layout):
         tail = gpu(v[f - T1]) if f >= T1 else None
         ih.ih_jih_update(gpu(v[f]), tail, bins, J, bits, layout=layout)
         lo = max(0, f - T1 + 1)
-        assert np.array_equal(bhw(J, layout), oracle.jih(v[lo:f + 1], bins, bits)), f
+        assert np.array_equal(bhw(J, layout), cum(oracle.jih(v[lo:f + 1], bins, bits), C, bins)), f
 
 
 def test_jih_update_every_tile_shape():
     ih = ihlib()
     C, H, W, bins = 2, 150, 333, 16
     v = video(11, 3, C, H, W, 8)
-    base = oracle.jih(v[0:2], bins, 8)
-    ref = oracle.jih(v[1:3], bins, 8)
+    base = cum(oracle.jih(v[0:2], bins, 8), C, bins)
+    ref = cum(oracle.jih(v[1:3], bins, 8), C, bins)
     shapes = [("bhw", th, tw, pg) for th, tw, pg in itertools.product((1, 7, 32, 64, 128), (64, 128, 256),
                                                                       (1, 2, 4, 8, 16))]
     shapes += [("hwb", th, tw, 64) for th, tw in itertools.product((1, 7, 32, 64, 256), (16, 32, 64))]
@@ -102,7 +109,7 @@ def test_jih_update_every_tile_shape():
 def test_jih_update_same_frame_is_identity_and_unaligned_output():
     ih = ihlib()
     v = video(12, 2, 1, 40, 257, 8)
-    base = oracle.jih(v, 8, 8)
+    base = cum(oracle.jih(v, 8, 8), 1, 8)
     flat = torch.empty(8 * 40 * 257 + 1, dtype=torch.int32, device=DEV)
     J = flat[1:].view(8, 40, 257)                # 4-byte aligned, not 16
     J.copy_(gpu(base))
@@ -110,7 +117,7 @@ def test_jih_update_same_frame_is_identity_and_unaligned_output():
     ih.ih_jih_update(f, f, 8, J, cfg=ih.TileCfg(16, 256, 4))
     assert np.array_equal(J.cpu().numpy(), base)
     ih.ih_jih_update(gpu(v[0]), f, 8, J, cfg=ih.TileCfg(16, 256, 4))
-    assert np.array_equal(J.cpu().numpy(), oracle.jih(v[[0, 0]], 8, 8))
+    assert np.array_equal(J.cpu().numpy(), cum(oracle.jih(v[[0, 0]], 8, 8), 1, 8))
 
 
 MEDIAN_CASES = [
@@ -132,7 +139,7 @@ def test_local_median_matches_oracle(C, H, W, bins, frames, wh, ww, layout):
     say("median", layout, C, H, W, bins, frames, wh, ww)
     ih = ihlib()
     v = video(H * W + frames, frames, C, H, W, 8)
-    J = gpu(to_layout(oracle.jih(v, bins, 8), layout))
+    J = gpu(to_layout(cum(oracle.jih(v, bins, 8), C, bins), layout))
     m = ih.ih_local_median(J, C, bins, frames, wh, ww, layout=layout)
     assert np.array_equal(m.cpu().numpy(), oracle.st_median(v, bins, 8, wh, ww))
 
@@ -173,7 +180,7 @@ def test_surveillance_768x576_256bins(layout):
             ref = oracle.st_median(v[f - T:f + 1, None], 256, 8, 3, 3)
             assert np.array_equal(med.cpu().numpy(), ref), f
             J = bhw(model.jih, layout)
-            assert np.array_equal(J[:, -1, -1], np.bincount(v[f - T:f + 1].ravel(), minlength=256))
+            assert np.array_equal(J[:, -1, -1], np.cumsum(np.bincount(v[f - T:f + 1].ravel(), minlength=256)))
 
 
 def test_median_errors():
