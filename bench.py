@@ -358,7 +358,7 @@ def camshift_leg(torch, ih, synth, n_starts=4096):
     L = torch.empty((H, W), dtype=torch.float32, device=dev)
     ws = torch.empty(ih.lib().ih_color_likelihood_workspace_size(), dtype=torch.uint8, device=dev)
     moms = tuple(torch.empty((H, W), dtype=torch.int32, device=dev) for _ in range(3))
-    mws = torch.empty(ih.workspace_size(H, W, 1, 1, False, None, "bhw"), dtype=torch.uint8, device=dev)
+    mws = torch.empty(ih.workspace_size(H, W, 1, 1, True, None, "bhw"), dtype=torch.uint8, device=dev)
     rng = np.random.default_rng(5)
     st_np = np.stack([r + h / 2 + rng.uniform(-h, h, n_starts), c + w / 2 + rng.uniform(-w, w, n_starts)], 1)
     starts = torch.from_numpy(st_np).to(dev)

@@ -413,12 +413,13 @@ int ih_color_likelihood(const uint8_t *rgb, int32_t H, int32_t W, ih_rect fg,
  *   S(r,c)  = sum over r' <= r, c' <= c of q(r',c')          (int32, exact)
  *   Sx(r,c) = sum of r' * q(r',c'),  Sy(r,c) = sum of c' * q(r',c')
  *             (uint32, modulo 2^32)
- * built by the integral-histogram passes with one plane and the weights q,
- * row * q and column * q.
+ * built by one integral-histogram build with one plane, the weights q and
+ * moments.
  *   q           device, H x W uint8; H * W * 255 <= 2^31 - 1.
  *   S, Sx, Sy   device, out: H x W each.
- *   cfg, ws, ws_bytes  as for ih_build with C = 1, bins = 1, IH_BHW
- *               (workspace: ih_build_workspace_size(H, W, 1, 1, 0, IH_BHW, cfg)).
+ *   cfg, ws, ws_bytes  as for ih_build with C = 1, bins = 1, IH_BHW and
+ *               moments (workspace: ih_build_workspace_size(H, W, 1, 1, 1,
+ *               IH_BHW, cfg)).
  * Returns IH_OK or IH_ERR_*.
  */
 int ih_moment_images(const uint8_t *q, int32_t H, int32_t W, int32_t *S,

@@ -64,7 +64,6 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
   g->diff = false;
   g->coord = 0;
   g->cum = false;
-  if (g->mom && g->wgt) return set_error(IH_ERR_UNSUPPORTED, "moments of a weighted histogram are not built");
   g->layout = layout;
   int TH, TW, PG;
   if (cfg) {

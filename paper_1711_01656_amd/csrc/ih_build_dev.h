@@ -112,13 +112,11 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
         }
         const uint32_t w = g.coord == 2   ? (uint32_t)(R0 + r) * (uint32_t)(R0 + r)
                            : g.coord == 3 ? (uint32_t)(C0 + cl) * (uint32_t)(C0 + cl)
-                           : g.coord == 4 ? (uint32_t)(R0 + r) * (uint32_t)wt_s[r * twp + cl]
-                           : g.coord == 5 ? (uint32_t)(C0 + cl) * (uint32_t)wt_s[r * twp + cl]
                            : g.wgt        ? (uint32_t)wt_s[r * twp + cl]
                                           : 1u;
         if (b >= 0 && b < nb && w) {
           atomicAdd(&hist[cl * stride + b], w);
-          if (g.mom) atomicAdd(&hist[colw + cl * stride + b], (uint32_t)(R0 + r));
+          if (g.mom) atomicAdd(&hist[colw + cl * stride + b], w * (uint32_t)(R0 + r));
         }
       }
     }
@@ -190,13 +188,11 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
         }
         const uint32_t w = g.coord == 2   ? (uint32_t)(R0 + r) * (uint32_t)(R0 + r)
                            : g.coord == 3 ? (uint32_t)(C0 + cl) * (uint32_t)(C0 + cl)
-                           : g.coord == 4 ? (uint32_t)(R0 + r) * (uint32_t)wt_s[r * twp + cl]
-                           : g.coord == 5 ? (uint32_t)(C0 + cl) * (uint32_t)wt_s[r * twp + cl]
                            : g.wgt        ? (uint32_t)wt_s[r * twp + cl]
                                           : 1u;
         if (b >= 0 && b < nb && w) {
           atomicAdd(&hist[r * stride + b], w);
-          if (g.mom) atomicAdd(&hist[roww + r * stride + b], (uint32_t)(C0 + cl));
+          if (g.mom) atomicAdd(&hist[roww + r * stride + b], w * (uint32_t)(C0 + cl));
         }
       }
     }
@@ -327,10 +323,9 @@ __device__ __forceinline__ uint32_t pixel_weight(const FinalArgs &a, const Geom 
 
 // Weight kinds of the weighted write-outs: 0 counts (weight 1); 1 the u8
 // weight plane (masked); 2, 3 row^2 and column^2 (second-moment integral
-// histograms); 4, 5 row and column times the u8 weight plane (first-moment
-// integral images of a weight map).  All modulo 2^32.
+// histograms, modulo 2^32).
 template <int WK>
-constexpr bool loads_weights() { return WK == 1 || WK == 4 || WK == 5; }
+constexpr bool loads_weights() { return WK == 1; }
 
 // The weight of pixel (r, c) given its u8 plane weight u.
 template <int WK>
@@ -338,8 +333,6 @@ __device__ __forceinline__ uint32_t kind_weight(int r, int c, uint32_t u) {
   if constexpr (WK == 1) return u;
   else if constexpr (WK == 2) return (uint32_t)r * (uint32_t)r;
   else if constexpr (WK == 3) return (uint32_t)c * (uint32_t)c;
-  else if constexpr (WK == 4) return (uint32_t)r * u;
-  else if constexpr (WK == 5) return (uint32_t)c * u;
   else return 1u;
 }
 
@@ -518,9 +511,29 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 #pragma unroll
           for (int e = 0; e < CPL; ++e) sw[e] = (e ? sw[e - 1] : 0u) + (b[e] == k ? wcur[e] : 0u);
           const uint32_t t0 = wave_incl_scan(sw[CPL - 1]) - sw[CPL - 1] + lcur[k];
+          uint32_t pre[CPL];
 #pragma unroll
-          for (int e = 0; e < CPL; ++e) col[k][e] += t0 + sw[e];
+          for (int e = 0; e < CPL; ++e) {
+            pre[e] = t0 + sw[e];
+            col[k][e] += pre[e];
+          }
           put<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec_ok);
+          if constexpr (MOM) {
+            // weighted moments: row * weight and column * weight
+            uint32_t y[CPL];
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) {
+              colx[k][e] += (uint32_t)r * pre[e];
+              y[e] = (b[e] == k) ? wcur[e] * (uint32_t)(cf + e) : 0u;
+            }
+#pragma unroll
+            for (int e = 1; e < CPL; ++e) y[e] += y[e - 1];
+            const uint32_t ey = wave_incl_scan(y[CPL - 1]) - y[CPL - 1] + lycur[k];
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) coly[k][e] += ey + y[e];
+            put<CPL>(reinterpret_cast<int32_t *>(mx_base) + k * HW + orow, colx[k], cf, g.W, vec_ok);
+            put<CPL>(reinterpret_cast<int32_t *>(my_base) + k * HW + orow, coly[k], cf, g.W, vec_ok);
+          }
         }
       } else if (k < nk) {
         uint32_t t = lcur[k];

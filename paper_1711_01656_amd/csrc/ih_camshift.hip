@@ -8,9 +8,9 @@
 //      FP32) and of its 8-bit code round-half-up(255 L) taken in integers,
 //      then the back-projection of every pixel through the tables.
 //   3. The moment integral images of the 8-bit map q: sums of q, row * q and
-//      column * q over [0, r] x [0, c], built by the integral-histogram passes
-//      with one plane and weight kinds "u8 plane", "row x plane" and
-//      "column x plane" (the last two modulo 2^32).
+//      column * q over [0, r] x [0, c], built by one pass of the
+//      integral-histogram build with one plane, the weights q and moments
+//      (the moment sums modulo 2^32).
 //   4. CAMSHIFT: one thread per start point; each step reads the window's
 //      M00 and first moments from the three images with four corners each
 //      (O(1) per step whatever the window size) and moves to the centroid.
@@ -117,10 +117,10 @@ __global__ __launch_bounds__(256) void k_camshift(const int32_t *__restrict__ S,
   iters[i] = it;
 }
 
-template <int WK>
-static final_fn pick_moment_t(const Geom &g) {
+// the one-plane weighted build with moments: sums of q, row * q, column * q
+static final_fn pick_moment(const Geom &g) {
 #define IH_F(C_) \
-  if (g.CPL == C_) return &k_final<uint8_t, C_, 1, false, WK>;
+  if (g.CPL == C_) return &k_final<uint8_t, C_, 1, true, 1>;
   IH_F(1) IH_F(2) IH_F(4)
 #undef IH_F
   return nullptr;
@@ -169,22 +169,16 @@ extern "C" int ih_moment_images(const uint8_t *q, int32_t H, int32_t W, int32_t 
   if (H >= 1 && W >= 1 && (int64_t)H * W * 255 > (int64_t)INT32_MAX)
     return set_error(IH_ERR_OVERFLOW, "H*W*255 = %lld may overflow the int32 sums", (long long)H * W * 255);
   Geom g;
-  int e = make_geom(H, W, 1, 1, 0, IH_BHW, cfg, &g, 1);
+  int e = make_geom(H, W, 1, 1, 1, IH_BHW, cfg, &g, 1);
   if (e) return e;
   if (!ws || ws_bytes < g.words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.words * 4,
                      ws ? ws_bytes : (size_t)0);
-  hipStream_t s = as_stream(stream);
-  for (int WK : {1, 4, 5}) {
-    g.coord = WK == 1 ? 0 : WK;
-    final_fn fin = WK == 1 ? pick_moment_t<1>(g) : WK == 4 ? pick_moment_t<4>(g) : pick_moment_t<5>(g);
-    if (!fin) return set_error(IH_ERR_UNSUPPORTED, "no write-out kernel for tile_w %d", g.TW);
-    int32_t *dst = WK == 1 ? S : reinterpret_cast<int32_t *>(WK == 4 ? Sx : Sy);
-    FinalArgs fa{q, dst, nullptr, nullptr, reinterpret_cast<uint32_t *>(ws), 8,
-                 (W % g.CPL == 0 && (uintptr_t)dst % 16 == 0) ? 1 : 0, q, nullptr};
-    if ((e = launch_build(g, IH_U8, q, nullptr, q, nullptr, 8, ws, fin, fa, s))) return e;
-  }
-  return IH_OK;
+  final_fn fin = pick_moment(g);
+  if (!fin) return set_error(IH_ERR_UNSUPPORTED, "no write-out kernel for tile_w %d", g.TW);
+  const bool aligned = (((uintptr_t)S | (uintptr_t)Sx | (uintptr_t)Sy) & 15) == 0;
+  FinalArgs fa{q, S, Sx, Sy, reinterpret_cast<uint32_t *>(ws), 8, (W % g.CPL == 0 && aligned) ? 1 : 0, q, nullptr};
+  return launch_build(g, IH_U8, q, nullptr, q, nullptr, 8, ws, fin, fa, as_stream(stream));
 }
 
 extern "C" int ih_camshift(const int32_t *S, const uint32_t *Sx, const uint32_t *Sy, int32_t H, int32_t W,

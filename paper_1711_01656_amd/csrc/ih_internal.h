@@ -97,7 +97,7 @@ struct Geom {
   bool mom;
   bool wgt;             // per-pixel u8 weights replace the unit count
   bool diff;            // a second (tail) image counts -1: joint-IH update
-  int coord;            // weight kind of the tile pass (2, 3: row^2, column^2; 4, 5: row, column x plane)
+  int coord;            // coordinate weight of the tile pass (2: row^2, 3: column^2); 0: none
   bool cum;             // cumulative planes: plane k counts bins <= k (joint-IH update)
   int layout;           // IH_BHW or IH_HWB
   // workspace sections (in 4-byte words)

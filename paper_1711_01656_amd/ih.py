@@ -457,7 +457,7 @@ def ih_moment_images(q: torch.Tensor, out=None, cfg: Optional[TileCfg] = None,
         _dev(t, name, torch.int32)
         if t.numel() != H * W:
             raise IHError("%s must hold H*W values" % name)
-    need = workspace_size(H, W, 1, 1, False, cfg, "bhw")
+    need = workspace_size(H, W, 1, 1, True, cfg, "bhw")
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=q.device)
     _check(lib().ih_moment_images(_p(q), H, W, _p(out[0]), _p(out[1]), _p(out[2]),
