@@ -4,10 +4,22 @@
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "ih_internal.h"
 
 namespace ih {
+
+// Calls f(std::integral_constant<int, i>{}) for i = 0 .. N-1 (unrolled, so
+// per-slot register arrays can be indexed by i).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // Column-count carry arrays (CC, CCX) are indexed [p][I][c] for the bin-major
 // write-out and [I][c][p] for the planes-innermost one, so that each form
@@ -427,58 +439,61 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
   uint32_t *mx_base = MOM ? a.mx + ((int64_t)ch * g.bins + kb) * HW + cf : nullptr;
   uint32_t *my_base = MOM ? a.my + ((int64_t)ch * g.bins + kb) * HW + cf : nullptr;
 
-  // the next row's pixels and row carries are loaded while this row is
-  // written (software pipelining hides their latency)
+  // rows are software-pipelined D deep: the pixels and row carries of the
+  // next D rows are in flight while a row is computed and written (D is
+  // larger when a row's registers are few)
+  constexpr int D = CPL * PG <= 4 ? 4 : (CPL * PG <= 16 ? 2 : 1);
   const T *timg = ACC && a.tail ? reinterpret_cast<const T *>(a.tail) + ch * HW : nullptr;
-  uint32_t px[CPL], lcv[PG], lcyv[MOM ? PG : 1], pw[WK ? CPL : 1], pt[ACC ? CPL : 1];
-  auto fetch = [&](int r) {
+  uint32_t px[D][CPL], lcv[D][PG], lcyv[D][MOM ? PG : 1], pw[D][WK ? CPL : 1], pt[D][ACC ? CPL : 1];
+  auto fetch = [&](int r, auto SLOT) {
+    constexpr int d = decltype(SLOT)::value;
 #pragma unroll
-    for (int e = 0; e < CPL; ++e) px[e] = cf + e < g.W ? (uint32_t)img[(int64_t)r * g.W + cf + e] : 0u;
+    for (int e = 0; e < CPL; ++e) px[d][e] = cf + e < g.W ? (uint32_t)img[(int64_t)r * g.W + cf + e] : 0u;
     if constexpr (ACC) {
       // a tail bin of -1 (value 2^bits) matches no plane
 #pragma unroll
       for (int e = 0; e < CPL; ++e)
-        pt[e] = (timg && cf + e < g.W) ? (uint32_t)timg[(int64_t)r * g.W + cf + e] : (1u << a.bits);
+        pt[d][e] = (timg && cf + e < g.W) ? (uint32_t)timg[(int64_t)r * g.W + cf + e] : (1u << a.bits);
     }
     if constexpr (WK != 0) {
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) pw[e] = cf + e < g.W ? pixel_weight_of<WK>(a, g, ch, r, cf + e) : 0u;
+      for (int e = 0; e < CPL; ++e) pw[d][e] = cf + e < g.W ? pixel_weight_of<WK>(a, g, ch, r, cf + e) : 0u;
     }
     const uint32_t *lc = lc_base + (int64_t)r * g.bins;
 #pragma unroll
-    for (int k = 0; k < PG; ++k) lcv[k] = k < nk ? lc[k] : 0u;
+    for (int k = 0; k < PG; ++k) lcv[d][k] = k < nk ? lc[k] : 0u;
     if constexpr (MOM) {
       const uint32_t *lcy = lcy_base + (int64_t)r * g.bins;
 #pragma unroll
-      for (int k = 0; k < PG; ++k) lcyv[k] = k < nk ? lcy[k] : 0u;
+      for (int k = 0; k < PG; ++k) lcyv[d][k] = k < nk ? lcy[k] : 0u;
     }
   };
-  if (rows > 0) fetch(R0);
-  for (int rr = 0; rr < rows; ++rr) {
+  auto row = [&](auto SLOT, int rr) {
+    constexpr int d = decltype(SLOT)::value;
     const int r = R0 + rr;
     int b[CPL];
 #pragma unroll
     for (int e = 0; e < CPL; ++e)
-      b[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : (ACC ? 1 << 30 : -1);
+      b[e] = cf + e < g.W ? (int)(((uint64_t)px[d][e] * g.bins) >> a.bits) - kb : (ACC ? 1 << 30 : -1);
     uint32_t lcur[PG], lycur[MOM ? PG : 1], wcur[WK ? CPL : 1];
     int bt[ACC ? CPL : 1];
     if constexpr (ACC) {
       // a tail bin past every plane (2^30) counts nowhere
 #pragma unroll
       for (int e = 0; e < CPL; ++e)
-        bt[e] = cf + e < g.W && pt[e] < (1u << a.bits) ? (int)(((uint64_t)pt[e] * g.bins) >> a.bits) - kb : 1 << 30;
+        bt[e] = cf + e < g.W && pt[d][e] < (1u << a.bits) ? (int)(((uint64_t)pt[d][e] * g.bins) >> a.bits) - kb : 1 << 30;
     }
 #pragma unroll
-    for (int k = 0; k < PG; ++k) lcur[k] = lcv[k];
+    for (int k = 0; k < PG; ++k) lcur[k] = lcv[d][k];
     if constexpr (WK != 0) {
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) wcur[e] = pw[e];
+      for (int e = 0; e < CPL; ++e) wcur[e] = pw[d][e];
     }
     if constexpr (MOM) {
 #pragma unroll
-      for (int k = 0; k < PG; ++k) lycur[k] = lcyv[k];
+      for (int k = 0; k < PG; ++k) lycur[k] = lcyv[d][k];
     }
-    if (rr + 1 < rows) fetch(r + 1);
+    if (rr + D < rows) fetch(r + D, SLOT);
     const int64_t orow = (int64_t)r * g.W;
 #pragma unroll
     for (int k = 0; k < PG; ++k) {
@@ -567,6 +582,14 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
         }
       }
     }
+  };
+  static_for<D>([&](auto SLOT) {
+    if (decltype(SLOT)::value < rows) fetch(R0 + decltype(SLOT)::value, SLOT);
+  });
+  for (int r0 = 0; r0 < rows; r0 += D) {
+    static_for<D>([&](auto SLOT) {
+      if (r0 + decltype(SLOT)::value < rows) row(SLOT, r0 + decltype(SLOT)::value);
+    });
   }
 }
 
