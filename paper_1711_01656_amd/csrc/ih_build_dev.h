@@ -326,6 +326,37 @@ __device__ __forceinline__ void put_add(int32_t *dst, const uint32_t (&v)[CPL], 
   }
 }
 
+// Adds col[k] (CPL consecutive values) to plane k of the int32 output in
+// place for k < nk, planes HW apart: all loads first, then the stores.
+template <int CPL, int PG>
+__device__ __forceinline__ void add_planes(int32_t *dst, int64_t HW, const uint32_t (&col)[PG][CPL], int nk, int cf,
+                                           int W, bool vec_ok) {
+  if (vec_ok && cf + CPL <= W) {
+    typedef typename vec_of<CPL>::type VT;
+    VT old[PG];
+#pragma unroll
+    for (int k = 0; k < PG; ++k)
+      if (k < nk) old[k] = *reinterpret_cast<const VT *>(dst + k * HW);
+#pragma unroll
+    for (int k = 0; k < PG; ++k) {
+      if (k < nk) {
+        int t[CPL];
+        if constexpr (CPL == 1) {
+          t[0] = old[k] + (int)col[k][0];
+        } else {
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) t[e] = old[k][e] + (int)col[k][e];
+        }
+        store_stream<CPL>(dst + k * HW, t);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PG; ++k)
+      if (k < nk) put_add<CPL>(dst + k * HW, col[k], cf, W, false);
+  }
+}
+
 // Weight of pixel (r, c) of channel ch in the weighted build: wt where the
 // mask is set (or there is no mask), else 0.
 __device__ __forceinline__ uint32_t pixel_weight(const FinalArgs &a, const Geom &g, int ch, int r, int c) {
@@ -441,8 +472,10 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 
   // rows are software-pipelined D deep: the pixels and row carries of the
   // next D rows are in flight while a row is computed and written (D is
-  // larger when a row's registers are few)
-  constexpr int D = CPL * PG <= 4 ? 4 : (CPL * PG <= 16 ? 2 : 1);
+  // larger when a row's registers are few).  The joint-IH update (ACC) keeps
+  // D = 1: its read-modify-write stores want occupancy more than deeper
+  // prefetch (two rows cost it 26 registers and two waves per SIMD).
+  constexpr int D = ACC ? 1 : (CPL * PG <= 4 ? 4 : (CPL * PG <= 16 ? 2 : 1));
   const T *timg = ACC && a.tail ? reinterpret_cast<const T *>(a.tail) + ch * HW : nullptr;
   uint32_t px[D][CPL], lcv[D][PG], lcyv[D][MOM ? PG : 1], pw[D][WK ? CPL : 1], pt[D][ACC ? CPL : 1];
   auto fetch = [&](int r, auto SLOT) {
@@ -516,7 +549,6 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
             t += (b[e] <= k ? 1u : 0u) - (bt[e] <= k ? 1u : 0u);
             col[k][e] += t;
           }
-          put_add<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec_ok);
         }
       } else if constexpr (WK != 0) {
         if (k < nk) {
@@ -581,6 +613,12 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
           put<CPL>(reinterpret_cast<int32_t *>(my_base) + k * HW + orow, coly[k], cf, g.W, vec_ok);
         }
       }
+    }
+    if constexpr (ACC) {
+      // read-modify-write of the row's planes with every load issued before
+      // the first store (the planes' addresses could alias as far as the
+      // compiler knows, so a per-plane load-add-store would serialise)
+      add_planes<CPL, PG>(out_base + orow, HW, col, nk, cf, g.W, vec_ok);
     }
   };
   static_for<D>([&](auto SLOT) {
@@ -1030,7 +1068,17 @@ __device__ __forceinline__ void copy_out_add(int32_t *__restrict__ dst, const ui
   if (vec) {
     const v4i *s4 = reinterpret_cast<const v4i *>(src);
     v4i *d4 = reinterpret_cast<v4i *>(dst);
-    for (int i = tid; i < (n >> 2); i += nt) __builtin_nontemporal_store(d4[i] + s4[i], d4 + i);
+    const int n4 = n >> 2;
+    // four loads of the stored values in flight before the four stores
+    for (int i0 = tid; i0 < n4; i0 += 4 * nt) {
+      v4i old[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (i0 + q * nt < n4) old[q] = d4[i0 + q * nt];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (i0 + q * nt < n4) __builtin_nontemporal_store(old[q] + s4[i0 + q * nt], d4 + i0 + q * nt);
+    }
   } else {
     for (int i = tid; i < n; i += nt) dst[i] = (int)((uint32_t)dst[i] + src[i]);
   }
@@ -1069,6 +1117,56 @@ __device__ __forceinline__ void final_hwb_acc_staged_body(const FinalArgs &a, co
   const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
   const bool vec = (g.P & 3) == 0 && ((uintptr_t)a.ih & 15) == 0;
   const int nseg = cols * g.P;
+  const bool full = cols == TW;
+  const bool words = full && ((((uintptr_t)a.img | (uintptr_t)a.tail) & 3) == 0) &&
+                     ((int64_t)g.W * sizeof(T)) % 4 == 0 && ((int64_t)C0 * sizeof(T)) % 4 == 0;
+  if (words) {
+    // full tiles whose rows are word-aligned: head and tail rows read as
+    // 32-bit words, the next row's words and row carry loaded while this
+    // row is computed and written
+    constexpr int PER = 4 / (int)sizeof(T);
+    constexpr uint32_t VMASK = (1u << (8 * sizeof(T))) - 1u;
+    uint32_t hw[TW / PER], tw[TW / PER] = {}, rcn = 0;
+    auto fetch = [&](int r) {
+      const uint32_t *hp = reinterpret_cast<const uint32_t *>(img + (int64_t)r * g.W + C0);
+#pragma unroll
+      for (int q = 0; q < TW / PER; ++q) hw[q] = hp[q];
+      if (timg) {
+        const uint32_t *tp = reinterpret_cast<const uint32_t *>(timg + (int64_t)r * g.W + C0);
+#pragma unroll
+        for (int q = 0; q < TW / PER; ++q) tw[q] = tp[q];
+      }
+      rcn = lc[(int64_t)r * g.bins];
+    };
+    if (rows > 0) fetch(R0);
+    for (int rr = 0; rr < rows; ++rr) {
+      const int r = R0 + rr;
+      uint32_t hcur[TW / PER], tcur[TW / PER];
+#pragma unroll
+      for (int q = 0; q < TW / PER; ++q) {
+        hcur[q] = hw[q];
+        tcur[q] = tw[q];
+      }
+      uint32_t rc = rcn;
+      if (rr + 1 < rows) fetch(r + 1);
+#pragma unroll
+      for (int c = 0; c < TW; ++c) {
+        const uint32_t hv = (hcur[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & VMASK;
+        uint32_t hit = (hv - lo) < width ? 1u : 0u;
+        if (timg) {
+          const uint32_t tv = (tcur[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & VMASK;
+          hit -= (tv - lo) < width ? 1u : 0u;
+        }
+        rc += hit;
+        col[c] += rc;
+        lds[c * g.P + p] = col[c];
+      }
+      __syncthreads();
+      copy_out_add(a.ih + ((int64_t)r * g.W + C0) * P, lds, nseg, vec);
+      __syncthreads();
+    }
+    return;
+  }
   for (int rr = 0; rr < rows; ++rr) {
     const int r = R0 + rr;
     const T *row = img + (int64_t)r * g.W + C0;
