@@ -243,6 +243,7 @@ int ih_pyramid_desc(const int32_t *ih, int32_t P, int32_t H, int32_t W,
  *   best       device, out: one int32, the lowest candidate index with the
  *              smallest distance (largest similarity for IH_PMK), or -1 if
  *              no candidate lies inside the frame.
+ * IH_ERR_RANGE when n >= 2^31 or, planes innermost, W * P >= 2^32.
  */
 int ih_match_candidates(const int32_t *ih, int32_t P, int32_t H, int32_t W,
                         int32_t layout, const int32_t *tmpl_desc,

@@ -273,6 +273,8 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
       if (!F.origins || !F.dist || !F.best) return set_error(IH_ERR_INVALID_ARG, "frame %d: NULL search buffer", f);
       if (F.win_h < 1 || F.win_w < 1) return set_error(IH_ERR_INVALID_ARG, "frame %d: window must be positive", f);
       if (F.n_cand >= ((int64_t)1 << 31)) return set_error(IH_ERR_RANGE, "frame %d: too many candidates", f);
+      if (hwb && (int64_t)F.W * P.g.P > 0xffffffffLL)
+        return set_error(IH_ERR_RANGE, "frame %d: W*P above 2^32-1 planes-innermost", f);
       if (!F.tmpl_desc && !F.tmpl_out)
         return set_error(IH_ERR_INVALID_ARG, "frame %d: need tmpl_desc or tmpl_out", f);
       P.tmpl_desc = F.tmpl_desc;

@@ -90,8 +90,15 @@ __global__ __launch_bounds__(256) void k_camshift(const int32_t *__restrict__ S,
   if (i >= n) return;
   double cr = starts[2 * i], cc = starts[2 * i + 1];
   int it = 0;
-  auto at32 = [&](const int32_t *t, int r, int c) -> int64_t { return (r < 0 || c < 0) ? 0 : t[(int64_t)r * W + c]; };
-  auto atu = [&](const uint32_t *t, int r, int c) -> uint32_t { return (r < 0 || c < 0) ? 0u : t[(int64_t)r * W + c]; };
+  // unconditional loads from clamped indexes, zero selected afterwards
+  auto at32 = [&](const int32_t *t, int r, int c) -> int64_t {
+    const int32_t v = t[(int64_t)max(r, 0) * W + max(c, 0)];
+    return (r < 0 || c < 0) ? 0 : v;
+  };
+  auto atu = [&](const uint32_t *t, int r, int c) -> uint32_t {
+    const uint32_t v = t[(int64_t)max(r, 0) * W + max(c, 0)];
+    return (r < 0 || c < 0) ? 0u : v;
+  };
   while (it < max_iter) {
     int r0 = (int)floor(cr - (wh - 1) / 2.0 + 0.5), c0 = (int)floor(cc - (ww - 1) / 2.0 + 0.5);
     r0 = min(max(r0, 0), H - wh);

@@ -83,9 +83,15 @@ struct Addr {
     if (layout == IH_BHW) { base = (int64_t)p * H * W; rs = W; cs = 1; }
     else { base = p; rs = (int64_t)W * P; cs = P; }
   }
+  // Entry (r, c); a row or column index of -1 (the virtual zero row/column
+  // before the image) reads as 0.  The load always goes to a valid address
+  // (the index clamped to 0) and the zero is selected afterwards: a load in
+  // a branch would make the compiler wait for each one before the next, so
+  // a query's corner reads could not be in flight together.
   template <typename T>
   __device__ __forceinline__ T at(const T *__restrict__ t, int r, int c) const {
-    return (r < 0 || c < 0) ? (T)0 : t[base + r * rs + c * cs];
+    const T v = t[base + (int64_t)max(r, 0) * rs + (int64_t)max(c, 0) * cs];
+    return (r < 0 || c < 0) ? (T)0 : v;
   }
 };
 

@@ -76,6 +76,9 @@ extern "C" int ih_match_candidates(const int32_t *ihp, int32_t P, int32_t H, int
     return set_error(IH_ERR_INVALID_ARG, "metric %d unknown", metric);
   if (n < 0 || n >= ((int64_t)1 << 31)) return set_error(IH_ERR_RANGE, "n=%lld outside 0..2^31-1", (long long)n);
   if (!ihp || !tmpl_desc || !origins || !dist || !best) return set_error(IH_ERR_INVALID_ARG, "NULL pointer");
+  // planes-innermost corner offsets within a pixel row are 32-bit
+  if (layout == IH_HWB && (int64_t)W * P > 0xffffffffLL)
+    return set_error(IH_ERR_RANGE, "W*P=%lld above 2^32-1 planes-innermost", (long long)W * P);
   hipStream_t s = as_stream(stream);
   int e;
   if (n > 0) {

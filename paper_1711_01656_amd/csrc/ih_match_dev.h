@@ -51,6 +51,10 @@ __device__ __forceinline__ void score_cells(const int32_t (&v)[(1 << (LEVELS - 1
                                             const int32_t *__restrict__ tmpl, int P, int p, double (&accf)[LEVELS],
                                             int64_t (&acci)[LEVELS]) {
   constexpr int G = 1 << (LEVELS - 1);
+  constexpr int CELLS = ((1 << (2 * LEVELS)) - 1) / 3;
+  int ty[CELLS];  // the template's cells of this plane, all loads issued first
+#pragma unroll
+  for (int k = 0; k < CELLS; ++k) ty[k] = tmpl[(int64_t)k * P + p];
   int k = 0;
 #pragma unroll
   for (int l = 0; l < LEVELS; ++l) {
@@ -61,13 +65,15 @@ __device__ __forceinline__ void score_cells(const int32_t (&v)[(1 << (LEVELS - 1
 #pragma unroll
       for (int b = 0; b < (1 << l); ++b, ++k) {
         const int x = v[(a + 1) * s][(b + 1) * s] - v[a * s][(b + 1) * s] - v[(a + 1) * s][b * s] + v[a * s][b * s];
-        const int y = tmpl[(int64_t)k * P + p];
+        const int y = ty[k];
         if constexpr (METRIC == IH_CHI2) {
+          // branch-free, so the template loads of all cells can be issued
+          // together; a cell with x + y = 0 adds +0.0, which leaves the
+          // non-negative sum unchanged
           const int sum = x + y;
-          if (sum > 0) {
-            const float d = (float)(x - y);
-            accf[l] += (double)(d * d / (float)sum);
-          }
+          const float d = (float)(x - y);
+          const float t = d * d / (float)(sum > 0 ? sum : 1);
+          accf[l] += sum > 0 ? (double)t : 0.0;
         } else if constexpr (METRIC == IH_L1) {
           li += x > y ? x - y : y - x;
         } else {
@@ -139,7 +145,8 @@ __device__ __forceinline__ void match_body(const int32_t *__restrict__ ih, int P
 #pragma unroll
         for (int b = 0; b <= G; ++b) {
           const int cc = c + co[b] - 1;
-          v[a][b] = (rr < 0 || cc < 0) ? 0 : ih[po + (int64_t)rr * W + cc];
+          const int32_t x = ih[po + (int64_t)max(rr, 0) * W + max(cc, 0)];  // unconditional load
+          v[a][b] = (rr < 0 || cc < 0) ? 0 : x;
         }
       }
       score_cells<LEVELS, METRIC>(v, tmpl, P, p, accf, acci);
@@ -180,16 +187,24 @@ __device__ __forceinline__ void match_hwb_body(const int32_t *__restrict__ ih, i
     if (lane == 0) dist[q] = METRIC == IH_PMK ? -INFINITY : INFINITY;
     return;
   }
-  int64_t off[G + 1][G + 1];  // element offsets of the corner grid; -1 reads as 0
+  // Corner grid as wave-uniform row pointers and 32-bit column offsets;
+  // corners on the virtual row/column -1 (only grid row 0 when r = 0, grid
+  // column 0 when c = 0) are read from row/column 0 and masked to zero, so
+  // every load is unconditional and the loads of a plane can all be in
+  // flight together.
+  const int32_t *rowp[G + 1];
+  uint32_t colo[G + 1];
 #pragma unroll
   for (int a = 0; a <= G; ++a) {
     const int rr = r + (int)((int64_t)a * win_h / G) - 1;
-#pragma unroll
-    for (int b = 0; b <= G; ++b) {
-      const int cc = c + (int)((int64_t)b * win_w / G) - 1;
-      off[a][b] = (rr < 0 || cc < 0) ? -1 : ((int64_t)rr * W + cc) * P;
-    }
+    rowp[a] = ih + (int64_t)max(rr, 0) * W * P;
   }
+#pragma unroll
+  for (int b = 0; b <= G; ++b) {
+    const int cc = c + (int)((int64_t)b * win_w / G) - 1;
+    colo[b] = (uint32_t)max(cc, 0) * (uint32_t)P;
+  }
+  const int32_t mrow = r > 0 ? -1 : 0, mcol = c > 0 ? -1 : 0;
   double accf[LEVELS];
   int64_t acci[LEVELS];
 #pragma unroll
@@ -199,7 +214,10 @@ __device__ __forceinline__ void match_hwb_body(const int32_t *__restrict__ ih, i
 #pragma unroll
     for (int a = 0; a <= G; ++a)
 #pragma unroll
-      for (int b = 0; b <= G; ++b) v[a][b] = off[a][b] < 0 ? 0 : ih[off[a][b] + p];
+      for (int b = 0; b <= G; ++b) {
+        const int32_t x = rowp[a][colo[b] + (uint32_t)p];
+        v[a][b] = a == 0 ? (b == 0 ? x & mrow & mcol : x & mrow) : (b == 0 ? x & mcol : x);
+      }
     score_cells<LEVELS, METRIC>(v, tmpl, P, p, accf, acci);
   }
   double tf;
