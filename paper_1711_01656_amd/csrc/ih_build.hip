@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_tile_hist(const T *__restrict__ img, Ge
                                                    uint32_t *__restrict__ ws, const uint8_t *__restrict__ wt,
                                                    const uint8_t *__restrict__ mask, const T *__restrict__ tail) {
   extern __shared__ uint32_t lds[];
-  tile_hist_body<T>(img, g, bits, bc, ws, blockIdx.x, lds, wt, mask, tail);
+  tile_hist_body<T>(img, g, bits, bc, ws, (int)xcd_tile(blockIdx.x, gridDim.x), lds, wt, mask, tail);
 }
 
 __global__ __launch_bounds__(256) void k_carry_scan(Geom g, int64_t nblk_a, int64_t nblk_b,

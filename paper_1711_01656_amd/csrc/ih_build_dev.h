@@ -1048,7 +1048,7 @@ __global__ __launch_bounds__(256) void k_final_hwb(FinalArgs a, Geom g) {
 template <typename T, int TW, bool MOM, int WK>
 __global__ __launch_bounds__(512) void k_final_hwb_staged(FinalArgs a, Geom g) {
   extern __shared__ uint32_t seg[];
-  final_hwb_staged_body<T, TW, MOM, WK>(a, g, blockIdx.x, seg);
+  final_hwb_staged_body<T, TW, MOM, WK>(a, g, xcd_tile(blockIdx.x, gridDim.x), seg);
 }
 
 // Enqueues the three passes of a build (tile histograms, carry scans, the

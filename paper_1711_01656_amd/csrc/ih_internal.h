@@ -44,6 +44,16 @@ __device__ __forceinline__ int uniform(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// The dispatcher hands workgroups to the chip's 8 XCDs round-robin (block b
+// to XCD b mod 8), and each XCD has its own L2.  Within every whole run of 64
+// blocks this swaps the two octal digits of the index, so that 8 consecutive
+// tiles, which share the input's cache lines when tiles are narrow, are
+// processed by one XCD and fetch each line once.  A bijection on [0, n).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
+  if (b >= (n & ~(int64_t)63)) return b;
+  return (b & ~(int64_t)63) | ((b & 7) << 3) | ((b >> 3) & 7);
+}
+
 __device__ __forceinline__ uint32_t read_lane(uint32_t v, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }

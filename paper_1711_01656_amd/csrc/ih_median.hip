@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_final_acc(FinalArgs a, Geom g) {
 template <typename T, int TW>
 __global__ __launch_bounds__(512) void k_final_hwb_acc(FinalArgs a, Geom g) {
   extern __shared__ uint32_t seg[];
-  final_hwb_acc_staged_body<T, TW>(a, g, blockIdx.x, seg);
+  final_hwb_acc_staged_body<T, TW>(a, g, xcd_tile(blockIdx.x, gridDim.x), seg);
 }
 
 // ------------------------------------------------------------- median --
