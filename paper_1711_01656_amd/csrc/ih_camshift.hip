@@ -112,8 +112,12 @@ __global__ __launch_bounds__(256) void k_camshift(const int32_t *__restrict__ S,
     const int64_t mr = (int64_t)r0 * m00 + (int64_t)(uint32_t)(sx - (uint32_t)r0 * (uint32_t)m00);
     const int64_t mc = (int64_t)c0 * m00 + (int64_t)(uint32_t)(sy - (uint32_t)c0 * (uint32_t)m00);
     ++it;
+    // the centroid is formed before the empty-window test, so that the
+    // moment loads are not held back behind it (a stand-in divisor for an
+    // empty window, whose centroid is not used)
+    const double dm = m00 == 0 ? 1.0 : (double)m00;
+    const double nr = (double)mr / dm, nc = (double)mc / dm;
     if (m00 == 0) break;
-    const double nr = (double)mr / (double)m00, nc = (double)mc / (double)m00;
     const double dr = nr - cr, dc = nc - cc;
     cr = nr;
     cc = nc;

@@ -248,10 +248,21 @@ __device__ __forceinline__ void argbest_body(const float *__restrict__ dist, int
                                              float *sv, int64_t *si) {
   float bv = 0.0f;
   int64_t bi = -1;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const float v = dist[i];
-    if (isinf(v)) continue;
-    if (bi < 0 || (LARGEST ? v > bv : v < bv)) { bv = v; bi = i; }
+  // 8 loads in flight per thread (indexes clamped to n-1, the values past
+  // the end ignored), then compared in increasing index order
+  constexpr int U = 8;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)U * blockDim.x) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      v[u] = dist[i < n ? i : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      if (i < n && !isinf(v[u]) && (bi < 0 || (LARGEST ? v[u] > bv : v[u] < bv))) { bv = v[u]; bi = i; }
+    }
   }
   sv[threadIdx.x] = bv;
   si[threadIdx.x] = bi;
