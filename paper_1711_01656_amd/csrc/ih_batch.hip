@@ -261,8 +261,8 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
     P.tiles = (int64_t)P.g.nTR * P.g.nTC * F.C;
     P.ws_off = (int64_t)carry;
     carry += a64(P.g.words);
-    P.nA = ((int64_t)P.g.P * F.W + 255) / 256;
-    P.nB = ((int64_t)F.C * F.H * F.bins + 255) / 256;
+    P.nA = (carry_threads_a(P.g) + 255) / 256;
+    P.nB = (carry_threads_b(P.g) + 255) / 256;
     const int groups = (F.bins + P.g.PG - 1) / P.g.PG;
     P.gy = (groups + 3) / 4;
     P.cnt[0] = P.tiles;

@@ -236,8 +236,8 @@ int ih::launch_build(const Geom &g, int dtype, const void *img, const void *tail
                        reinterpret_cast<const uint16_t *>(tail));
   if ((e = hip_check(hipGetLastError(), "tile_hist launch"))) return e;
 
-  const int64_t nA = ((int64_t)g.P * g.W + 255) / 256;
-  const int64_t nB = ((int64_t)g.C * g.H * g.bins + 255) / 256;
+  const int64_t nA = (carry_threads_a(g) + 255) / 256;
+  const int64_t nB = (carry_threads_b(g) + 255) / 256;
   const int64_t nC = g.P;
   hipLaunchKernelGGL(k_carry_scan, dim3((unsigned)(nA + nB + nC)), dim3(256), 0, s, g, nA, nB, w32);
   if ((e = hip_check(hipGetLastError(), "carry_scan launch"))) return e;

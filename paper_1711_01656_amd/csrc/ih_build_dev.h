@@ -243,7 +243,18 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
 template <int CH>
 __device__ __forceinline__ void excl_scan_strided(uint32_t *__restrict__ a, int64_t step, int n) {
   uint32_t run = 0;
-  for (int j0 = 0; j0 < n; j0 += CH) {
+  int j0 = 0;
+  for (; j0 + CH <= n; j0 += CH) {  // whole chunks: no per-element tests
+    uint32_t v[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) v[q] = a[(int64_t)(j0 + q) * step];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      a[(int64_t)(j0 + q) * step] = run;
+      run += v[q];
+    }
+  }
+  if (j0 < n) {
     uint32_t v[CH];
 #pragma unroll
     for (int q = 0; q < CH; ++q) v[q] = j0 + q < n ? a[(int64_t)(j0 + q) * step] : 0u;
@@ -257,24 +268,37 @@ __device__ __forceinline__ void excl_scan_strided(uint32_t *__restrict__ a, int6
   }
 }
 
+// Threads of the carry scans: column carries (one per plane and column, per
+// carry array) and row carries (one per channel, row and bin, per array).
+// The count and moment arrays are scanned by separate threads.
+__host__ __device__ __forceinline__ int64_t carry_threads_a(const Geom &g) {
+  return (g.mom ? 2 : 1) * (int64_t)g.P * g.W;
+}
+__host__ __device__ __forceinline__ int64_t carry_threads_b(const Geom &g) {
+  return (g.mom ? 2 : 1) * (int64_t)g.C * g.H * g.bins;
+}
+
 __device__ __forceinline__ void carry_scan_body(const Geom &g, int64_t nblk_a, int64_t nblk_b,
                                                 uint32_t *__restrict__ ws, int64_t blk) {
   if (blk < nblk_a) {
-    const int64_t idx = blk * 256 + threadIdx.x;
-    if (idx >= (int64_t)g.P * g.W) return;
+    int64_t idx = blk * 256 + threadIdx.x;
+    if (idx >= carry_threads_a(g)) return;
+    const int64_t per = (int64_t)g.P * g.W;
+    const bool second = idx >= per;  // the moment array
+    if (second) idx -= per;
     int64_t p, c;
     if (g.layout == IH_BHW) { p = idx / g.W; c = idx - p * g.W; }
     else { c = idx / g.P; p = idx - c * g.P; }
     const int64_t step = cc_index(g, p, 1, c) - cc_index(g, p, 0, c);
-    excl_scan_strided<16>(ws + g.off_cc + cc_index(g, p, 0, c), step, g.nTR);
-    if (g.mom) excl_scan_strided<16>(ws + g.off_ccx + cc_index(g, p, 0, c), step, g.nTR);
+    excl_scan_strided<16>(ws + (second ? g.off_ccx : g.off_cc) + cc_index(g, p, 0, c), step, g.nTR);
   } else if (blk < nblk_a + nblk_b) {
-    const int64_t idx = (blk - nblk_a) * 256 + threadIdx.x;
-    const int64_t per_ch = (int64_t)g.H * g.bins;
-    if (idx >= per_ch * g.C) return;
+    int64_t idx = (blk - nblk_a) * 256 + threadIdx.x;
+    if (idx >= carry_threads_b(g)) return;
+    const int64_t per_ch = (int64_t)g.H * g.bins, per = per_ch * g.C;
+    const bool second = idx >= per;
+    if (second) idx -= per;
     const int64_t ch = idx / per_ch, rk = idx - ch * per_ch;
-    excl_scan_strided<16>(ws + g.off_rc + ch * g.nTC * per_ch + rk, per_ch, g.nTC);
-    if (g.mom) excl_scan_strided<16>(ws + g.off_rcy + ch * g.nTC * per_ch + rk, per_ch, g.nTC);
+    excl_scan_strided<16>(ws + (second ? g.off_rcy : g.off_rc) + ch * g.nTC * per_ch + rk, per_ch, g.nTC);
   } else {
     const int64_t p = blk - nblk_a - nblk_b;
     const int arrays = g.mom ? 3 : 1;
