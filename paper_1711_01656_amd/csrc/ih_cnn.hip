@@ -183,9 +183,14 @@ __device__ __forceinline__ float block_sum(float v, float *sh) {
 // Score-map value s(u, v) = wh . a3[:, u, v] + bh.
 __device__ __forceinline__ float score_at(const uint16_t *__restrict__ a3, const float *__restrict__ wh, float bh,
                                           int b, int u, int v) {
+  // the channel values are loaded together, then summed in channel order
+  uint16_t x[LP_CO];
+  const uint16_t *p = a3 + (((int64_t)b * LP_CO) * LP_SMAP + u) * LP_SMAP + v;
+#pragma unroll
+  for (int c = 0; c < LP_CO; ++c) x[c] = p[(int64_t)c * LP_SMAP * LP_SMAP];
   float acc = bh;
-  for (int c = 0; c < LP_CO; ++c)
-    acc += wh[c] * bf2f(a3[(((int64_t)b * LP_CO + c) * LP_SMAP + u) * LP_SMAP + v]);
+#pragma unroll
+  for (int c = 0; c < LP_CO; ++c) acc += wh[c] * bf2f(x[c]);
   return acc;
 }
 

@@ -56,12 +56,12 @@ struct CumWin {
   __device__ __forceinline__ uint32_t at(int64_t pix, int64_t p) const {
     return (uint32_t)(layout == IH_BHW ? J[p * HW + pix] : J[pix * P + p]);
   }
+  // The four corner loads are unconditional (a corner outside the JIH has
+  // offset 0, a valid pixel, and is masked afterwards), so they are in
+  // flight together rather than one after another behind branches.
   __device__ __forceinline__ uint32_t sum(int64_t p) const {
-    uint32_t v = at(o11, p);
-    if (top) v -= at(o01, p);
-    if (left) v -= at(o10, p);
-    if (top && left) v += at(o00, p);
-    return v;
+    const uint32_t v11 = at(o11, p), v01 = at(o01, p), v10 = at(o10, p), v00 = at(o00, p);
+    return v11 - (top ? v01 : 0u) - (left ? v10 : 0u) + (top && left ? v00 : 0u);
   }
 };
 
