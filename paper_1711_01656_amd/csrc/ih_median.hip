@@ -125,14 +125,23 @@ __global__ __launch_bounds__(256) void k_median_hwb(const int32_t *__restrict__ 
   cw.o00 = cw.top && cw.left ? (int64_t)(w.r0 - 1) * W + w.c0 - 1 : 0;
   const uint32_t n = (uint32_t)frames * (uint32_t)((w.r1 - w.r0 + 1) * (w.c1 - w.c0 + 1));
   const uint32_t target = (n + 1) / 2;
+  // Two 64-bin chunks per step, their loads issued together (bin indexes
+  // past the last bin clamped to it and masked out of the ballot): the
+  // second chunk is in flight while the first is tested.
   int med = bins - 1;
-  for (int k0 = 0; k0 < bins; k0 += 64) {
-    const int k = k0 + lane;
-    const bool valid = k < bins;
-    const uint32_t cum = valid ? cw.sum((int64_t)ch * bins + k) : 0u;
-    const uint64_t m = ballot(valid && cum >= target);
-    if (m) {
-      med = k0 + (int)__builtin_ctzll(m);
+  const int64_t p0 = (int64_t)ch * bins;
+  for (int k0 = 0; k0 < bins; k0 += 128) {
+    const int ka = k0 + lane, kb = k0 + 64 + lane;
+    const uint32_t ca = cw.sum(p0 + min(ka, bins - 1));
+    const uint32_t cb = cw.sum(p0 + min(kb, bins - 1));
+    const uint64_t ma = ballot(ka < bins && ca >= target);
+    const uint64_t mb = ballot(kb < bins && cb >= target);
+    if (ma) {
+      med = k0 + (int)__builtin_ctzll(ma);
+      break;
+    }
+    if (mb) {
+      med = k0 + 64 + (int)__builtin_ctzll(mb);
       break;
     }
   }
