@@ -33,7 +33,7 @@ namespace ih {
 
 static size_t align64(size_t w) { return (w + 63) & ~(size_t)63; }
 
-int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds) {
+int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds, int max_bc) {
   const int twp = g.TW + 4;
   const size_t stage = ((size_t)g.TH * twp * (g.wgt || g.diff ? 2 : 1) + 3) & ~(size_t)3;
   const int span = g.TH > g.TW ? g.TH : g.TW;
@@ -42,6 +42,7 @@ int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds) {
   long words = ((long)lds_budget - (long)stage) / 4 - carries;
   int b = (int)(words / ((long)span * arrays)) - 1;
   if (b > g.bins) b = g.bins;
+  if (b > max_bc) b = max_bc;
   if (b < 1) return set_error(IH_ERR_UNSUPPORTED, "tile %dx%d leaves no LDS for histograms", g.TH, g.TW);
   *bc = b;
   *lds = stage + (size_t)span * (b + 1) * arrays * 4 + (size_t)carries * 4;
@@ -224,14 +225,16 @@ int ih::launch_build(const Geom &g, int dtype, const void *img, const void *tail
                      const uint8_t *mask, int bits, void *ws, final_fn fin, const FinalArgs &fa, hipStream_t s) {
   int bc, e;
   size_t lds;
-  if ((e = pick_bc(g, kLdsBudget, &bc, &lds))) return e;
+  if ((e = pick_bc(g, kLdsBudget, &bc, &lds, g.cum ? kCumChunk : (1 << 30)))) return e;
   uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
   const unsigned tiles = (unsigned)((int64_t)g.nTR * g.nTC * g.C);
+  const unsigned hblocks = tiles * (unsigned)tile_chunks(g, bc);
   if (dtype == IH_U8)
-    hipLaunchKernelGGL(k_tile_hist<uint8_t>, dim3(tiles), dim3(256), lds, s, reinterpret_cast<const uint8_t *>(img),
-                       g, bits, bc, w32, wt, mask, reinterpret_cast<const uint8_t *>(tail));
+    hipLaunchKernelGGL(k_tile_hist<uint8_t>, dim3(hblocks), dim3(256), lds, s,
+                       reinterpret_cast<const uint8_t *>(img), g, bits, bc, w32, wt, mask,
+                       reinterpret_cast<const uint8_t *>(tail));
   else
-    hipLaunchKernelGGL(k_tile_hist<uint16_t>, dim3(tiles), dim3(256), lds, s,
+    hipLaunchKernelGGL(k_tile_hist<uint16_t>, dim3(hblocks), dim3(256), lds, s,
                        reinterpret_cast<const uint16_t *>(img), g, bits, bc, w32, wt, mask,
                        reinterpret_cast<const uint16_t *>(tail));
   if ((e = hip_check(hipGetLastError(), "tile_hist launch"))) return e;

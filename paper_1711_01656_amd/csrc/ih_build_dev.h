@@ -57,9 +57,10 @@ inline size_t staged_lds(const Geom &g) {
 //    -1 (modulo 2^32) in its pixels' bins; the carries then hold the counts
 //    of head minus tail, exact modulo 2^32.  With cumulative planes (g.cum)
 //    each column's and each row's counts are prefixed over the bins in LDS
-//    before they are written (running carries across bin passes), so every
-//    carry counts the bins <= k; the tile totals, sums of the column counts,
-//    follow.
+//    before they are written, so every carry counts the bins <= k; the tile
+//    totals, sums of the column counts, follow.  Each chunk of bc bins is
+//    then a block of its own, which starts its prefixes from the samples of
+//    the lower bins in each column and row, counted from the staged bins.
 template <typename T>
 __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const Geom &g, int bits, int bc,
                                                uint32_t *__restrict__ ws, int blkid, uint32_t *lds,
@@ -79,8 +80,11 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
   const int tid = threadIdx.x;
   int blk = blkid;
   const int j = blk % g.nTC; blk /= g.nTC;
-  const int I = blk % g.nTR;
-  const int ch = blk / g.nTR;
+  const int I = blk % g.nTR; blk /= g.nTR;
+  const int ch = blk % g.C;
+  // cumulative planes: this block's chunk of bc bins; otherwise all bins
+  const int b_begin = g.cum ? (blk / g.C) * bc : 0;
+  const int b_end = g.cum ? min(g.bins, b_begin + bc) : g.bins;
   const int R0 = I * g.TH, C0 = j * g.TW;
   const int th = min(g.TH, g.H - R0), tw = min(g.TW, g.W - C0);
   const T *src = img + (int64_t)ch * g.H * g.W;
@@ -96,12 +100,26 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
     }
     if (g.diff) wt_s[r * twp + c] = (uint8_t)(((uint64_t)tail[(int64_t)ch * g.H * g.W + i] * g.bins) >> bits);
   }
+  if (g.cum && b_begin > 0) {
+    // bin-prefix carries of a later chunk: the samples of bins below it in
+    // each column and row (head +1, tail -1), counted from the staged bins
+    __syncthreads();
+    for (int idx = tid; idx < th * tw; idx += 256) {
+      const int r = idx / tw, c = idx - r * tw;
+      const int below = ((int)bin_s[r * twp + c] < b_begin ? 1 : 0) -
+                        (g.diff && (int)wt_s[r * twp + c] < b_begin ? 1 : 0);
+      if (below) {
+        atomicAdd(&ccarry[c], (uint32_t)below);
+        atomicAdd(&rcarry[r], (uint32_t)below);
+      }
+    }
+  }
   uint32_t *CC = ws + g.off_cc, *RC = ws + g.off_rc, *TT = ws + g.off_tt;
   uint32_t *CCX = ws + g.off_ccx, *RCY = ws + g.off_rcy;
   uint32_t *TTX = ws + g.off_ttx, *TTY = ws + g.off_tty;
   const int stride = bc + 1;
 
-  for (int b0 = 0; b0 < g.bins; b0 += bc) {
+  for (int b0 = b_begin; b0 < b_end; b0 += bc) {
     const int nb = min(bc, g.bins - b0);
     // ---- columns: each thread owns a column, rows split over segments
     const int nseg = g.TW >= 256 ? 1 : 256 / g.TW;

@@ -126,8 +126,19 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
 // LDS budget of the tile-histogram pass of the stand-alone build (bytes).
 constexpr int kLdsBudget = 64 * 1024;
 
-// Bins per histogram pass (bc) and dynamic LDS bytes of the tile-histogram
-// pass for a tile shape within lds_budget bytes.
-int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds);
+// Bins per histogram pass (bc, at most max_bc) and dynamic LDS bytes of the
+// tile-histogram pass for a tile shape within lds_budget bytes.
+int pick_bc(const Geom &g, int lds_budget, int *bc, size_t *lds, int max_bc = 1 << 30);
+
+// Bins per tile-pass block of a cumulative-plane build: each chunk of bins is
+// its own block (its bin-prefix carries counted directly from the pixels), so
+// the few large tiles of the joint-IH update still fill the chip.
+constexpr int kCumChunk = 64;
+
+// Tile-pass blocks per tile: one per chunk of bc bins for cumulative planes,
+// else one (that block loops over the chunks).
+__host__ __device__ __forceinline__ int tile_chunks(const Geom &g, int bc) {
+  return g.cum ? (g.bins + bc - 1) / bc : 1;
+}
 
 }  // namespace ih
