@@ -16,26 +16,45 @@ namespace ih {
 __host__ __device__ __forceinline__ int per_block(int P) { return P >= 256 ? 1 : 256 / P; }
 
 // ------------------------------------------------------------- Eq. 2.16 --
+// Each thread answers one plane of kRectPerThread windows; the 16 corner
+// loads are issued before any is used (invalid or empty windows read the
+// clamped corner (0, 0) and discard it), so a thread makes one memory round
+// trip instead of four.
+constexpr int kRectPerThread = 4;
+
 __global__ __launch_bounds__(256) void k_query_rect(const int32_t *__restrict__ ih, int P, int H, int W, int layout,
                                                     const ih_rect *__restrict__ rects, int64_t n,
                                                     int32_t *__restrict__ out) {
+  constexpr int K = kRectPerThread;
   const int qpb = per_block(P);
   for (int idx = threadIdx.x; idx < qpb * P; idx += blockDim.x) {
     const int ql = idx / P, p = idx - ql * P;
-    const int64_t q = (int64_t)blockIdx.x * qpb + ql;
-    if (q >= n) return;
-    const ih_rect R = rects[q];
-    int32_t v;
-    if (R.r0 < 0 || R.c0 < 0 || R.r0 > R.r1 || R.c0 > R.c1 || R.r1 > H || R.c1 > W) {
-      v = -1;
-    } else if (R.r0 == R.r1 || R.c0 == R.c1) {
-      v = 0;
-    } else {
-      const Addr A(layout, p, P, H, W);
-      v = A.at(ih, R.r1 - 1, R.c1 - 1) - A.at(ih, R.r0 - 1, R.c1 - 1) - A.at(ih, R.r1 - 1, R.c0 - 1) +
-          A.at(ih, R.r0 - 1, R.c0 - 1);
+    const Addr A(layout, p, P, H, W);
+    ih_rect Rs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t q = ((int64_t)blockIdx.x * K + k) * qpb + ql;
+      Rs[k] = rects[q < n ? q : n - 1];
     }
-    out[q * P + p] = v;
+    int32_t v[K][4];
+    int kind[K];  // 0: outside the frame (-1), 1: empty (0), 2: a region
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ih_rect R = Rs[k];
+      if (R.r0 < 0 || R.c0 < 0 || R.r0 > R.r1 || R.c0 > R.c1 || R.r1 > H || R.c1 > W) kind[k] = 0;
+      else if (R.r0 == R.r1 || R.c0 == R.c1) kind[k] = 1;
+      else kind[k] = 2;
+      if (kind[k] != 2) R = ih_rect{0, 0, 0, 0};
+      v[k][0] = A.at(ih, R.r1 - 1, R.c1 - 1);
+      v[k][1] = A.at(ih, R.r0 - 1, R.c1 - 1);
+      v[k][2] = A.at(ih, R.r1 - 1, R.c0 - 1);
+      v[k][3] = A.at(ih, R.r0 - 1, R.c0 - 1);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t q = ((int64_t)blockIdx.x * K + k) * qpb + ql;
+      if (q < n) out[q * P + p] = kind[k] == 2 ? v[k][0] - v[k][1] - v[k][2] + v[k][3] : (kind[k] == 1 ? 0 : -1);
+    }
   }
 }
 
@@ -139,8 +158,8 @@ extern "C" int ih_query_rect(const int32_t *ihp, int32_t P, int32_t H, int32_t W
   if (e) return e;
   if (n == 0) return IH_OK;
   if (!ihp || !rects || !out) return set_error(IH_ERR_INVALID_ARG, "NULL pointer");
-  const int qpb = per_block(P);
-  const int64_t blocks = (n + qpb - 1) / qpb;
+  const int64_t per = (int64_t)per_block(P) * kRectPerThread;
+  const int64_t blocks = (n + per - 1) / per;
   if (blocks > 0x7fffffff) return set_error(IH_ERR_RANGE, "too many queries");
   hipLaunchKernelGGL(k_query_rect, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), ihp, P, H, W, layout,
                      rects, n, out);
