@@ -64,6 +64,8 @@ UPDATE_SHAPES = [
     (1, 64, 64, 256, 8),
     (3, 45, 77, 16, 8),
     (1, 33, 1030, 8, 16),
+    (2, 50, 90, 100, 8),      # two channels, each with two 64-bin chunks in the tile pass
+    (1, 21, 300, 256, 16),    # four chunks from 16-bit values
 ]
 
 
@@ -102,6 +104,25 @@ def test_jih_update_every_tile_shape():
             with pytest.raises(ih.IHError, match="no LDS"):
                 ih.ih_jih_update(h, t, bins, J, cfg=cfg, layout=layout)
             continue
+        ih.ih_jih_update(h, t, bins, J, cfg=cfg, layout=layout)
+        assert np.array_equal(bhw(J, layout), ref), (layout, cfg)
+
+
+def test_jih_update_many_chunks_every_tile_shape():
+    """The update's tile pass splits the bins into 64-bin chunks, each a
+    block that starts from the counts of the lower bins; 150 bins over two
+    channels make three uneven chunks per channel."""
+    ih = ihlib()
+    C, H, W, bins = 2, 70, 203, 150
+    v = video(13, 3, C, H, W, 8)
+    base = cum(oracle.jih(v[0:2], bins, 8), C, bins)
+    ref = cum(oracle.jih(v[1:3], bins, 8), C, bins)
+    h, t = gpu(v[2]), gpu(v[0])
+    for layout, th, tw, pg in [("bhw", 1, 64, 1), ("bhw", 16, 128, 8), ("bhw", 64, 256, 4), ("bhw", 7, 128, 16),
+                               ("hwb", 16, 32, 64), ("hwb", 64, 16, 64), ("hwb", 1, 32, 64)]:
+        cfg = ih.TileCfg(th, tw, pg)
+        say("chunks", layout, cfg)
+        J = gpu(to_layout(base, layout))
         ih.ih_jih_update(h, t, bins, J, cfg=cfg, layout=layout)
         assert np.array_equal(bhw(J, layout), ref), (layout, cfg)
 
