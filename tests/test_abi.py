@@ -98,6 +98,9 @@ def test_host_argument_errors(lib):
     assert lib.ih_match_candidates(fake, 8, 4, 4, 0, fake, 2, 2, 3, fake, 1, 7, fake, fake, None) == -1
     assert lib.ih_match_candidates(fake, 8, 4, 4, 0, fake, 0, 2, 3, fake, 1, 0, fake, fake, None) == -1
     assert lib.ih_match_candidates(fake, 8, 4, 4, 2, fake, 2, 2, 3, fake, 1, 0, fake, fake, None) == -1
+    # planes innermost, a pixel row of W*P >= 2^32 entries: refused before any launch
+    assert lib.ih_match_candidates(fake, 4096, 1, 1 << 20, 1, fake, 2, 2, 3, fake, 1, 0, fake, fake, None) == -2
+    assert b"W*P" in lib.ih_last_error()
     assert lib.ih_profile_events(fake, None) == -1
 
 
