@@ -70,7 +70,27 @@ typedef struct {
 } ih_rect;
 
 /*
- * Tile shape of the build: tiles of tile_h rows by tile_w columns.
+ * How the build is organised (ih_tile_cfg.passes).
+ *   IH_PASSES_DEFAULT  the library's choice for the shape and layout.
+ *   IH_PASSES_ONE      one pass (bin-major layout only): row bands of tile_h
+ *                      rows, each walked from left to right in tiles of
+ *                      tile_w columns by one wavefront per group of
+ *                      planes_per_wave planes, which keeps its band's row
+ *                      carries on chip; the top boundary of every tile comes
+ *                      from the bands above by a look-back over their
+ *                      published aggregates and inclusive bottom rows.
+ *                      tile_h in [1, 1024]; tile_w 64, 128 or 256;
+ *                      planes_per_wave 1, 2 or 4.
+ *   IH_PASSES_THREE    three passes: per-tile histograms, scans of the tile
+ *                      carries, write-out (the shapes below).
+ */
+#define IH_PASSES_DEFAULT 0
+#define IH_PASSES_ONE 1
+#define IH_PASSES_THREE 3
+
+/*
+ * Tile shape of the build: tiles of tile_h rows by tile_w columns.  With
+ * three passes:
  *   IH_BHW: each wavefront of the write-out pass owns one tile and
  *           planes_per_wave consecutive planes of one channel; its lanes map
  *           to columns.  tile_h in [1, 256]; tile_w 64, 128 or 256;
@@ -78,13 +98,29 @@ typedef struct {
  *   IH_HWB: each wavefront owns one tile and 64 consecutive planes; its lanes
  *           map to planes.  tile_h in [1, 256]; tile_w 16, 32 or 64;
  *           planes_per_wave must be 64.
- * NULL selects a shape from a built-in heuristic.
+ * With one pass, see IH_PASSES_ONE.  NULL (or tile_h == 0 with one pass)
+ * selects a shape from a built-in heuristic.
  */
 typedef struct {
   int32_t tile_h;
   int32_t tile_w;
   int32_t planes_per_wave;
+  int32_t passes;           /* IH_PASSES_*                                  */
 } ih_tile_cfg;
+
+/*
+ * Device status bits of a build, left in the first 4 bytes of its workspace
+ * (a uint32) once the build has run; the caller reads them after the stream
+ * has reached the end of the build.  Every build clears them first.
+ *   IH_STATUS_VALUE_RANGE   some pixel value was >= 2^value_bits (the
+ *                           results are then unspecified but the build
+ *                           stays in bounds).
+ *   IH_STATUS_WAIT_TIMEOUT  a single-pass build's wait for another band gave
+ *                           up (after about a second); the build completed
+ *                           but its result is invalid.
+ */
+#define IH_STATUS_VALUE_RANGE 1u
+#define IH_STATUS_WAIT_TIMEOUT 2u
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int ih_version(void);
@@ -111,7 +147,8 @@ size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins,
  *   bins        bins per channel, 1..256 and at most 2^value_bits.
  *   value_bits  significant bits per value: 1..8 for IH_U8, 1..16 for
  *               IH_U16.  Every value must be < 2^value_bits; larger values
- *               give unspecified (but in-bounds) results.
+ *               give unspecified (but in-bounds) results and set
+ *               IH_STATUS_VALUE_RANGE in the workspace's status word.
  *   layout      IH_BHW or IH_HWB, for ih and the moment tensors.
  *   ih          device, out: P x H x W int32 integral histogram (in layout).
  *   mom_x,      device, out, both NULL or both non-NULL: P x H x W uint32
@@ -123,9 +160,12 @@ size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins,
  *               coordinates is a combination of 1, row and column.  Region
  *               sums taken from them (four corners, modulo 2^32) are exact
  *               whenever the true regional sum is below 2^32.
- *   cfg         tile shape, or NULL for the heuristic.
+ *   cfg         tile shape and number of passes, or NULL for the
+ *               library's choice.
  *   ws          device workspace of ws_bytes >= ih_build_workspace_size().
- *               Its contents on entry do not matter; they are garbage after.
+ *               Its contents on entry do not matter; after the build its
+ *               first word holds the IH_STATUS_* bits, the rest is garbage.
+ *               Two builds must not use one workspace at the same time.
  *   stream      hipStream_t.
  * Returns IH_OK or IH_ERR_*.  Outputs must not overlap the image or ws.
  */
@@ -503,6 +543,20 @@ int ih_jih_update(const void *head, const void *tail, int32_t dtype,
 int ih_local_median(const int32_t *jih, int32_t C, int32_t bins, int32_t H,
                     int32_t W, int32_t layout, int32_t frames, int32_t win_h,
                     int32_t win_w, int32_t *median, void *stream);
+
+/*
+ * ih_set_lookback_patience - look-back policy of the single-pass build
+ * (IH_PASSES_ONE), for every later build in this process.  A band worker
+ * polls the flag of the band directly above at most `polls` times for its
+ * inclusive bottom row; if that row has not been published by then, the
+ * worker publishes its own band's aggregate (so that the bands below need
+ * not wait for it) and walks further up, adding aggregates until a band with
+ * an inclusive row.  polls = -1 (the default) always waits for the band
+ * above; 0 publishes and walks at once.  Results are identical for every
+ * value; only the time differs.  Returns IH_OK, or IH_ERR_INVALID_ARG for
+ * polls < -1.
+ */
+int ih_set_lookback_patience(int32_t polls);
 
 /*
  * ih_profile_events - profiling hook.  When both are non-NULL (hipEvent_t),

@@ -234,6 +234,8 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
     if (F.bins > (1 << F.value_bits)) return set_error(IH_ERR_INVALID_ARG, "frame %d: bins exceed 2^value_bits", f);
     if (F.layout != IH_BHW && F.layout != IH_HWB)
       return set_error(IH_ERR_INVALID_ARG, "frame %d: layout %d unknown", f, F.layout);
+    if (F.tile.passes == IH_PASSES_ONE)
+      return set_error(IH_ERR_UNSUPPORTED, "frame %d: batches build in three passes", f);
     const bool hwb = F.layout == IH_HWB;
     // without a tile shape, batch defaults: many frames already fill the GPU,
     // so tiles are taller than the single-frame heuristic's (fewer, longer units)

@@ -27,6 +27,8 @@
 // (weights row and column, Eq. 3.4) ride along in the same passes: their
 // row-direction carry is row * LC and needs no array; the column-direction
 // ones are kept.
+#include <algorithm>
+
 #include "ih_build_dev.h"
 
 namespace ih {
@@ -108,7 +110,7 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
   g->nTR = (H + TH - 1) / TH;
   g->nTC = (W + TW - 1) / TW;
   const size_t P = (size_t)g->P;
-  size_t o = 0;
+  size_t o = kWsHeaderWords;  // word 0: the build's status bits
   g->off_cc = o;  o = align64(o + P * g->nTR * (size_t)W);
   g->off_rc = o;  o = align64(o + P * g->nTC * (size_t)H);
   g->off_tt = o;  o = align64(o + P * g->nTR * (size_t)g->nTC);
@@ -206,11 +208,41 @@ static final_fn pick_final(int dtype, const Geom &g) {
 
 using namespace ih;
 
+// Whether a build of this shape runs in one pass: when cfg asks for it, and
+// by default for bin-major outputs.
+static bool use_onepass(int32_t layout, const ih_tile_cfg *cfg) {
+  if (cfg) return cfg->passes == IH_PASSES_ONE;
+  return layout == IH_BHW && kOnePassDefault;
+}
+
 extern "C" size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
                                           int32_t layout, const ih_tile_cfg *cfg) {
+  size_t one = 0;
+  if (use_onepass(layout, cfg)) {
+    OpGeom og;
+    if (layout != IH_BHW) {
+      set_error(IH_ERR_UNSUPPORTED, "the single-pass build writes the bin-major layout only");
+      return 0;
+    }
+    if (make_op_geom(H, W, C, bins, moments, cfg, &og) != IH_OK) return 0;
+    one = (size_t)og.words * 4;
+    if (cfg) return one;
+  }
+  // without a configuration the same size also serves the three-pass builds
+  // of the shape (weighted, second-moment, moment-image builds)
   Geom g;
   if (make_geom(H, W, C, bins, moments, layout, cfg, &g) != IH_OK) return 0;
-  return g.words * 4;
+  return std::max(one, g.words * 4);
+}
+
+// Polls of the band above before a single-pass worker publishes its own
+// aggregate and looks further up (-1: wait for the band above).
+static int g_patience = -1;
+
+extern "C" int ih_set_lookback_patience(int32_t polls) {
+  if (polls < -1) return set_error(IH_ERR_INVALID_ARG, "patience %d below -1", polls);
+  g_patience = polls;
+  return IH_OK;
 }
 
 extern "C" int ih_profile_events(void *start, void *stop) {
@@ -280,6 +312,24 @@ static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const u
     return set_error(IH_ERR_INVALID_ARG, "value_bits %d outside 1..%d", value_bits, maxbits);
   if (bins > (1 << value_bits)) return set_error(IH_ERR_INVALID_ARG, "bins %d exceed 2^value_bits", bins);
   const bool mom = mom_x != nullptr;
+  if (cfg && cfg->passes != IH_PASSES_DEFAULT && cfg->passes != IH_PASSES_ONE && cfg->passes != IH_PASSES_THREE)
+    return set_error(IH_ERR_INVALID_ARG, "passes %d is not 0, 1 or 3", cfg->passes);
+  if (!wt && use_onepass(layout, cfg)) {
+    if (layout != IH_BHW)
+      return set_error(IH_ERR_UNSUPPORTED, "the single-pass build writes the bin-major layout only");
+    OpGeom og;
+    int e = make_op_geom(H, W, C, bins, mom, cfg, &og);
+    if (e) return e;
+    if (!ws || ws_bytes < (size_t)og.words * 4)
+      return set_error(IH_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", (size_t)og.words * 4,
+                       ws ? ws_bytes : (size_t)0);
+    const bool aligned = ((uintptr_t)ih % 16 == 0) && ((uintptr_t)mom_x % 16 == 0) && ((uintptr_t)mom_y % 16 == 0);
+    OpArgs oa{img, ih, mom_x, mom_y, reinterpret_cast<uint32_t *>(ws), value_bits,
+              (W % og.CPL == 0 && aligned) ? 1 : 0, g_patience};
+    return launch_onepass(og, dtype, oa, as_stream(stream));
+  }
+  if (wt && cfg && cfg->passes == IH_PASSES_ONE)
+    return set_error(IH_ERR_UNSUPPORTED, "the weighted build has no single-pass form");
   Geom g;
   int e = make_geom(H, W, C, bins, mom, layout, cfg, &g, wt != nullptr);
   if (e) return e;
@@ -291,7 +341,8 @@ static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const u
     return set_error(IH_ERR_UNSUPPORTED, "no write-out kernel for tile_w %d planes_per_wave %d", g.TW, g.PG);
   const bool aligned = ((uintptr_t)ih % 16 == 0) && ((uintptr_t)mom_x % 16 == 0) && ((uintptr_t)mom_y % 16 == 0);
   FinalArgs fa{img, ih, mom_x, mom_y, reinterpret_cast<uint32_t *>(ws), value_bits,
-               (W % g.CPL == 0 && aligned) ? 1 : 0, wt, mask};
+               (W % g.CPL == 0 && aligned) ? 1 : 0, wt, mask, nullptr,
+               wt ? nullptr : reinterpret_cast<uint32_t *>(ws)};
   return launch_build(g, dtype, img, nullptr, wt, mask, value_bits, ws, fin, fa, as_stream(stream));
 }
 

@@ -298,6 +298,8 @@ __host__ __device__ __forceinline__ int64_t carry_threads_b(const Geom &g) {
 
 __device__ __forceinline__ void carry_scan_body(const Geom &g, int64_t nblk_a, int64_t nblk_b,
                                                 uint32_t *__restrict__ ws, int64_t blk) {
+  // the status word ahead of the carries: cleared here, set by the write-out
+  if (blk == 0 && threadIdx.x == 0) ws[0] = 0u;
   if (blk < nblk_a) {
     int64_t idx = blk * 256 + threadIdx.x;
     if (idx >= carry_threads_a(g)) return;
@@ -344,7 +346,14 @@ struct FinalArgs {
   int vec_ok;  // bin-major: W divisible by CPL and the outputs 16-byte aligned
   const uint8_t *wt, *mask;  // weighted build: C x H x W weights, optional mask
   const void *tail;          // joint-IH update: the frame leaving the window (or NULL)
+  uint32_t *status;          // count build: status word that a value >= 2^bits sets (or NULL)
 };
+
+// Sets IH_STATUS_VALUE_RANGE in *status when any lane saw a value >= 2^bits.
+__device__ __forceinline__ void report_range(uint32_t *status, uint32_t bad) {
+  if (status && ballot(bad != 0) && (threadIdx.x & 63) == 0)
+    __hip_atomic_fetch_or(status, (uint32_t)IH_STATUS_VALUE_RANGE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Adds CPL consecutive values to the int32 output in place (the joint-IH
 // update's read-modify-write store).
@@ -543,6 +552,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
       for (int k = 0; k < PG; ++k) lcyv[d][k] = k < nk ? lcy[k] : 0u;
     }
   };
+  uint32_t bad = 0;
   auto row = [&](auto SLOT, int rr) {
     constexpr int d = decltype(SLOT)::value;
     const int r = R0 + rr;
@@ -550,6 +560,10 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 #pragma unroll
     for (int e = 0; e < CPL; ++e)
       b[e] = cf + e < g.W ? (int)(((uint64_t)px[d][e] * g.bins) >> a.bits) - kb : (ACC ? 1 << 30 : -1);
+    if constexpr (WK == 0 && !ACC) {
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) bad |= px[d][e] >> a.bits;
+    }
     uint32_t lcur[PG], lycur[MOM ? PG : 1], wcur[WK ? CPL : 1];
     int bt[ACC ? CPL : 1];
     if constexpr (ACC) {
@@ -671,6 +685,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
       if (r0 + decltype(SLOT)::value < rows) row(SLOT, r0 + decltype(SLOT)::value);
     });
   }
+  if constexpr (WK == 0 && !ACC) report_range(a.status, bad);
 }
 
 // --------------------------------------------------------------------------
@@ -775,6 +790,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
   const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
                      ((int64_t)C0 * sizeof(T)) % 4 == 0 && (!loads_weights<WK>() || weight_words(a, g, C0));
   constexpr int PER = 4 / (int)sizeof(T);  // pixels per 32-bit word
+  uint32_t bad = 0;
   auto row_step = [&](auto FULL, int rr) {
     constexpr bool F = decltype(FULL)::value;
     const int r = R0 + rr;
@@ -789,6 +805,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
     int32_t *dmx = reinterpret_cast<int32_t *>(a.mx) + rbase + p;
     int32_t *dmy = reinterpret_cast<int32_t *>(a.my) + rbase + p;
     auto pixel = [&](int c, uint32_t val, uint32_t w) {
+      if constexpr (WK == 0) bad |= val >> a.bits;
       const uint32_t hit = (val - lo) < width ? w : 0u;
       const int64_t cw = (int64_t)c * P;
       rc += hit;
@@ -824,6 +841,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
   } else {
     for (int rr = 0; rr < rows; ++rr) row_step(std::false_type{}, rr);
   }
+  if constexpr (WK == 0) report_range(a.status, bad);
 }
 
 
@@ -973,6 +991,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
   const int nseg = cols * g.P;
   uint32_t *s0 = lds, *s1 = lds + TW * g.P, *s2 = lds + 2 * TW * g.P;
   constexpr int PER = 4 / (int)sizeof(T);
+  uint32_t bad = 0;
   auto row_step = [&](auto FULL, int rr) {
     constexpr bool F = decltype(FULL)::value;
     const int r = R0 + rr;
@@ -981,6 +1000,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
     uint32_t ry = 0;
     if constexpr (MOM) ry = lcy[(int64_t)r * g.bins];
     auto pixel = [&](int c, uint32_t val, uint32_t w) {
+      if constexpr (WK == 0) bad |= val >> a.bits;
       const uint32_t hit = (val - lo) < width ? w : 0u;
       rc += hit;
       col[c] += rc;
@@ -1046,6 +1066,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
 #pragma unroll
       for (int c = 0; c < TW; ++c) {
         const uint32_t val = (cur[c / PER] >> (8 * (int)sizeof(T) * (c % PER))) & ((1u << (8 * sizeof(T))) - 1u);
+        if constexpr (WK == 0) bad |= val >> a.bits;
         const uint32_t w = weight_byte<WK>(wq, r, C0, c);
         const uint32_t hit = (val - lo) < width ? w : 0u;
         rc += hit;
@@ -1073,6 +1094,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
   } else {
     for (int rr = 0; rr < rows; ++rr) row_step(std::false_type{}, rr);
   }
+  if constexpr (WK == 0) report_range(a.status, bad);
 }
 
 

@@ -123,6 +123,38 @@ struct Geom {
 int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, int32_t layout,
               const ih_tile_cfg *cfg, Geom *g, int32_t weighted = 0);
 
+// Words at the start of every build workspace ahead of its arrays; word 0
+// holds the build's IH_STATUS_* bits.
+constexpr int kWsHeaderWords = 64;
+
+// Whether ih_build without a tile configuration writes bin-major outputs in
+// one pass (else in three).
+constexpr bool kOnePassDefault = false;
+
+// Geometry and arguments of the single-pass bin-major build (ih_onepass.hip).
+struct OpGeom {
+  int H, W, C, bins, P;
+  int R, TW, PG, CPL;   // band rows, tile columns (64 * CPL), planes per worker
+  int nB, nT, gpc, nG;  // bands, tiles per band, groups per channel, groups
+  int mom, arrays;      // moments; payload arrays (1 or 3)
+  int slot;             // payload words per (band, group, tile) and array: PG * TW
+  int64_t off_flag, off_inc, off_agg, words;  // workspace sections (4-byte words)
+};
+
+struct OpArgs {
+  const void *img;
+  int32_t *ih;
+  uint32_t *mx, *my;
+  uint32_t *ws;
+  int bits;
+  int vec_ok;    // W divisible by the columns per lane and the outputs 16-byte aligned
+  int patience;  // polls of the band above before a worker publishes its aggregate
+};
+
+int make_op_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, const ih_tile_cfg *cfg,
+                 OpGeom *g);
+int launch_onepass(const OpGeom &g, int dtype, const OpArgs &a, hipStream_t s);
+
 // LDS budget of the tile-histogram pass of the stand-alone build (bytes).
 constexpr int kLdsBudget = 64 * 1024;
 

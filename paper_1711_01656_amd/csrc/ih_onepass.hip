@@ -1,0 +1,468 @@
+// Single-pass integral-histogram build (Eq. 2.15) for the bin-major layout,
+// with the tile-to-tile carry handed over by a look-back across row bands.
+//
+// The image is cut into bands of R rows.  One wavefront (a "worker") owns one
+// band and a group of PG planes of one channel, and walks the band's tiles of
+// TW = 64 * CPL columns from left to right; lanes map to columns.  The worker
+// keeps the row carries of its band (the plane-k count of row r left of the
+// tile, per row and plane) in its own LDS slice, so no row-carry array is
+// ever written.  For the column direction, tile j of band b needs its top
+// boundary H(p, R0-1, c) for the tile's columns, which the band above
+// produces.  Per tile the worker:
+//   1. counts its plane-group pixels per column over the band's rows and forms
+//      the band's local aggregate in integral form,
+//        A(p, c) = sum_{r in band} sum_{c' <= c} [bin(r, c') = p]
+//      (row carries from the left included);
+//   2. obtains the top boundary by looking back over the bands above: each
+//      band publishes, per (group, tile), a flag and either its aggregate
+//      (state 1) or its inclusive bottom row H(p, R1-1, c) (state 2).  The
+//      worker waits for the band above; if that band has only an aggregate,
+//      the worker adds it and looks further up, until a band with an
+//      inclusive row (or the top of the image) ends the walk.  How long a
+//      worker waits for the band directly above before it publishes its own
+//      aggregate and starts walking is a launch parameter (`patience`);
+//   3. publishes its own inclusive bottom row (top + A, state 2);
+//   4. writes the tile's R rows: the row prefix of a one-hot plane is a ballot
+//      plus mbcnt (as in the three-pass write-out), the column prefix a
+//      per-lane register sum starting from the top boundary.
+// Workers take their (band, group) from a ticket counter in the order they
+// start, so a worker only ever waits for bands whose workers have already
+// started: the waits always end.  Every wait is also bounded; a wait that
+// gives up sets IH_STATUS_WAIT_TIMEOUT and an abort word that ends all other
+// waits, and the kernel completes (with that build's result invalid).
+//
+// Cross-workgroup data (flags, aggregates, inclusive rows) is written and read
+// with device-scope relaxed atomics, which bypass the per-XCD L2 caches, and
+// ordered with the wave's own store counter: the payload's stores complete
+// before its flag is stored, and the flag is read before the payload.  The
+// integral histogram itself is written with streaming stores.
+//
+// Moment tensors (Eq. 3.4) ride along: their aggregates and inclusive rows
+// travel with the counts, the column-moment row carries live beside the
+// count row carries, and the row moment needs no carry of its own
+// (its row prefix is the row index times the count prefix).
+#include <algorithm>
+
+#include "ih_build_dev.h"
+
+namespace ih {
+
+enum { kHdrStatus = 0, kHdrTicket = 1, kHdrAbort = 2 };
+// Polls of a flag before a wait gives up (each poll is a device-scope load
+// plus a short sleep, so this is a fraction of a second).
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+// ------------------------------------------------------------ ordering --
+__device__ __forceinline__ uint32_t ld_dev(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// All earlier vector-memory operations of this wave (the payload stores)
+// have completed before anything after this point (the flag store) issues.
+__device__ __forceinline__ void order_release() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8));  // vmcnt(0)
+}
+// The flag load has returned before the payload loads that follow.
+__device__ __forceinline__ void order_acquire() {
+  __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8));  // vmcnt(0)
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Polls *f until it is non-zero, at most `polls` times (polls < 0: until the
+// bounded wait gives up).  Returns the flag, or 0.  Wave-uniform.
+__device__ __forceinline__ uint32_t op_poll(const uint32_t *f, uint32_t *hdr, int polls) {
+  for (uint32_t it = 0;; ++it) {
+    const uint32_t v = (uint32_t)uniform((int)ld_dev(f));
+    if (v) {
+      order_acquire();
+      return v;
+    }
+    if (polls >= 0 && it >= (uint32_t)polls) return 0;
+    if ((it & 63) == 63) {
+      if (uniform((int)ld_dev(hdr + kHdrAbort))) return 0;
+      if (it >= kSpinLimit) {
+        if ((threadIdx.x & 63) == 0) {
+          __hip_atomic_fetch_or(hdr + kHdrStatus, (uint32_t)IH_STATUS_WAIT_TIMEOUT, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+          st_dev(hdr + kHdrAbort, 1u);
+        }
+        return 0;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ void load_px(const T *__restrict__ row, int cf, int W, bool vec, uint32_t (&px)[CPL]) {
+  if constexpr (CPL == 4 && sizeof(T) == 2) {
+    if (vec && cf + 4 <= W) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(row + cf);
+      px[0] = v.x & 0xffffu; px[1] = v.x >> 16; px[2] = v.y & 0xffffu; px[3] = v.y >> 16;
+      return;
+    }
+  } else if constexpr (CPL == 4 && sizeof(T) == 1) {
+    if (vec && cf + 4 <= W) {
+      const uint32_t v = *reinterpret_cast<const uint32_t *>(row + cf);
+      px[0] = v & 0xffu; px[1] = (v >> 8) & 0xffu; px[2] = (v >> 16) & 0xffu; px[3] = v >> 24;
+      return;
+    }
+  } else if constexpr (CPL == 2 && sizeof(T) == 2) {
+    if (vec && cf + 2 <= W) {
+      const uint32_t v = *reinterpret_cast<const uint32_t *>(row + cf);
+      px[0] = v & 0xffffu; px[1] = v >> 16;
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < CPL; ++e) px[e] = cf + e < W ? (uint32_t)row[cf + e] : 0u;
+}
+
+// One worker: band b, plane group gi.  lc: this wave's LDS slice of
+// R * PG (count row carries) [+ R * PG (column-moment row carries)] words.
+template <typename T, int CPL, int PG, bool MOM>
+__device__ __forceinline__ void op_bhw_worker(const OpArgs &a, const OpGeom &g, int t, uint32_t *lc) {
+  const int lane = threadIdx.x & 63;
+  uint32_t *hdr = a.ws;
+  uint32_t *F = a.ws + g.off_flag;
+  const int b = t / g.nG, gi = t - b * g.nG;
+  const int ch = gi / g.gpc, kb = (gi - ch * g.gpc) * PG;
+  const int nk = min(PG, g.bins - kb);
+  const int R0 = b * g.R, rows = min(g.R, g.H - R0);
+  const int64_t HW = (int64_t)g.H * g.W;
+  const T *img = reinterpret_cast<const T *>(a.img) + (int64_t)ch * HW;
+  const bool vec = a.vec_ok != 0;
+  // pixels are loaded as words when every row is aligned for them
+  const bool pvec = ((uintptr_t)a.img % (CPL * sizeof(T)) == 0) && (g.W % CPL == 0);
+  const int TW = 64 * CPL;
+  const bool last_band = b == g.nB - 1;
+  uint32_t *lcy = lc + g.R * PG;
+
+  for (int i = lane; i < g.R * PG * (MOM ? 2 : 1); i += 64) lc[i] = 0u;
+  wave_sync();
+  // band sums of the row carries: sum_r LC, sum_r r * LC, sum_r LCY per plane
+  uint32_t lcs[PG] = {}, lcxs[PG] = {}, lcys[PG] = {};
+  uint32_t bad = 0;
+
+  int32_t *out_base = a.ih + ((int64_t)ch * g.bins + kb) * HW;
+  int32_t *mx_base = MOM ? reinterpret_cast<int32_t *>(a.mx) + ((int64_t)ch * g.bins + kb) * HW : nullptr;
+  int32_t *my_base = MOM ? reinterpret_cast<int32_t *>(a.my) + ((int64_t)ch * g.bins + kb) * HW : nullptr;
+
+  for (int j = 0; j < g.nT; ++j) {
+    const int C0 = j * TW;
+    const int cf = C0 + lane * CPL;
+    // ---- 1. per-column counts of the band's rows
+    uint32_t cnt[PG][CPL] = {}, cntx[MOM ? PG : 1][CPL] = {};
+    {
+      int rr = 0;
+      for (; rr + 4 <= rows; rr += 4) {
+        uint32_t px[4][CPL];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) load_px<T, CPL>(img + (int64_t)(R0 + rr + q) * g.W, cf, g.W, pvec, px[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            bad |= px[q][e] >> a.bits;
+            const int bb = cf + e < g.W ? (int)(((uint64_t)px[q][e] * g.bins) >> a.bits) - kb : -1;
+#pragma unroll
+            for (int k = 0; k < PG; ++k) {
+              const uint32_t hit = bb == k ? 1u : 0u;
+              cnt[k][e] += hit;
+              if constexpr (MOM) cntx[k][e] += hit * (uint32_t)(R0 + rr + q);
+            }
+          }
+        }
+      }
+      for (; rr < rows; ++rr) {
+        uint32_t px[CPL];
+        load_px<T, CPL>(img + (int64_t)(R0 + rr) * g.W, cf, g.W, pvec, px);
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          bad |= px[e] >> a.bits;
+          const int bb = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
+#pragma unroll
+          for (int k = 0; k < PG; ++k) {
+            const uint32_t hit = bb == k ? 1u : 0u;
+            cnt[k][e] += hit;
+            if constexpr (MOM) cntx[k][e] += hit * (uint32_t)(R0 + rr);
+          }
+        }
+      }
+    }
+    // ---- aggregates in integral form, and this tile's totals
+    uint32_t A[PG][CPL], AX[MOM ? PG : 1][CPL], AY[MOM ? PG : 1][CPL];
+    uint32_t tot[PG], totx[MOM ? PG : 1], toty[MOM ? PG : 1];
+#pragma unroll
+    for (int k = 0; k < PG; ++k) {
+      uint32_t v[CPL];
+      v[0] = cnt[k][0];
+#pragma unroll
+      for (int e = 1; e < CPL; ++e) v[e] = v[e - 1] + cnt[k][e];
+      const uint32_t inc = wave_incl_scan(v[CPL - 1]);
+      const uint32_t ex = inc - v[CPL - 1];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) A[k][e] = lcs[k] + ex + v[e];
+      tot[k] = read_lane(inc, 63);
+      if constexpr (MOM) {
+        uint32_t vx[CPL], vy[CPL];
+        vx[0] = cntx[k][0];
+        vy[0] = cnt[k][0] * (uint32_t)cf;
+#pragma unroll
+        for (int e = 1; e < CPL; ++e) {
+          vx[e] = vx[e - 1] + cntx[k][e];
+          vy[e] = vy[e - 1] + cnt[k][e] * (uint32_t)(cf + e);
+        }
+        const uint32_t ix = wave_incl_scan(vx[CPL - 1]), iy = wave_incl_scan(vy[CPL - 1]);
+        const uint32_t exx = ix - vx[CPL - 1], exy = iy - vy[CPL - 1];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          AX[k][e] = lcxs[k] + exx + vx[e];
+          AY[k][e] = lcys[k] + exy + vy[e];
+        }
+        totx[k] = read_lane(ix, 63);
+        toty[k] = read_lane(iy, 63);
+      }
+    }
+    // ---- 2. top boundary from the bands above
+    uint32_t top[PG][CPL] = {}, topx[MOM ? PG : 1][CPL] = {}, topy[MOM ? PG : 1][CPL] = {};
+    const int64_t fstride = (int64_t)g.nG * g.nT;       // flag distance between bands
+    const int64_t fidx = ((int64_t)b * g.nG + gi) * g.nT + j;
+    auto slot = [&](int64_t off, int64_t fi, int arr) { return a.ws + off + (fi * g.arrays + arr) * g.slot; };
+    auto add_payload = [&](int64_t off, int64_t fi) {
+      const int el = lane * CPL;
+#pragma unroll
+      for (int k = 0; k < PG; ++k) {
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          top[k][e] += ld_dev(slot(off, fi, 0) + k * TW + el + e);
+          if constexpr (MOM) {
+            topx[k][e] += ld_dev(slot(off, fi, 1) + k * TW + el + e);
+            topy[k][e] += ld_dev(slot(off, fi, 2) + k * TW + el + e);
+          }
+        }
+      }
+    };
+    auto publish = [&](int64_t off, int64_t fi, uint32_t state, const uint32_t (&v)[PG][CPL],
+                       const uint32_t (&vx)[MOM ? PG : 1][CPL], const uint32_t (&vy)[MOM ? PG : 1][CPL]) {
+      const int el = lane * CPL;
+#pragma unroll
+      for (int k = 0; k < PG; ++k) {
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          st_dev(slot(off, fi, 0) + k * TW + el + e, v[k][e]);
+          if constexpr (MOM) {
+            st_dev(slot(off, fi, 1) + k * TW + el + e, vx[k][e]);
+            st_dev(slot(off, fi, 2) + k * TW + el + e, vy[k][e]);
+          }
+        }
+      }
+      order_release();
+      if (lane == 0) st_dev(F + fi, state);
+    };
+    if (b > 0) {
+      int64_t fp = fidx - fstride;  // the band above
+      uint32_t f = op_poll(F + fp, hdr, a.patience);
+      if (f != 2) {
+        // not ready yet: publish this band's aggregate so that the bands
+        // below need not wait for this one, then walk up
+        if (!last_band) publish(g.off_agg, fidx, 1u, A, AX, AY);
+        for (int bb = b - 1;;) {
+          f = op_poll(F + fp, hdr, -1);
+          if (f == 2) {
+            add_payload(g.off_inc, fp);
+            break;
+          }
+          if (f != 1) break;  // the wait gave up (status word set)
+          add_payload(g.off_agg, fp);
+          if (--bb < 0) break;
+          fp -= fstride;
+        }
+      } else {
+        add_payload(g.off_inc, fp);
+      }
+    }
+    // ---- 3. inclusive bottom row of this band for the bands below
+    if (!last_band) {
+      uint32_t I[PG][CPL], IX[MOM ? PG : 1][CPL], IY[MOM ? PG : 1][CPL];
+#pragma unroll
+      for (int k = 0; k < PG; ++k) {
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          I[k][e] = top[k][e] + A[k][e];
+          if constexpr (MOM) {
+            IX[k][e] = topx[k][e] + AX[k][e];
+            IY[k][e] = topy[k][e] + AY[k][e];
+          }
+        }
+      }
+      publish(g.off_inc, fidx, 2u, I, IX, IY);
+    }
+    // ---- 4. write-out of the band's rows of this tile
+    uint32_t (&col)[PG][CPL] = top;
+    for (int rr = 0; rr < rows; ++rr) {
+      const int r = R0 + rr;
+      uint32_t px[CPL];
+      load_px<T, CPL>(img + (int64_t)r * g.W, cf, g.W, pvec, px);
+      int bq[CPL];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) bq[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
+      const int64_t orow = (int64_t)r * g.W + cf;
+#pragma unroll
+      for (int k = 0; k < PG; ++k) {
+        if (k < nk) {
+          const uint32_t lcur = (uint32_t)uniform((int)lc[rr * PG + k]);
+          uint32_t tq = lcur;
+          uint64_t m[CPL];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) m[e] = ballot(bq[e] == k);
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) tq = lanes_below(m[e], tq);
+          uint32_t pre[CPL];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            tq += bq[e] == k ? 1u : 0u;
+            pre[e] = tq;
+            col[k][e] += tq;
+          }
+          put<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec);
+          const uint32_t nlc = read_lane(tq, 63);
+          if constexpr (MOM) {
+            const uint32_t lycur = (uint32_t)uniform((int)lcy[rr * PG + k]);
+            uint32_t y[CPL];
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) {
+              topx[k][e] += (uint32_t)r * pre[e];
+              y[e] = bq[e] == k ? (uint32_t)(cf + e) : 0u;
+            }
+#pragma unroll
+            for (int e = 1; e < CPL; ++e) y[e] += y[e - 1];
+            const uint32_t iy = wave_incl_scan(y[CPL - 1]);
+            const uint32_t ey = iy - y[CPL - 1] + lycur;
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) topy[k][e] += ey + y[e];
+            put<CPL>(mx_base + k * HW + orow, topx[k], cf, g.W, vec);
+            put<CPL>(my_base + k * HW + orow, topy[k], cf, g.W, vec);
+            const uint32_t nly = lycur + read_lane(iy, 63);
+            if (lane == 0) lcy[rr * PG + k] = nly;
+          }
+          if (lane == 0) lc[rr * PG + k] = nlc;
+        }
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < PG; ++k) {
+      lcs[k] += tot[k];
+      if constexpr (MOM) {
+        lcxs[k] += totx[k];
+        lcys[k] += toty[k];
+      }
+    }
+  }
+  if (ballot(bad != 0) && lane == 0)
+    __hip_atomic_fetch_or(hdr + kHdrStatus, (uint32_t)IH_STATUS_VALUE_RANGE, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kOpWaves = 4;
+
+template <typename T, int CPL, int PG, bool MOM>
+__global__ __launch_bounds__(64 * kOpWaves) void k_op_bhw(OpArgs a, OpGeom g) {
+  extern __shared__ uint32_t lds[];
+  const int wave = threadIdx.x >> 6;
+  uint32_t *lc = lds + (size_t)wave * g.R * PG * (MOM ? 2 : 1);
+  int t = 0;
+  if ((threadIdx.x & 63) == 0)
+    t = (int)__hip_atomic_fetch_add(a.ws + kHdrTicket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  t = uniform(t);
+  if (t >= g.nB * g.nG) return;
+  op_bhw_worker<T, CPL, PG, MOM>(a, g, t, lc);
+}
+
+// Clears the header (status, ticket, abort) and the flags.
+__global__ __launch_bounds__(256) void k_op_init(uint32_t *ws, int64_t off_flag, int64_t nflags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kWsHeaderWords) ws[i] = 0u;
+  for (int64_t f = i; f < nflags; f += (int64_t)gridDim.x * blockDim.x) ws[off_flag + f] = 0u;
+}
+
+// ------------------------------------------------------------------ host --
+typedef void (*op_fn)(OpArgs, OpGeom);
+
+template <typename T, bool MOM>
+static op_fn pick_op_t(int CPL, int PG) {
+#define IH_O(C_, G_) \
+  if (CPL == C_ && PG == G_) return &k_op_bhw<T, C_, G_, MOM>;
+  IH_O(1, 1) IH_O(1, 2) IH_O(1, 4)
+  IH_O(2, 1) IH_O(2, 2) IH_O(2, 4)
+  IH_O(4, 1) IH_O(4, 2) IH_O(4, 4)
+#undef IH_O
+  return nullptr;
+}
+
+static size_t op_lds(const OpGeom &g) { return (size_t)kOpWaves * g.R * g.PG * (g.mom ? 2 : 1) * 4; }
+
+int make_op_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, const ih_tile_cfg *cfg,
+                 OpGeom *g) {
+  if (H < 1 || W < 1 || C < 1)
+    return set_error(IH_ERR_INVALID_ARG, "image shape %dx%dx%d must be positive", C, H, W);
+  if ((int64_t)H * W >= ((int64_t)1 << 31))
+    return set_error(IH_ERR_OVERFLOW, "H*W = %lld does not fit int32 counts", (long long)H * W);
+  if (bins < 1 || bins > 256) return set_error(IH_ERR_INVALID_ARG, "bins %d outside 1..256", bins);
+  g->H = H; g->W = W; g->C = C; g->bins = bins; g->P = C * bins;
+  g->mom = moments != 0;
+  g->arrays = g->mom ? 3 : 1;
+  int R, TW, PG;
+  if (cfg && cfg->tile_h > 0) {
+    R = cfg->tile_h; TW = cfg->tile_w; PG = cfg->planes_per_wave;
+  } else {
+    // default bands: tall enough that the chain of bands is short, short
+    // enough that there are several bands per frame
+    R = H >= 4096 ? 256 : H >= 1024 ? 128 : H >= 256 ? 64 : 32;
+    TW = W >= 2048 ? 256 : W >= 512 ? 128 : 64;
+    PG = 1;
+  }
+  if (R < 1 || R > 1024) return set_error(IH_ERR_INVALID_ARG, "band rows %d outside 1..1024", R);
+  if (TW != 64 && TW != 128 && TW != 256)
+    return set_error(IH_ERR_INVALID_ARG, "tile_w %d not 64, 128 or 256 for the single-pass build", TW);
+  if (PG != 1 && PG != 2 && PG != 4)
+    return set_error(IH_ERR_INVALID_ARG, "planes_per_wave %d not 1, 2 or 4 for the single-pass build", PG);
+  g->R = R; g->TW = TW; g->PG = PG; g->CPL = TW / 64;
+  if (op_lds(*g) > 64 * 1024)
+    return set_error(IH_ERR_UNSUPPORTED, "band of %d rows x %d planes needs too much LDS", R, PG);
+  g->nB = (H + R - 1) / R;
+  g->nT = (W + TW - 1) / TW;
+  g->gpc = (bins + PG - 1) / PG;
+  g->nG = C * g->gpc;
+  if ((int64_t)g->nB * g->nG >= ((int64_t)1 << 31))
+    return set_error(IH_ERR_RANGE, "too many band workers");
+  g->slot = PG * TW;
+  const int64_t units = (int64_t)g->nB * g->nG * g->nT;
+  g->off_flag = kWsHeaderWords;
+  g->off_inc = (g->off_flag + units + 63) & ~(int64_t)63;
+  g->off_agg = g->off_inc + units * g->arrays * g->slot;
+  g->words = g->off_agg + units * g->arrays * g->slot;
+  return IH_OK;
+}
+
+int launch_onepass(const OpGeom &g, int dtype, const OpArgs &a, hipStream_t s) {
+  op_fn fn = dtype == IH_U8 ? (g.mom ? pick_op_t<uint8_t, true>(g.CPL, g.PG) : pick_op_t<uint8_t, false>(g.CPL, g.PG))
+                            : (g.mom ? pick_op_t<uint16_t, true>(g.CPL, g.PG)
+                                     : pick_op_t<uint16_t, false>(g.CPL, g.PG));
+  if (!fn) return set_error(IH_ERR_UNSUPPORTED, "no single-pass kernel for tile_w %d, %d planes", g.TW, g.PG);
+  int e;
+  const int64_t nflags = (int64_t)g.nB * g.nG * g.nT;
+  const int64_t iblocks = std::min<int64_t>((nflags + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(k_op_init, dim3((unsigned)iblocks), dim3(256), 0, s, a.ws, g.off_flag, nflags);
+  if ((e = hip_check(hipGetLastError(), "single-pass init launch"))) return e;
+  const int64_t workers = (int64_t)g.nB * g.nG;
+  hipLaunchKernelGGL(fn, dim3((unsigned)((workers + kOpWaves - 1) / kOpWaves)), dim3(64 * kOpWaves), op_lds(g), s,
+                     a, g);
+  return hip_check(hipGetLastError(), "single-pass launch");
+}
+
+}  // namespace ih

@@ -66,6 +66,7 @@ SIGNATURES = {
     "ih_match_candidates": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P, _I64, _I32,
                                            _P, _P, _P]),
     "ih_profile_events": (ctypes.c_int, [_P, _P]),
+    "ih_set_lookback_patience": (ctypes.c_int, [_I32]),
     "ih_batch_plan_bytes": (_SZ, [_I32]),
     "ih_batch_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _SZ, ctypes.POINTER(_SZ)]),
     "ih_build_batch": (ctypes.c_int, [_P, _P, _P, _SZ, _I32, _P]),
@@ -92,16 +93,42 @@ class IHError(RuntimeError):
     pass
 
 
+PASSES_DEFAULT, PASSES_ONE, PASSES_THREE = 0, 1, 3
+STATUS_VALUE_RANGE, STATUS_WAIT_TIMEOUT = 1, 2
+
+
 class TileCfg(ctypes.Structure):
-    """Tile shape of the build (see ih_tile_cfg in include/ih.h)."""
+    """Tile shape and pass count of the build (see ih_tile_cfg in include/ih.h).
+    ``passes``: 0 or 3 for the three-pass build, 1 for the single-pass one."""
     _fields_ = [("tile_h", ctypes.c_int32), ("tile_w", ctypes.c_int32),
-                ("planes_per_wave", ctypes.c_int32)]
+                ("planes_per_wave", ctypes.c_int32), ("passes", ctypes.c_int32)]
 
     def __repr__(self):
+        if self.passes:
+            return "TileCfg(%d, %d, %d, passes=%d)" % (self.tile_h, self.tile_w, self.planes_per_wave, self.passes)
         return "TileCfg(%d, %d, %d)" % (self.tile_h, self.tile_w, self.planes_per_wave)
 
     def key(self):
-        return (self.tile_h, self.tile_w, self.planes_per_wave)
+        return (self.tile_h, self.tile_w, self.planes_per_wave, self.passes)
+
+
+def onepass(tile_h: int = 0, tile_w: int = 256, planes_per_wave: int = 1) -> TileCfg:
+    """Configuration of the single-pass build: bands of tile_h rows (0: the
+    library's choice), tiles of tile_w columns, planes_per_wave planes per
+    worker."""
+    return TileCfg(tile_h, tile_w, planes_per_wave, PASSES_ONE)
+
+
+def status(ws: torch.Tensor) -> int:
+    """The IH_STATUS_* bits a build left in the first word of its workspace
+    (synchronises with the device)."""
+    return int(ws.view(torch.uint8)[:4].view(torch.int32).item()) & 0xFFFFFFFF
+
+
+def set_lookback_patience(polls: int):
+    """Polls of the band above before a single-pass worker publishes its own
+    aggregate and looks further up (-1: always wait for the band above)."""
+    _check(lib().ih_set_lookback_patience(int(polls)), "ih_set_lookback_patience")
 
 
 class Frame(ctypes.Structure):

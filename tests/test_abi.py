@@ -147,3 +147,25 @@ def test_batch_plan_host_only(lib):
     assert lib.ih_batch_plan(ctypes.byref(arr), n, 0, 0, buf, nb, ctypes.byref(ws)) == 0
     assert lib.ih_build_batch(buf, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 16, 0, None) == -6
     assert lib.ih_build_batch(buf, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 30, 7, None) == -1
+
+
+def test_onepass_host_checks(lib):
+    from paper_1711_01656_amd import ih
+    one = ih.onepass(64, 256, 1)
+    n = ih.workspace_size(480, 640, 1, 32, cfg=one)
+    assert n > 0
+    # header + flags + two payload areas of about 1/64 of the output each
+    assert n < 0.1 * 480 * 640 * 32 * 4
+    assert ih.workspace_size(480, 640, 1, 32, True, cfg=one) > n
+    # bad single-pass shapes and layouts are refused on the host
+    for bad in (ih.onepass(64, 96, 1), ih.onepass(64, 256, 3), ih.onepass(2000, 256, 1)):
+        assert lib.ih_build_workspace_size(480, 640, 1, 32, 0, 0, ctypes.byref(bad)) == 0
+    assert lib.ih_build_workspace_size(480, 640, 1, 32, 0, 1, ctypes.byref(one)) == 0
+    assert b"bin-major" in lib.ih_last_error()
+    big = ih.onepass(1024, 256, 4)   # 64 KB of row carries per block: no room for moments
+    assert lib.ih_build_workspace_size(4096, 640, 1, 32, 1, 0, ctypes.byref(big)) == 0
+    assert lib.ih_set_lookback_patience(-2) != 0
+    assert lib.ih_set_lookback_patience(-1) == 0
+    # a three-pass workspace of a shape also fits its single-pass default build
+    dflt = ih.workspace_size(1080, 1920, 7, 16, True)
+    assert dflt >= lib.ih_build_workspace_size(1080, 1920, 7, 16, 1, 0, ctypes.byref(ih.onepass()))

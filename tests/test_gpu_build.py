@@ -87,12 +87,13 @@ def test_build_moments_exact_mod_2_32(C, H, W, bins, bits, layout):
     assert np.array_equal(mod32(bhw(my, layout)), mod32(omy))
 
 
-def test_build_every_tile_shape():
+@pytest.mark.parametrize("bits", [8, 16])
+def test_build_every_tile_shape(bits):
     ih = ihlib()
     C, H, W, bins = 2, 150, 333, 16
-    img = rand_img(5, C, H, W, 8)
-    ref = oracle.ih(img, bins, 8)
-    omx, omy = oracle.moments(img, bins, 8)
+    img = rand_img(5 + bits, C, H, W, bits)
+    ref = oracle.ih(img, bins, bits)
+    omx, omy = oracle.moments(img, bins, bits)
     t = gpu(img)
     shapes = [("bhw", th, tw, pg) for th, tw, pg in itertools.product((1, 7, 32, 64, 128), (64, 128, 256),
                                                                       (1, 2, 4, 8, 16))]
@@ -102,10 +103,10 @@ def test_build_every_tile_shape():
             continue
         cfg = ih.TileCfg(th, tw, pg)
         say("tile", layout, cfg)
-        assert np.array_equal(bhw(ih.ih_build(t, bins, cfg=cfg, layout=layout), layout), ref), cfg
+        assert np.array_equal(bhw(ih.ih_build(t, bins, bits, cfg=cfg, layout=layout), layout), ref), cfg
         mom_ok = (pg * tw // 64 <= 32) if layout == "bhw" else tw <= 32
         if mom_ok:
-            o, mx, my = ih.ih_build(t, bins, cfg=cfg, moments=True, layout=layout)
+            o, mx, my = ih.ih_build(t, bins, bits, cfg=cfg, moments=True, layout=layout)
             assert np.array_equal(bhw(o, layout), ref), cfg
             assert np.array_equal(mod32(bhw(mx, layout)), mod32(omx)), cfg
             assert np.array_equal(mod32(bhw(my, layout)), mod32(omy)), cfg
