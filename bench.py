@@ -1,24 +1,26 @@
 """Benchmark of the integral-histogram hot path on one MI355X.
 
-One step = one pass of the whole path over one synthetic 1920x1080 frame with
-7 uint8 feature channels x 16 bins (112 planes):
-  1. ih_build with coordinate moments (binning, row/column scans, carries,
-     write-out of three 112 x 1080 x 1920 int32 tensors);
-  2. 100,000 Manhattan-weighted local histograms (SWIH), windows 16-256 px;
-  3. 100,000 plain four-corner region histograms over the same windows;
-  4. a 3-level pyramid descriptor of a 32x32 template and the pyramid
+One step = one pass of the whole path over the 8192x8192 uint16 aerial-style
+frame (64 bins, a 17.2 GB int32 integral histogram):
+  1. ih_build (binning, row/column scans, carries, write-out);
+  2. 1,000,000 plain four-corner rectangle histograms (sides 4-200 px);
+  3. the 3-level pyramid descriptor of a 32x32 template and the pyramid
      chi-square search over a 129 x 129 grid of candidate origins.
-Inputs are resident in HBM before timing.  Prints one JSON line.
+Inputs are resident in HBM before timing.  Prints one JSON line whose value is
+that step's throughput; the headline layout is planes innermost (the one the
+queries read fast) and the bin-major layout is reported beside it.
 
-The line also carries the tracker workload ("tracker"): a 1280x720, 300-frame
-synthetic video (7 feature channels x 16 bins), the exhaustive 65x65
-pyramid-distance search against the learned proposal (BF16 network trained
-here on exhaustive-search labels of independent sequences, top 64 scored
-exactly, exhaustive fallback), reported as frames per second and agreement.
+The line also carries the other workloads ("workloads": the 640x480 frame,
+the 1920x1080 7-channel frame with 100k weighted windows, the 64-frame batch
+and the further rows), the tracker workload ("tracker": a 1280x720, 300-frame
+synthetic video, exhaustive 65x65 search against the learned proposal), and
+for every workload the oracle timed on the host's cores.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import platform
@@ -31,12 +33,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the write-out kernel measured with rocprofv3 PMC
-# counters (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy)
-# for this workload and tile; see profiles/k_final_hwb_staged_1920x1080x112_moments.md.
-# Reported only when the benchmark runs the same kernel and tile.
-PROFILED_TRAFFIC = {("hwb", "TileCfg(128, 16, 64)"): 2944712090}
 METRIC = "integral-hist Gpx·bins/s (% HBM peak); queries/s; tracker fps learned vs exhaustive"
+# kernel sources whose hash keys the committed traffic figures (a counter
+# figure is reported only while the kernels it was taken from are unchanged)
+KERNEL_SOURCES = ("paper_1711_01656_amd/csrc/ih_build_dev.h", "paper_1711_01656_amd/csrc/ih_build.hip",
+                  "paper_1711_01656_amd/csrc/ih_onepass.hip", "paper_1711_01656_amd/csrc/ih_internal.h")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 summaries (lines `traffic: <kernel> | <workload> | <sources
+    hash> | <bytes>`), or None when none was taken from the current sources."""
+    want = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic:"):
+                    continue
+                parts = [x.strip() for x in line[len("traffic:"):].split("|")]
+                if len(parts) == 4 and parts[0] == kernel and parts[1] == workload and parts[2] == want:
+                    return int(parts[3])
+    return None
 
 
 def parse():
@@ -46,14 +71,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--trials", type=int, default=5, help="graph-replay trials of --steps steps; median reported")
     ap.add_argument("--layout", choices=["hwb", "bhw"], default="hwb",
-                    help="memory layout of the integral histograms for the headline step")
+                    help="memory layout of the integral histogram for the headline step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--no-other", action="store_true", help="skip timing the other layout")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run one device fill and one copy of this many MiB (counter calibration)")
     ap.add_argument("--no-tracker", action="store_true", help="skip the tracker workload")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the other workloads (640x480, 8192^2 u16, 64-frame batch)")
+                    help="skip the other workloads (640x480, 1920x1080x112, 64-frame batch, further rows)")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the further rows' legs (PHoG, median, SWIH kernels, CAMSHIFT) among the workloads")
     ap.add_argument("--fixed-tiles", action="store_true",
                     help="other workloads: use the tile shapes the autotuners chose on an MI355X instead of tuning")
     ap.add_argument("--workloads-only", action="store_true",
@@ -71,13 +98,54 @@ def parse():
     ap.add_argument("--train-videos", type=int, default=800)
     ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--tile", type=str, default="",
-                    help="tile_h,tile_w,planes_per_wave (default: autotuned at start-up)")
+                    help="tile_h,tile_w,planes_per_wave[,passes] of the headline layout (default: the library's)")
     return ap.parse_args()
 
 
-def cpu_baseline(w, origins, tmpl_win, min_seconds=10.0, threads=0):
-    """The oracle, as it stands, on the same workload, repeated for >= min_seconds
-    (threads: OpenMP threads, 0 = all host cores)."""
+def _host():
+    return platform.processor() or platform.machine()
+
+
+def cpu_config3(w, min_seconds=10.0, threads=0):
+    """The oracle on the 8192^2 workload, streamed one plane at a time (the
+    17 GB histogram does not fit the host comfortably): planes are built by
+    the Alg. 5 recurrence and their 1M rectangle queries answered until
+    `min_seconds` have passed, then the full 129x129 search runs once by
+    direct counting; the step time scales the per-plane times to 64 planes."""
+    import oracle
+    oracle.set_threads(threads)
+    t_b = t_q = 0.0
+    planes = 0
+    t0 = time.perf_counter()
+    while planes == 0 or (time.perf_counter() - t0 < min_seconds and planes < w.P):
+        a = time.perf_counter()
+        pl = oracle.ih_plane(w.img, w.bins, w.bits, planes)
+        b = time.perf_counter()
+        oracle.query_rect(pl[None], w.rects)
+        c = time.perf_counter()
+        t_b += b - a
+        t_q += c - b
+        planes += 1
+        del pl
+    a = time.perf_counter()
+    tmpl = oracle.pyramid_desc_direct(w.img, w.bins, w.bits, [w.tmpl_win], 3)[0]
+    oracle.match_direct(w.img, w.bins, w.bits, tmpl, 32, 32, 3, w.origins, "chi2")
+    t_m = time.perf_counter() - a
+    cores = oracle.num_threads()
+    oracle.set_threads(0)
+    step = (t_b + t_q) / planes * w.P + t_m
+    return {"value": round(w.H * w.W * w.P / step / 1e9, 4), "unit": "Gpx·bins/s", "cores": cores,
+            "kind": "oracle",
+            "sample": ("%d of %d planes of the 8192x8192 frame built by the Alg. 5 recurrence (one at a time) "
+                       "with their 1M rectangle queries, scaled to %d planes, plus the 129x129 pyramid chi2 "
+                       "search by direct counting; step %.2f s (build %.3f s/plane, 1M queries %.3f s/plane, "
+                       "search %.3f s)" % (planes, w.P, w.P, step, t_b / planes, t_q / planes, t_m)),
+            "host": _host()}
+
+
+def cpu_config2(w, origins, tmpl_win, min_seconds=5.0, threads=0):
+    """The oracle on the 1920x1080x112 step (count + moment IHs, 100k SWIH
+    queries, 100k rect queries, 129x129 search), repeated for >= min_seconds."""
     import oracle
     oracle.set_threads(threads)
     reps, t_build, t_wq, t_rq, t_m = 0, 0.0, 0.0, 0.0, 0.0
@@ -103,21 +171,192 @@ def cpu_baseline(w, origins, tmpl_win, min_seconds=10.0, threads=0):
     t_step = (t_build + t_wq + t_rq + t_m) / reps
     cores = oracle.num_threads()
     oracle.set_threads(0)
+    return {"value": round(w.H * w.W * w.P / t_step / 1e9, 4), "unit": "Gpx·bins/s", "cores": cores,
+            "kind": "oracle",
+            "sample": ("the full step (count + moment IHs by the Alg. 5 recurrence, 100k SWIH queries, 100k "
+                       "rect queries, 129x129 pyramid chi2 search) repeated %d times in %.1f s; per step: "
+                       "build %.3f s, weighted %.3f s, rect %.3f s, match %.3f s"
+                       % (reps, t_build + t_wq + t_rq + t_m, t_build / reps, t_wq / reps, t_rq / reps,
+                          t_m / reps)),
+            "host": _host()}
+
+
+def cpu_config1(w, min_seconds=3.0, threads=0):
+    """The oracle on the 640x480 frame: build and 10,000 rectangle queries."""
+    import oracle
+    oracle.set_threads(threads)
+    reps, tb, tq = 0, 0.0, 0.0
+    t0 = time.perf_counter()
+    while reps == 0 or time.perf_counter() - t0 < min_seconds:
+        a = time.perf_counter()
+        h = oracle.ih(w.img, w.bins, w.bits)
+        b = time.perf_counter()
+        oracle.query_rect(h, w.rects)
+        tq += time.perf_counter() - b
+        tb += b - a
+        reps += 1
+    cores = oracle.num_threads()
+    oracle.set_threads(0)
+    return {"value": round(w.H * w.W * w.P / (tb / reps) / 1e9, 4), "unit": "Gpx·bins/s (build)", "cores": cores,
+            "kind": "oracle", "build_ms": round(tb / reps * 1e3, 3), "rect_ms": round(tq / reps * 1e3, 3),
+            "sample": "build + 10k rectangle queries repeated %d times" % reps, "host": _host()}
+
+
+def cpu_config4(frames, min_seconds=6.0, threads=0):
+    """The oracle on the 64-frame batch, one frame at a time (build by the Alg.
+    5 recurrence, template descriptor, 4,096-candidate chi-square search by
+    direct counting) until min_seconds have passed; the batch time scales the
+    sampled frames' time by their share of the batch's histogram elements."""
+    import oracle
+    oracle.set_threads(threads)
+    total = sum(f.img.shape[1] * f.img.shape[2] * f.bins for f in frames)
+    done = 0
+    t = 0.0
+    n = 0
+    t0 = time.perf_counter()
+    for f in frames:
+        if n and time.perf_counter() - t0 >= min_seconds:
+            break
+        a = time.perf_counter()
+        h = oracle.ih(f.img, f.bins, f.bits)
+        tmpl = oracle.pyramid_desc(h, [f.tmpl_win], 3)[0]
+        oracle.match_direct(f.img, f.bins, f.bits, tmpl, 32, 32, 3, f.origins, "chi2")
+        t += time.perf_counter() - a
+        done += f.img.shape[1] * f.img.shape[2] * f.bins
+        n += 1
+        del h
+    cores = oracle.num_threads()
+    oracle.set_threads(0)
+    batch_s = t * total / done
+    return {"value": round(total / batch_s / 1e9, 4), "unit": "Gpx·bins/s", "cores": cores, "kind": "oracle",
+            "batch_ms": round(batch_s * 1e3, 1),
+            "sample": "%d of %d frames (build + template + 4,096-candidate search each), scaled by histogram size"
+                      % (n, len(frames)), "host": _host()}
+
+
+class Step3:
+    """Preallocated buffers and the three calls of one step on the 8192^2
+    frame, in one layout and build configuration."""
+
+    def __init__(self, ih, torch, w, img, rects, origins, tmpl_win, layout, cfg):
+        dev = img.device
+        self.ih, self.torch, self.layout, self.cfg = ih, torch, layout, cfg
+        self.img, self.rects, self.origins, self.tmpl_win = img, rects, origins, tmpl_win
+        self.bins, self.bits, P = w.bins, w.bits, w.P
+        self.out = torch.empty(ih.shape_of(P, w.H, w.W, layout), dtype=torch.int32, device=dev)
+        self.ws = torch.empty(ih.workspace_size(w.H, w.W, 1, w.bins, False, cfg, layout), dtype=torch.uint8,
+                              device=dev)
+        self.q = torch.empty((rects.shape[0], P), dtype=torch.int32, device=dev)
+        self.desc = torch.empty((1, 21, P), dtype=torch.int32, device=dev)
+        self.dist = torch.empty(origins.shape[0], dtype=torch.float32, device=dev)
+        self.best = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def build(self):
+        self.ih.ih_build(self.img, self.bins, self.bits, cfg=self.cfg, out=self.out, ws=self.ws, layout=self.layout)
+
+    def rect(self):
+        self.ih.ih_query_rect(self.out, self.rects, out=self.q, layout=self.layout)
+
+    def match(self):
+        self.ih.ih_pyramid_desc(self.out, self.tmpl_win, 3, out=self.desc, layout=self.layout)
+        self.ih.ih_match_candidates(self.out, self.desc, 32, 32, self.origins, 3, "chi2", dist=self.dist,
+                                    best=self.best, layout=self.layout)
+
+    def after_build(self):
+        self.rect()
+        self.match()
+
+    def __call__(self):
+        self.build()
+        self.after_build()
+
+    def outputs(self):
+        return (self.out, self.q, self.dist, self.best)
+
+    def stages(self):
+        return {"rect": self.rect, "match": self.match}
+
+
+def measure_step(torch, ih, step, steps, warmup, trials, alg_bytes, workload):
+    """Times a step: `warmup` eager steps, then `steps` eager steps with the
+    build bracketed by events on its stream (whole build) and the dominant
+    kernel by the library's events, then the step captured once as a HIP
+    graph and replayed (`trials` trials of `steps` replays, median), every
+    replayed result checked bit for bit against the eager one."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev_b = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    ev_k = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev_b + ev_k:          # torch creates the HIP event on first record
+        a.record()
+        b.record()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for k in range(steps):
+        ih.ih_profile_events(*ev_k[k])
+        ev_b[k][0].record()
+        step.build()
+        ev_b[k][1].record()
+        step.after_build()
+    t1.record()
+    torch.cuda.synchronize()
+    ih.ih_profile_events(None, None)
+    eager_ms = t0.elapsed_time(t1) / steps
+    build_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_b]))
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_k]))
+    status = ih.status(step.ws)
+    ref = [t.clone() for t in step.outputs()]
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        step()
+    for _ in range(warmup):
+        graph.replay()
+    tr = []
+    for _ in range(max(1, trials)):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            graph.replay()
+        b.record()
+        torch.cuda.synchronize()
+        tr.append(a.elapsed_time(b) / steps)
+    same = all(torch.equal(x, y) for x, y in zip(ref, step.outputs()))
+    if not same:
+        raise SystemExit("graph replay results differ from the eager step")
+    del ref, graph
+    stages = {"build": round(build_ms, 4), "dominant_kernel": round(k_ms, 4)}
+    for name, fn in step.stages().items():
+        stages[name] = round(time_calls(torch, fn, 5), 4)
+    one = ih.build_passes(step.layout, step.cfg) == 1
+    kname = "single-pass band kernel" if one else "three-pass write-out"
     return {
-        "value": round(w.H * w.W * w.P / t_step / 1e9, 4),
-        "unit": "Gpx·bins/s",
-        "cores": cores,
-        "kind": "oracle",
-        "sample": ("the full step (count + moment IHs by the Alg. 5 recurrence, 100k SWIH queries, 100k "
-                   "rect queries, 129x129 pyramid chi2 search) repeated %d times in %.1f s; per step: "
-                   "build %.3f s, weighted %.3f s, rect %.3f s, match %.3f s"
-                   % (reps, t_build + t_wq + t_rq + t_m, t_build / reps, t_wq / reps, t_rq / reps, t_m / reps)),
-        "host": platform.processor() or platform.machine(),
+        "layout": step.layout, "cfg": repr(step.cfg) if step.cfg is not None else "library default",
+        "build": "one pass" if one else "three passes",
+        "ms_per_step": float(np.median(tr)), "graph_trials_ms": [round(t, 4) for t in tr],
+        "eager_ms_per_step": round(eager_ms, 4), "graph_replays_match_eager": same, "stages_ms": stages,
+        "build_status_bits": status,
+        "build_roofline": {"bound": "hbm", "kernel": "whole build (%s)" % ("init + band kernel" if one else
+                                                                          "tile pass + carry scan + write-out"),
+                           "achieved": round(alg_bytes / build_ms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(alg_bytes / build_ms / 1e6 / HBM_PEAK_GBS, 4)},
+        "dominant_kernel": {"kernel": kname, "ms": round(k_ms, 4),
+                            "achieved": round(alg_bytes / k_ms / 1e6, 1),
+                            "frac": round(alg_bytes / k_ms / 1e6 / HBM_PEAK_GBS, 4),
+                            "traffic": profiled_traffic(kname, "%s %s %s" % (workload, step.layout,
+                                                                             repr(step.cfg)))},
     }
 
 
-class Step:
-    """Preallocated buffers and the five calls of one step, in one layout."""
+class Step2:
+    """Preallocated buffers and the calls of one step on the 1920x1080 frame
+    with 7 channels x 16 bins: build with moments, 100k weighted and 100k
+    plain window histograms, template descriptor and 129x129 search."""
 
     def __init__(self, ih, torch, w, img, wins, origins, tmpl_win, layout, cfg):
         dev = img.device
@@ -152,11 +391,53 @@ class Step:
         self.ih.ih_match_candidates(self.out, self.desc, 32, 32, self.origins, 3, "chi2", dist=self.dist,
                                     best=self.best, layout=self.layout)
 
-    def __call__(self):
-        self.build()
+    def after_build(self):
         self.weighted()
         self.rect()
         self.match()
+
+    def __call__(self):
+        self.build()
+        self.after_build()
+
+    def outputs(self):
+        return (self.out, self.mx, self.my, self.wq, self.rq, self.dist, self.best)
+
+    def stages(self):
+        return {"weighted": self.weighted, "rect": self.rect, "match": self.match}
+
+
+def config2_leg(torch, ih, synth, args):
+    """The 1920x1080 frame with 7 u8 channels x 16 bins (112 planes): build
+    with both moment tensors, 100k Manhattan-weighted and 100k plain window
+    histograms (16-256 px), a 129x129 pyramid chi2 search; per layout the
+    step graph-replayed and the whole build and its dominant kernel timed."""
+    dev = torch.device("cuda:0")
+    w = synth.config2()
+    rng_win = np.random.default_rng(205)
+    H, W, P = w.H, w.W, w.P
+    img = torch.from_numpy(w.img).to(dev)
+    wins = torch.from_numpy(w.windows).to(dev)
+    tr = int(rng_win.integers(64, H - 32 - 64))
+    tc = int(rng_win.integers(64, W - 32 - 64))
+    origins_np = synth.grid_origins(tr - 64, tc - 64, 129, 129)
+    origins = torch.from_numpy(origins_np).to(dev)
+    tmpl_win = torch.tensor([[tr, tc, 32, 32]], dtype=torch.int32, device=dev)
+    alg = 3 * P * H * W * 4 + w.C * H * W
+    res = {"workload": "1920x1080 frame, 7 u8 channels x 16 bins (112 planes), count + 2 moment IHs; 100k "
+                       "weighted + 100k plain window queries (16-256 px); 129x129 pyramid chi2 search",
+           "alg_bytes_per_build": alg, "layouts": {}}
+    for layout in ("hwb", "bhw"):
+        step = Step2(ih, torch, w, img, wins, origins, tmpl_win, layout, None)
+        r = measure_step(torch, ih, step, min(args.steps, 20), 3, 3, alg, "1920x1080x112 moments")
+        r["gpxbins_per_s"] = round(H * W * P / r["ms_per_step"] / 1e6, 2)
+        r["weighted_queries_per_s"] = round(wins.shape[0] / r["stages_ms"]["weighted"] * 1e3, 1)
+        res["layouts"][layout] = r
+        del step
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_config2(w, origins_np, (tr, tc, 32, 32))
+    return res
 
 
 def time_calls(torch, fn, n):
@@ -438,84 +719,53 @@ def graph_median(torch, fn, n=10, trials=3, per=1):
     return float(np.median([time_calls(torch, g.replay, n) for _ in range(trials)])) / per
 
 
-def config_legs(torch, ih, synth, fixed=False):
-    """The other benchmark workloads, each timed on the device (median of
-    repeated calls): 640x480 u8 with 32 bins and 10,000 rectangles; the
-    8192x8192 u16 frame with 64 bins (17 GB integral histogram), 1M rectangles
-    and a 129x129 pyramid search; 64 uneven frames built and searched as one
-    batch (phased launches replayed from a HIP graph, and one cooperative
-    launch; the batch's tile shape chosen by timing the whole batch) against
-    the same frames built and searched one call at a time (each frame with
-    its own autotuned tile)."""
-    from paper_1711_01656_amd import tune
+def config1_leg(torch, ih, synth, args):
+    """640x480 u8 with 32 bins and 10,000 rectangles: the build in both layouts
+    with the library's default configuration (one launch each, graph-replayed),
+    the rectangle queries, and the same frame 64 times as one batch (phased,
+    graph-replayed) for the per-frame cost when frames arrive together."""
     dev = torch.device("cuda:0")
-    res = {}
-
-    def med(fn, n=10, trials=3, per=1):
-        return graph_median(torch, fn, n, trials, per)
-
-    # 640x480, 32 bins, 10k rectangles
     w = synth.config1()
     img = torch.from_numpy(w.img).to(dev)
-    cfg = ih.TileCfg(*FIXED_TILES["640x480"]) if fixed else tune.tune(img, w.bins, w.bits, layout="hwb", reps=3)[0]
-    out = torch.empty(ih.shape_of(w.P, w.H, w.W, "hwb"), dtype=torch.int32, device=dev)
-    ws = torch.empty(ih.workspace_size(w.H, w.W, w.C, w.bins, False, cfg, "hwb"), dtype=torch.uint8, device=dev)
     rects = torch.from_numpy(w.rects).to(dev)
-    q = torch.empty((rects.shape[0], w.P), dtype=torch.int32, device=dev)
-    tb = med(lambda: ih.ih_build(img, w.bins, w.bits, cfg=cfg, out=out, ws=ws, layout="hwb"), 10, per=20)
-    tq = med(lambda: ih.ih_query_rect(out, rects, out=q, layout="hwb"), 10, per=20)
     alg = w.P * w.H * w.W * 4 + w.H * w.W
-    res["640x480_u8_32bins"] = {"build_ms": round(tb, 4), "gpxbins_per_s": round(w.H * w.W * w.P / tb / 1e6, 2),
-                                "build_hbm_gbs": round(alg / tb / 1e6, 1), "rect_queries": int(rects.shape[0]),
-                                "rect_ms": round(tq, 4), "rect_queries_per_s": round(rects.shape[0] / tq * 1e3, 1),
-                                "tile": repr(cfg)}
-    del out, ws, q
+    res = {"workload": "640x480 u8, 32 bins, 10,000 rectangles (sides 4-200)", "alg_bytes_per_build": alg,
+           "layouts": {}}
+    for layout in ("bhw", "hwb"):
+        out = torch.empty(ih.shape_of(w.P, w.H, w.W, layout), dtype=torch.int32, device=dev)
+        ws = torch.empty(ih.workspace_size(w.H, w.W, w.C, w.bins, False, None, layout), dtype=torch.uint8, device=dev)
+        q = torch.empty((rects.shape[0], w.P), dtype=torch.int32, device=dev)
+        tb = graph_median(torch, lambda: ih.ih_build(img, w.bins, w.bits, out=out, ws=ws, layout=layout), 10, per=20)
+        tq = graph_median(torch, lambda: ih.ih_query_rect(out, rects, out=q, layout=layout), 10, per=20)
+        res["layouts"][layout] = {"build": "one pass" if ih.build_passes(layout) == 1 else "three passes",
+                                  "build_ms": round(tb, 4), "gpxbins_per_s": round(w.H * w.W * w.P / tb / 1e6, 2),
+                                  "build_frac_of_peak": round(alg / tb / 1e6 / HBM_PEAK_GBS, 4),
+                                  "rect_ms": round(tq, 4), "rect_queries_per_s": round(rects.shape[0] / tq * 1e3, 1)}
+        del out, ws, q
+    frames = [dict(img=img, bins=w.bins, value_bits=w.bits, tile=None) for _ in range(64)]
+    for layout in ("hwb", "bhw"):
+        batch = ih.Batch(frames, "chi2", layout=layout)
+        t = graph_median(torch, lambda: batch.run("phased"), 5)
+        res["layouts"][layout]["batch_of_64_ms_per_frame"] = round(t / 64, 4)
+        res["layouts"][layout]["batch_of_64_frac_of_peak"] = round(64 * alg / t / 1e6 / HBM_PEAK_GBS, 4)
+        del batch
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_config1(w)
+    return res
 
-    # magnitude-weighted orientation histogram of the 1920x1080 scene
-    res["phog_1920x1080_16bins"] = phog_leg(torch, ih, synth)
-    # spatio-temporal median of a 768x576 video
-    res["median_768x576_256bins"] = median_leg(torch, ih, synth)
-    # spatial kernels: exact SWIH against the wedding cake
-    res["swih_kernels_1920x1080x112"] = kernels_leg(torch, ih, synth)
-    # colour likelihood and CAMSHIFT on the tracking frame
-    res["camshift_1280x720"] = camshift_leg(torch, ih, synth)
 
-    # 8192x8192 u16, 64 bins, 1M rectangles, 129x129 search
-    w = synth.config3()
-    img = torch.from_numpy(w.img).to(dev)
-    cfg = ih.TileCfg(*FIXED_TILES["8192x8192"]) if fixed else tune.tune(img, w.bins, w.bits, layout="hwb", reps=1)[0]
-    out = torch.empty(ih.shape_of(w.P, w.H, w.W, "hwb"), dtype=torch.int32, device=dev)
-    ws = torch.empty(ih.workspace_size(w.H, w.W, w.C, w.bins, False, cfg, "hwb"), dtype=torch.uint8, device=dev)
-    rects = torch.from_numpy(w.rects).to(dev)
-    q = torch.empty((rects.shape[0], w.P), dtype=torch.int32, device=dev)
-    origins = torch.from_numpy(w.origins).to(dev)
-    tw = torch.tensor([list(w.tmpl_win)], dtype=torch.int32, device=dev)
-    desc = torch.empty((1, 21, w.P), dtype=torch.int32, device=dev)
-    dist = torch.empty(origins.shape[0], dtype=torch.float32, device=dev)
-    best = torch.empty(1, dtype=torch.int32, device=dev)
-    tb = med(lambda: ih.ih_build(img, w.bins, w.bits, cfg=cfg, out=out, ws=ws, layout="hwb"), 5)
-    tq = med(lambda: ih.ih_query_rect(out, rects, out=q, layout="hwb"), 5)
-
-    def search():
-        ih.ih_pyramid_desc(out, tw, 3, out=desc, layout="hwb")
-        ih.ih_match_candidates(out, desc, 32, 32, origins, 3, "chi2", dist=dist, best=best, layout="hwb")
-
-    tm = med(search, 10)
-    alg = w.P * w.H * w.W * 4 + w.H * w.W * 2
-    res["8192x8192_u16_64bins"] = {"ih_bytes": out.numel() * 4, "build_ms": round(tb, 3),
-                                   "gpxbins_per_s": round(w.H * w.W * w.P / tb / 1e6, 2),
-                                   "build_hbm_gbs": round(alg / tb / 1e6, 1),
-                                   "build_frac_of_peak": round(alg / tb / 1e6 / HBM_PEAK_GBS, 4),
-                                   "rect_queries": int(rects.shape[0]), "rect_ms": round(tq, 3),
-                                   "rect_queries_per_s": round(rects.shape[0] / tq * 1e3, 1),
-                                   "search_candidates": int(origins.shape[0]), "search_ms": round(tm, 4),
-                                   "tile": repr(cfg)}
-    del out, ws, q, img
-
-    # 64 uneven frames as one batch
+def batch_leg(torch, ih, synth, args, fixed=False):
+    """64 uneven frames (320x240 to 2048x2048, 8-64 bins) built and searched
+    (4,096 candidates each) as one batch: phased launches replayed from a HIP
+    graph, the cooperative single launch eagerly and replayed from a graph,
+    against the same frames one call at a time."""
+    from paper_1711_01656_amd import tune
+    dev = torch.device("cuda:0")
+    fr_np = synth.config4()
     frames = []
     total = 0
-    for f in synth.config4():
+    for f in fr_np:
         g = torch.from_numpy(f.img).to(dev)
         frames.append(dict(img=g, bins=f.bins, value_bits=f.bits, tile=None,
                            origins=torch.from_numpy(f.origins).to(dev), win=(32, 32), tmpl_win=f.tmpl_win))
@@ -530,13 +780,21 @@ def config_legs(torch, ih, synth, fixed=False):
         batch.run("phased")
         torch.cuda.synchronize()
         ref = [b.clone() for b in batch.best]
-        t_graph = med(lambda: batch.run("phased"), 5)
+        t_graph = graph_median(torch, lambda: batch.run("phased"), 5)
         t_coop = float(np.median([time_calls(torch, lambda: batch.run("cooperative"), 5) for _ in range(3)]))
         same = all(torch.equal(a, b) for a, b in zip(ref, batch.best))
+        coop_graph = None
+        try:
+            coop_graph = round(graph_median(torch, lambda: batch.run("cooperative"), 5), 3)
+            same = same and all(torch.equal(a, b) for a, b in zip(ref, batch.best))
+        except Exception as e:          # capture refused by the runtime: reported as such
+            coop_graph = "capture failed: %s" % str(e).splitlines()[0][:160]
         per_layout[lay] = {"tile": repr(tile), "graph_phased_ms": round(t_graph, 3),
-                           "cooperative_ms": round(t_coop, 3),
+                           "cooperative_ms": round(t_coop, 3), "cooperative_graph_ms": coop_graph,
                            "gpxbins_per_s_graph": round(total / t_graph / 1e6, 2),
-                           "ih_write_gbs_graph": round(total * 4 / t_graph / 1e6, 1), "modes_agree": same}
+                           "ih_write_gbs_graph": round(total * 4 / t_graph / 1e6, 1),
+                           "frac_of_peak_graph": round(total * 4 / t_graph / 1e6 / HBM_PEAK_GBS, 4),
+                           "modes_agree": same}
         del batch, ref
         torch.cuda.empty_cache()
     seq = []
@@ -560,9 +818,30 @@ def config_legs(torch, ih, synth, fixed=False):
             ih.ih_pyramid_desc(o, tww, 3, out=d, layout="bhw")
             ih.ih_match_candidates(o, d, 32, 32, fr["origins"], 3, "chi2", dist=di, best=bb, layout="bhw")
 
-    t_seq = med(one_by_one, 3)
-    res["batch_64_uneven_frames"] = {"frames": len(frames), "ih_bytes": total * 4, "candidates_per_frame": 4096,
-                                     "layouts": per_layout, "one_call_per_frame_bhw_ms": round(t_seq, 3)}
+    t_seq = graph_median(torch, one_by_one, 3)
+    del seq
+    torch.cuda.empty_cache()
+    res = {"frames": len(frames), "ih_bytes": total * 4, "candidates_per_frame": 4096, "layouts": per_layout,
+           "one_call_per_frame_bhw_ms": round(t_seq, 3)}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_config4(fr_np)
+    return res
+
+
+def config_legs(torch, ih, synth, args):
+    """Every workload other than the headline step, each with its CPU oracle
+    baseline where the oracle covers it."""
+    res = {"640x480_u8_32bins": config1_leg(torch, ih, synth, args)}
+    torch.cuda.empty_cache()
+    res["1920x1080x112_moments"] = config2_leg(torch, ih, synth, args)
+    torch.cuda.empty_cache()
+    res["batch_64_uneven_frames"] = batch_leg(torch, ih, synth, args, args.fixed_tiles)
+    torch.cuda.empty_cache()
+    if not args.no_rows:
+        res["phog_1920x1080_16bins"] = phog_leg(torch, ih, synth)
+        res["median_768x576_256bins"] = median_leg(torch, ih, synth)
+        res["swih_kernels_1920x1080x112"] = kernels_leg(torch, ih, synth)
+        res["camshift_1280x720"] = camshift_leg(torch, ih, synth)
     return res
 
 
@@ -607,18 +886,56 @@ def search_cost_vs_targets(torch, trk, lp, tr, net, frame, box0, counts=(1, 4, 1
     return out
 
 
+def cpu_tracker(frames_np, box0, ex_origins, min_seconds=6.0, threads=0):
+    """The oracle's exhaustive search (frame histogram by the Alg. 5
+    recurrence, 65x65 candidates scored by direct counting, fixed frame-0
+    template) on frames of the video, each from the GPU exhaustive track's
+    previous origin, until min_seconds have passed; frames per second."""
+    import oracle
+    oracle.set_threads(threads)
+    h, w = int(box0[2]), int(box0[3])
+    tmpl = oracle.pyramid_desc_direct(frames_np[0], 16, 8, [list(box0)], 3)[0]
+    d = np.arange(-32, 33)
+    n, t = 0, 0.0
+    agree = 0
+    t0 = time.perf_counter()
+    for f in range(1, len(frames_np)):
+        if n and time.perf_counter() - t0 >= min_seconds:
+            break
+        prev = ex_origins[f - 1]
+        origins = np.stack(np.meshgrid(prev[0] + d, prev[1] + d, indexing="ij"), -1).reshape(-1, 2).astype(np.int32)
+        a = time.perf_counter()
+        hist = oracle.ih(frames_np[f], 16, 8)
+        dist = oracle.match_direct(frames_np[f], 16, 8, tmpl, h, w, 3, origins, "chi2")[0]
+        t += time.perf_counter() - a
+        best = int(np.argmin(np.where(np.isfinite(dist), dist, np.inf)))
+        agree += int(tuple(origins[best]) == tuple(ex_origins[f]))
+        n += 1
+        del hist
+    cores = oracle.num_threads()
+    oracle.set_threads(0)
+    return {"value": round(n / t, 2), "unit": "frames/s (exhaustive)", "cores": cores, "kind": "oracle",
+            "sample": "%d frames of the 1280x720 video: histogram of the frame + 4,225-candidate search each; "
+                      "the oracle's pick equals the GPU exhaustive track on %d of them" % (n, agree),
+            "host": _host()}
+
+
+# the learned search's settings, chosen on validation sequences (seeds
+# 600-607) disjoint from the training and benchmark sequences
+TRACKER_TAU, TRACKER_ROUNDS, TRACKER_Q = 0.1, 2, 2
+
+
 def tracker_leg(torch, args):
     """Learned vs exhaustive tracking on the 1280x720, 300-frame video."""
     from paper_1711_01656_amd import proposal as lp
     from paper_1711_01656_amd import tracker as trk
-    from paper_1711_01656_amd import tune
     from synth.video import config5, render, training_videos
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     # training data: independent 640x360 sequences labelled by the exhaustive search
     th, tw, tf = 360, 640, 16
-    ttr = trk.PyramidTracker(th, tw)
+    ttr = trk.PyramidTracker(th, tw, region=True)
     stack, parts = [], []
     for i, v in enumerate(training_videos(args.train_videos, tf, th, tw)):
         f = torch.from_numpy(render(v, threads=16)).to(dev)
@@ -628,7 +945,6 @@ def tracker_leg(torch, args):
     stack = torch.cat(stack)
     samples = trk.concat(parts)
     t_data = time.perf_counter() - t0
-    # chosen on validation sequences (seeds 600-607) disjoint from this video
     batch, lr, jitter = 64, 0.01, 20
     net = lp.ProposalNet(lp.init_params(1), max_batch=batch)
     torch.cuda.synchronize()
@@ -641,14 +957,15 @@ def tracker_leg(torch, args):
           file=sys.stderr, flush=True)
 
     video = config5()
-    frames = torch.from_numpy(render(video, threads=16)).to(dev)
+    frames_np = render(video, threads=16)
+    frames = torch.from_numpy(frames_np).to(dev)
     box0 = video.target_box(0)
-    cfg, _ = tune.tune(frames[0], 16, moments=False, layout="hwb", reps=3)
-    tr = trk.PyramidTracker(video.H, video.W, cfg=cfg)
+    tr_f = trk.PyramidTracker(video.H, video.W)                  # the frame's histogram (the thesis's tracker)
+    tr_r = trk.PyramidTracker(video.H, video.W, region=True)     # the search region's histogram
     prior = trk.distance_prior().to(dev)
-    tau = 0.25
+    tau, rounds, q = TRACKER_TAU, TRACKER_ROUNDS, TRACKER_Q
 
-    def timed(learned=None, graph=True):
+    def timed(tr, learned=None, graph=True):
         """Free-running track on the device (one captured step replayed per
         frame); frames per second of wall time, template set-up excluded."""
         trk.track_device(frames[:8], box0, tr, learned, graph=graph)          # warm-up
@@ -658,44 +975,49 @@ def tracker_leg(torch, args):
         torch.cuda.synchronize()
         return res, (len(frames) - 1) / (time.perf_counter() - a)
 
-    ex, fps_ex = timed()
-    learned = trk.LearnedTracker(tr, net, k=64, tau=tau)
-    free, fps_l = timed(learned)
-    base = trk.LearnedTracker(tr, None, k=64, tau=tau, prior_logits=prior)
-    free_b, fps_b = timed(base)
-    _, fps_ex_eager = timed(None, graph=False)
-    _, fps_l_eager = timed(learned, graph=False)
+    ex, fps_ex = timed(tr_f)
+    ex_r, fps_ex_r = timed(tr_r)
+    learned = trk.LearnedTracker(tr_r, net, k=64, tau=tau, refine_rounds=rounds, refine_q=q)
+    free, fps_l = timed(tr_r, learned)
+    base = trk.LearnedTracker(tr_r, None, k=64, tau=tau, prior_logits=prior, refine_rounds=rounds, refine_q=q)
+    free_b, fps_b = timed(tr_r, base)
+    unref = trk.LearnedTracker(tr_r, net, k=64, tau=tau)
     # per-frame agreement: every search starts from the exhaustive trajectory
-    forced = trk.track(frames, box0, tr, learned, teacher=ex)
-    forced_b = trk.track(frames, box0, tr, base, teacher=ex)
+    forced = trk.track(frames, box0, tr_r, learned, teacher=ex)
+    forced_b = trk.track(frames, box0, tr_r, base, teacher=ex)
+    forced_u = trk.track(frames, box0, tr_r, unref, teacher=ex)
     held = trk.samples_from_track(ex, box0[2:])
 
     def agree(a, b, px=0):
         return float(np.mean(np.all(np.abs(a.origins[1:] - b.origins[1:]) <= px, axis=1)))
 
-    # network forward alone (B = 1), timed on the device
     x = net.crop(frames[1], torch.tensor([[box0[0] + box0[2] // 2, box0[1] + box0[3] // 2]], dtype=torch.int32,
                                          device=dev))
     fwd_ms = time_calls(torch, lambda: net.forward(x), 50)
-    scaling = search_cost_vs_targets(torch, trk, lp, tr, net, frames[1], box0)
-    return {
-        "workload": "1280x720 synthetic video, 300 frames, 7 channels x 16 bins; 65x65 offsets; top-64 learned",
+    scaling = search_cost_vs_targets(torch, trk, lp, tr_f, net, frames[1], box0)
+    res = {
+        "workload": "1280x720 synthetic video, 300 frames, 7 channels x 16 bins; 65x65 offsets; top-64 learned "
+                    "+ %d rounds of %dx%d local refinement; exhaustive fallback" % (rounds, 2 * q + 1, 2 * q + 1),
         "fps_exhaustive": round(fps_ex, 1),
+        "fps_exhaustive_region_ih": round(fps_ex_r, 1),
         "fps_learned": round(fps_l, 1),
         "fps_no_network": round(fps_b, 1),
-        "fps_exhaustive_eager": round(fps_ex_eager, 1),
-        "fps_learned_eager": round(fps_l_eager, 1),
-        "tau": tau,
+        "fps_learned_over_exhaustive": round(fps_l / fps_ex, 3),
+        "fps_learned_over_exhaustive_region_ih": round(fps_l / fps_ex_r, 3),
+        "region_ih_track_equals_frame_ih_track": bool(np.array_equal(ex.origins, ex_r.origins)
+                                                      and np.array_equal(ex.dists, ex_r.dists)),
+        "tau": tau, "refine_rounds": rounds, "refine_window": 2 * q + 1,
         "agreement_per_frame": agree(forced, ex),
         "agreement_per_frame_no_network": agree(forced_b, ex),
+        "agreement_per_frame_without_refinement": agree(forced_u, ex),
         "fallback_rate": float(forced.fallback[1:].mean()),
         "fallback_rate_no_network": float(forced_b.fallback[1:].mean()),
+        "fallback_rate_without_refinement": float(forced_u.fallback[1:].mean()),
         "recall_top64": round(trk.recall(net, frames, held), 4),
         "recall_top64_no_network": round(trk.recall(prior, frames, held), 4),
         "free_running_within_1px": agree(free, ex, 1),
         "free_running_within_1px_no_network": agree(free_b, ex, 1),
         "free_running_fallback_rate": float(free.fallback[1:].mean()),
-        "free_running_fallback_rate_no_network": float(free_b.fallback[1:].mean()),
         "network_forward_ms": round(fwd_ms, 4),
         "search_ms_vs_targets": scaling,
         "training": {"samples": int(len(samples.frame)), "steps": args.train_steps, "batch": batch,
@@ -703,8 +1025,10 @@ def tracker_leg(torch, args):
                      "seconds": round(t_train, 2), "ms_per_step": round(t_train / args.train_steps * 1e3, 3),
                      "loss_first": round(float(np.mean(losses[:20])), 4),
                      "loss_last": round(float(np.mean(losses[-100:])), 4)},
-        "ih_tile": repr(cfg),
     }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_tracker(frames_np, box0, ex.origins)
+    return res
 
 
 def main():
@@ -722,7 +1046,7 @@ def main():
         print(json.dumps(tracker_leg(torch, args)), flush=True)
         return
     if args.workloads_only:
-        print(json.dumps(config_legs(torch, ih, synth, args.fixed_tiles)), flush=True)
+        print(json.dumps(config_legs(torch, ih, synth, args)), flush=True)
         return
     if args.camshift_only:
         print(json.dumps(camshift_leg(torch, ih, synth)), flush=True)
@@ -744,162 +1068,91 @@ def main():
         return
 
     dev = torch.device("cuda:0")
-    w = synth.config2()
-    rng_win = np.random.default_rng(205)
-    C, H, W, P, bins = w.C, w.H, w.W, w.P, w.bins
+    w = synth.config3()
+    H, W, P = w.H, w.W, w.P
     img = torch.from_numpy(w.img).to(dev)
-    wins = torch.from_numpy(w.windows).to(dev)
+    rects = torch.from_numpy(w.rects).to(dev)
+    origins = torch.from_numpy(w.origins).to(dev)
+    tmpl_win = torch.tensor([list(w.tmpl_win)], dtype=torch.int32, device=dev)
+    alg = P * H * W * 4 + H * W * 2          # int32 histogram written, u16 image read
+    wl = "8192x8192 u16 64 bins"
+    cfgs = {"hwb": None, "bhw": None}
     if args.tile:
-        cfg = ih.TileCfg(*(int(v) for v in args.tile.split(",")))
-    else:
-        from paper_1711_01656_amd import tune
-        cfg, _ = tune.tune(img, bins, moments=True, layout=args.layout, reps=3)
-        print("autotuned tile %r" % cfg, file=sys.stderr, flush=True)
-    # template: a 32x32 window of the frame; candidates: 129 x 129 origins around it
-    tr = int(rng_win.integers(64, H - 32 - 64))
-    tc = int(rng_win.integers(64, W - 32 - 64))
-    origins_np = synth.grid_origins(tr - 64, tc - 64, 129, 129)
-    origins = torch.from_numpy(origins_np).to(dev)
-    tmpl_win = torch.tensor([[tr, tc, 32, 32]], dtype=torch.int32, device=dev)
-
-    step = Step(ih, torch, w, img, wins, origins, tmpl_win, args.layout, cfg)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print("warmup done", file=sys.stderr, flush=True)
-
-    # timed region; the write-out kernel of each build is bracketed by events
-    # recorded by the library on the same stream
-    ev_k = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in range(args.steps)]
-    for a, b in ev_k:          # torch creates the HIP event on first record
-        a.record()
-        b.record()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t0.record()
-    for k in range(args.steps):
-        ih.ih_profile_events(*ev_k[k])
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ih.ih_profile_events(None, None)
-    eager_ms = t0.elapsed_time(t1) / args.steps
-    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_k]))
-    print("eager: %d steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
-
-    # the same step captured once as a HIP graph and replayed: each trial times
-    # exactly --steps replays between synchronisations; the median trial is
-    # reported, and every replayed result is checked against the eager one
-    ref = [t.clone() for t in (step.out, step.mx, step.my, step.wq, step.rq, step.dist, step.best)]
-    graph = torch.cuda.CUDAGraph()
-    torch.cuda.synchronize()
-    with torch.cuda.graph(graph):
-        step()
-    for _ in range(args.warmup):
-        graph.replay()
-    trials = []
-    for _ in range(max(1, args.trials)):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record()
-        for _ in range(args.steps):
-            graph.replay()
-        b.record()
-        torch.cuda.synchronize()
-        trials.append(a.elapsed_time(b) / args.steps)
-    same = all(torch.equal(x, y) for x, y in zip(ref, (step.out, step.mx, step.my, step.wq, step.rq, step.dist,
-                                                       step.best)))
-    if not same:
-        raise SystemExit("graph replay results differ from the eager step")
-    del ref
-    ms = float(np.median(trials))
-    print("graph: %d trials of %d replays, median %.4f ms/step" % (len(trials), args.steps, ms), file=sys.stderr,
-          flush=True)
+        cfgs[args.layout] = ih.TileCfg(*(int(v) for v in args.tile.split(",")))
+    layouts = [args.layout] + ([] if args.no_other else [lo for lo in ("hwb", "bhw") if lo != args.layout])
+    per = {}
+    for lay in layouts:
+        step = Step3(ih, torch, w, img, rects, origins, tmpl_win, lay, cfgs[lay])
+        n = args.steps if lay == args.layout else max(3, min(args.steps, 10))
+        per[lay] = measure_step(torch, ih, step, n, args.warmup, args.trials if lay == args.layout else 3, alg, wl)
+        per[lay]["gpxbins_per_s"] = round(H * W * P / per[lay]["ms_per_step"] / 1e6, 3)
+        per[lay]["rect_queries_per_s"] = round(rects.shape[0] / per[lay]["stages_ms"]["rect"] * 1e3, 1)
+        print("%s: step %.4f ms, build %.4f ms (%.3f of peak)" % (lay, per[lay]["ms_per_step"],
+                                                                 per[lay]["stages_ms"]["build"],
+                                                                 per[lay]["build_roofline"]["frac"]),
+              file=sys.stderr, flush=True)
+        del step
+        torch.cuda.empty_cache()
+    del img, rects, origins
 
     # measured stream-write ceiling: a 2 GiB device fill, best of 5
     fill = torch.empty(1 << 29, dtype=torch.int32, device=dev)
     fill_ms = min(time_calls(torch, lambda: fill.fill_(1), 3) for _ in range(5))
     write_peak = fill.numel() * 4 / (fill_ms * 1e-3) / 1e9
     del fill
-
-    stages = {s: round(time_calls(torch, getattr(step, s), 5), 4) for s in ("build", "weighted", "rect", "match")}
-    stages["final_kernel"] = round(k_ms, 4)
-    other = None
-    if not args.no_other:
-        lo = "bhw" if args.layout == "hwb" else "hwb"
-        from paper_1711_01656_amd import tune
-        ocfg, _ = tune.tune(img, bins, moments=True, layout=lo, reps=3)
-        so = Step(ih, torch, w, img, wins, origins, tmpl_win, lo, ocfg)
-        oms = time_calls(torch, so, 5)
-        other = {"layout": lo, "tile": repr(ocfg), "ms_per_step": round(oms, 4),
-                 "stages_ms": {s: round(time_calls(torch, getattr(so, s), 5), 4)
-                               for s in ("build", "weighted", "rect", "match")}}
-        del so
-
     if args.copy_calib:
         copy_calibration(torch, args.copy_calib)
 
-    alg_bytes = 3 * P * H * W * 4 + C * H * W   # three int32 tensors written, u8 image read
-    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    gpx = H * W * P / (ms * 1e-3) / 1e9
-    nq = int(wins.shape[0])
+    head = per[args.layout]
+    ms = head["ms_per_step"]
+    dk = head["dominant_kernel"]
     res = {
         "metric": METRIC,
-        "value": round(gpx, 3),
+        "value": round(H * W * P / (ms * 1e-3) / 1e9, 3),
         "unit": "Gpx·bins/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
-        "timing": {"graph_trials_ms": [round(t, 4) for t in trials], "eager_ms_per_step": round(eager_ms, 4),
-                   "graph_replays_match_eager": same},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": "1920x1080 frame, 7 u8 channels x 16 bins (112 planes), count + 2 moment IHs; "
-                        "100k weighted + 100k plain window queries (16-256 px); 129x129 pyramid chi2 search",
-            "H": H, "W": W, "channels": C, "bins_per_channel": bins, "planes": P,
-            "weighted_queries": nq, "rect_queries": nq, "candidates": int(origins.shape[0]),
-            "layout": args.layout, "tile": repr(cfg),
+            "workload": "8192x8192 u16 aerial-style frame, 64 bins (17.2 GB int32 integral histogram); 1M "
+                        "rectangle queries (sides 4-200); 3-level pyramid chi2 search of a 32x32 template over "
+                        "129x129 candidate origins",
+            "H": H, "W": W, "channels": 1, "bins": w.bins, "planes": P, "rect_queries": int(w.rects.shape[0]),
+            "candidates": int(w.origins.shape[0]), "layout": args.layout, "build": head["build"],
+            "cfg": head["cfg"],
         },
-        "stages_ms": stages,
-        "build_gpxbins_per_s": round(H * W * P / (stages["build"] * 1e-3) / 1e9, 3),
-        "weighted_queries_per_s": round(nq / (stages["weighted"] * 1e-3), 1),
-        "rect_queries_per_s": round(nq / (stages["rect"] * 1e-3), 1),
-        "other_layout": other,
         "roofline": {
             "bound": "hbm",
-            "kernel": "integral-histogram write-out (%s, with moments)" % args.layout,
-            "achieved": round(achieved, 1),
+            "kernel": head["build_roofline"]["kernel"],
+            "achieved": head["build_roofline"]["achieved"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": head["build_roofline"]["frac"],
+            "traffic": dk["traffic"],
+            "alg_bytes_per_launch": alg,
+            "dominant_kernel": {"kernel": dk["kernel"], "achieved": dk["achieved"], "frac": dk["frac"],
+                                "ms": dk["ms"]},
             "measured_write_peak": round(write_peak, 1),
-            "frac_of_measured_write_peak": round(achieved / write_peak, 4),
-            "traffic": PROFILED_TRAFFIC.get((args.layout, repr(cfg))),
-            "alg_bytes_per_launch": alg_bytes,
+            "frac_of_measured_write_peak": round(head["build_roofline"]["achieved"] / write_peak, 4),
         },
+        "layouts": per,
     }
     if not args.no_configs:
         print("other workloads ...", file=sys.stderr, flush=True)
-        del step, graph
-        torch.cuda.empty_cache()
-        res["workloads"] = config_legs(torch, ih, synth, args.fixed_tiles)
+        res["workloads"] = config_legs(torch, ih, synth, args)
     if not args.no_tracker:
         print("tracker ...", file=sys.stderr, flush=True)
         res["tracker"] = tracker_leg(torch, args)
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(w, origins_np, (tr, tc, 32, 32))
-        res["cpu_baseline_1thread"] = cpu_baseline(w, origins_np, (tr, tc, 32, 32), min_seconds=1.0, threads=1)
+        res["cpu_baseline"] = cpu_config3(w)
+        res["cpu_baseline_1thread"] = cpu_config3(w, min_seconds=8.0, threads=1)
     print(json.dumps(res), flush=True)
 
 

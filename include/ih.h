@@ -545,6 +545,12 @@ int ih_local_median(const int32_t *jih, int32_t C, int32_t bins, int32_t H,
                     int32_t win_w, int32_t *median, void *stream);
 
 /*
+ * ih_build_passes - the number of passes (1 or 3) ih_build uses for a
+ * layout and configuration (cfg may be NULL), or IH_ERR_INVALID_ARG.
+ */
+int ih_build_passes(int32_t layout, const ih_tile_cfg *cfg);
+
+/*
  * ih_set_lookback_patience - look-back policy of the single-pass build
  * (IH_PASSES_ONE), for every later build in this process.  A band worker
  * polls the flag of the band directly above at most `polls` times for its
@@ -562,7 +568,8 @@ int ih_set_lookback_patience(int32_t polls);
  * ih_profile_events - profiling hook.  When both are non-NULL (hipEvent_t),
  * every later build on this thread (ih_build, ih_build_weighted,
  * ih_build_moments2, ih_jih_update) records `start` on its stream just
- * before its final write-out kernel and `stop` just after it, so that the
+ * before its dominant kernel (the final write-out of a three-pass build, the
+ * band kernel of a single-pass one) and `stop` just after it, so that the
  * caller can time that kernel alone.  Passing NULL, NULL turns it off.
  */
 int ih_profile_events(void *start, void *stop);

@@ -216,6 +216,34 @@ int ih_track_commit(ih_track_state *st, const float *kdist,
                     const int32_t *exh_best, int32_t radius, int32_t *rec,
                     int32_t n_rec, void *stream);
 
+/* Search region of the frame (C x H x W uint8): the (2 radius + win_h) x
+   (2 radius + win_w) block around st->origin that holds every candidate
+   window of the offsets -radius..radius, shifted inside the frame (it must
+   fit: IH_ERR_RANGE otherwise), is copied to region [C][rh][rw], and
+   rbase [2] receives st->origin in region coordinates.  The candidate search
+   over the region's integral histogram with origins rbase + offset gives the
+   same distances as over the frame's (windows inside the frame lie inside the
+   region; windows leaving the frame leave the region), so a tracker need not
+   build the frame's whole histogram. */
+int ih_track_region(const void *frame, int32_t C, int32_t H, int32_t W,
+                    const ih_track_state *st, int32_t radius, int32_t win_h,
+                    int32_t win_w, void *region, int32_t *rbase, void *stream);
+
+/* Local refinement of the best proposal.  refine_origins writes the origins
+   base + offset of the (2q+1)^2 offsets around idx[kbest[0]] (row-major; an
+   offset outside -radius..radius gets an origin outside every frame; all of
+   them when kbest[0] < 0).  After ih_match_candidates over those origins
+   (ndist, nbest), refine_pick keeps the better of the current best and the
+   neighbourhood's best (smaller distance, or equal distance at a lower offset
+   index, the exhaustive search's tie rule) and stores it in slot 0:
+   idx[0] = offset index, kdist[0] = distance, kbest[0] = 0.  1 <= q <= 32. */
+int ih_track_refine_origins(const int32_t *idx, const int32_t *kbest, int32_t q,
+                            int32_t radius, const int32_t *base,
+                            int32_t *origins, void *stream);
+int ih_track_refine_pick(int32_t *idx, float *kdist, int32_t *kbest,
+                         const float *ndist, const int32_t *nbest, int32_t q,
+                         int32_t radius, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -235,6 +235,11 @@ extern "C" size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32
   return std::max(one, g.words * 4);
 }
 
+extern "C" int ih_build_passes(int32_t layout, const ih_tile_cfg *cfg) {
+  if (layout != IH_BHW && layout != IH_HWB) return set_error(IH_ERR_INVALID_ARG, "layout %d unknown", layout);
+  return use_onepass(layout, cfg) ? 1 : 3;
+}
+
 // Polls of the band above before a single-pass worker publishes its own
 // aggregate and looks further up (-1: wait for the band above).
 static int g_patience = -1;
@@ -326,7 +331,7 @@ static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const u
     const bool aligned = ((uintptr_t)ih % 16 == 0) && ((uintptr_t)mom_x % 16 == 0) && ((uintptr_t)mom_y % 16 == 0);
     OpArgs oa{img, ih, mom_x, mom_y, reinterpret_cast<uint32_t *>(ws), value_bits,
               (W % og.CPL == 0 && aligned) ? 1 : 0, g_patience};
-    return launch_onepass(og, dtype, oa, as_stream(stream));
+    return launch_onepass(og, dtype, oa, as_stream(stream), g_hook.start, g_hook.stop);
   }
   if (wt && cfg && cfg->passes == IH_PASSES_ONE)
     return set_error(IH_ERR_UNSUPPORTED, "the weighted build has no single-pass form");

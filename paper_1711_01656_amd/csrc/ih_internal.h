@@ -153,7 +153,10 @@ struct OpArgs {
 
 int make_op_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, const ih_tile_cfg *cfg,
                  OpGeom *g);
-int launch_onepass(const OpGeom &g, int dtype, const OpArgs &a, hipStream_t s);
+// Enqueues the single-pass build; when start/stop are set they are recorded
+// just before and after its band kernel (after the flag-clearing launch).
+int launch_onepass(const OpGeom &g, int dtype, const OpArgs &a, hipStream_t s, hipEvent_t start = nullptr,
+                   hipEvent_t stop = nullptr);
 
 // LDS budget of the tile-histogram pass of the stand-alone build (bytes).
 constexpr int kLdsBudget = 64 * 1024;

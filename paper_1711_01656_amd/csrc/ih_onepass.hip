@@ -449,7 +449,7 @@ int make_op_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
   return IH_OK;
 }
 
-int launch_onepass(const OpGeom &g, int dtype, const OpArgs &a, hipStream_t s) {
+int launch_onepass(const OpGeom &g, int dtype, const OpArgs &a, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   op_fn fn = dtype == IH_U8 ? (g.mom ? pick_op_t<uint8_t, true>(g.CPL, g.PG) : pick_op_t<uint8_t, false>(g.CPL, g.PG))
                             : (g.mom ? pick_op_t<uint16_t, true>(g.CPL, g.PG)
                                      : pick_op_t<uint16_t, false>(g.CPL, g.PG));
@@ -460,9 +460,12 @@ int launch_onepass(const OpGeom &g, int dtype, const OpArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_op_init, dim3((unsigned)iblocks), dim3(256), 0, s, a.ws, g.off_flag, nflags);
   if ((e = hip_check(hipGetLastError(), "single-pass init launch"))) return e;
   const int64_t workers = (int64_t)g.nB * g.nG;
+  if (start && (e = hip_check(hipEventRecord(start, s), "profile start"))) return e;
   hipLaunchKernelGGL(fn, dim3((unsigned)((workers + kOpWaves - 1) / kOpWaves)), dim3(64 * kOpWaves), op_lds(g), s,
                      a, g);
-  return hip_check(hipGetLastError(), "single-pass launch");
+  if ((e = hip_check(hipGetLastError(), "single-pass launch"))) return e;
+  if (stop && (e = hip_check(hipEventRecord(stop, s), "profile stop"))) return e;
+  return IH_OK;
 }
 
 }  // namespace ih

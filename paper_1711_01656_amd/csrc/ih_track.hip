@@ -98,9 +98,119 @@ __global__ void k_track_commit(ih_track_state *__restrict__ st, const float *__r
   st->frame = f + 1;
 }
 
+// Search region of the current frame: the (2 radius + win) x (2 radius + win)
+// block of pixels that every candidate window around the previous origin can
+// touch, shifted inside the frame.  region [C][rh][rw] gets those pixels;
+// rbase [2] the previous origin in region coordinates, so that candidate
+// origins rbase + offset address the region's integral histogram.  Every
+// candidate window inside the frame lies inside the region, and every window
+// that leaves the frame also leaves the region, so the search over the
+// region's histogram equals the search over the frame's.
+__global__ void k_track_region(const uint8_t *__restrict__ frame, int C, int H, int W,
+                               const ih_track_state *__restrict__ st, int radius, int rh, int rw,
+                               uint8_t *__restrict__ region, int32_t *__restrict__ rbase) {
+  const int r0 = min(max(st->origin[0] - radius, 0), H - rh);
+  const int c0 = min(max(st->origin[1] - radius, 0), W - rw);
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) {
+    rbase[0] = st->origin[0] - r0;
+    rbase[1] = st->origin[1] - c0;
+  }
+  const int64_t n = (int64_t)C * rh * rw;
+  for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ch = i / ((int64_t)rh * rw);
+    const int rem = (int)(i - ch * rh * rw);
+    const int y = rem / rw, x = rem - y * rw;
+    region[i] = frame[(ch * H + r0 + y) * W + c0 + x];
+  }
+}
+
+// Local refinement of the best candidate found so far (idx[kbest[0]],
+// kdist[kbest[0]]): the origins of the (2q+1)^2 offsets around it, in
+// row-major order, those outside the search range set outside every frame.
+__global__ void k_track_refine_origins(const int32_t *__restrict__ idx, const int32_t *__restrict__ kbest, int q,
+                                       int radius, const int32_t *__restrict__ base, int32_t *__restrict__ out) {
+  const int m = 2 * q + 1, n = 2 * radius + 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m * m) return;
+  const int b = kbest[0];
+  int32_t r = kFar, c = kFar;
+  if (b >= 0) {
+    const int off = idx[b];
+    const int oy = off / n - radius + i / m - q, ox = off % n - radius + i % m - q;
+    if (oy >= -radius && oy <= radius && ox >= -radius && ox <= radius) {
+      r = base[0] + oy;
+      c = base[1] + ox;
+    }
+  }
+  out[2 * i] = r;
+  out[2 * i + 1] = c;
+}
+
+// Moves the best candidate to the neighbourhood's best (nbest, ndist) when
+// that is smaller, or equal at a lower offset index (the exhaustive search's
+// tie rule), and stores the result in slot 0: idx[0], kdist[0], kbest[0] = 0.
+__global__ void k_track_refine_pick(int32_t *__restrict__ idx, float *__restrict__ kdist, int32_t *__restrict__ kbest,
+                                    const float *__restrict__ ndist, const int32_t *__restrict__ nbest, int q,
+                                    int radius) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const int m = 2 * q + 1, n = 2 * radius + 1;
+  const int b = kbest[0];
+  if (b < 0) return;
+  int off = idx[b];
+  float d = kdist[b];
+  const int nb = nbest[0];
+  if (nb >= 0) {
+    const int noff = off + (nb / m - q) * n + (nb % m - q);
+    const float nd = ndist[nb];
+    if (nd < d || (nd == d && noff < off)) {
+      off = noff;
+      d = nd;
+    }
+  }
+  idx[0] = off;
+  kdist[0] = d;
+  kbest[0] = 0;
+}
+
 }  // namespace ih
 
 using namespace ih;
+
+extern "C" int ih_track_region(const void *frame, int32_t C, int32_t H, int32_t W, const ih_track_state *st,
+                               int32_t radius, int32_t win_h, int32_t win_w, void *region, int32_t *rbase,
+                               void *stream) {
+  if (!frame || !st || !region || !rbase || C < 1 || H < 1 || W < 1 || radius < 0 || win_h < 1 || win_w < 1)
+    return set_error(IH_ERR_INVALID_ARG, "bad track-region arguments");
+  const int64_t rh = 2 * (int64_t)radius + win_h, rw = 2 * (int64_t)radius + win_w;
+  if (rh > H || rw > W)
+    return set_error(IH_ERR_RANGE, "search region %lldx%lld larger than the %dx%d frame", (long long)rh,
+                     (long long)rw, H, W);
+  const int64_t n = (int64_t)C * rh * rw;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_track_region, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), (const uint8_t *)frame,
+                     C, H, W, st, radius, (int)rh, (int)rw, (uint8_t *)region, rbase);
+  return hip_check(hipGetLastError(), "track region launch");
+}
+
+extern "C" int ih_track_refine_origins(const int32_t *idx, const int32_t *kbest, int32_t q, int32_t radius,
+                                       const int32_t *base, int32_t *origins, void *stream) {
+  if (!idx || !kbest || !base || !origins || q < 1 || q > 32 || radius < 0 || radius > 4096)
+    return set_error(IH_ERR_INVALID_ARG, "bad track-refine arguments");
+  const int m = 2 * q + 1;
+  hipLaunchKernelGGL(k_track_refine_origins, dim3((m * m + 255) / 256), dim3(256), 0, as_stream(stream), idx, kbest,
+                     q, radius, base, origins);
+  return hip_check(hipGetLastError(), "track refine-origins launch");
+}
+
+extern "C" int ih_track_refine_pick(int32_t *idx, float *kdist, int32_t *kbest, const float *ndist,
+                                    const int32_t *nbest, int32_t q, int32_t radius, void *stream) {
+  if (!idx || !kdist || !kbest || !ndist || !nbest || q < 1 || q > 32 || radius < 0 || radius > 4096)
+    return set_error(IH_ERR_INVALID_ARG, "bad track-refine arguments");
+  hipLaunchKernelGGL(k_track_refine_pick, dim3(1), dim3(64), 0, as_stream(stream), idx, kdist, kbest, ndist, nbest,
+                     q, radius);
+  return hip_check(hipGetLastError(), "track refine-pick launch");
+}
 
 extern "C" int ih_track_fetch(const void *stack, int64_t frame_bytes, int32_t n_frames, const ih_track_state *st,
                               void *dst, void *stream) {

@@ -67,6 +67,7 @@ SIGNATURES = {
                                            _P, _P, _P]),
     "ih_profile_events": (ctypes.c_int, [_P, _P]),
     "ih_set_lookback_patience": (ctypes.c_int, [_I32]),
+    "ih_build_passes": (ctypes.c_int, [_I32, _P]),
     "ih_batch_plan_bytes": (_SZ, [_I32]),
     "ih_batch_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _SZ, ctypes.POINTER(_SZ)]),
     "ih_build_batch": (ctypes.c_int, [_P, _P, _P, _SZ, _I32, _P]),
@@ -86,6 +87,9 @@ SIGNATURES = {
     "ih_track_gate": (ctypes.c_int, [_P, _P, _P, _P, _I32, ctypes.c_double, _P, _P, _P]),
     "ih_track_commit": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _I32, _P]),
     "ih_track_fetch": (ctypes.c_int, [_P, _I64, _I32, _P, _P, _P]),
+    "ih_track_region": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P, _P, _P]),
+    "ih_track_refine_origins": (ctypes.c_int, [_P, _P, _I32, _I32, _P, _P, _P]),
+    "ih_track_refine_pick": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I32, _P]),
 }
 
 
@@ -123,6 +127,13 @@ def status(ws: torch.Tensor) -> int:
     """The IH_STATUS_* bits a build left in the first word of its workspace
     (synchronises with the device)."""
     return int(ws.view(torch.uint8)[:4].view(torch.int32).item()) & 0xFFFFFFFF
+
+
+def build_passes(layout: str = "bhw", cfg: Optional[TileCfg] = None) -> int:
+    """Passes (1 or 3) ih_build uses for this layout and configuration."""
+    n = lib().ih_build_passes(_layout(layout), ctypes.byref(cfg) if cfg is not None else None)
+    _check(0 if n > 0 else n, "ih_build_passes")
+    return n
 
 
 def set_lookback_patience(polls: int):

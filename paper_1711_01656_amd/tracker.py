@@ -8,12 +8,16 @@ tracker.  Two searches:
 
 * exhaustive: all 65 x 65 window offsets (-32..32 px per axis);
 * learned: the proposal network ranks the offsets from a crop centred on the
-  previous position, only the top k are scored exactly, and the exhaustive
-  search runs instead whenever the best of them scores worse than the margin
-  (1 + tau) d*, where d* is the distance accepted at the previous frame.
+  previous position, only the top k are scored exactly, the best of them is
+  optionally moved by a local search among its neighbouring offsets, and
+  the exhaustive search runs instead whenever the result scores worse than
+  the margin (1 + tau) d*, where d* is the distance accepted at the previous
+  frame.
 
-All scoring, network and index work runs in libih.so; the host reads back
-one index and one distance per search.
+Either search can run on the integral histogram of the whole frame (as the
+thesis's tracker does) or of the search region only.  All scoring, network
+and index work runs in libih.so with the target state on the device; the
+host reads the records back once.
 """
 from __future__ import annotations
 
@@ -33,65 +37,92 @@ N_OFF = lp.N_OFFSETS
 
 
 class PyramidTracker:
-    """Exhaustive pyramid-distance search over one frame size."""
+    """Exhaustive pyramid-distance search over one frame size.
+
+    With ``region`` the tracker never builds a whole frame's integral
+    histogram: per frame it copies the search region around the previous
+    origin (every candidate window of the 65 x 65 offsets, shifted inside the
+    frame) and builds that region's histogram; candidate origins are then
+    given in region coordinates.  Distances and the chosen window are the
+    same as with the frame's histogram."""
 
     def __init__(self, H: int, W: int, C: int = 7, bins: int = 16, levels: int = 3, metric: str = "chi2",
-                 layout: str = "hwb", cfg: Optional[TileCfg] = None, device="cuda"):
+                 layout: str = "hwb", cfg: Optional[TileCfg] = None, device="cuda", region: bool = False):
         self.H, self.W, self.C, self.bins, self.levels = H, W, C, bins, levels
-        self.metric, self.layout, self.cfg = metric, layout, cfg
+        self.metric, self.layout, self.cfg, self.region = metric, layout, cfg, region
         self.P = C * bins
         dev = torch.device(device)
         self.device = dev
-        self.ih = torch.empty(shape_of(self.P, H, W, layout), dtype=torch.int32, device=dev)
-        self.ws = torch.empty(max(1, workspace_size(H, W, C, bins, False, cfg, layout)), dtype=torch.uint8,
-                              device=dev)
+        self.ih = None
+        self.ws = None
+        if not region:
+            self._alloc(H, W)
         self.origins = torch.empty((N_OFF, 2), dtype=torch.int32, device=dev)
         self.dist = torch.empty(N_OFF, dtype=torch.float32, device=dev)
         self.best = torch.empty(1, dtype=torch.int32, device=dev)
-        self.base = torch.empty((1, 2), dtype=torch.int32, device=dev)
+        self.base = torch.empty((1, 2), dtype=torch.int32, device=dev)   # previous origin (frame coordinates)
+        self.sbase = self.base if not region else torch.empty((1, 2), dtype=torch.int32, device=dev)
         self.tmpl = None
         self.win = None
 
+    def _alloc(self, h, w):
+        self.ih = torch.empty(shape_of(self.P, h, w, self.layout), dtype=torch.int32, device=self.device)
+        self.ws = torch.empty(max(1, workspace_size(h, w, self.C, self.bins, False, self.cfg, self.layout)),
+                              dtype=torch.uint8, device=self.device)
+
     def build(self, feat: torch.Tensor):
+        """Integral histogram of a whole frame (frame mode)."""
         ih_build(feat, self.bins, out=self.ih, ws=self.ws, cfg=self.cfg, layout=self.layout)
 
     def set_template(self, feat0: torch.Tensor, box: Sequence[int]):
         """Template = pyramid descriptor of window box = (row, col, h, w) in feat0."""
-        self.build(feat0)
         wins = torch.tensor([list(box)], dtype=torch.int32, device=self.device)
-        self.tmpl = ih_pyramid_desc(self.ih, wins, self.levels, layout=self.layout).reshape(-1).clone()
+        if self.region:
+            full = ih_build(feat0, self.bins, cfg=None, layout=self.layout)
+            self.tmpl = ih_pyramid_desc(full, wins, self.levels, layout=self.layout).reshape(-1).clone()
+            del full
+            h, w = int(box[2]), int(box[3])
+            if self.win != (h, w):
+                self.rh, self.rw = 2 * RADIUS + h, 2 * RADIUS + w
+                self.reg = torch.empty((self.C, self.rh, self.rw), dtype=torch.uint8, device=self.device)
+                self._alloc(self.rh, self.rw)
+        else:
+            self.build(feat0)
+            self.tmpl = ih_pyramid_desc(self.ih, wins, self.levels, layout=self.layout).reshape(-1).clone()
         self.win = (int(box[2]), int(box[3]))
 
-    def set_base(self, origin):
-        self.base.copy_(torch.tensor([[int(origin[0]), int(origin[1])]], dtype=torch.int32))
+    def frame_step(self, cur: torch.Tensor, state: torch.Tensor):
+        """Enqueue this frame's histogram: of the whole frame, or of the search
+        region around state's origin (which also sets sbase)."""
+        if not self.region:
+            self.build(cur)
+            return
+        h, w = self.win
+        _check(lib().ih_track_region(_p(cur), self.C, self.H, self.W, _p(state), RADIUS, h, w, _p(self.reg),
+                                     _p(self.sbase), _stream(cur)), "ih_track_region")
+        ih_build(self.reg, self.bins, out=self.ih, ws=self.ws, cfg=self.cfg, layout=self.layout)
 
     def score(self, origins: torch.Tensor, dist: torch.Tensor, best: torch.Tensor):
         return ih_match_candidates(self.ih, self.tmpl, self.win[0], self.win[1], origins, self.levels,
                                    self.metric, dist, best, self.layout)
 
-    def exhaustive(self, origin):
-        """Best window origin among all offsets around origin, and its distance
-        (origin unchanged and +inf when no candidate lies inside the frame)."""
-        self.set_base(origin)
-        lp.lp_origins(self.base, RADIUS, out=self.origins)
-        self.score(self.origins, self.dist, self.best)
-        b = int(self.best.item())
-        if b < 0:
-            return (int(origin[0]), int(origin[1])), math.inf
-        dy, dx = lp.offset_of(b)
-        return (int(origin[0]) + int(dy), int(origin[1]) + int(dx)), float(self.dist[b].item())
-
 
 class LearnedTracker:
-    """Top-k proposals from the network, exact scoring, exhaustive fallback."""
+    """Top-k proposals from the network, exact scoring, optional local
+    refinement of the best proposal, exhaustive fallback."""
 
     def __init__(self, tracker: PyramidTracker, net: Optional[lp.ProposalNet], k: int = 64, tau: float = 0.25,
-                 prior_logits: Optional[torch.Tensor] = None):
+                 prior_logits: Optional[torch.Tensor] = None, refine_rounds: int = 0, refine_q: int = 2):
         """net=None with prior_logits ranks the offsets by a fixed score instead
-        of the network (the no-network baseline)."""
+        of the network (the no-network baseline).  refine_rounds rounds of the
+        local search move the best candidate to the best of the (2 refine_q + 1)^2
+        offsets around it."""
         if net is None and prior_logits is None:
             raise IHError("need a network or fixed prior logits")
+        if tracker.metric == "pmk":
+            raise IHError("the fallback rule needs a distance (chi2 or l1); pmk is a similarity")
         self.tr, self.net, self.k, self.tau = tracker, net, k, tau
+        self.rounds, self.q = int(refine_rounds), int(refine_q)
         dev = tracker.device
         self.prior = prior_logits
         self.idx = torch.empty((1, k), dtype=torch.int32, device=dev)
@@ -99,6 +130,10 @@ class LearnedTracker:
         self.kdist = torch.empty(k, dtype=torch.float32, device=dev)
         self.kbest = torch.empty(1, dtype=torch.int32, device=dev)
         self.center = torch.empty((1, 2), dtype=torch.int32, device=dev)
+        m = 2 * self.q + 1
+        self.norig = torch.empty((m * m, 2), dtype=torch.int32, device=dev)
+        self.ndist = torch.empty(m * m, dtype=torch.float32, device=dev)
+        self.nbest = torch.empty(1, dtype=torch.int32, device=dev)
 
     def propose(self, feat: torch.Tensor, origin=None):
         """Enqueue the ranking of the offsets; fills self.idx.  The crop is
@@ -115,20 +150,19 @@ class LearnedTracker:
         logits = self.net.forward(x)
         lp.lp_topk(logits.view(1, -1), self.k, self.idx)
 
-    def step(self, feat: torch.Tensor, origin, d_prev: float):
-        """(new origin, distance, fell_back, proposed offset indices on the host)."""
-        tr = self.tr
-        tr.set_base(origin)
-        self.propose(feat, origin)
-        lp.lp_origins(tr.base, RADIUS, idx=self.idx, out=self.korig)
+    def search(self, cur: torch.Tensor):
+        """Enqueue proposals, their exact scores and the local refinement."""
+        tr, L = self.tr, lib()
+        self.propose(cur)
+        lp.lp_origins(tr.sbase, RADIUS, idx=self.idx, out=self.korig)
         tr.score(self.korig, self.kdist, self.kbest)
-        b = int(self.kbest.item())
-        d = float(self.kdist[b].item()) if b >= 0 else math.inf
-        if b < 0 or not d <= (1.0 + self.tau) * d_prev:
-            o, d = tr.exhaustive(origin)
-            return o, d, True
-        dy, dx = lp.offset_of(int(self.idx[0, b].item()))
-        return (int(origin[0]) + int(dy), int(origin[1]) + int(dx)), d, False
+        s = _stream(cur)
+        for _ in range(self.rounds):
+            _check(L.ih_track_refine_origins(_p(self.idx), _p(self.kbest), self.q, RADIUS, _p(tr.sbase),
+                                             _p(self.norig), s), "ih_track_refine_origins")
+            tr.score(self.norig, self.ndist, self.nbest)
+            _check(L.ih_track_refine_pick(_p(self.idx), _p(self.kdist), _p(self.kbest), _p(self.ndist),
+                                          _p(self.nbest), self.q, RADIUS, s), "ih_track_refine_pick")
 
 
 @dataclass
@@ -138,86 +172,90 @@ class Track:
     fallback: np.ndarray      # T bool (learned search only)
 
 
-def track(frames, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker] = None,
-          teacher: Optional[Track] = None) -> Track:
-    """Track through frames (sequence of C x H x W uint8 device tensors, or a
-    stacked tensor).  With `teacher`, every search starts from the teacher's
-    previous position and distance (per-frame agreement)."""
-    T = len(frames)
-    tracker.set_template(frames[0], box0)
-    org = np.zeros((T, 2), np.int64)
-    dist = np.zeros(T)
-    fb = np.zeros(T, bool)
-    org[0] = box0[:2]
-    for t in range(1, T):
-        prev, dprev = (teacher.origins[t - 1], teacher.dists[t - 1]) if teacher is not None else (org[t - 1],
-                                                                                                 dist[t - 1])
-        tracker.build(frames[t])
-        if learned is None:
-            o, d = tracker.exhaustive(prev)
+class _Stepper:
+    """One frame's step with the target state on the device: fetch the frame
+    into a fixed buffer, build (frame or search region), search (learned with
+    its fallback rule, or exhaustive), commit the new state and its record."""
+
+    def __init__(self, frames: torch.Tensor, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker]):
+        if frames.dim() != 4 or frames.dtype != torch.uint8 or not frames.is_contiguous():
+            raise IHError("frames must be a contiguous T x C x H x W uint8 tensor")
+        if tracker.metric == "pmk":
+            raise IHError("the tracker minimises a distance (chi2 or l1); pmk is a similarity")
+        self.frames, self.tr, self.learned = frames, tracker, learned
+        self.T = frames.shape[0]
+        dev = tracker.device
+        tracker.set_template(frames[0], box0)
+        self.state = torch.from_numpy(np.array([box0[0], box0[1], 0, -1, 1], np.int32)).to(dev)  # dist 0.0, frame 1
+        self.exh = torch.empty((N_OFF, 2), dtype=torch.int32, device=dev)
+        self.rec = torch.zeros((self.T, 4), dtype=torch.int32, device=dev)
+        self.rec[0, 0], self.rec[0, 1] = int(box0[0]), int(box0[1])
+        self.cur = torch.empty(frames.shape[1:], dtype=torch.uint8, device=dev)
+        self.use_net = learned is not None and learned.net is not None
+        if self.use_net and not learned.net.packed:
+            learned.net.pack()
+
+    def set_state(self, t: int, origin, dist: float):
+        st = np.array([int(origin[0]), int(origin[1]), 0, -1, t], np.int32)
+        st[2] = np.array([dist], np.float32).view(np.int32)[0]
+        self.state.copy_(torch.from_numpy(st))
+
+    def step(self):
+        L, tr, lt = lib(), self.tr, self.learned
+        s = _stream(self.state)
+        h, w = tr.win
+        _check(L.ih_track_fetch(_p(self.frames), self.cur.numel(), self.T, _p(self.state), _p(self.cur), s),
+               "ih_track_fetch")
+        _check(L.ih_track_prepare(_p(self.state), h, w, _p(tr.base), _p(lt.center) if self.use_net else None, s),
+               "ih_track_prepare")
+        tr.frame_step(self.cur, self.state)
+        if lt is not None:
+            lt.search(self.cur)
+            _check(L.ih_track_gate(_p(self.state), _p(lt.idx), _p(lt.kdist), _p(lt.kbest), RADIUS, float(lt.tau),
+                                   _p(tr.sbase), _p(self.exh), s), "ih_track_gate")
         else:
-            o, d, fb[t] = learned.step(frames[t], prev, dprev)
-        org[t], dist[t] = o, d
-    return Track(org, dist, fb)
+            lp.lp_origins(tr.sbase, RADIUS, out=self.exh)
+        tr.score(self.exh, tr.dist, tr.best)
+        _check(L.ih_track_commit(_p(self.state), _p(lt.kdist) if lt is not None else None,
+                                 _p(lt.kbest) if lt is not None else None, _p(tr.dist), _p(tr.best), RADIUS,
+                                 _p(self.rec), self.T, s), "ih_track_commit")
+
+    def result(self) -> Track:
+        r = self.rec.cpu().numpy()
+        fb = r[:, 3].astype(bool) if self.learned is not None else np.zeros(self.T, bool)
+        return Track(r[:, :2].astype(np.int64), r[:, 2].copy().view(np.float32).astype(np.float64), fb)
+
+
+def track(frames: torch.Tensor, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker] = None,
+          teacher: Optional[Track] = None) -> Track:
+    """Track through a resident T x C x H x W uint8 stack, one frame at a time.
+    With `teacher`, every search starts from the teacher's previous position
+    and distance (per-frame agreement)."""
+    st = _Stepper(frames, box0, tracker, learned)
+    for t in range(1, st.T):
+        if teacher is not None:
+            st.set_state(t, teacher.origins[t - 1], float(teacher.dists[t - 1]))
+        st.step()
+    return st.result()
 
 
 def track_device(frames: torch.Tensor, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker] = None,
                  graph: bool = False) -> Track:
-    """The free-running track() with the state kept on the device.  frames is
-    a resident T x C x H x W uint8 stack; every frame's step (fetch the frame
-    into a fixed buffer, build, search, fallback rule, commit) is enqueued
-    without a host round trip, and the records are read back once at the end.
-    With `graph`, the step is captured once in a HIP graph and replayed per
-    frame.  Returns the same track as track(frames, box0, tracker, learned)."""
-    L = lib()
-    if frames.dim() != 4 or frames.dtype != torch.uint8 or not frames.is_contiguous():
-        raise IHError("frames must be a contiguous T x C x H x W uint8 tensor")
-    T = frames.shape[0]
-    dev = tracker.device
-    tracker.set_template(frames[0], box0)
-    h, w = tracker.win
-    state = torch.from_numpy(np.array([box0[0], box0[1], 0, -1, 1], np.int32)).to(dev)   # dist 0.0, frame 1
-    exh = torch.empty((N_OFF, 2), dtype=torch.int32, device=dev)
-    rec = torch.zeros((T, 4), dtype=torch.int32, device=dev)
-    rec[0, 0], rec[0, 1] = int(box0[0]), int(box0[1])
-    cur = torch.empty(frames.shape[1:], dtype=torch.uint8, device=dev)
-    fbytes = cur.numel()
-    use_net = learned is not None and learned.net is not None
-    if use_net and not learned.net.packed:
-        learned.net.pack()
-
-    def step():
-        s = _stream(state)
-        _check(L.ih_track_fetch(_p(frames), fbytes, T, _p(state), _p(cur), s), "ih_track_fetch")
-        tracker.build(cur)
-        _check(L.ih_track_prepare(_p(state), h, w, _p(tracker.base), _p(learned.center) if use_net else None, s),
-               "ih_track_prepare")
-        if learned is not None:
-            learned.propose(cur)
-            lp.lp_origins(tracker.base, RADIUS, idx=learned.idx, out=learned.korig)
-            tracker.score(learned.korig, learned.kdist, learned.kbest)
-            _check(L.ih_track_gate(_p(state), _p(learned.idx), _p(learned.kdist), _p(learned.kbest), RADIUS,
-                                   float(learned.tau), _p(tracker.base), _p(exh), s), "ih_track_gate")
-        else:
-            lp.lp_origins(tracker.base, RADIUS, out=exh)
-        tracker.score(exh, tracker.dist, tracker.best)
-        _check(L.ih_track_commit(_p(state), _p(learned.kdist) if learned is not None else None,
-                                 _p(learned.kbest) if learned is not None else None, _p(tracker.dist),
-                                 _p(tracker.best), RADIUS, _p(rec), T, s), "ih_track_commit")
-
-    if graph and T > 1:
+    """The free-running track() with every step enqueued without a host round
+    trip; with `graph`, the step is captured once in a HIP graph and replayed
+    per frame.  Returns the same track as track(frames, box0, tracker, learned)."""
+    st = _Stepper(frames, box0, tracker, learned)
+    if graph and st.T > 1:
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            step()
-        for _ in range(1, T):
+            st.step()
+        for _ in range(1, st.T):
             g.replay()
     else:
-        for _ in range(1, T):
-            step()
-    r = rec.cpu().numpy()
-    fb = r[:, 3].astype(bool) if learned is not None else np.zeros(T, bool)
-    return Track(r[:, :2].astype(np.int64), r[:, 2].copy().view(np.float32).astype(np.float64), fb)
+        for _ in range(1, st.T):
+            st.step()
+    return st.result()
 
 
 def distance_prior() -> torch.Tensor:

@@ -91,13 +91,69 @@ def test_zero_network_falls_back_on_every_frame(env):
     np.testing.assert_array_equal(res.origins, env["ex"].origins)
 
 
-@pytest.mark.parametrize("mode", ["exhaustive", "no_network", "random_network"])
+def test_region_histogram_search_equals_frame_search(env):
+    """The search over the search region's integral histogram returns the
+    same windows and bit-identical distances as over the frame's, for the
+    exhaustive and the learned search, including windows at the frame border."""
+    trk, lp = env["tracker"], env["lp"]
+    reg = trk.PyramidTracker(H, W, bins=BINS, region=True)
+    ex_r = trk.track(env["stack"], env["box0"], reg)
+    np.testing.assert_array_equal(ex_r.origins, env["ex"].origins)
+    np.testing.assert_array_equal(ex_r.dists, env["ex"].dists)
+    # a target starting in a corner: its search region is shifted inside the frame
+    corner = (2, W - 60, 40, 56)
+    a = trk.track(env["stack"][:12], corner, env["tr"])
+    b = trk.track(env["stack"][:12], corner, reg)
+    np.testing.assert_array_equal(a.origins, b.origins)
+    np.testing.assert_array_equal(a.dists, b.dists)
+    net = lp.ProposalNet(lp.init_params(5), max_batch=1)
+    la = trk.track(env["stack"], env["box0"], env["tr"], trk.LearnedTracker(env["tr"], net, k=64, tau=0.25,
+                                                                            refine_rounds=2))
+    lb = trk.track(env["stack"], env["box0"], reg, trk.LearnedTracker(reg, net, k=64, tau=0.25, refine_rounds=2))
+    np.testing.assert_array_equal(la.origins, lb.origins)
+    np.testing.assert_array_equal(la.dists, lb.dists)
+    np.testing.assert_array_equal(la.fallback, lb.fallback)
+
+
+def test_refinement_reaches_a_local_minimum(env):
+    """With every proposal accepted (tau = +inf, from frame 2), each refinement
+    round can only lower the accepted distance, and after enough rounds the
+    accepted window is a minimum of its (2q+1)^2 neighbourhood (checked against
+    the oracle's distances)."""
+    trk, ex, feats = env["tracker"], env["ex"], env["feats"]
+    prior = trk.distance_prior().cuda()
+    prev = None
+    for rounds in (0, 1, 3, 40):
+        lt = trk.LearnedTracker(env["tr"], None, k=8, tau=math.inf, prior_logits=prior, refine_rounds=rounds,
+                                refine_q=1)
+        res = trk.track(env["stack"], env["box0"], env["tr"], lt, teacher=ex)
+        if prev is not None:
+            assert np.all(res.dists[2:] <= prev.dists[2:])
+        prev = res
+    box0 = env["box0"]
+    h, w = box0[2], box0[3]
+    tmpl = oracle.pyramid_desc_direct(feats[0], BINS, 8, np.array([box0], np.int32), 3)[0]
+    for t in (2, 9, T - 1):
+        o = prev.origins[t]
+        d = np.arange(-1, 2)
+        nb = np.stack(np.meshgrid(o[0] + d, o[1] + d, indexing="ij"), -1).reshape(-1, 2)
+        dist, _ = oracle.match_direct(feats[t], BINS, 8, tmpl, h, w, 3, nb)
+        base = ex.origins[t - 1]
+        inside = np.all(np.abs(nb - base) <= 32, axis=1)
+        assert dist[4] <= dist[inside].min() * (1 + 1e-5) + 1e-9, t
+
+
+@pytest.mark.parametrize("mode", ["exhaustive", "no_network", "random_network", "region_refined"])
 def test_device_loop_matches_host_loop(env, mode):
     trk, lp, tr = env["tracker"], env["lp"], env["tr"]
     if mode == "exhaustive":
         lt = None
     elif mode == "no_network":
         lt = trk.LearnedTracker(tr, None, k=64, tau=0.25, prior_logits=trk.distance_prior().cuda())
+    elif mode == "region_refined":
+        tr = trk.PyramidTracker(H, W, bins=BINS, region=True)
+        lt = trk.LearnedTracker(tr, lp.ProposalNet(lp.init_params(5), max_batch=1), k=64, tau=0.1,
+                                refine_rounds=2, refine_q=2)
     else:
         lt = trk.LearnedTracker(tr, lp.ProposalNet(lp.init_params(5), max_batch=1), k=64, tau=0.25)
     host = trk.track(env["stack"], env["box0"], tr, lt)
@@ -108,7 +164,7 @@ def test_device_loop_matches_host_loop(env, mode):
         np.testing.assert_array_equal(dev.dists, host.dists)
         if lt is not None:
             np.testing.assert_array_equal(dev.fallback, host.fallback)
-    if mode == "random_network":
+    if mode in ("random_network", "region_refined"):
         assert host.fallback[1:].any()
 
 
