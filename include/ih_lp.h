@@ -6,7 +6,7 @@
  * models as a direction it does not build.  This library adds one: a small
  * convolutional network that looks at a crop of the 7 feature channels
  * (R, G, B, intensity, gradient orientation, gradient magnitude, edges; the
- * fused features of the tracker in Chapter 4) centred on the previous target
+ * fused features of the tracker of Sec. 2.4.3-2.4.4) centred on the previous target
  * position and scores each of the 65 x 65 candidate offsets (-32..32 pixels per
  * axis).  The tracker then scores only the k best-ranked offsets exactly.
  *

@@ -1,7 +1,7 @@
 // Learned candidate proposal: a small BF16 convolutional network trained and
 // run by these kernels (gfx950).
 //
-//   x  (7x128x128) -conv 3x3 s2-> a1 (32x64x64) -conv 3x3 d2-> a2 -conv 3x3 d4-> a3
+//   x  (7x128x128) -conv 3x3 s2-> a1 (32x64x64) -conv 3x3 d3-> a2 -conv 3x3 d9-> a3
 //   s = wh . a3 + bh (64x64);  logits(dy,dx) = bilinear(s, 32 + dy/2, 32 + dx/2)
 //
 // Convolutions, their input gradients and their weight gradients are implicit
