@@ -175,6 +175,38 @@ int ih_build(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C,
              void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Bytes of device scratch that ih_build_noalloc has on each GPU (64 MiB).
+ */
+#define IH_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * ih_build_noalloc - ih_build for callers that cannot allocate memory: code
+ * being captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same computation, arguments and results as ih_build, without
+ * the workspace: the build uses a scratch array the library holds on each
+ * GPU (IH_NOALLOC_SCRATCH_BYTES, set up on the first call on that device and
+ * kept until the process ends).  The call allocates nothing and frees
+ * nothing.
+ *
+ *   img ... cfg as for ih_build; the stream must belong to the current
+ *               device.
+ *   status      device, out, or NULL: receives the build's IH_STATUS_* word
+ *               (a uint32) once the stream reaches the end of the build.
+ * Returns IH_ERR_WORKSPACE, enqueuing nothing, when the shape needs more than
+ * IH_NOALLOC_SCRATCH_BYTES of workspace (ih_build_workspace_size() tells the
+ * need); otherwise as ih_build.  Every call on one GPU shares that GPU's
+ * scratch array: two calls whose builds overlap in time on one GPU (on
+ * different streams, or from different threads) race and both results are
+ * undefined; calls ordered on one stream are safe.  Everything the build
+ * needs zeroed it clears itself, so stale scratch contents do not matter.
+ */
+int ih_build_noalloc(const void *img, int32_t dtype, int32_t H, int32_t W,
+                     int32_t C, int32_t bins, int32_t value_bits,
+                     int32_t layout, int32_t *ih, uint32_t *mom_x,
+                     uint32_t *mom_y, const ih_tile_cfg *cfg, uint32_t *status,
+                     void *stream);
+
+/*
  * ih_build_weighted - weighted integral histogram: the plane-p entry sums a
  * per-pixel weight instead of counting (Alg. 2 step 4, the PHoG building
  * block: gradient orientation binned, gradient magnitude as the weight, edge

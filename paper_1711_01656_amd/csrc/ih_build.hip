@@ -28,6 +28,7 @@
 // row-direction carry is row * LC and needs no array; the column-direction
 // ones are kept.
 #include <algorithm>
+#include <mutex>
 
 #include "ih_build_dev.h"
 
@@ -215,24 +216,33 @@ static bool use_onepass(int32_t layout, const ih_tile_cfg *cfg) {
   return layout == IH_BHW && kOnePassDefault;
 }
 
-extern "C" size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
-                                          int32_t layout, const ih_tile_cfg *cfg) {
+// Workspace bytes of a build of this shape into *bytes, or an IH_ERR_* code.
+static int ws_bytes_for(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, int32_t layout,
+                        const ih_tile_cfg *cfg, size_t *bytes) {
   size_t one = 0;
+  int e;
   if (use_onepass(layout, cfg)) {
     OpGeom og;
-    if (layout != IH_BHW) {
-      set_error(IH_ERR_UNSUPPORTED, "the single-pass build writes the bin-major layout only");
-      return 0;
-    }
-    if (make_op_geom(H, W, C, bins, moments, cfg, &og) != IH_OK) return 0;
+    if (layout != IH_BHW) return set_error(IH_ERR_UNSUPPORTED, "the single-pass build writes the bin-major layout only");
+    if ((e = make_op_geom(H, W, C, bins, moments, cfg, &og))) return e;
     one = (size_t)og.words * 4;
-    if (cfg) return one;
+    if (cfg) {
+      *bytes = one;
+      return IH_OK;
+    }
   }
   // without a configuration the same size also serves the three-pass builds
   // of the shape (weighted, second-moment, moment-image builds)
   Geom g;
-  if (make_geom(H, W, C, bins, moments, layout, cfg, &g) != IH_OK) return 0;
-  return std::max(one, g.words * 4);
+  if ((e = make_geom(H, W, C, bins, moments, layout, cfg, &g))) return e;
+  *bytes = std::max(one, g.words * 4);
+  return IH_OK;
+}
+
+extern "C" size_t ih_build_workspace_size(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments,
+                                          int32_t layout, const ih_tile_cfg *cfg) {
+  size_t b = 0;
+  return ws_bytes_for(H, W, C, bins, moments, layout, cfg, &b) == IH_OK ? b : 0;
 }
 
 extern "C" int ih_build_passes(int32_t layout, const ih_tile_cfg *cfg) {
@@ -367,4 +377,66 @@ extern "C" int ih_build_weighted(const void *img, int32_t dtype, const uint8_t *
     return set_error(IH_ERR_OVERFLOW, "H*W*255 = %lld may overflow int32 sums", (long long)H * W * 255);
   return build_impl(img, dtype, weight, mask, H, W, C, bins, value_bits, layout, ih, nullptr, nullptr, cfg, ws,
                     ws_bytes, stream);
+}
+
+// ------------------------------------------------- allocation-free build --
+// The workspace of ih_build_noalloc: one array per GPU, alive until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it only names the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = IH_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint32_t scratch[kScratchBytes / 4];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch array, resolved once per device.
+int scratch_ptr(void **out) {
+  int dev = 0;
+  int e;
+  if ((e = hip_check(hipGetDevice(&dev), "hipGetDevice"))) return e;
+  if (dev < 0 || dev >= kMaxDevices) return set_error(IH_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if ((e = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))) return e;
+    if (!p) return set_error(IH_ERR_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return IH_OK;
+}
+
+__global__ void k_copy_status(const uint32_t *__restrict__ ws, uint32_t *__restrict__ status) {
+  if (threadIdx.x == 0) *status = ws[0];
+}
+}  // namespace
+
+extern "C" int ih_build_noalloc(const void *img, int32_t dtype, int32_t H, int32_t W, int32_t C, int32_t bins,
+                                int32_t value_bits, int32_t layout, int32_t *ih, uint32_t *mom_x, uint32_t *mom_y,
+                                const ih_tile_cfg *cfg, uint32_t *status, void *stream) {
+  if (layout != IH_BHW && layout != IH_HWB) return set_error(IH_ERR_INVALID_ARG, "layout %d unknown", layout);
+  if (cfg && cfg->passes != IH_PASSES_DEFAULT && cfg->passes != IH_PASSES_ONE && cfg->passes != IH_PASSES_THREE)
+    return set_error(IH_ERR_INVALID_ARG, "passes %d is not 0, 1 or 3", cfg->passes);
+  size_t need = 0;
+  int e;
+  if ((e = ws_bytes_for(H, W, C, bins, mom_x != nullptr, layout, cfg, &need))) return e;
+  if (need > kScratchBytes)
+    return set_error(IH_ERR_WORKSPACE,
+                     "the allocation-free build has %zu bytes of scratch; this shape needs %zu (use ih_build "
+                     "with a workspace)",
+                     kScratchBytes, need);
+  void *ws = nullptr;
+  if ((e = scratch_ptr(&ws))) return e;
+  if ((e = build_impl(img, dtype, nullptr, nullptr, H, W, C, bins, value_bits, layout, ih, mom_x, mom_y, cfg, ws,
+                      kScratchBytes, stream)))
+    return e;
+  if (status) {
+    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, as_stream(stream),
+                       reinterpret_cast<const uint32_t *>(ws), status);
+    if ((e = hip_check(hipGetLastError(), "status copy launch"))) return e;
+  }
+  return IH_OK;
 }

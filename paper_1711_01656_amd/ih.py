@@ -45,6 +45,7 @@ SIGNATURES = {
     "ih_last_error": (ctypes.c_char_p, []),
     "ih_build_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I32, _I32, _P]),
     "ih_build": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "ih_build_noalloc": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "ih_build_weighted": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ,
                                          _P]),
     "ih_jih_update_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I32, _P]),
@@ -277,6 +278,47 @@ def ih_build(img: torch.Tensor, bins: int, value_bits: Optional[int] = None, mom
                         ws.numel() * ws.element_size(), _stream(img))
     _check(rc, "ih_build")
     return (out, mx, my) if moments else out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ih_build_noalloc(img: torch.Tensor, bins: int, out: torch.Tensor, value_bits: Optional[int] = None,
+                     mom_out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, cfg: Optional[TileCfg] = None,
+                     status: Optional[torch.Tensor] = None, layout: str = "bhw"):
+    """ih_build without a workspace (the library's per-GPU scratch array):
+    the caller passes every output, and nothing is allocated.  ``status`` (a
+    one-element int32 tensor, optional) receives the build's status word."""
+    _dev(img, "img")
+    if img.dim() == 2:
+        img = img.unsqueeze(0)
+    if img.dtype == torch.uint8:
+        dt, maxbits = IH_U8, 8
+    elif img.dtype == torch.uint16:
+        dt, maxbits = IH_U16, 16
+    else:
+        raise IHError("img must be uint8 or uint16")
+    C, H, W = img.shape
+    bits = maxbits if value_bits is None else value_bits
+    P = C * bins
+    _dev(out, "out", torch.int32)
+    if out.numel() != P * H * W:
+        raise IHError("out must hold P*H*W values")
+    mx = my = None
+    if mom_out is not None:
+        mx, my = mom_out
+        _dev(mx, "mom_x", torch.int32)
+        _dev(my, "mom_y", torch.int32)
+        if mx.numel() != P * H * W or my.numel() != P * H * W:
+            raise IHError("moment outputs must hold P*H*W values")
+    if status is not None:
+        _dev(status, "status", torch.int32)
+        if status.numel() < 1:
+            raise IHError("status must hold one value")
+    rc = lib().ih_build_noalloc(_p(img), dt, H, W, C, bins, bits, _layout(layout), _p(out), _p(mx), _p(my),
+                                ctypes.byref(cfg) if cfg is not None else None, _p(status), _stream(img))
+    _check(rc, "ih_build_noalloc")
+    return out
 
 
 def ih_build_weighted(img: torch.Tensor, bins: int, weight: torch.Tensor, mask: Optional[torch.Tensor] = None,
