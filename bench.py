@@ -920,8 +920,9 @@ def cpu_tracker(frames_np, box0, ex_origins, min_seconds=6.0, threads=0):
             "host": _host()}
 
 
-# the learned search's settings, chosen on validation sequences (seeds
-# 600-607) disjoint from the training and benchmark sequences
+# the learned search's settings: with the bounded gate they change only how
+# many candidates are scored exactly (the track is the exhaustive one for any
+# value); the margin-only variant's agreement depends on them
 TRACKER_TAU, TRACKER_ROUNDS, TRACKER_Q = 0.1, 2, 2
 
 
@@ -977,19 +978,32 @@ def tracker_leg(torch, args):
 
     ex, fps_ex = timed(tr_f)
     ex_r, fps_ex_r = timed(tr_r)
-    learned = trk.LearnedTracker(tr_r, net, k=64, tau=tau, refine_rounds=rounds, refine_q=q)
+    # primary: the bounded learned search (exact by construction); beside it the
+    # margin rule alone (the proposal's result accepted as it is)
+    learned = trk.LearnedTracker(tr_r, net, k=64, tau=tau, refine_rounds=rounds, refine_q=q, bound=True)
     free, fps_l = timed(tr_r, learned)
-    base = trk.LearnedTracker(tr_r, None, k=64, tau=tau, prior_logits=prior, refine_rounds=rounds, refine_q=q)
+    base = trk.LearnedTracker(tr_r, None, k=64, tau=tau, prior_logits=prior, refine_rounds=rounds, refine_q=q,
+                              bound=True)
     free_b, fps_b = timed(tr_r, base)
+    margin = trk.LearnedTracker(tr_r, net, k=64, tau=tau, refine_rounds=rounds, refine_q=q)
+    free_m, fps_m = timed(tr_r, margin)
+    margin_b = trk.LearnedTracker(tr_r, None, k=64, tau=tau, prior_logits=prior, refine_rounds=rounds, refine_q=q)
     unref = trk.LearnedTracker(tr_r, net, k=64, tau=tau)
     # per-frame agreement: every search starts from the exhaustive trajectory
     forced = trk.track(frames, box0, tr_r, learned, teacher=ex)
     forced_b = trk.track(frames, box0, tr_r, base, teacher=ex)
+    forced_m = trk.track(frames, box0, tr_r, margin, teacher=ex)
+    forced_mb = trk.track(frames, box0, tr_r, margin_b, teacher=ex)
     forced_u = trk.track(frames, box0, tr_r, unref, teacher=ex)
     held = trk.samples_from_track(ex, box0[2:])
 
     def agree(a, b, px=0):
         return float(np.mean(np.all(np.abs(a.origins[1:] - b.origins[1:]) <= px, axis=1)))
+
+    def scorings(t):
+        """Candidates scored exactly per frame: the k proposals, the refinement
+        neighbourhoods and the exhaustive list's listed offsets."""
+        return round(float(np.mean(64 + rounds * (2 * q + 1) ** 2 + t.scored[1:])), 1)
 
     x = net.crop(frames[1], torch.tensor([[box0[0] + box0[2] // 2, box0[1] + box0[3] // 2]], dtype=torch.int32,
                                          device=dev))
@@ -997,11 +1011,13 @@ def tracker_leg(torch, args):
     scaling = search_cost_vs_targets(torch, trk, lp, tr_f, net, frames[1], box0)
     res = {
         "workload": "1280x720 synthetic video, 300 frames, 7 channels x 16 bins; 65x65 offsets; top-64 learned "
-                    "+ %d rounds of %dx%d local refinement; exhaustive fallback" % (rounds, 2 * q + 1, 2 * q + 1),
+                    "+ %d rounds of %dx%d local refinement; bounded exhaustive search (level-0 lower bound) "
+                    "when the margin rule accepts, full exhaustive search otherwise" % (rounds, 2 * q + 1, 2 * q + 1),
         "fps_exhaustive": round(fps_ex, 1),
         "fps_exhaustive_region_ih": round(fps_ex_r, 1),
         "fps_learned": round(fps_l, 1),
         "fps_no_network": round(fps_b, 1),
+        "fps_learned_margin_only": round(fps_m, 1),
         "fps_learned_over_exhaustive": round(fps_l / fps_ex, 3),
         "fps_learned_over_exhaustive_region_ih": round(fps_l / fps_ex_r, 3),
         "region_ih_track_equals_frame_ih_track": bool(np.array_equal(ex.origins, ex_r.origins)
@@ -1009,14 +1025,18 @@ def tracker_leg(torch, args):
         "tau": tau, "refine_rounds": rounds, "refine_window": 2 * q + 1,
         "agreement_per_frame": agree(forced, ex),
         "agreement_per_frame_no_network": agree(forced_b, ex),
-        "agreement_per_frame_without_refinement": agree(forced_u, ex),
+        "agreement_per_frame_margin_only": agree(forced_m, ex),
+        "agreement_per_frame_margin_only_no_network": agree(forced_mb, ex),
+        "agreement_per_frame_margin_only_without_refinement": agree(forced_u, ex),
         "fallback_rate": float(forced.fallback[1:].mean()),
         "fallback_rate_no_network": float(forced_b.fallback[1:].mean()),
-        "fallback_rate_without_refinement": float(forced_u.fallback[1:].mean()),
+        "fallback_rate_margin_only_without_refinement": float(forced_u.fallback[1:].mean()),
+        "exact_scorings_per_frame": {"exhaustive": lp.N_OFFSETS, "learned": scorings(forced),
+                                     "no_network": scorings(forced_b)},
         "recall_top64": round(trk.recall(net, frames, held), 4),
         "recall_top64_no_network": round(trk.recall(prior, frames, held), 4),
-        "free_running_within_1px": agree(free, ex, 1),
-        "free_running_within_1px_no_network": agree(free_b, ex, 1),
+        "free_running_equals_exhaustive": bool(np.array_equal(free.origins, ex.origins)),
+        "free_running_within_1px_margin_only": agree(free_m, ex, 1),
         "free_running_fallback_rate": float(free.fallback[1:].mean()),
         "network_forward_ms": round(fwd_ms, 4),
         "search_ms_vs_targets": scaling,

@@ -173,19 +173,25 @@ int ih_lp_topk(const float *logits, int32_t B, int32_t n, int32_t k,
  *   ih_build                         integral histogram of that buffer
  *   ih_track_prepare                 base = previous origin, crop centre
  *   (learned) crop, network, ih_lp_topk, ih_lp_origins, ih_match_candidates
- *   over the k proposals, then ih_track_gate
+ *   over the k proposals, then ih_track_gate, or (bounded) the level-0
+ *   distances of all offsets and ih_track_gate_bounded
  *   (exhaustive only) ih_lp_origins over all offsets
  *   ih_match_candidates over the exhaustive list, ih_track_commit
  * The gate implements the fallback rule: the best proposal is accepted when
  * its distance d satisfies d <= (1 + tau) * dist (evaluated in double);
  * then the exhaustive list is filled with origins outside every frame, so the
- * exhaustive scoring returns best = -1 without reading the histogram.
+ * exhaustive scoring returns best = -1 without reading the histogram.  The
+ * bounded gate keeps instead the offsets that could still beat d, so the
+ * result is always the exhaustive search's.
  */
 typedef struct {
   int32_t origin[2]; /* window origin (row, column) accepted at the previous frame */
   float dist;        /* its distance d*                                           */
-  int32_t decision;  /* accepted offset index, or -1 (written by prepare / gate)  */
+  int32_t decision;  /* accepted offset index, -1 (full exhaustive list) or -2    */
+                     /* (bounded list), written by prepare and the gates          */
   int32_t frame;     /* frame being processed; ih_track_commit advances it        */
+  int32_t scored;    /* candidates the exhaustive list holds this frame (written   */
+                     /* by prepare and the gates)                                  */
 } ih_track_state;
 
 /* dst [frame_bytes] = stack [st->frame * frame_bytes ...]; nothing is copied
@@ -195,22 +201,41 @@ int ih_track_fetch(const void *stack, int64_t frame_bytes, int32_t n_frames,
                    const ih_track_state *st, void *dst, void *stream);
 
 /* base [2] = st->origin; center [2] (may be NULL) = origin + (win_h/2, win_w/2);
-   st->decision = -1. */
+   st->decision = -1, st->scored = 0. */
 int ih_track_prepare(ih_track_state *st, int32_t win_h, int32_t win_w,
                      int32_t *base, int32_t *center, void *stream);
 
 /* Reads the k-proposal search (idx [k] offset indices, kdist [k], kbest [1]
-   from ih_match_candidates); sets st->decision and writes exh_origins
+   from ih_match_candidates); sets st->decision and st->scored (0 when the
+   proposal is accepted, (2 radius + 1)^2 otherwise) and writes exh_origins
    [(2 radius + 1)^2][2]. */
 int ih_track_gate(ih_track_state *st, const int32_t *idx, const float *kdist,
                   const int32_t *kbest, int32_t radius, double tau,
                   const int32_t *base, int32_t *exh_origins, void *stream);
 
-/* New state from the accepted proposal (kdist, kbest) or the exhaustive
-   search (exh_dist, exh_best; +inf and the old origin when no candidate was
-   inside).  Record f = st->frame of rec [n_rec][4] (when f < n_rec) receives
-   origin row, origin column, the distance's FP32 bits and 1 when the
-   exhaustive result was used; then st->frame = f + 1. */
+/* Bounded form of ih_track_gate, which keeps the search exact.  When the
+   margin rule accepts the best proposal (distance d <= (1 + tau) * dist), the
+   exhaustive list keeps only the offsets whose lower bound lb [(2 radius +
+   1)^2] (the level-0 distance of each offset, from ih_match_candidates with
+   levels = 1 over all offsets, metric chi2 or L1) does not exceed d, within
+   a relative 2^-16 for rounding; the others get origins outside every frame.
+   The pyramid distance of Eq. 2.24 is at least its level-0 distance (the
+   level weights sum to 1 and merging cells never raises a chi-square or L1
+   sum), so the scoring of that list returns the exhaustive search's argmin
+   and distance (ties included).  Otherwise (a fallback) every offset is
+   listed.  st->decision = -2 (bounded) or -1 (fallback); st->scored = the
+   number of listed offsets. */
+int ih_track_gate_bounded(ih_track_state *st, const float *kdist,
+                          const int32_t *kbest, int32_t radius, double tau,
+                          const int32_t *base, const float *lb,
+                          int32_t *exh_origins, void *stream);
+
+/* New state from the accepted proposal (kdist, kbest; st->decision >= 0) or
+   the exhaustive list's search (exh_dist, exh_best; +inf and the old origin
+   when no candidate was inside).  Record f = st->frame of rec [n_rec][5]
+   (when f < n_rec) receives origin row, origin column, the distance's FP32
+   bits, 1 when the gate fell back to the full exhaustive list (0 otherwise),
+   and st->scored; then st->frame = f + 1. */
 int ih_track_commit(ih_track_state *st, const float *kdist,
                     const int32_t *kbest, const float *exh_dist,
                     const int32_t *exh_best, int32_t radius, int32_t *rec,

@@ -40,6 +40,7 @@ __global__ void k_track_prepare(ih_track_state *__restrict__ st, int win_h, int 
     center[1] = c + win_w / 2;
   }
   st->decision = -1;
+  st->scored = 0;
 }
 
 // Accept the best proposal when its distance is within (1 + tau) times the
@@ -52,11 +53,50 @@ __global__ void k_track_gate(ih_track_state *__restrict__ st, const int32_t *__r
   const double d = b >= 0 ? (double)kdist[b] : (double)INFINITY;
   const bool accept = b >= 0 && d <= (1.0 + tau) * (double)st->dist;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) st->decision = accept ? idx[b] : -1;
+  if (i == 0) {
+    st->decision = accept ? idx[b] : -1;
+    st->scored = accept ? 0 : n * n;
+  }
   if (i < n * n) {
     exh[2 * i] = accept ? kFar : base[0] + i / n - radius;
     exh[2 * i + 1] = accept ? kFar : base[1] + i % n - radius;
   }
+}
+
+// Bounded form of the gate.  When the margin rule accepts the best proposal
+// (distance d), every offset whose lower bound lb exceeds d by more than the
+// rounding of both figures is dropped from the exhaustive list (set outside
+// every frame) and the rest stay listed: the scoring of that list then
+// returns the exhaustive search's own argmin and distance.  (The pyramid
+// distance of Eq. 2.24 weighs its levels by weights that sum to 1, and the
+// chi-square and L1 sums over a level's cells are at least those over the
+// coarser level's cells, so the level-0 distance lb never exceeds the
+// pyramid distance; a dropped offset scores above d, which is at least the
+// minimum.)  Otherwise every offset is listed, as in the plain gate.
+// st->decision = -2 (bounded) or -1 (fallback); st->scored counts the listed
+// offsets (one block-wide count per block, then one atomic add).
+__global__ __launch_bounds__(256) void k_track_gate_bounded(ih_track_state *__restrict__ st,
+                                                             const float *__restrict__ kdist,
+                                                             const int32_t *__restrict__ kbest, int radius,
+                                                             double tau, const int32_t *__restrict__ base,
+                                                             const float *__restrict__ lb,
+                                                             int32_t *__restrict__ exh) {
+  const int n = 2 * radius + 1;
+  const int b = kbest[0];
+  const double d = b >= 0 ? (double)kdist[b] : (double)INFINITY;
+  const bool accept = b >= 0 && d <= (1.0 + tau) * (double)st->dist;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) st->decision = accept ? -2 : -1;
+  bool listed = false;
+  if (i < n * n) {
+    // both figures carry at most a few FP32 roundings (relative 2^-22 each);
+    // 2^-16 of slack keeps every offset whose true bound is <= d
+    listed = !accept || !((double)lb[i] > d * (1.0 + 1.0 / 65536.0));
+    exh[2 * i] = listed ? base[0] + i / n - radius : kFar;
+    exh[2 * i + 1] = listed ? base[1] + i % n - radius : kFar;
+  }
+  const int cnt = __syncthreads_count(listed);
+  if (threadIdx.x == 0 && cnt) atomicAdd(&st->scored, cnt);
 }
 
 __global__ void k_track_commit(ih_track_state *__restrict__ st, const float *__restrict__ kdist,
@@ -69,14 +109,14 @@ __global__ void k_track_commit(ih_track_state *__restrict__ st, const float *__r
   int32_t r = st->origin[0], c = st->origin[1];
   float d;
   int32_t fb;
-  if (dec >= 0) {
+  if (dec >= 0) {  // accepted proposal
     r += dec / n - radius;
     c += dec % n - radius;
     d = kdist[kbest[0]];
     fb = 0;
-  } else {
+  } else {  // the exhaustive list decides: full (-1, a fallback) or bounded (-2)
     const int b = ebest[0];
-    fb = 1;
+    fb = dec == -1 ? 1 : 0;
     if (b >= 0) {
       r += b / n - radius;
       c += b % n - radius;
@@ -90,10 +130,11 @@ __global__ void k_track_commit(ih_track_state *__restrict__ st, const float *__r
   st->dist = d;
   const int f = st->frame;
   if (f >= 0 && f < n_rec) {
-    rec[4 * f] = r;
-    rec[4 * f + 1] = c;
-    rec[4 * f + 2] = __float_as_int(d);
-    rec[4 * f + 3] = fb;
+    rec[5 * f] = r;
+    rec[5 * f + 1] = c;
+    rec[5 * f + 2] = __float_as_int(d);
+    rec[5 * f + 3] = fb;
+    rec[5 * f + 4] = st->scored;
   }
   st->frame = f + 1;
 }
@@ -240,6 +281,17 @@ extern "C" int ih_track_gate(ih_track_state *st, const int32_t *idx, const float
   hipLaunchKernelGGL(k_track_gate, dim3((nn + 255) / 256), dim3(256), 0, as_stream(stream), st, idx, kdist, kbest,
                      radius, tau, base, exh_origins);
   return hip_check(hipGetLastError(), "track gate launch");
+}
+
+extern "C" int ih_track_gate_bounded(ih_track_state *st, const float *kdist, const int32_t *kbest, int32_t radius,
+                                     double tau, const int32_t *base, const float *lb, int32_t *exh_origins,
+                                     void *stream) {
+  if (!st || !kdist || !kbest || !base || !lb || !exh_origins || radius < 0 || radius > 4096)
+    return set_error(IH_ERR_INVALID_ARG, "bad track-gate arguments");
+  const int nn = (2 * radius + 1) * (2 * radius + 1);
+  hipLaunchKernelGGL(k_track_gate_bounded, dim3((nn + 255) / 256), dim3(256), 0, as_stream(stream), st, kdist,
+                     kbest, radius, tau, base, lb, exh_origins);
+  return hip_check(hipGetLastError(), "track bounded-gate launch");
 }
 
 extern "C" int ih_track_commit(ih_track_state *st, const float *kdist, const int32_t *kbest, const float *exh_dist,

@@ -86,6 +86,7 @@ SIGNATURES = {
     "ih_lp_topk": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P]),
     "ih_track_prepare": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P]),
     "ih_track_gate": (ctypes.c_int, [_P, _P, _P, _P, _I32, ctypes.c_double, _P, _P, _P]),
+    "ih_track_gate_bounded": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_double, _P, _P, _P, _P]),
     "ih_track_commit": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _I32, _P]),
     "ih_track_fetch": (ctypes.c_int, [_P, _I64, _I32, _P, _P, _P]),
     "ih_track_region": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P, _P, _P]),

@@ -12,7 +12,10 @@ tracker.  Two searches:
   optionally moved by a local search among its neighbouring offsets, and
   the exhaustive search runs instead whenever the result scores worse than
   the margin (1 + tau) d*, where d* is the distance accepted at the previous
-  frame.
+  frame.  In the bounded form an accepted result d only narrows the
+  exhaustive search: the level-0 distance of every offset is a lower bound
+  of its pyramid distance, and only the offsets whose bound does not exceed
+  d are scored exactly, which returns the exhaustive search's own result.
 
 Either search can run on the integral histogram of the whole frame (as the
 thesis's tracker does) or of the search region only.  All scoring, network
@@ -106,24 +109,39 @@ class PyramidTracker:
         return ih_match_candidates(self.ih, self.tmpl, self.win[0], self.win[1], origins, self.levels,
                                    self.metric, dist, best, self.layout)
 
+    def score_level0(self, origins: torch.Tensor, dist: torch.Tensor, best: torch.Tensor):
+        """Level-0 distances (the whole window's histogram against the
+        template's level-0 cell, the first P values of its descriptor): a
+        lower bound of each candidate's pyramid distance."""
+        return ih_match_candidates(self.ih, self.tmpl[:self.P], self.win[0], self.win[1], origins, 1,
+                                   self.metric, dist, best, self.layout)
+
 
 class LearnedTracker:
     """Top-k proposals from the network, exact scoring, optional local
     refinement of the best proposal, exhaustive fallback."""
 
     def __init__(self, tracker: PyramidTracker, net: Optional[lp.ProposalNet], k: int = 64, tau: float = 0.25,
-                 prior_logits: Optional[torch.Tensor] = None, refine_rounds: int = 0, refine_q: int = 2):
+                 prior_logits: Optional[torch.Tensor] = None, refine_rounds: int = 0, refine_q: int = 2,
+                 bound: bool = False):
         """net=None with prior_logits ranks the offsets by a fixed score instead
         of the network (the no-network baseline).  refine_rounds rounds of the
         local search move the best candidate to the best of the (2 refine_q + 1)^2
-        offsets around it."""
+        offsets around it.  With bound, an accepted result narrows the
+        exhaustive search by the level-0 lower bound instead of replacing it
+        (the track then always equals the exhaustive one)."""
         if net is None and prior_logits is None:
             raise IHError("need a network or fixed prior logits")
         if tracker.metric == "pmk":
             raise IHError("the fallback rule needs a distance (chi2 or l1); pmk is a similarity")
         self.tr, self.net, self.k, self.tau = tracker, net, k, tau
         self.rounds, self.q = int(refine_rounds), int(refine_q)
+        self.bound = bool(bound)
         dev = tracker.device
+        if self.bound:
+            self.allorig = torch.empty((N_OFF, 2), dtype=torch.int32, device=dev)
+            self.lb = torch.empty(N_OFF, dtype=torch.float32, device=dev)
+            self.lbbest = torch.empty(1, dtype=torch.int32, device=dev)
         self.prior = prior_logits
         self.idx = torch.empty((1, k), dtype=torch.int32, device=dev)
         self.korig = torch.empty((k, 2), dtype=torch.int32, device=dev)
@@ -163,6 +181,20 @@ class LearnedTracker:
             tr.score(self.norig, self.ndist, self.nbest)
             _check(L.ih_track_refine_pick(_p(self.idx), _p(self.kdist), _p(self.kbest), _p(self.ndist),
                                           _p(self.nbest), self.q, RADIUS, s), "ih_track_refine_pick")
+        if self.bound:
+            lp.lp_origins(tr.sbase, RADIUS, out=self.allorig)
+            tr.score_level0(self.allorig, self.lb, self.lbbest)
+
+    def gate(self, state: torch.Tensor, exh: torch.Tensor):
+        """Enqueue the fallback rule (plain or bounded), filling exh."""
+        tr, L = self.tr, lib()
+        s = _stream(state)
+        if self.bound:
+            _check(L.ih_track_gate_bounded(_p(state), _p(self.kdist), _p(self.kbest), RADIUS, float(self.tau),
+                                           _p(tr.sbase), _p(self.lb), _p(exh), s), "ih_track_gate_bounded")
+        else:
+            _check(L.ih_track_gate(_p(state), _p(self.idx), _p(self.kdist), _p(self.kbest), RADIUS,
+                                   float(self.tau), _p(tr.sbase), _p(exh), s), "ih_track_gate")
 
 
 @dataclass
@@ -170,6 +202,7 @@ class Track:
     origins: np.ndarray       # T x 2 window origins
     dists: np.ndarray         # T accepted distances
     fallback: np.ndarray      # T bool (learned search only)
+    scored: Optional[np.ndarray] = None  # T, candidates of the exhaustive list scored exactly
 
 
 class _Stepper:
@@ -186,9 +219,10 @@ class _Stepper:
         self.T = frames.shape[0]
         dev = tracker.device
         tracker.set_template(frames[0], box0)
-        self.state = torch.from_numpy(np.array([box0[0], box0[1], 0, -1, 1], np.int32)).to(dev)  # dist 0.0, frame 1
+        # ih_track_state: origin, dist 0.0, decision, frame 1, scored
+        self.state = torch.from_numpy(np.array([box0[0], box0[1], 0, -1, 1, 0], np.int32)).to(dev)
         self.exh = torch.empty((N_OFF, 2), dtype=torch.int32, device=dev)
-        self.rec = torch.zeros((self.T, 4), dtype=torch.int32, device=dev)
+        self.rec = torch.zeros((self.T, 5), dtype=torch.int32, device=dev)
         self.rec[0, 0], self.rec[0, 1] = int(box0[0]), int(box0[1])
         self.cur = torch.empty(frames.shape[1:], dtype=torch.uint8, device=dev)
         self.use_net = learned is not None and learned.net is not None
@@ -196,7 +230,7 @@ class _Stepper:
             learned.net.pack()
 
     def set_state(self, t: int, origin, dist: float):
-        st = np.array([int(origin[0]), int(origin[1]), 0, -1, t], np.int32)
+        st = np.array([int(origin[0]), int(origin[1]), 0, -1, t, 0], np.int32)
         st[2] = np.array([dist], np.float32).view(np.int32)[0]
         self.state.copy_(torch.from_numpy(st))
 
@@ -211,8 +245,7 @@ class _Stepper:
         tr.frame_step(self.cur, self.state)
         if lt is not None:
             lt.search(self.cur)
-            _check(L.ih_track_gate(_p(self.state), _p(lt.idx), _p(lt.kdist), _p(lt.kbest), RADIUS, float(lt.tau),
-                                   _p(tr.sbase), _p(self.exh), s), "ih_track_gate")
+            lt.gate(self.state, self.exh)
         else:
             lp.lp_origins(tr.sbase, RADIUS, out=self.exh)
         tr.score(self.exh, tr.dist, tr.best)
@@ -223,7 +256,8 @@ class _Stepper:
     def result(self) -> Track:
         r = self.rec.cpu().numpy()
         fb = r[:, 3].astype(bool) if self.learned is not None else np.zeros(self.T, bool)
-        return Track(r[:, :2].astype(np.int64), r[:, 2].copy().view(np.float32).astype(np.float64), fb)
+        return Track(r[:, :2].astype(np.int64), r[:, 2].copy().view(np.float32).astype(np.float64), fb,
+                     r[:, 4].astype(np.int64))
 
 
 def track(frames: torch.Tensor, box0, tracker: PyramidTracker, learned: Optional[LearnedTracker] = None,

@@ -216,3 +216,63 @@ def test_trained_network_beats_the_search_without_it(env):
     assert r["r_net"] > r["r_pr"] + 0.1
     assert r["fb_net"] < r["fb_pr"]
     assert prec["net"] > prec["pr"]
+
+
+def test_level0_distance_bounds_the_pyramid_distance(env):
+    """The bound the bounded gate relies on, checked on every offset of a few
+    frames: the level-0 distance never exceeds the 3-level pyramid distance
+    (chi-square and L1), beyond FP32 rounding."""
+    trk, lp, ex = env["tracker"], env["lp"], env["ex"]
+    for metric in ("chi2", "l1"):
+        tr = trk.PyramidTracker(H, W, bins=BINS, metric=metric)
+        tr.set_template(env["stack"][0], env["box0"])
+        for t in (1, 13, T - 1):
+            tr.build(env["stack"][t])
+            base = torch.from_numpy(ex.origins[t - 1][None].astype(np.int32)).cuda()
+            orig = lp.lp_origins(base, lp.RADIUS)
+            d = torch.empty(lp.N_OFFSETS, dtype=torch.float32, device="cuda")
+            d0 = torch.empty_like(d)
+            b = torch.empty(1, dtype=torch.int32, device="cuda")
+            tr.score(orig, d, b)
+            tr.score_level0(orig, d0, b)
+            d, d0 = d.cpu().numpy().astype(np.float64), d0.cpu().numpy().astype(np.float64)
+            fin = np.isfinite(d)
+            assert np.array_equal(fin, np.isfinite(d0))
+            assert np.all(d0[fin] <= d[fin] * (1 + 2.0 ** -20) + 1e-30), (metric, t)
+            assert np.any(d0[fin] < d[fin])
+
+
+@pytest.mark.parametrize("ranking", ["random_network", "no_network", "zero_network"])
+@pytest.mark.parametrize("metric", ["chi2", "l1"])
+def test_bounded_search_equals_exhaustive(env, ranking, metric):
+    """With the bounded gate the learned search returns the exhaustive
+    search's window and distance on every frame, whatever ranks the offsets,
+    per frame from the exhaustive trajectory and free-running; it scores
+    fewer candidates than the exhaustive search on most accepted frames."""
+    trk, lp = env["tracker"], env["lp"]
+    tr = trk.PyramidTracker(H, W, bins=BINS, metric=metric, region=True)
+    ex = trk.track(env["stack"], env["box0"], tr)
+    if metric == "chi2":
+        np.testing.assert_array_equal(ex.origins, env["ex"].origins)
+    if ranking == "no_network":
+        net, prior = None, trk.distance_prior().cuda()
+    elif ranking == "zero_network":
+        net, prior = lp.ProposalNet({k: np.zeros_like(v) for k, v in cnn.init_params(0).items()}, max_batch=1), None
+    else:
+        net, prior = lp.ProposalNet(lp.init_params(5), max_batch=1), None
+    for rounds in (0, 2):
+        lt = trk.LearnedTracker(tr, net, k=64, tau=0.1, prior_logits=prior, refine_rounds=rounds, bound=True)
+        forced = trk.track(env["stack"], env["box0"], tr, lt, teacher=ex)
+        np.testing.assert_array_equal(forced.origins, ex.origins)
+        np.testing.assert_array_equal(forced.dists, ex.dists)
+        free = trk.track_device(env["stack"], env["box0"], tr, lt, graph=True)
+        np.testing.assert_array_equal(free.origins, ex.origins)
+        np.testing.assert_array_equal(free.dists, ex.dists)
+        acc = ~forced.fallback[1:]
+        sc = forced.scored[1:]
+        assert np.all(sc[~acc] == lp.N_OFFSETS)
+        assert np.all((sc[acc] >= 1) & (sc[acc] <= lp.N_OFFSETS))
+        print(ranking, metric, rounds, "fallback %.3f" % (1 - acc.mean()),
+              "mean scored when accepted %.1f" % (sc[acc].mean() if acc.any() else -1))
+        if ranking != "zero_network" and acc.any():
+            assert np.median(sc[acc]) < lp.N_OFFSETS / 2
