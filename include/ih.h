@@ -72,15 +72,16 @@ typedef struct {
 /*
  * How the build is organised (ih_tile_cfg.passes).
  *   IH_PASSES_DEFAULT  the library's choice for the shape and layout.
- *   IH_PASSES_ONE      one pass (bin-major layout only): row bands of tile_h
- *                      rows, each walked from left to right in tiles of
+ *   IH_PASSES_ONE      one launch (bin-major layout only): row bands of
+ *                      tile_h rows, each swept from left to right in tiles of
  *                      tile_w columns by one wavefront per group of
- *                      planes_per_wave planes, which keeps its band's row
- *                      carries on chip; the top boundary of every tile comes
- *                      from the bands above by a look-back over their
- *                      published aggregates and inclusive bottom rows.
- *                      tile_h in [1, 1024]; tile_w 64, 128 or 256;
- *                      planes_per_wave 1, 2 or 4.
+ *                      planes_per_wave planes, first counting (publishing
+ *                      every tile's band aggregate), then writing out with
+ *                      its band's row carries on chip; the top boundary of
+ *                      every tile comes from the bands above by a look-back
+ *                      to the nearest published inclusive bottom row through
+ *                      the aggregates in between.  tile_h in [1, 1024];
+ *                      tile_w 64, 128 or 256; planes_per_wave 1, 2 or 4.
  *   IH_PASSES_THREE    three passes: per-tile histograms, scans of the tile
  *                      carries, write-out (the shapes below).
  */
@@ -584,15 +585,13 @@ int ih_build_passes(int32_t layout, const ih_tile_cfg *cfg);
 
 /*
  * ih_set_lookback_patience - look-back policy of the single-pass build
- * (IH_PASSES_ONE), for every later build in this process.  A band worker
- * polls the flag of the band directly above at most `polls` times for its
- * inclusive bottom row; if that row has not been published by then, the
- * worker publishes its own band's aggregate (so that the bands below need
- * not wait for it) and walks further up, adding aggregates until a band with
- * an inclusive row.  polls = -1 (the default) always waits for the band
- * above; 0 publishes and walks at once.  Results are identical for every
- * value; only the time differs.  Returns IH_OK, or IH_ERR_INVALID_ARG for
- * polls < -1.
+ * (IH_PASSES_ONE), for every later build in this process.  Before each
+ * tile's look-back, a band worker polls the flag of the band directly above
+ * at most `polls` times for its inclusive bottom row; then (or at once for
+ * polls <= 0, the default -1 included) it takes the nearest inclusive row
+ * published above plus the aggregates of the bands in between.  Results are
+ * identical for every value; only the time differs.  Returns IH_OK, or
+ * IH_ERR_INVALID_ARG for polls < -1.
  */
 int ih_set_lookback_patience(int32_t polls);
 

@@ -28,6 +28,7 @@
 // row-direction carry is row * LC and needs no array; the column-direction
 // ones are kept.
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 
 #include "ih_build_dev.h"
@@ -103,6 +104,7 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
     const int64_t out_bytes = (int64_t)g->P * H * W * 4 * (g->mom ? 3 : 1);
     if (out_bytes < ((int64_t)128 << 20)) { TH = 8; TW = 16; }
     else if (g->mom) { TH = 128; TW = 16; }
+    else if (out_bytes >= ((int64_t)4 << 30)) { TH = 128; TW = 32; }
     else { TH = 32; TW = 32; }
   }
   g->TH = TH; g->TW = TW; g->PG = PG;
@@ -250,9 +252,22 @@ extern "C" int ih_build_passes(int32_t layout, const ih_tile_cfg *cfg) {
   return use_onepass(layout, cfg) ? 1 : 3;
 }
 
-// Polls of the band above before a single-pass worker publishes its own
-// aggregate and looks further up (-1: wait for the band above).
+// Polls of the band above's inclusive row before a single-pass worker takes
+// the nearest published row and the aggregates in between (-1, 0: at once).
 static int g_patience = -1;
+
+// Tiles by which a single-pass worker's counting sweep leads its write-out
+// sweep (IH_ONEPASS_AHEAD in the environment overrides the default, 1): 0
+// counts each tile just before writing it, larger leads publish aggregates
+// earlier so that the bands below wait less, at the price of the counted
+// pixels leaving the cache before they are written.
+static int onepass_ahead() {
+  static const int v = [] {
+    const char *e = getenv("IH_ONEPASS_AHEAD");
+    return e && *e ? std::max(0, atoi(e)) : 1;
+  }();
+  return v;
+}
 
 extern "C" int ih_set_lookback_patience(int32_t polls) {
   if (polls < -1) return set_error(IH_ERR_INVALID_ARG, "patience %d below -1", polls);
@@ -340,7 +355,7 @@ static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const u
                        ws ? ws_bytes : (size_t)0);
     const bool aligned = ((uintptr_t)ih % 16 == 0) && ((uintptr_t)mom_x % 16 == 0) && ((uintptr_t)mom_y % 16 == 0);
     OpArgs oa{img, ih, mom_x, mom_y, reinterpret_cast<uint32_t *>(ws), value_bits,
-              (W % og.CPL == 0 && aligned) ? 1 : 0, g_patience};
+              (W % og.CPL == 0 && aligned) ? 1 : 0, g_patience, onepass_ahead()};
     return launch_onepass(og, dtype, oa, as_stream(stream), g_hook.start, g_hook.stop);
   }
   if (wt && cfg && cfg->passes == IH_PASSES_ONE)

@@ -148,7 +148,8 @@ struct OpArgs {
   uint32_t *ws;
   int bits;
   int vec_ok;    // W divisible by the columns per lane and the outputs 16-byte aligned
-  int patience;  // polls of the band above before a worker publishes its aggregate
+  int patience;  // polls of the band above for its inclusive row before each look-back
+  int ahead;     // tiles the counting sweep runs ahead of the write-out sweep
 };
 
 int make_op_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, const ih_tile_cfg *cfg,

@@ -2,39 +2,39 @@
 // with the tile-to-tile carry handed over by a look-back across row bands.
 //
 // The image is cut into bands of R rows.  One wavefront (a "worker") owns one
-// band and a group of PG planes of one channel, and walks the band's tiles of
-// TW = 64 * CPL columns from left to right; lanes map to columns.  The worker
-// keeps the row carries of its band (the plane-k count of row r left of the
-// tile, per row and plane) in its own LDS slice, so no row-carry array is
-// ever written.  For the column direction, tile j of band b needs its top
-// boundary H(p, R0-1, c) for the tile's columns, which the band above
-// produces.  Per tile the worker:
-//   1. counts its plane-group pixels per column over the band's rows and forms
-//      the band's local aggregate in integral form,
+// band and a group of PG planes of one channel and walks the band's tiles of
+// TW = 64 * CPL columns from left to right; lanes map to columns.  Tile j of
+// band b needs its top boundary H(p, R0-1, c) for the tile's columns, which
+// depends on every band above.  The worker runs two sweeps over its band:
+//   A. counting only: for every tile, the band's aggregate in integral form,
 //        A(p, c) = sum_{r in band} sum_{c' <= c} [bin(r, c') = p]
-//      (row carries from the left included);
-//   2. obtains the top boundary by looking back over the bands above: each
-//      band publishes, per (group, tile), a flag and either its aggregate
-//      (state 1) or its inclusive bottom row H(p, R1-1, c) (state 2).  The
-//      worker waits for the band above; if that band has only an aggregate,
-//      the worker adds it and looks further up, until a band with an
-//      inclusive row (or the top of the image) ends the walk.  How long a
-//      worker waits for the band directly above before it publishes its own
-//      aggregate and starts walking is a launch parameter (`patience`);
-//   3. publishes its own inclusive bottom row (top + A, state 2);
-//   4. writes the tile's R rows: the row prefix of a one-hot plane is a ballot
-//      plus mbcnt (as in the three-pass write-out), the column prefix a
-//      per-lane register sum starting from the top boundary.
-// Workers take their (band, group) from a ticket counter in the order they
-// start, so a worker only ever waits for bands whose workers have already
-// started: the waits always end.  Every wait is also bounded; a wait that
-// gives up sets IH_STATUS_WAIT_TIMEOUT and an abort word that ends all other
-// waits, and the kernel completes (with that build's result invalid).
+//      (the per-column counts of the band's rows, prefix-summed along the
+//      row with the totals of the tiles to the left carried in registers),
+//      published per (band, group, tile) with a flag in state 1.  Band 0 has
+//      nothing above it, so its aggregate is its inclusive bottom row
+//      H(p, R1-1, c), published in state 2.  This sweep never waits.
+//   B. write-out: for tile j, the top boundary is the inclusive row of the
+//      nearest band above that has published one plus the aggregates of the
+//      bands in between.  Lane i reads the flag of the i-th band above, so one
+//      load inspects 64 bands; the worker waits only while some band it needs
+//      has not finished sweep A.  It then publishes its own inclusive bottom
+//      row (top + its aggregate, state 2), which shortens the walks of the
+//      bands below, and writes the tile's R rows: the row prefix of a one-hot
+//      plane is a ballot plus mbcnt, the column prefix a per-lane register sum
+//      starting from the top boundary, and the row carries (the plane-k count
+//      of each row left of the tile) live in the worker's LDS slice, so no
+//      row-carry array is ever written.
+// Because sweep A never waits, no band waits for another band's write-out, and
+// all bands write concurrently.  Workers take their (band, group) from a
+// ticket counter in the order they start, so a worker only waits for workers
+// that have started; every wait is also bounded: one that gives up sets
+// IH_STATUS_WAIT_TIMEOUT and an abort word that ends all other waits, and the
+// kernel completes (with that build's result invalid).
 //
 // Cross-workgroup data (flags, aggregates, inclusive rows) is written and read
 // with device-scope relaxed atomics, which bypass the per-XCD L2 caches, and
-// ordered with the wave's own store counter: the payload's stores complete
-// before its flag is stored, and the flag is read before the payload.  The
+// ordered with the wave's own memory counter: the payload's stores complete
+// before its flag is stored, and the flags are read before the payload.  The
 // integral histogram itself is written with streaming stores.
 //
 // Moment tensors (Eq. 3.4) ride along: their aggregates and inclusive rows
@@ -71,31 +71,6 @@ __device__ __forceinline__ void order_acquire() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Polls *f until it is non-zero, at most `polls` times (polls < 0: until the
-// bounded wait gives up).  Returns the flag, or 0.  Wave-uniform.
-__device__ __forceinline__ uint32_t op_poll(const uint32_t *f, uint32_t *hdr, int polls) {
-  for (uint32_t it = 0;; ++it) {
-    const uint32_t v = (uint32_t)uniform((int)ld_dev(f));
-    if (v) {
-      order_acquire();
-      return v;
-    }
-    if (polls >= 0 && it >= (uint32_t)polls) return 0;
-    if ((it & 63) == 63) {
-      if (uniform((int)ld_dev(hdr + kHdrAbort))) return 0;
-      if (it >= kSpinLimit) {
-        if ((threadIdx.x & 63) == 0) {
-          __hip_atomic_fetch_or(hdr + kHdrStatus, (uint32_t)IH_STATUS_WAIT_TIMEOUT, __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
-          st_dev(hdr + kHdrAbort, 1u);
-        }
-        return 0;
-      }
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-}
-
 template <typename T, int CPL>
 __device__ __forceinline__ void load_px(const T *__restrict__ row, int cf, int W, bool vec, uint32_t (&px)[CPL]) {
   if constexpr (CPL == 4 && sizeof(T) == 2) {
@@ -121,6 +96,49 @@ __device__ __forceinline__ void load_px(const T *__restrict__ row, int cf, int W
   for (int e = 0; e < CPL; ++e) px[e] = cf + e < W ? (uint32_t)row[cf + e] : 0u;
 }
 
+// Band aggregate of one tile from the per-column counts of the band's rows:
+//   A(p, c) = sum over the band's rows and columns c' <= c of [bin = p]
+// (this tile's column prefix plus the band's totals of the tiles to its left,
+// lcs), its moment versions, and the tile's totals (tot).
+template <int CPL, int PG, bool MOM>
+__device__ __forceinline__ void op_aggregate(const uint32_t (&cnt)[PG][CPL], const uint32_t (&cntx)[MOM ? PG : 1][CPL],
+                                             int cf, const uint32_t (&lcs)[PG], const uint32_t (&lcxs)[PG],
+                                             const uint32_t (&lcys)[PG], uint32_t (&A)[PG][CPL],
+                                             uint32_t (&AX)[MOM ? PG : 1][CPL], uint32_t (&AY)[MOM ? PG : 1][CPL],
+                                             uint32_t (&tot)[PG], uint32_t (&totx)[PG], uint32_t (&toty)[PG]) {
+#pragma unroll
+  for (int k = 0; k < PG; ++k) {
+    uint32_t v[CPL];
+    v[0] = cnt[k][0];
+#pragma unroll
+    for (int e = 1; e < CPL; ++e) v[e] = v[e - 1] + cnt[k][e];
+    const uint32_t inc = wave_incl_scan(v[CPL - 1]);
+    const uint32_t ex = inc - v[CPL - 1];
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) A[k][e] = lcs[k] + ex + v[e];
+    tot[k] = read_lane(inc, 63);
+    if constexpr (MOM) {
+      uint32_t vx[CPL], vy[CPL];
+      vx[0] = cntx[k][0];
+      vy[0] = cnt[k][0] * (uint32_t)cf;
+#pragma unroll
+      for (int e = 1; e < CPL; ++e) {
+        vx[e] = vx[e - 1] + cntx[k][e];
+        vy[e] = vy[e - 1] + cnt[k][e] * (uint32_t)(cf + e);
+      }
+      const uint32_t ix = wave_incl_scan(vx[CPL - 1]), iy = wave_incl_scan(vy[CPL - 1]);
+      const uint32_t exx = ix - vx[CPL - 1], exy = iy - vy[CPL - 1];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) {
+        AX[k][e] = lcxs[k] + exx + vx[e];
+        AY[k][e] = lcys[k] + exy + vy[e];
+      }
+      totx[k] = read_lane(ix, 63);
+      toty[k] = read_lane(iy, 63);
+    }
+  }
+}
+
 // One worker: band b, plane group gi.  lc: this wave's LDS slice of
 // R * PG (count row carries) [+ R * PG (column-moment row carries)] words.
 template <typename T, int CPL, int PG, bool MOM>
@@ -139,99 +157,98 @@ __device__ __forceinline__ void op_bhw_worker(const OpArgs &a, const OpGeom &g, 
   const bool pvec = ((uintptr_t)a.img % (CPL * sizeof(T)) == 0) && (g.W % CPL == 0);
   const int TW = 64 * CPL;
   const bool last_band = b == g.nB - 1;
+  const int64_t fstride = (int64_t)g.nG * g.nT;  // flag distance between bands
+  const int64_t fgrp = (int64_t)gi * g.nT;       // flag index of (band 0, this group, tile 0)
   uint32_t *lcy = lc + g.R * PG;
-
-  for (int i = lane; i < g.R * PG * (MOM ? 2 : 1); i += 64) lc[i] = 0u;
-  wave_sync();
-  // band sums of the row carries: sum_r LC, sum_r r * LC, sum_r LCY per plane
-  uint32_t lcs[PG] = {}, lcxs[PG] = {}, lcys[PG] = {};
   uint32_t bad = 0;
 
-  int32_t *out_base = a.ih + ((int64_t)ch * g.bins + kb) * HW;
-  int32_t *mx_base = MOM ? reinterpret_cast<int32_t *>(a.mx) + ((int64_t)ch * g.bins + kb) * HW : nullptr;
-  int32_t *my_base = MOM ? reinterpret_cast<int32_t *>(a.my) + ((int64_t)ch * g.bins + kb) * HW : nullptr;
+  auto slot = [&](int64_t off, int64_t fi, int arr) { return a.ws + off + (fi * g.arrays + arr) * g.slot; };
+  auto publish = [&](int64_t off, int64_t fi, uint32_t state, const uint32_t (&v)[PG][CPL],
+                     const uint32_t (&vx)[MOM ? PG : 1][CPL], const uint32_t (&vy)[MOM ? PG : 1][CPL]) {
+    const int el = lane * CPL;
+#pragma unroll
+    for (int k = 0; k < PG; ++k) {
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) {
+        st_dev(slot(off, fi, 0) + k * TW + el + e, v[k][e]);
+        if constexpr (MOM) {
+          st_dev(slot(off, fi, 1) + k * TW + el + e, vx[k][e]);
+          st_dev(slot(off, fi, 2) + k * TW + el + e, vy[k][e]);
+        }
+      }
+    }
+    order_release();
+    if (lane == 0) st_dev(F + fi, state);
+  };
 
-  for (int j = 0; j < g.nT; ++j) {
-    const int C0 = j * TW;
-    const int cf = C0 + lane * CPL;
-    // ---- 1. per-column counts of the band's rows
+  // Rows are software-pipelined D deep in both sweeps: the pixels (and in
+  // the write-out the row carries) of the next D rows are in flight while a
+  // row is counted or written.
+  constexpr int D = CPL * PG <= 4 ? 4 : (CPL * PG <= 8 ? 2 : 1);
+
+  // ---- sweep A, one tile: its band aggregate, published at once (band 0
+  //      has nothing above it: its aggregate is already its inclusive bottom
+  //      row).  Nothing here waits.
+  uint32_t lcs[PG] = {}, lcxs[PG] = {}, lcys[PG] = {};
+  auto count_tile = [&](int j) {
+    const int cf = j * TW + lane * CPL;
     uint32_t cnt[PG][CPL] = {}, cntx[MOM ? PG : 1][CPL] = {};
-    {
-      int rr = 0;
-      for (; rr + 4 <= rows; rr += 4) {
-        uint32_t px[4][CPL];
+    uint32_t px[D][CPL];
+    static_for<D>([&](auto SLOT) {
+      constexpr int d = decltype(SLOT)::value;
+      if (d < rows) load_px<T, CPL>(img + (int64_t)(R0 + d) * g.W, cf, g.W, pvec, px[d]);
+    });
+    for (int r0 = 0; r0 < rows; r0 += D) {
+      static_for<D>([&](auto SLOT) {
+        constexpr int d = decltype(SLOT)::value;
+        const int rr = r0 + d;
+        if (rr < rows) {
+          uint32_t cur[CPL];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) load_px<T, CPL>(img + (int64_t)(R0 + rr + q) * g.W, cf, g.W, pvec, px[q]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
+          for (int e = 0; e < CPL; ++e) cur[e] = px[d][e];
+          if (rr + D < rows) load_px<T, CPL>(img + (int64_t)(R0 + rr + D) * g.W, cf, g.W, pvec, px[d]);
 #pragma unroll
           for (int e = 0; e < CPL; ++e) {
-            bad |= px[q][e] >> a.bits;
-            const int bb = cf + e < g.W ? (int)(((uint64_t)px[q][e] * g.bins) >> a.bits) - kb : -1;
+            bad |= cur[e] >> a.bits;
+            const int bb = cf + e < g.W ? (int)(((uint64_t)cur[e] * g.bins) >> a.bits) - kb : -1;
 #pragma unroll
             for (int k = 0; k < PG; ++k) {
               const uint32_t hit = bb == k ? 1u : 0u;
               cnt[k][e] += hit;
-              if constexpr (MOM) cntx[k][e] += hit * (uint32_t)(R0 + rr + q);
+              if constexpr (MOM) cntx[k][e] += hit * (uint32_t)(R0 + rr);
             }
           }
         }
-      }
-      for (; rr < rows; ++rr) {
-        uint32_t px[CPL];
-        load_px<T, CPL>(img + (int64_t)(R0 + rr) * g.W, cf, g.W, pvec, px);
-#pragma unroll
-        for (int e = 0; e < CPL; ++e) {
-          bad |= px[e] >> a.bits;
-          const int bb = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
-#pragma unroll
-          for (int k = 0; k < PG; ++k) {
-            const uint32_t hit = bb == k ? 1u : 0u;
-            cnt[k][e] += hit;
-            if constexpr (MOM) cntx[k][e] += hit * (uint32_t)(R0 + rr);
-          }
-        }
-      }
+      });
     }
-    // ---- aggregates in integral form, and this tile's totals
     uint32_t A[PG][CPL], AX[MOM ? PG : 1][CPL], AY[MOM ? PG : 1][CPL];
-    uint32_t tot[PG], totx[MOM ? PG : 1], toty[MOM ? PG : 1];
+    uint32_t tot[PG], totx[PG], toty[PG];
+    op_aggregate<CPL, PG, MOM>(cnt, cntx, cf, lcs, lcxs, lcys, A, AX, AY, tot, totx, toty);
+    if (!last_band) {
+      if (b == 0) publish(g.off_inc, fgrp + j, 2u, A, AX, AY);
+      else publish(g.off_agg, (int64_t)b * fstride + fgrp + j, 1u, A, AX, AY);
+    }
 #pragma unroll
     for (int k = 0; k < PG; ++k) {
-      uint32_t v[CPL];
-      v[0] = cnt[k][0];
-#pragma unroll
-      for (int e = 1; e < CPL; ++e) v[e] = v[e - 1] + cnt[k][e];
-      const uint32_t inc = wave_incl_scan(v[CPL - 1]);
-      const uint32_t ex = inc - v[CPL - 1];
-#pragma unroll
-      for (int e = 0; e < CPL; ++e) A[k][e] = lcs[k] + ex + v[e];
-      tot[k] = read_lane(inc, 63);
+      lcs[k] += tot[k];
       if constexpr (MOM) {
-        uint32_t vx[CPL], vy[CPL];
-        vx[0] = cntx[k][0];
-        vy[0] = cnt[k][0] * (uint32_t)cf;
-#pragma unroll
-        for (int e = 1; e < CPL; ++e) {
-          vx[e] = vx[e - 1] + cntx[k][e];
-          vy[e] = vy[e - 1] + cnt[k][e] * (uint32_t)(cf + e);
-        }
-        const uint32_t ix = wave_incl_scan(vx[CPL - 1]), iy = wave_incl_scan(vy[CPL - 1]);
-        const uint32_t exx = ix - vx[CPL - 1], exy = iy - vy[CPL - 1];
-#pragma unroll
-        for (int e = 0; e < CPL; ++e) {
-          AX[k][e] = lcxs[k] + exx + vx[e];
-          AY[k][e] = lcys[k] + exy + vy[e];
-        }
-        totx[k] = read_lane(ix, 63);
-        toty[k] = read_lane(iy, 63);
+        lcxs[k] += totx[k];
+        lcys[k] += toty[k];
       }
     }
-    // ---- 2. top boundary from the bands above
+  };
+
+  // ---- sweep B, one tile: top boundary by look-back, this band's inclusive
+  //      row for the bands below, then the write-out of the band's rows
+  int32_t *out_base = a.ih + ((int64_t)ch * g.bins + kb) * HW;
+  int32_t *mx_base = MOM ? reinterpret_cast<int32_t *>(a.mx) + ((int64_t)ch * g.bins + kb) * HW : nullptr;
+  int32_t *my_base = MOM ? reinterpret_cast<int32_t *>(a.my) + ((int64_t)ch * g.bins + kb) * HW : nullptr;
+  bool gave_up = false;
+  auto write_tile = [&](int j) {
+    const int C0 = j * TW;
+    const int cf = C0 + lane * CPL;
+    const int64_t gj = fgrp + j;
     uint32_t top[PG][CPL] = {}, topx[MOM ? PG : 1][CPL] = {}, topy[MOM ? PG : 1][CPL] = {};
-    const int64_t fstride = (int64_t)g.nG * g.nT;       // flag distance between bands
-    const int64_t fidx = ((int64_t)b * g.nG + gi) * g.nT + j;
-    auto slot = [&](int64_t off, int64_t fi, int arr) { return a.ws + off + (fi * g.arrays + arr) * g.slot; };
     auto add_payload = [&](int64_t off, int64_t fi) {
       const int el = lane * CPL;
 #pragma unroll
@@ -246,122 +263,160 @@ __device__ __forceinline__ void op_bhw_worker(const OpArgs &a, const OpGeom &g, 
         }
       }
     };
-    auto publish = [&](int64_t off, int64_t fi, uint32_t state, const uint32_t (&v)[PG][CPL],
-                       const uint32_t (&vx)[MOM ? PG : 1][CPL], const uint32_t (&vy)[MOM ? PG : 1][CPL]) {
-      const int el = lane * CPL;
-#pragma unroll
-      for (int k = 0; k < PG; ++k) {
-#pragma unroll
-        for (int e = 0; e < CPL; ++e) {
-          st_dev(slot(off, fi, 0) + k * TW + el + e, v[k][e]);
-          if constexpr (MOM) {
-            st_dev(slot(off, fi, 1) + k * TW + el + e, vx[k][e]);
-            st_dev(slot(off, fi, 2) + k * TW + el + e, vy[k][e]);
-          }
+    // top boundary H(p, R0 - 1, c): the nearest band above that has published
+    // its inclusive bottom row, plus the aggregates of the bands in between.
+    // Lane i reads the flag of band hi - i, so one load covers 64 bands.  A
+    // band publishes its aggregate in sweep A, which never waits, so every
+    // wait here ends.
+    if (b > 0 && !gave_up) {
+      if (a.patience > 0) {  // optionally give the band above time to publish its row
+        for (int it = 0; it < a.patience; ++it) {
+          if (uniform((int)ld_dev(F + (int64_t)(b - 1) * fstride + gj)) == 2) break;
+          __builtin_amdgcn_s_sleep(1);
         }
       }
-      order_release();
-      if (lane == 0) st_dev(F + fi, state);
-    };
-    if (b > 0) {
-      int64_t fp = fidx - fstride;  // the band above
-      uint32_t f = op_poll(F + fp, hdr, a.patience);
-      if (f != 2) {
-        // not ready yet: publish this band's aggregate so that the bands
-        // below need not wait for this one, then walk up
-        if (!last_band) publish(g.off_agg, fidx, 1u, A, AX, AY);
-        for (int bb = b - 1;;) {
-          f = op_poll(F + fp, hdr, -1);
-          if (f == 2) {
-            add_payload(g.off_inc, fp);
+      for (int hi = b - 1; hi >= 0; hi -= 64) {
+        const int mb = hi - lane;
+        const uint64_t live = hi >= 63 ? ~0ull : ((1ull << (hi + 1)) - 1);
+        uint64_t m2 = 0;
+        int n_agg = 0;
+        bool ready = false;
+        for (uint32_t it = 0;; ++it) {
+          const uint32_t f = mb >= 0 ? ld_dev(F + (int64_t)mb * fstride + gj) : 0u;
+          m2 = ballot(mb >= 0 && f == 2u);
+          const uint64_t m0 = ballot(mb >= 0 && f == 0u);
+          const uint64_t cover = m2 ? (((m2 & (~m2 + 1)) << 1) - 1) : live;
+          if ((m0 & cover) == 0) {
+            n_agg = m2 ? (int)__builtin_ctzll(m2) : __builtin_popcountll(live);
+            ready = true;
             break;
           }
-          if (f != 1) break;  // the wait gave up (status word set)
-          add_payload(g.off_agg, fp);
-          if (--bb < 0) break;
-          fp -= fstride;
-        }
-      } else {
-        add_payload(g.off_inc, fp);
-      }
-    }
-    // ---- 3. inclusive bottom row of this band for the bands below
-    if (!last_band) {
-      uint32_t I[PG][CPL], IX[MOM ? PG : 1][CPL], IY[MOM ? PG : 1][CPL];
-#pragma unroll
-      for (int k = 0; k < PG; ++k) {
-#pragma unroll
-        for (int e = 0; e < CPL; ++e) {
-          I[k][e] = top[k][e] + A[k][e];
-          if constexpr (MOM) {
-            IX[k][e] = topx[k][e] + AX[k][e];
-            IY[k][e] = topy[k][e] + AY[k][e];
+          if ((it & 63) == 63) {
+            if (uniform((int)ld_dev(hdr + kHdrAbort))) break;
+            if (it >= kSpinLimit) {
+              if (lane == 0) {
+                __hip_atomic_fetch_or(hdr + kHdrStatus, (uint32_t)IH_STATUS_WAIT_TIMEOUT, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                st_dev(hdr + kHdrAbort, 1u);
+              }
+              break;
+            }
           }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (!ready) {
+          gave_up = true;  // the result is invalid; the status word says so
+          break;
+        }
+        order_acquire();
+        for (int i = 0; i < n_agg; ++i) add_payload(g.off_agg, (int64_t)(hi - i) * fstride + gj);
+        if (m2) {
+          add_payload(g.off_inc, (int64_t)(hi - n_agg) * fstride + gj);
+          break;
         }
       }
-      publish(g.off_inc, fidx, 2u, I, IX, IY);
-    }
-    // ---- 4. write-out of the band's rows of this tile
-    uint32_t (&col)[PG][CPL] = top;
-    for (int rr = 0; rr < rows; ++rr) {
-      const int r = R0 + rr;
-      uint32_t px[CPL];
-      load_px<T, CPL>(img + (int64_t)r * g.W, cf, g.W, pvec, px);
-      int bq[CPL];
+      if (!last_band) {
+        uint32_t I[PG][CPL], IX[MOM ? PG : 1][CPL], IY[MOM ? PG : 1][CPL];
+        const int64_t own = (int64_t)b * fstride + gj;
+        const int el = lane * CPL;
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) bq[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
-      const int64_t orow = (int64_t)r * g.W + cf;
-#pragma unroll
-      for (int k = 0; k < PG; ++k) {
-        if (k < nk) {
-          const uint32_t lcur = (uint32_t)uniform((int)lc[rr * PG + k]);
-          uint32_t tq = lcur;
-          uint64_t m[CPL];
-#pragma unroll
-          for (int e = 0; e < CPL; ++e) m[e] = ballot(bq[e] == k);
-#pragma unroll
-          for (int e = 0; e < CPL; ++e) tq = lanes_below(m[e], tq);
-          uint32_t pre[CPL];
+        for (int k = 0; k < PG; ++k) {
 #pragma unroll
           for (int e = 0; e < CPL; ++e) {
-            tq += bq[e] == k ? 1u : 0u;
-            pre[e] = tq;
-            col[k][e] += tq;
-          }
-          put<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec);
-          const uint32_t nlc = read_lane(tq, 63);
-          if constexpr (MOM) {
-            const uint32_t lycur = (uint32_t)uniform((int)lcy[rr * PG + k]);
-            uint32_t y[CPL];
-#pragma unroll
-            for (int e = 0; e < CPL; ++e) {
-              topx[k][e] += (uint32_t)r * pre[e];
-              y[e] = bq[e] == k ? (uint32_t)(cf + e) : 0u;
+            I[k][e] = top[k][e] + ld_dev(slot(g.off_agg, own, 0) + k * TW + el + e);
+            if constexpr (MOM) {
+              IX[k][e] = topx[k][e] + ld_dev(slot(g.off_agg, own, 1) + k * TW + el + e);
+              IY[k][e] = topy[k][e] + ld_dev(slot(g.off_agg, own, 2) + k * TW + el + e);
             }
-#pragma unroll
-            for (int e = 1; e < CPL; ++e) y[e] += y[e - 1];
-            const uint32_t iy = wave_incl_scan(y[CPL - 1]);
-            const uint32_t ey = iy - y[CPL - 1] + lycur;
-#pragma unroll
-            for (int e = 0; e < CPL; ++e) topy[k][e] += ey + y[e];
-            put<CPL>(mx_base + k * HW + orow, topx[k], cf, g.W, vec);
-            put<CPL>(my_base + k * HW + orow, topy[k], cf, g.W, vec);
-            const uint32_t nly = lycur + read_lane(iy, 63);
-            if (lane == 0) lcy[rr * PG + k] = nly;
           }
-          if (lane == 0) lc[rr * PG + k] = nlc;
         }
+        publish(g.off_inc, own, 2u, I, IX, IY);
       }
+    }
+    // write-out of the band's rows of this tile
+    uint32_t (&col)[PG][CPL] = top;
+    uint32_t px[D][CPL], lcv[D][PG], lcyv[D][MOM ? PG : 1];
+    auto fetch = [&](int rr, auto SLOT) {
+      constexpr int d = decltype(SLOT)::value;
+      load_px<T, CPL>(img + (int64_t)(R0 + rr) * g.W, cf, g.W, pvec, px[d]);
+#pragma unroll
+      for (int k = 0; k < PG; ++k) {
+        lcv[d][k] = lc[rr * PG + k];
+        if constexpr (MOM) lcyv[d][k] = lcy[rr * PG + k];
+      }
+    };
+    static_for<D>([&](auto SLOT) {
+      if (decltype(SLOT)::value < rows) fetch(decltype(SLOT)::value, SLOT);
+    });
+    for (int r0 = 0; r0 < rows; r0 += D) {
+      static_for<D>([&](auto SLOT) {
+        constexpr int d = decltype(SLOT)::value;
+        const int rr = r0 + d;
+        if (rr < rows) {
+          const int r = R0 + rr;
+          int bq[CPL];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e)
+            bq[e] = cf + e < g.W ? (int)(((uint64_t)px[d][e] * g.bins) >> a.bits) - kb : -1;
+          uint32_t lcur[PG], lycur[MOM ? PG : 1];
+#pragma unroll
+          for (int k = 0; k < PG; ++k) {
+            lcur[k] = (uint32_t)uniform((int)lcv[d][k]);
+            if constexpr (MOM) lycur[k] = (uint32_t)uniform((int)lcyv[d][k]);
+          }
+          if (rr + D < rows) fetch(rr + D, SLOT);
+          const int64_t orow = (int64_t)r * g.W + cf;
+#pragma unroll
+          for (int k = 0; k < PG; ++k) {
+            if (k < nk) {
+              uint32_t tq = lcur[k];
+              uint64_t m[CPL];
+#pragma unroll
+              for (int e = 0; e < CPL; ++e) m[e] = ballot(bq[e] == k);
+#pragma unroll
+              for (int e = 0; e < CPL; ++e) tq = lanes_below(m[e], tq);
+              uint32_t pre[CPL];
+#pragma unroll
+              for (int e = 0; e < CPL; ++e) {
+                tq += bq[e] == k ? 1u : 0u;
+                pre[e] = tq;
+                col[k][e] += tq;
+              }
+              put<CPL>(out_base + k * HW + orow, col[k], cf, g.W, vec);
+              const uint32_t nlc = read_lane(tq, 63);
+              if constexpr (MOM) {
+                uint32_t y[CPL];
+#pragma unroll
+                for (int e = 0; e < CPL; ++e) {
+                  topx[k][e] += (uint32_t)r * pre[e];
+                  y[e] = bq[e] == k ? (uint32_t)(cf + e) : 0u;
+                }
+#pragma unroll
+                for (int e = 1; e < CPL; ++e) y[e] += y[e - 1];
+                const uint32_t iy = wave_incl_scan(y[CPL - 1]);
+                const uint32_t ey = iy - y[CPL - 1] + lycur[k];
+#pragma unroll
+                for (int e = 0; e < CPL; ++e) topy[k][e] += ey + y[e];
+                put<CPL>(mx_base + k * HW + orow, topx[k], cf, g.W, vec);
+                put<CPL>(my_base + k * HW + orow, topy[k], cf, g.W, vec);
+                if (lane == 0) lcy[rr * PG + k] = lycur[k] + read_lane(iy, 63);
+              }
+              if (lane == 0) lc[rr * PG + k] = nlc;
+            }
+          }
+        }
+      });
     }
     wave_sync();
-#pragma unroll
-    for (int k = 0; k < PG; ++k) {
-      lcs[k] += tot[k];
-      if constexpr (MOM) {
-        lcxs[k] += totx[k];
-        lcys[k] += toty[k];
-      }
-    }
+  };
+
+  // ---- the two sweeps, sweep A running `ahead` tiles in front of sweep B
+  for (int i = lane; i < g.R * PG * (MOM ? 2 : 1); i += 64) lc[i] = 0u;
+  wave_sync();
+  const int L = min(max(a.ahead, 0), g.nT);
+  for (int s2 = 0; s2 < g.nT + L; ++s2) {
+    if (s2 < g.nT) count_tile(s2);
+    if (s2 >= L) write_tile(s2 - L);
   }
   if (ballot(bad != 0) && lane == 0)
     __hip_atomic_fetch_or(hdr + kHdrStatus, (uint32_t)IH_STATUS_VALUE_RANGE, __ATOMIC_RELAXED,

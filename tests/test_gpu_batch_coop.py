@@ -22,3 +22,30 @@ def test_batch_cooperative_equals_phased(layout):
     torch.cuda.synchronize()
     for a, b in zip(coop, batch.ih):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("layout", ["bhw", "hwb"])
+def test_batch_cooperative_64_uneven_frames(layout):
+    """The benchmark's 64 uneven frames (4,096 candidates each): the
+    cooperative launch's histograms, distances and best candidates equal the
+    phased launches', which the oracle checks in test_batch_64_uneven_frames."""
+    import paper_1711_01656_amd as ih
+    import synth
+    print("64 uneven frames, cooperative vs phased", layout, flush=True)
+    frames = [dict(img=torch.from_numpy(f.img).cuda(), bins=f.bins, value_bits=f.bits,
+                   origins=torch.from_numpy(f.origins).cuda(), win=(32, 32), tmpl_win=f.tmpl_win)
+              for f in synth.config4()]
+    batch = ih.Batch(frames, "chi2", layout=layout)
+    batch.run("phased")
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in batch.ih]
+    ref_d = [t.clone() for t in batch.dist]
+    ref_b = [t.clone() for t in batch.best]
+    for t in batch.ih:
+        t.fill_(-1)
+    batch.run("cooperative")
+    torch.cuda.synchronize()
+    for i in range(len(frames)):
+        assert torch.equal(batch.ih[i], ref[i]), i
+        assert torch.equal(batch.dist[i], ref_d[i]), i
+        assert torch.equal(batch.best[i], ref_b[i]), i
