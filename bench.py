@@ -22,6 +22,7 @@ import argparse
 import glob
 import hashlib
 import json
+import math
 import os
 import platform
 import sys
@@ -344,7 +345,9 @@ def measure_step(torch, ih, step, steps, warmup, trials, alg_bytes, workload):
         "build_roofline": {"bound": "hbm", "kernel": "whole build (%s)" % ("init + band kernel" if one else
                                                                           "tile pass + carry scan + write-out"),
                            "achieved": round(alg_bytes / build_ms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(alg_bytes / build_ms / 1e6 / HBM_PEAK_GBS, 4)},
+                           "frac": round(alg_bytes / build_ms / 1e6 / HBM_PEAK_GBS, 4),
+                           "traffic": profiled_traffic("whole build", "%s %s %s" % (workload, step.layout,
+                                                                                    repr(step.cfg)))},
         "dominant_kernel": {"kernel": kname, "ms": round(k_ms, 4),
                             "achieved": round(alg_bytes / k_ms / 1e6, 1),
                             "frac": round(alg_bytes / k_ms / 1e6 / HBM_PEAK_GBS, 4),
@@ -758,7 +761,7 @@ def config1_leg(torch, ih, synth, args):
 def batch_leg(torch, ih, synth, args, fixed=False):
     """64 uneven frames (320x240 to 2048x2048, 8-64 bins) built and searched
     (4,096 candidates each) as one batch: phased launches replayed from a HIP
-    graph, the cooperative single launch eagerly and replayed from a graph,
+    graph and the cooperative single launch (which cannot be captured),
     against the same frames one call at a time."""
     from paper_1711_01656_amd import tune
     dev = torch.device("cuda:0")
@@ -783,14 +786,8 @@ def batch_leg(torch, ih, synth, args, fixed=False):
         t_graph = graph_median(torch, lambda: batch.run("phased"), 5)
         t_coop = float(np.median([time_calls(torch, lambda: batch.run("cooperative"), 5) for _ in range(3)]))
         same = all(torch.equal(a, b) for a, b in zip(ref, batch.best))
-        coop_graph = None
-        try:
-            coop_graph = round(graph_median(torch, lambda: batch.run("cooperative"), 5), 3)
-            same = same and all(torch.equal(a, b) for a, b in zip(ref, batch.best))
-        except Exception as e:          # capture refused by the runtime: reported as such
-            coop_graph = "capture failed: %s" % str(e).splitlines()[0][:160]
         per_layout[lay] = {"tile": repr(tile), "graph_phased_ms": round(t_graph, 3),
-                           "cooperative_ms": round(t_coop, 3), "cooperative_graph_ms": coop_graph,
+                           "cooperative_ms": round(t_coop, 3),
                            "gpxbins_per_s_graph": round(total / t_graph / 1e6, 2),
                            "ih_write_gbs_graph": round(total * 4 / t_graph / 1e6, 1),
                            "frac_of_peak_graph": round(total * 4 / t_graph / 1e6 / HBM_PEAK_GBS, 4),
@@ -923,7 +920,8 @@ def cpu_tracker(frames_np, box0, ex_origins, min_seconds=6.0, threads=0):
 # the learned search's settings: with the bounded gate they change only how
 # many candidates are scored exactly (the track is the exhaustive one for any
 # value); the margin-only variant's agreement depends on them
-TRACKER_TAU, TRACKER_ROUNDS, TRACKER_Q = 0.1, 2, 2
+TRACKER_TAU, TRACKER_ROUNDS, TRACKER_Q = 0.1, 0, 2
+MARGIN_ONLY_ROUNDS = 2
 
 
 def tracker_leg(torch, args):
@@ -985,9 +983,10 @@ def tracker_leg(torch, args):
     base = trk.LearnedTracker(tr_r, None, k=64, tau=tau, prior_logits=prior, refine_rounds=rounds, refine_q=q,
                               bound=True)
     free_b, fps_b = timed(tr_r, base)
-    margin = trk.LearnedTracker(tr_r, net, k=64, tau=tau, refine_rounds=rounds, refine_q=q)
+    margin = trk.LearnedTracker(tr_r, net, k=64, tau=tau, refine_rounds=MARGIN_ONLY_ROUNDS, refine_q=q)
     free_m, fps_m = timed(tr_r, margin)
-    margin_b = trk.LearnedTracker(tr_r, None, k=64, tau=tau, prior_logits=prior, refine_rounds=rounds, refine_q=q)
+    margin_b = trk.LearnedTracker(tr_r, None, k=64, tau=tau, prior_logits=prior, refine_rounds=MARGIN_ONLY_ROUNDS,
+                                  refine_q=q)
     unref = trk.LearnedTracker(tr_r, net, k=64, tau=tau)
     # per-frame agreement: every search starts from the exhaustive trajectory
     forced = trk.track(frames, box0, tr_r, learned, teacher=ex)
@@ -1005,14 +1004,24 @@ def tracker_leg(torch, args):
         neighbourhoods and the exhaustive list's listed offsets."""
         return round(float(np.mean(64 + rounds * (2 * q + 1) ** 2 + t.scored[1:])), 1)
 
+    sweep = {}
+    for r, tau_s in ((0, tau), (1, tau), (2, tau), (4, tau), (0, 0.5), (0, math.inf)):
+        lt_r = trk.LearnedTracker(tr_r, net, k=64, tau=tau_s, refine_rounds=r, refine_q=q, bound=True)
+        _, fps_r = timed(tr_r, lt_r)
+        f_r = trk.track(frames, box0, tr_r, lt_r, teacher=ex)
+        sweep["rounds %d tau %s" % (r, tau_s)] = {
+            "fps": round(fps_r, 1), "agreement_per_frame": agree(f_r, ex),
+            "exact_scorings_per_frame": round(float(np.mean(64 + r * (2 * q + 1) ** 2 + f_r.scored[1:])), 1),
+            "fallback_rate": float(f_r.fallback[1:].mean())}
     x = net.crop(frames[1], torch.tensor([[box0[0] + box0[2] // 2, box0[1] + box0[3] // 2]], dtype=torch.int32,
                                          device=dev))
     fwd_ms = time_calls(torch, lambda: net.forward(x), 50)
     scaling = search_cost_vs_targets(torch, trk, lp, tr_f, net, frames[1], box0)
     res = {
         "workload": "1280x720 synthetic video, 300 frames, 7 channels x 16 bins; 65x65 offsets; top-64 learned "
-                    "+ %d rounds of %dx%d local refinement; bounded exhaustive search (level-0 lower bound) "
-                    "when the margin rule accepts, full exhaustive search otherwise" % (rounds, 2 * q + 1, 2 * q + 1),
+                    "proposals%s; bounded exhaustive search (2-level pyramid lower bound) when the margin rule "
+                    "accepts, full exhaustive search otherwise"
+                    % (" + %d rounds of %dx%d local refinement" % (rounds, 2 * q + 1, 2 * q + 1) if rounds else ""),
         "fps_exhaustive": round(fps_ex, 1),
         "fps_exhaustive_region_ih": round(fps_ex_r, 1),
         "fps_learned": round(fps_l, 1),
@@ -1023,6 +1032,7 @@ def tracker_leg(torch, args):
         "region_ih_track_equals_frame_ih_track": bool(np.array_equal(ex.origins, ex_r.origins)
                                                       and np.array_equal(ex.dists, ex_r.dists)),
         "tau": tau, "refine_rounds": rounds, "refine_window": 2 * q + 1,
+        "margin_only_refine_rounds": MARGIN_ONLY_ROUNDS,
         "agreement_per_frame": agree(forced, ex),
         "agreement_per_frame_no_network": agree(forced_b, ex),
         "agreement_per_frame_margin_only": agree(forced_m, ex),
@@ -1033,6 +1043,7 @@ def tracker_leg(torch, args):
         "fallback_rate_margin_only_without_refinement": float(forced_u.fallback[1:].mean()),
         "exact_scorings_per_frame": {"exhaustive": lp.N_OFFSETS, "learned": scorings(forced),
                                      "no_network": scorings(forced_b)},
+        "bounded_sweep": sweep,
         "recall_top64": round(trk.recall(net, frames, held), 4),
         "recall_top64_no_network": round(trk.recall(prior, frames, held), 4),
         "free_running_equals_exhaustive": bool(np.array_equal(free.origins, ex.origins)),
@@ -1154,10 +1165,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["build_roofline"]["frac"],
-            "traffic": dk["traffic"],
+            "traffic": head["build_roofline"]["traffic"],
             "alg_bytes_per_launch": alg,
             "dominant_kernel": {"kernel": dk["kernel"], "achieved": dk["achieved"], "frac": dk["frac"],
-                                "ms": dk["ms"]},
+                                "ms": dk["ms"], "traffic": dk["traffic"]},
             "measured_write_peak": round(write_peak, 1),
             "frac_of_measured_write_peak": round(head["build_roofline"]["achieved"] / write_peak, 4),
         },

@@ -383,7 +383,11 @@ typedef enum {
  *   mode       ih_batch_mode; both produce identical results.
  * Phases: tile histograms, carry scans, write-out, template descriptors,
  * candidate scoring, best candidate; each phase of a frame depends only on
- * earlier phases of the same frame.
+ * earlier phases of the same frame.  The phased mode allocates and
+ * synchronises nothing and may be captured in a HIP graph.  The cooperative
+ * mode returns IH_ERR_UNSUPPORTED, enqueuing nothing, when the stream is
+ * capturing: a captured cooperative launch becomes a plain kernel node whose
+ * grid barrier has no co-residency guarantee.
  */
 int ih_build_batch(const void *plan_host, const void *plan_dev, void *ws,
                    size_t ws_bytes, int32_t mode, void *stream);

@@ -173,8 +173,8 @@ int ih_lp_topk(const float *logits, int32_t B, int32_t n, int32_t k,
  *   ih_build                         integral histogram of that buffer
  *   ih_track_prepare                 base = previous origin, crop centre
  *   (learned) crop, network, ih_lp_topk, ih_lp_origins, ih_match_candidates
- *   over the k proposals, then ih_track_gate, or (bounded) the level-0
- *   distances of all offsets and ih_track_gate_bounded
+ *   over the k proposals, then ih_track_gate, or (bounded) the pyramid
+ *   distances of all offsets with one level fewer and ih_track_gate_bounded
  *   (exhaustive only) ih_lp_origins over all offsets
  *   ih_match_candidates over the exhaustive list, ih_track_commit
  * The gate implements the fallback rule: the best proposal is accepted when
@@ -216,13 +216,15 @@ int ih_track_gate(ih_track_state *st, const int32_t *idx, const float *kdist,
 /* Bounded form of ih_track_gate, which keeps the search exact.  When the
    margin rule accepts the best proposal (distance d <= (1 + tau) * dist), the
    exhaustive list keeps only the offsets whose lower bound lb [(2 radius +
-   1)^2] (the level-0 distance of each offset, from ih_match_candidates with
-   levels = 1 over all offsets, metric chi2 or L1) does not exceed d, within
-   a relative 2^-16 for rounding; the others get origins outside every frame.
-   The pyramid distance of Eq. 2.24 is at least its level-0 distance (the
-   level weights sum to 1 and merging cells never raises a chi-square or L1
-   sum), so the scoring of that list returns the exhaustive search's argmin
-   and distance (ties included).  Otherwise (a fallback) every offset is
+   1)^2] does not exceed d, within a relative 2^-16 for rounding; the others
+   get origins outside every frame.  lb is the pyramid distance of each
+   offset with one level fewer (ih_match_candidates with levels - 1 levels
+   over all offsets and the leading part of the template descriptor, metric
+   chi2 or L1): merging cells never raises a chi-square or L1 sum, so the
+   level sums grow with the level, and the Eq. 2.24 distance of L + 1 levels
+   minus that of L levels is a non-negative combination of those sums'
+   differences; so the scoring of that list returns the exhaustive search's
+   argmin and distance (ties included).  Otherwise (a fallback) every offset is
    listed.  st->decision = -2 (bounded) or -1 (fallback); st->scored = the
    number of listed offsets. */
 int ih_track_gate_bounded(ih_track_state *st, const float *kdist,

@@ -248,6 +248,7 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
       return set_error(IH_ERR_UNSUPPORTED, "frame %d: planes_per_wave %d > 8 in a batch", f, P.g.PG);
     size_t l;
     if ((e = pick_bc(P.g, kBatchLds, &P.bc, &l))) return set_error(e, "frame %d: %s", f, ih_last_error());
+    if (tile_fast(P.g)) l = tile_fast_lds(P.g);
     if (l > lds) lds = l;
     if (l > lph[0]) lph[0] = l;
     P.img = F.img;
@@ -363,7 +364,16 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
   if (per_cu < 1) return set_error(IH_ERR_UNSUPPORTED, "batch kernel cannot be resident (LDS %d)", h->lds);
   const int64_t resident = (int64_t)per_cu * cus;
   void *args[] = {(void *)&hd, (void *)&fd, (void *)&w32};
-  return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(cf), dim3((unsigned)resident), dim3(256),
-                                              args, (unsigned)h->lds, s),
+  // A cooperative launch recorded by stream capture becomes a plain kernel
+  // node, whose grid barrier then has no co-residency guarantee, so the
+  // cooperative mode refuses to be captured (the phased mode is the one to
+  // capture in a graph).
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if ((e = hip_check(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing"))) return e;
+  if (cs != hipStreamCaptureStatusNone)
+    return set_error(IH_ERR_UNSUPPORTED,
+                     "the cooperative batch launch cannot be captured in a graph (capture the phased mode)");
+  return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(cf), dim3((unsigned)resident),
+                                              dim3(256), args, (unsigned)h->lds, s),
                    "cooperative batch launch");
 }

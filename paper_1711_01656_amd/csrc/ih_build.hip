@@ -288,6 +288,7 @@ int ih::launch_build(const Geom &g, int dtype, const void *img, const void *tail
   int bc, e;
   size_t lds;
   if ((e = pick_bc(g, kLdsBudget, &bc, &lds, g.cum ? kCumChunk : (1 << 30)))) return e;
+  if (tile_fast(g)) lds = tile_fast_lds(g);  // registers count; LDS holds only the bins and totals
   uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
   const unsigned tiles = (unsigned)((int64_t)g.nTR * g.nTC * g.C);
   const unsigned hblocks = tiles * (unsigned)tile_chunks(g, bc);

@@ -61,6 +61,155 @@ inline size_t staged_lds(const Geom &g) {
 //    totals, sums of the column counts, follow.  Each chunk of bc bins is
 //    then a block of its own, which starts its prefixes from the samples of
 //    the lower bins in each column and row, counted from the staged bins.
+// Tile pass of a plain count build (with or without coordinate moments),
+// from the tile's bins staged in LDS: per-column counts over the tile's rows,
+// per-row counts over its columns and per-bin tile totals, counted in
+// registers four bins at a time (compares and adds, no histogram atomics),
+// each LDS word read bringing four bins.  Threads take (four columns or a
+// row, chunk of four bins) in the order that makes the stores coalesce:
+// column groups fastest for bin-major column carries (unit stride along
+// columns: one 16-byte store per bin), chunks fastest where the carries are
+// contiguous along bins (planes-innermost column carries, row carries: one
+// 16-byte store per chunk when bins is a multiple of four).
+// tot: 3 x bins words of LDS.
+template <bool MOM>
+__device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *bin_s, int twp, int ch, int I, int j,
+                                                 int R0, int C0, int th, int tw, uint32_t *__restrict__ ws,
+                                                 uint32_t *tot) {
+  constexpr int NB = 4;
+  const int tid = threadIdx.x;
+  const int nq = (g.bins + NB - 1) / NB;
+  const bool v4 = (g.bins & 3) == 0 && ((uintptr_t)ws & 15) == 0;
+  uint32_t *CC = ws + g.off_cc, *RC = ws + g.off_rc, *TT = ws + g.off_tt;
+  uint32_t *CCX = ws + g.off_ccx, *RCY = ws + g.off_rcy;
+  uint32_t *TTX = ws + g.off_ttx, *TTY = ws + g.off_tty;
+  for (int i = tid; i < 3 * g.bins; i += blockDim.x) tot[i] = 0u;
+  auto store4 = [&](uint32_t *dst, const uint32_t (&v)[NB], int k0) {
+    if (v4) {
+      *reinterpret_cast<uint4 *>(dst) = make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk)
+        if (k0 + kk < g.bins) dst[kk] = v[kk];
+    }
+  };
+  // ---- columns, four per thread (one LDS word per row)
+  const bool bhw = g.layout == IH_BHW;
+  const int ng = (tw + 3) / 4;
+  const bool cvec = ((uintptr_t)ws & 15) == 0 && (g.W & 3) == 0;  // bin-major rows of CC 16-byte aligned
+  for (int idx = tid; idx < ng * nq; idx += blockDim.x) {
+    const int cg = bhw ? idx % ng : idx / nq;
+    const int k0 = (bhw ? idx / ng : idx % nq) * NB;
+    uint32_t n[4][NB], nx[MOM ? 4 : 1][NB];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk) {
+        n[e][kk] = 0u;
+        if constexpr (MOM) nx[e][kk] = 0u;
+      }
+    const uint8_t *col = bin_s + 4 * cg;
+#pragma unroll 4
+    for (int r = 0; r < th; ++r) {
+      const uint32_t word = *reinterpret_cast<const uint32_t *>(col + r * twp);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int b = (int)((word >> (8 * e)) & 0xffu) - k0;
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk) {
+          const uint32_t hit = b == kk ? 1u : 0u;
+          n[e][kk] += hit;
+          if constexpr (MOM) nx[e][kk] += hit * (uint32_t)(R0 + r);
+        }
+      }
+    }
+    const int64_t p0 = (int64_t)ch * g.bins + k0;
+    const int cl0 = 4 * cg;
+    if (bhw) {
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk) {
+        if (k0 + kk >= g.bins) continue;
+        const int64_t o = cc_index(g, p0 + kk, I, C0 + cl0);
+        if (cvec && cl0 + 4 <= tw) {
+          *reinterpret_cast<uint4 *>(CC + o) = make_uint4(n[0][kk], n[1][kk], n[2][kk], n[3][kk]);
+          if constexpr (MOM)
+            *reinterpret_cast<uint4 *>(CCX + o) = make_uint4(nx[0][kk], nx[1][kk], nx[2][kk], nx[3][kk]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (cl0 + e < tw) {
+              CC[o + e] = n[e][kk];
+              if constexpr (MOM) CCX[o + e] = nx[e][kk];
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (cl0 + e < tw) {
+          const int64_t o = cc_index(g, p0, I, C0 + cl0 + e);  // planes consecutive
+          store4(CC + o, n[e], k0);
+          if constexpr (MOM) store4(CCX + o, nx[e], k0);
+        }
+      }
+    }
+  }
+  __syncthreads();  // tot cleared before the rows add to it
+  // ---- rows (four bins per LDS word), and the tile totals
+  for (int idx = tid; idx < th * nq; idx += blockDim.x) {
+    const int r = idx / nq, k0 = (idx % nq) * NB;
+    uint32_t n[NB] = {0u, 0u, 0u, 0u}, ny[NB] = {0u, 0u, 0u, 0u};
+    const uint8_t *row = bin_s + r * twp;
+    const int tw4 = tw & ~3;
+#pragma unroll 4
+    for (int c = 0; c < tw4; c += 4) {
+      const uint32_t word = *reinterpret_cast<const uint32_t *>(row + c);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int b = (int)((word >> (8 * e)) & 0xffu) - k0;
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk) {
+          const uint32_t hit = b == kk ? 1u : 0u;
+          n[kk] += hit;
+          if constexpr (MOM) ny[kk] += hit * (uint32_t)(C0 + c + e);
+        }
+      }
+    }
+    for (int c = tw4; c < tw; ++c) {
+      const int b = (int)row[c] - k0;
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk) {
+        const uint32_t hit = b == kk ? 1u : 0u;
+        n[kk] += hit;
+        if constexpr (MOM) ny[kk] += hit * (uint32_t)(C0 + c);
+      }
+    }
+    const size_t o = (((size_t)ch * g.nTC + j) * g.H + R0 + r) * g.bins + k0;
+    store4(RC + o, n, k0);
+    if constexpr (MOM) store4(RCY + o, ny, k0);
+#pragma unroll
+    for (int kk = 0; kk < NB; ++kk) {
+      if (k0 + kk < g.bins && n[kk]) {
+        atomicAdd(&tot[k0 + kk], n[kk]);
+        if constexpr (MOM) {
+          atomicAdd(&tot[g.bins + k0 + kk], n[kk] * (uint32_t)(R0 + r));
+          atomicAdd(&tot[2 * g.bins + k0 + kk], ny[kk]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < g.bins; k += blockDim.x) {
+    const size_t o = (((size_t)ch * g.bins + k) * g.nTR + I) * (size_t)g.nTC + j;
+    TT[o] = tot[k];
+    if constexpr (MOM) {
+      TTX[o] = tot[g.bins + k];
+      TTY[o] = tot[2 * g.bins + k];
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const Geom &g, int bits, int bc,
                                                uint32_t *__restrict__ ws, int blkid, uint32_t *lds,
@@ -117,6 +266,12 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
   uint32_t *CC = ws + g.off_cc, *RC = ws + g.off_rc, *TT = ws + g.off_tt;
   uint32_t *CCX = ws + g.off_ccx, *RCY = ws + g.off_rcy;
   uint32_t *TTX = ws + g.off_ttx, *TTY = ws + g.off_tty;
+  if (tile_fast(g)) {
+    __syncthreads();
+    if (g.mom) tile_counts_fast<true>(g, bin_s, twp, ch, I, j, R0, C0, th, tw, ws, hist);
+    else tile_counts_fast<false>(g, bin_s, twp, ch, I, j, R0, C0, th, tw, ws, hist);
+    return;
+  }
   const int stride = bc + 1;
 
   for (int b0 = b_begin; b0 < b_end; b0 += bc) {

@@ -107,41 +107,80 @@ __global__ __launch_bounds__(256) void k_lp_conv(const uint16_t *__restrict__ in
   }
 }
 
-// Weight-gradient partial sums.  Block (kt, chunk): 4 waves, each summing a
-// quarter of the chunk's output pixels for a 32 (co) x 32 (k) tile; the waves'
-// tiles are added in a fixed order and written to part[chunk][co][k],
-// k = 0..K (k = K: the bias gradient).
+// Weight-gradient partial sums.  Block (kt, chunk) owns a 32 (co) x 32 (k)
+// tile of dW = sum_pixels dZ[co][pixel] X[k][pixel] over one chunk of output
+// pixels, k = kt .. kt+31 (k = K is the column of ones: the bias gradient).
+// The chunk is walked in steps of kWgStep pixels: each thread decodes its
+// pixel once per step and stages that pixel's dZ column (32 channels) and
+// im2col column (the tile's 32 k) in LDS, loads coalesced along the row;
+// then each wave runs the matrix instructions over its quarter of the step
+// (8 pixels per instruction), its accumulator carried across steps.  The four
+// waves' tiles are added in a fixed order and written to part[chunk][co][k].
+constexpr int kWgStep = 256;
+constexpr int kWgLd = kWgStep + 4;  // LDS row of one channel / k: 8 bytes of padding keep b64 reads conflict-free
+
 __global__ __launch_bounds__(256) void k_lp_wgrad(const uint16_t *__restrict__ in, const uint16_t *__restrict__ dz,
                                                   float *__restrict__ part, ConvShape s, int64_t chunk) {
-  __shared__ float red[4][LP_CO * 32];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
+  constexpr int kStageBytes = 2 * 32 * kWgLd * 2;
+  constexpr int kRedBytes = 4 * LP_CO * 32 * 4;
+  __shared__ __align__(16) unsigned char lds[kStageBytes > kRedBytes ? kStageBytes : kRedBytes];
+  uint16_t *zs = reinterpret_cast<uint16_t *>(lds);
+  uint16_t *xs = zs + 32 * kWgLd;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
   const int kt = blockIdx.x * 32;
-  const int64_t npix = (int64_t)s.B * s.Hout * s.Wout;
+  const int64_t hw = (int64_t)s.Hout * s.Wout;
+  const int64_t npix = (int64_t)s.B * hw;
   const int64_t p_begin = (int64_t)blockIdx.y * chunk;
   const int64_t p_end = p_begin + chunk < npix ? p_begin + chunk : npix;
-  const int64_t quarter = (chunk / 4 + 7) & ~(int64_t)7;
-  const int64_t w_begin = p_begin + wave * quarter;
-  const int64_t w_end = w_begin + quarter < p_end ? w_begin + quarter : p_end;
-  const int co_a = lane & 31, k_b = kt + (lane & 31);
+  const int64_t in_plane = (int64_t)s.Hin * s.Win;
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int64_t p0 = w_begin; p0 < w_end; p0 += 8) {
-    bf16x4 a, bv;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t p = p0 + 4 * half + j;
-      if (p < w_end) {
-        const int x = (int)(p % s.Wout), y = (int)((p / s.Wout) % s.Hout), b = (int)(p / ((int64_t)s.Wout * s.Hout));
-        a[j] = (short)dz[(((int64_t)b * LP_CO + co_a) * s.Hout + y) * s.Wout + x];
-        bv[j] = im2col(in, s, k_b, b, y, x);
-      } else {
-        a[j] = 0;
-        bv[j] = 0;
+  for (int64_t p0 = p_begin; p0 < p_end; p0 += kWgStep) {
+    const int64_t p = p0 + tid;
+    const bool live = p < p_end;
+    int b = 0, y = 0, x = 0;
+    if (live) {
+      const int64_t q = p / s.Wout;
+      x = (int)(p - q * s.Wout);
+      b = (int)(q / s.Hout);
+      y = (int)(q - (int64_t)b * s.Hout);
+    }
+    __syncthreads();  // the previous step's operands have been read
+    {
+      const uint16_t *zp = dz + ((int64_t)b * LP_CO * s.Hout + y) * s.Wout + x;
+#pragma unroll 8
+      for (int co = 0; co < LP_CO; ++co) zs[co * kWgLd + tid] = live ? zp[co * hw] : (uint16_t)0;
+    }
+    {
+      const uint16_t *ib = in + (int64_t)b * s.Cin * in_plane;
+      const int ry = y * s.stride - s.pad, rx = x * s.stride - s.pad;
+#pragma unroll 4
+      for (int kk = 0; kk < 32; ++kk) {
+        const int k = kt + kk;  // wave-uniform
+        uint16_t v = 0;
+        if (k < s.K) {
+          const int ci = k / 9, t = k - ci * 9, kh = t / 3, kw = t - kh * 3;
+          const int r = ry + kh * s.dil, c = rx + kw * s.dil;
+          if (live && r >= 0 && c >= 0 && r < s.Hin && c < s.Win) v = ib[(int64_t)ci * in_plane + (int64_t)r * s.Win + c];
+        } else if (k == s.K) {
+          v = live ? (uint16_t)0x3f80 : (uint16_t)0;  // bf16 1.0
+        }
+        xs[kk * kWgLd + tid] = v;
       }
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+    __syncthreads();
+    const int cl = lane & 31;
+#pragma unroll
+    for (int st = 0; st < kWgStep / 4 / 8; ++st) {
+      const int px = wave * (kWgStep / 4) + st * 8 + 4 * half;
+      const bf16x4 av = *reinterpret_cast<const bf16x4 *>(zs + cl * kWgLd + px);
+      const bf16x4 bv = *reinterpret_cast<const bf16x4 *>(xs + cl * kWgLd + px);
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+    }
   }
+  __syncthreads();  // the staging area becomes the reduction area
+  float(*red)[LP_CO * 32] = reinterpret_cast<float(*)[LP_CO * 32]>(lds);
 #pragma unroll
   for (int r = 0; r < 16; ++r) red[wave][(8 * (r >> 2) + 4 * half + (r & 3)) * 32 + (lane & 31)] = acc[r];
   __syncthreads();

@@ -173,6 +173,21 @@ constexpr int kCumChunk = 64;
 
 // Tile-pass blocks per tile: one per chunk of bc bins for cumulative planes,
 // else one (that block loops over the chunks).
+// Whether the tile pass counts in registers (plain counts, with or without
+// the coordinate moments) instead of accumulating LDS histograms: when both
+// of its passes have at least one work item per thread of the block (groups
+// of four columns, or rows, times chunks of four bins); narrower tiles and
+// fewer bins leave most threads idle there and keep the LDS histograms.  And
+// the LDS bytes that path needs: the staged bins of the tile plus the tile's
+// totals (count, row moment, column moment per bin).
+__host__ __device__ __forceinline__ bool tile_fast(const Geom &g) {
+  const int nq = (g.bins + 3) / 4;
+  return !g.wgt && !g.diff && !g.cum && g.coord == 0 && ((g.TW + 3) / 4) * nq >= 256 && g.TH * nq >= 256;
+}
+__host__ __device__ __forceinline__ size_t tile_fast_lds(const Geom &g) {
+  return (((size_t)g.TH * (g.TW + 4) + 3) & ~(size_t)3) + (size_t)3 * g.bins * 4;
+}
+
 __host__ __device__ __forceinline__ int tile_chunks(const Geom &g, int bc) {
   return g.cum ? (g.bins + bc - 1) / bc : 1;
 }

@@ -67,12 +67,13 @@ __global__ void k_track_gate(ih_track_state *__restrict__ st, const int32_t *__r
 // (distance d), every offset whose lower bound lb exceeds d by more than the
 // rounding of both figures is dropped from the exhaustive list (set outside
 // every frame) and the rest stay listed: the scoring of that list then
-// returns the exhaustive search's own argmin and distance.  (The pyramid
-// distance of Eq. 2.24 weighs its levels by weights that sum to 1, and the
-// chi-square and L1 sums over a level's cells are at least those over the
-// coarser level's cells, so the level-0 distance lb never exceeds the
-// pyramid distance; a dropped offset scores above d, which is at least the
-// minimum.)  Otherwise every offset is listed, as in the plain gate.
+// returns the exhaustive search's own argmin and distance.  (lb is the
+// pyramid distance with one level fewer: merging cells never raises a
+// chi-square or L1 sum, so each level's sum is at least the coarser one's,
+// and with Eq. 2.24's weights the distance of L + 1 levels exceeds that of L
+// levels by a non-negative combination of those differences; a dropped
+// offset therefore scores above d, which is at least the minimum.)
+// Otherwise every offset is listed, as in the plain gate.
 // st->decision = -2 (bounded) or -1 (fallback); st->scored counts the listed
 // offsets (one block-wide count per block, then one atomic add).
 __global__ __launch_bounds__(256) void k_track_gate_bounded(ih_track_state *__restrict__ st,

@@ -13,9 +13,10 @@ tracker.  Two searches:
   the exhaustive search runs instead whenever the result scores worse than
   the margin (1 + tau) d*, where d* is the distance accepted at the previous
   frame.  In the bounded form an accepted result d only narrows the
-  exhaustive search: the level-0 distance of every offset is a lower bound
-  of its pyramid distance, and only the offsets whose bound does not exceed
-  d are scored exactly, which returns the exhaustive search's own result.
+  exhaustive search: the pyramid distance of every offset with one level
+  fewer is a lower bound of its full pyramid distance, and only the offsets
+  whose bound does not exceed d are scored exactly, which returns the
+  exhaustive search's own result.
 
 Either search can run on the integral histogram of the whole frame (as the
 thesis's tracker does) or of the search region only.  All scoring, network
@@ -109,11 +110,13 @@ class PyramidTracker:
         return ih_match_candidates(self.ih, self.tmpl, self.win[0], self.win[1], origins, self.levels,
                                    self.metric, dist, best, self.layout)
 
-    def score_level0(self, origins: torch.Tensor, dist: torch.Tensor, best: torch.Tensor):
-        """Level-0 distances (the whole window's histogram against the
-        template's level-0 cell, the first P values of its descriptor): a
-        lower bound of each candidate's pyramid distance."""
-        return ih_match_candidates(self.ih, self.tmpl[:self.P], self.win[0], self.win[1], origins, 1,
+    def score_coarse(self, origins: torch.Tensor, dist: torch.Tensor, best: torch.Tensor):
+        """Pyramid distances with one level fewer (the template's descriptor
+        of those levels is the leading part of its full descriptor): a lower
+        bound of each candidate's pyramid distance."""
+        lv = max(1, self.levels - 1)
+        n = self.P * sum(4 ** l for l in range(lv))
+        return ih_match_candidates(self.ih, self.tmpl[:n], self.win[0], self.win[1], origins, lv,
                                    self.metric, dist, best, self.layout)
 
 
@@ -128,7 +131,8 @@ class LearnedTracker:
         of the network (the no-network baseline).  refine_rounds rounds of the
         local search move the best candidate to the best of the (2 refine_q + 1)^2
         offsets around it.  With bound, an accepted result narrows the
-        exhaustive search by the level-0 lower bound instead of replacing it
+        exhaustive search by a lower bound (the pyramid distance with one level
+        fewer) instead of replacing it
         (the track then always equals the exhaustive one)."""
         if net is None and prior_logits is None:
             raise IHError("need a network or fixed prior logits")
@@ -183,7 +187,7 @@ class LearnedTracker:
                                           _p(self.nbest), self.q, RADIUS, s), "ih_track_refine_pick")
         if self.bound:
             lp.lp_origins(tr.sbase, RADIUS, out=self.allorig)
-            tr.score_level0(self.allorig, self.lb, self.lbbest)
+            tr.score_coarse(self.allorig, self.lb, self.lbbest)
 
     def gate(self, state: torch.Tensor, exh: torch.Tensor):
         """Enqueue the fallback rule (plain or bounded), filling exh."""

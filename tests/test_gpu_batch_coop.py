@@ -49,3 +49,25 @@ def test_batch_cooperative_64_uneven_frames(layout):
         assert torch.equal(batch.ih[i], ref[i]), i
         assert torch.equal(batch.dist[i], ref_d[i]), i
         assert torch.equal(batch.best[i], ref_b[i]), i
+
+
+def test_cooperative_batch_refuses_graph_capture():
+    """Under stream capture the cooperative mode returns an error before
+    enqueuing anything (a captured cooperative launch would lose its
+    co-residency guarantee); the phased mode of the same batch captures."""
+    import paper_1711_01656_amd as ih
+    frames = make_frames(23, np.uint8, n=4)
+    batch = ih.Batch(frames, "chi2", layout="bhw")
+    batch.run("phased")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with pytest.raises(ih.IHError, match="cannot be captured"):
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                batch.run("cooperative")
+    torch.cuda.synchronize()
+    batch.run("cooperative")                      # eager: still runs, same results
+    torch.cuda.synchronize()
+    check(batch, frames, "chi2", "bhw")

@@ -187,3 +187,36 @@ def test_build_config3_full_sampled():
         assert np.array_equal(out[p].cpu().numpy(), oracle.ih_plane(w.img, w.bins, w.bits, p))
     del out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("layout", ["bhw", "hwb"])
+@pytest.mark.parametrize("H,W,bins,bits,tile", [
+    (301, 777, 64, 16, (128, 256, 4)),      # bin-major 8192^2-style tile, ragged in both directions
+    (130, 515, 64, 8, (64, 256, 2)),
+    (97, 260, 255, 8, (64, 128, 1)),        # bins not a multiple of four
+    (257, 300, 64, 16, (128, 64, 64)),      # planes-innermost tile that counts in registers
+    (70, 129, 128, 8, (32, 64, 64)),
+])
+def test_build_register_tile_pass(layout, H, W, bins, bits, tile):
+    """Tile shapes whose tile pass counts in registers (four columns or one row
+    times four bins per thread), against the oracle, with and without moments."""
+    ih = ihlib()
+    th, tw, pg = tile
+    if (layout == "hwb") != (pg == 64):
+        pytest.skip("tile shape of the other layout")
+    img = rand_img(H + 3 * W + bins, 1, H, W, bits)
+    t = gpu(img)
+    ref = oracle.ih(img, bins, bits)
+    cfg = ih.TileCfg(th, tw, pg, 3)
+    out = ih.ih_build(t, bins, bits, cfg=cfg, layout=layout)
+    got = out.cpu().numpy()
+    if layout == "hwb":
+        got = got.transpose(2, 0, 1)
+    assert np.array_equal(got, ref)
+    if layout == "bhw" or tw <= 32:
+        o, mx, my = ih.ih_build(t, bins, bits, cfg=cfg, layout=layout, moments=True)
+        omx, omy = oracle.moments(img, bins, bits)
+        tr = (lambda a: a.cpu().numpy().transpose(2, 0, 1)) if layout == "hwb" else (lambda a: a.cpu().numpy())
+        assert np.array_equal(tr(o), ref)
+        assert np.array_equal(tr(mx).astype(np.int64) & 0xFFFFFFFF, np.asarray(omx).astype(np.int64) & 0xFFFFFFFF)
+        assert np.array_equal(tr(my).astype(np.int64) & 0xFFFFFFFF, np.asarray(omy).astype(np.int64) & 0xFFFFFFFF)

@@ -218,10 +218,11 @@ def test_trained_network_beats_the_search_without_it(env):
     assert prec["net"] > prec["pr"]
 
 
-def test_level0_distance_bounds_the_pyramid_distance(env):
-    """The bound the bounded gate relies on, checked on every offset of a few
-    frames: the level-0 distance never exceeds the 3-level pyramid distance
-    (chi-square and L1), beyond FP32 rounding."""
+def test_coarser_distances_bound_the_pyramid_distance(env):
+    """The bounds the bounded gate relies on, checked on every offset of a few
+    frames: the level-0 distance and the two-level distance (the one the gate
+    uses) never exceed the 3-level pyramid distance (chi-square and L1),
+    beyond FP32 rounding, and the two-level bound is the tighter one."""
     trk, lp, ex = env["tracker"], env["lp"], env["ex"]
     for metric in ("chi2", "l1"):
         tr = trk.PyramidTracker(H, W, bins=BINS, metric=metric)
@@ -231,15 +232,19 @@ def test_level0_distance_bounds_the_pyramid_distance(env):
             base = torch.from_numpy(ex.origins[t - 1][None].astype(np.int32)).cuda()
             orig = lp.lp_origins(base, lp.RADIUS)
             d = torch.empty(lp.N_OFFSETS, dtype=torch.float32, device="cuda")
-            d0 = torch.empty_like(d)
+            d2 = torch.empty_like(d)
             b = torch.empty(1, dtype=torch.int32, device="cuda")
             tr.score(orig, d, b)
-            tr.score_level0(orig, d0, b)
-            d, d0 = d.cpu().numpy().astype(np.float64), d0.cpu().numpy().astype(np.float64)
+            tr.score_coarse(orig, d2, b)
+            from paper_1711_01656_amd import ih_match_candidates
+            d0 = ih_match_candidates(tr.ih, tr.tmpl[:tr.P], tr.win[0], tr.win[1], orig, 1, metric,
+                                     layout=tr.layout)[0]
+            d, d2, d0 = (x.cpu().numpy().astype(np.float64) for x in (d, d2, d0))
             fin = np.isfinite(d)
-            assert np.array_equal(fin, np.isfinite(d0))
-            assert np.all(d0[fin] <= d[fin] * (1 + 2.0 ** -20) + 1e-30), (metric, t)
-            assert np.any(d0[fin] < d[fin])
+            assert np.array_equal(fin, np.isfinite(d0)) and np.array_equal(fin, np.isfinite(d2))
+            assert np.all(d0[fin] <= d2[fin] * (1 + 2.0 ** -20) + 1e-30), (metric, t)
+            assert np.all(d2[fin] <= d[fin] * (1 + 2.0 ** -20) + 1e-30), (metric, t)
+            assert np.any(d2[fin] < d[fin]) and np.any(d0[fin] < d2[fin])
 
 
 @pytest.mark.parametrize("ranking", ["random_network", "no_network", "zero_network"])
