@@ -238,7 +238,63 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
   const int th = min(g.TH, g.H - R0), tw = min(g.TW, g.W - C0);
   const T *src = img + (int64_t)ch * g.H * g.W;
 
-  for (int idx = tid; idx < th * tw; idx += 256) {
+  // Full-width tiles with 16-byte aligned rows load 16-byte chunks, eight
+  // per thread in flight, and store their bins as words; other tiles load
+  // pixel by pixel.
+  constexpr int PER = 16 / (int)sizeof(T);  // values per chunk
+  const bool chunked = !g.wgt && !g.diff && tw == g.TW && (g.TW % PER) == 0 &&
+                       (((uintptr_t)src | ((uintptr_t)g.W * sizeof(T)) | ((uintptr_t)C0 * sizeof(T))) & 15) == 0;
+  if (chunked) {
+    const int cpr = g.TW / PER, sh = __builtin_ctz((unsigned)cpr);  // chunks per row, a power of two
+    const int nch = th * cpr;
+    constexpr int U = 8;
+    for (int base = 0; base < nch; base += 256 * U) {
+      uint4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * 256 + tid;
+        if (idx < nch) {
+          const int r = idx >> sh, c = (idx & (cpr - 1)) * PER;
+          v[u] = *reinterpret_cast<const uint4 *>(src + (int64_t)(R0 + r) * g.W + C0 + c);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * 256 + tid;
+        if (idx < nch) {
+          const int r = idx >> sh, c = (idx & (cpr - 1)) * PER;
+          const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+          uint32_t *dst = reinterpret_cast<uint32_t *>(bin_s + r * twp + c);
+          if constexpr (sizeof(T) == 2) {
+            // 8 values -> 8 bins -> two words
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              uint32_t packed = 0;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const uint32_t val = (w[2 * q + e / 2] >> (16 * (e & 1))) & 0xffffu;
+                packed |= ((((uint32_t)val * (uint32_t)g.bins) >> bits) & 0xffu) << (8 * e);
+              }
+              dst[q] = packed;
+            }
+          } else {
+            // 16 values -> 16 bins -> four words
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              uint32_t packed = 0;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const uint32_t val = (w[q] >> (8 * e)) & 0xffu;
+                packed |= ((((uint32_t)val * (uint32_t)g.bins) >> bits) & 0xffu) << (8 * e);
+              }
+              dst[q] = packed;
+            }
+          }
+        }
+      }
+    }
+  }
+  for (int idx = chunked ? th * tw : tid; idx < th * tw; idx += 256) {
     const int r = idx / tw, c = idx - r * tw;
     const int64_t i = (int64_t)(R0 + r) * g.W + C0 + c;
     const uint32_t v = src[i];
