@@ -247,6 +247,7 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
     if (!hwb && P.g.PG > 8)
       return set_error(IH_ERR_UNSUPPORTED, "frame %d: planes_per_wave %d > 8 in a batch", f, P.g.PG);
     size_t l;
+    P.g.c16 = F.H < 65536 && F.W < 65536;  // count carries fit 16 bits
     if ((e = pick_bc(P.g, kBatchLds, &P.bc, &l))) return set_error(e, "frame %d: %s", f, ih_last_error());
     if (tile_fast(P.g)) l = tile_fast_lds(P.g);
     if (l > lds) lds = l;

@@ -69,6 +69,7 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
   g->diff = false;
   g->coord = 0;
   g->cum = false;
+  g->c16 = false;
   g->layout = layout;
   int TH, TW, PG;
   if (cfg) {
@@ -94,7 +95,7 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
     if (out_bytes < ((int64_t)64 << 20)) { TH = 16; TW = 64; PG = 2; }
     else if (g->P <= 32 && out_bytes < ((int64_t)1 << 30)) { TH = 32; TW = 64; PG = 2; }
     else if (out_bytes < ((int64_t)128 << 20)) { TH = 16; TW = 64; PG = 2; }
-    else if (W >= 4096) { TH = 128; TW = 256; PG = g->mom ? 8 : 8; }
+    else if (W >= 4096) { TH = 128; TW = g->mom ? 256 : 128; PG = g->mom ? 8 : 2; }
     else { TH = 64; TW = 64; PG = 1; }
     while (PG > 1 && PG > bins) PG >>= 1;
   } else {
@@ -364,6 +365,8 @@ static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const u
   Geom g;
   int e = make_geom(H, W, C, bins, mom, layout, cfg, &g, wt != nullptr);
   if (e) return e;
+  // plain counts: every column carry is below H and every row carry below W
+  g.c16 = !wt && H < 65536 && W < 65536;
   if (!ws || ws_bytes < g.words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.words * 4,
                      ws ? ws_bytes : (size_t)0);

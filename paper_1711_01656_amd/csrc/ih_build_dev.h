@@ -28,6 +28,18 @@ __host__ __device__ __forceinline__ int64_t cc_index(const Geom &g, int64_t p, i
   return g.layout == IH_BHW ? (p * g.nTR + I) * (int64_t)g.W + c : ((int64_t)I * g.W + c) * g.P + p;
 }
 
+// Element i of a count-carry array (CC or RC) at word offset `off` of the
+// workspace: 16-bit values when g.c16 (plain counts of a frame whose sides are
+// below 2^16, so every carry fits), else 32-bit.  The arrays keep their
+// 32-bit sizes either way.
+__device__ __forceinline__ uint32_t cget(const Geom &g, const uint32_t *ws, size_t off, int64_t i) {
+  return g.c16 ? (uint32_t)reinterpret_cast<const uint16_t *>(ws + off)[i] : ws[off + i];
+}
+__device__ __forceinline__ void cput(const Geom &g, uint32_t *ws, size_t off, int64_t i, uint32_t v) {
+  if (g.c16) reinterpret_cast<uint16_t *>(ws + off)[i] = (uint16_t)v;
+  else ws[off + i] = v;
+}
+
 // --------------------------------------------------------------------------
 // 1. Per-tile histograms.  One workgroup per (channel, tile).
 //    CC  (p, I, c)        plane-p count of column c over the tile's rows
@@ -80,7 +92,7 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
   const int tid = threadIdx.x;
   const int nq = (g.bins + NB - 1) / NB;
   const bool v4 = (g.bins & 3) == 0 && ((uintptr_t)ws & 15) == 0;
-  uint32_t *CC = ws + g.off_cc, *RC = ws + g.off_rc, *TT = ws + g.off_tt;
+  uint32_t *CC = ws + g.off_cc, *TT = ws + g.off_tt;
   uint32_t *CCX = ws + g.off_ccx, *RCY = ws + g.off_rcy;
   uint32_t *TTX = ws + g.off_ttx, *TTY = ws + g.off_tty;
   for (int i = tid; i < 3 * g.bins; i += blockDim.x) tot[i] = 0u;
@@ -91,6 +103,19 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
 #pragma unroll
       for (int kk = 0; kk < NB; ++kk)
         if (k0 + kk < g.bins) dst[kk] = v[kk];
+    }
+  };
+  // four consecutive elements of a count-carry array (16- or 32-bit)
+  auto store4c = [&](size_t off, int64_t o, const uint32_t (&v)[NB], int k0) {
+    if (!g.c16) {
+      store4(ws + off + o, v, k0);
+    } else if (v4) {
+      *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(ws + off) + o) =
+          make_uint2((v[0] & 0xffffu) | (v[1] << 16), (v[2] & 0xffffu) | (v[3] << 16));
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk)
+        if (k0 + kk < g.bins) cput(g, ws, off, o + kk, v[kk]);
     }
   };
   // ---- columns, four per thread (one LDS word per row)
@@ -131,14 +156,18 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
         if (k0 + kk >= g.bins) continue;
         const int64_t o = cc_index(g, p0 + kk, I, C0 + cl0);
         if (cvec && cl0 + 4 <= tw) {
-          *reinterpret_cast<uint4 *>(CC + o) = make_uint4(n[0][kk], n[1][kk], n[2][kk], n[3][kk]);
+          if (g.c16)
+            *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(CC) + o) =
+                make_uint2((n[0][kk] & 0xffffu) | (n[1][kk] << 16), (n[2][kk] & 0xffffu) | (n[3][kk] << 16));
+          else
+            *reinterpret_cast<uint4 *>(CC + o) = make_uint4(n[0][kk], n[1][kk], n[2][kk], n[3][kk]);
           if constexpr (MOM)
             *reinterpret_cast<uint4 *>(CCX + o) = make_uint4(nx[0][kk], nx[1][kk], nx[2][kk], nx[3][kk]);
         } else {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             if (cl0 + e < tw) {
-              CC[o + e] = n[e][kk];
+              cput(g, ws, g.off_cc, o + e, n[e][kk]);
               if constexpr (MOM) CCX[o + e] = nx[e][kk];
             }
           }
@@ -149,7 +178,7 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
       for (int e = 0; e < 4; ++e) {
         if (cl0 + e < tw) {
           const int64_t o = cc_index(g, p0, I, C0 + cl0 + e);  // planes consecutive
-          store4(CC + o, n[e], k0);
+          store4c(g.off_cc, o, n[e], k0);
           if constexpr (MOM) store4(CCX + o, nx[e], k0);
         }
       }
@@ -186,7 +215,7 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
       }
     }
     const size_t o = (((size_t)ch * g.nTC + j) * g.H + R0 + r) * g.bins + k0;
-    store4(RC + o, n, k0);
+    store4c(g.off_rc, (int64_t)o, n, k0);
     if constexpr (MOM) store4(RCY + o, ny, k0);
 #pragma unroll
     for (int kk = 0; kk < NB; ++kk) {
@@ -319,7 +348,7 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       }
     }
   }
-  uint32_t *CC = ws + g.off_cc, *RC = ws + g.off_rc, *TT = ws + g.off_tt;
+  uint32_t *TT = ws + g.off_tt;
   uint32_t *CCX = ws + g.off_ccx, *RCY = ws + g.off_rcy;
   uint32_t *TTX = ws + g.off_ttx, *TTY = ws + g.off_tty;
   if (tile_fast(g)) {
@@ -378,7 +407,7 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
       if (g.layout == IH_BHW) { k = i / tw; cl = i - k * tw; }     // unit stride along columns
       else { cl = i / nb; k = i - cl * nb; }                       // unit stride along planes
       const int64_t o = cc_index(g, (int64_t)ch * g.bins + b0 + k, I, C0 + cl);
-      CC[o] = hist[cl * stride + k];
+      cput(g, ws, g.off_cc, o, hist[cl * stride + k]);
       if (g.mom) CCX[o] = hist[colw + cl * stride + k];
     }
     // tile totals: 16 threads per bin sum every 16th column, then combine
@@ -452,7 +481,7 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
     for (int i = tid; i < th * nb; i += 256) {
       const int r = i / nb, k = i - r * nb;
       const size_t o = (((size_t)ch * g.nTC + j) * g.H + R0 + r) * g.bins + b0 + k;
-      RC[o] = hist[r * stride + k];
+      cput(g, ws, g.off_rc, (int64_t)o, hist[r * stride + k]);
       if (g.mom) RCY[o] = hist[roww + r * stride + k];
     }
   }
@@ -469,8 +498,8 @@ __device__ __forceinline__ void tile_hist_body(const T *__restrict__ img, const 
 // values are loaded CH at a time before any of them is stored, so the loads of
 // a chunk are in flight together instead of each waiting behind the previous
 // store (the compiler cannot prove the strided addresses distinct).
-template <int CH>
-__device__ __forceinline__ void excl_scan_strided(uint32_t *__restrict__ a, int64_t step, int n) {
+template <int CH, typename E = uint32_t>
+__device__ __forceinline__ void excl_scan_strided(E *__restrict__ a, int64_t step, int n) {
   uint32_t run = 0;
   int j0 = 0;
   for (; j0 + CH <= n; j0 += CH) {  // whole chunks: no per-element tests
@@ -479,7 +508,7 @@ __device__ __forceinline__ void excl_scan_strided(uint32_t *__restrict__ a, int6
     for (int q = 0; q < CH; ++q) v[q] = a[(int64_t)(j0 + q) * step];
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-      a[(int64_t)(j0 + q) * step] = run;
+      a[(int64_t)(j0 + q) * step] = (E)run;
       run += v[q];
     }
   }
@@ -490,7 +519,7 @@ __device__ __forceinline__ void excl_scan_strided(uint32_t *__restrict__ a, int6
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       if (j0 + q < n) {
-        a[(int64_t)(j0 + q) * step] = run;
+        a[(int64_t)(j0 + q) * step] = (E)run;
         run += v[q];
       }
     }
@@ -521,7 +550,10 @@ __device__ __forceinline__ void carry_scan_body(const Geom &g, int64_t nblk_a, i
     if (g.layout == IH_BHW) { p = idx / g.W; c = idx - p * g.W; }
     else { c = idx / g.P; p = idx - c * g.P; }
     const int64_t step = cc_index(g, p, 1, c) - cc_index(g, p, 0, c);
-    excl_scan_strided<16>(ws + (second ? g.off_ccx : g.off_cc) + cc_index(g, p, 0, c), step, g.nTR);
+    if (!second && g.c16)
+      excl_scan_strided<16>(reinterpret_cast<uint16_t *>(ws + g.off_cc) + cc_index(g, p, 0, c), step, g.nTR);
+    else
+      excl_scan_strided<16>(ws + (second ? g.off_ccx : g.off_cc) + cc_index(g, p, 0, c), step, g.nTR);
   } else if (blk < nblk_a + nblk_b) {
     int64_t idx = (blk - nblk_a) * 256 + threadIdx.x;
     if (idx >= carry_threads_b(g)) return;
@@ -529,7 +561,10 @@ __device__ __forceinline__ void carry_scan_body(const Geom &g, int64_t nblk_a, i
     const bool second = idx >= per;
     if (second) idx -= per;
     const int64_t ch = idx / per_ch, rk = idx - ch * per_ch;
-    excl_scan_strided<16>(ws + (second ? g.off_rcy : g.off_rc) + ch * g.nTC * per_ch + rk, per_ch, g.nTC);
+    if (!second && g.c16)
+      excl_scan_strided<16>(reinterpret_cast<uint16_t *>(ws + g.off_rc) + ch * g.nTC * per_ch + rk, per_ch, g.nTC);
+    else
+      excl_scan_strided<16>(ws + (second ? g.off_rcy : g.off_rc) + ch * g.nTC * per_ch + rk, per_ch, g.nTC);
   } else {
     const int64_t p = blk - nblk_a - nblk_b;
     const int arrays = g.mom ? 3 : 1;
@@ -700,7 +735,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
       const int64_t cidx = (p * g.nTR + I) * (int64_t)g.nTC + j;
       uint32_t v[CPL], raw[CPL];
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) raw[e] = (cf + e < g.W) ? a.ws[g.off_cc + crow + cf + e] : 0u;
+      for (int e = 0; e < CPL; ++e) raw[e] = (cf + e < g.W) ? cget(g, a.ws, g.off_cc, crow + cf + e) : 0u;
       v[0] = raw[0];
 #pragma unroll
       for (int e = 1; e < CPL; ++e) v[e] = v[e - 1] + raw[e];
@@ -726,7 +761,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
     }
   }
 
-  const uint32_t *lc_base = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + kb;
+  const int64_t lc_base = (((int64_t)ch * g.nTC + j) * g.H) * g.bins + kb;  // in the RC array
   const uint32_t *lcy_base = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + kb;
   int32_t *out_base = a.ih + ((int64_t)ch * g.bins + kb) * HW + cf;
   uint32_t *mx_base = MOM ? a.mx + ((int64_t)ch * g.bins + kb) * HW + cf : nullptr;
@@ -754,9 +789,8 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, const Geom &g, in
 #pragma unroll
       for (int e = 0; e < CPL; ++e) pw[d][e] = cf + e < g.W ? pixel_weight_of<WK>(a, g, ch, r, cf + e) : 0u;
     }
-    const uint32_t *lc = lc_base + (int64_t)r * g.bins;
 #pragma unroll
-    for (int k = 0; k < PG; ++k) lcv[d][k] = k < nk ? lc[k] : 0u;
+    for (int k = 0; k < PG; ++k) lcv[d][k] = k < nk ? cget(g, a.ws, g.off_rc, lc_base + (int64_t)r * g.bins + k) : 0u;
     if constexpr (MOM) {
       const uint32_t *lcy = lcy_base + (int64_t)r * g.bins;
 #pragma unroll
@@ -981,7 +1015,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
     for (int c = 0; c < TW; ++c) {
       if (c < cols) {
         const int64_t o = ((int64_t)I * g.W + C0 + c) * P + p;
-        const uint32_t v = live ? a.ws[g.off_cc + o] : 0u;
+        const uint32_t v = live ? cget(g, a.ws, g.off_cc, o) : 0u;
         run += v;
         col[c] = run;
         if constexpr (MOM) {
@@ -993,7 +1027,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
       }
     }
   }
-  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const int64_t lc = (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;  // in the RC array
   const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
   // A full tile row can be read as 32-bit words when every row of the tile
   // starts on a 4-byte boundary.
@@ -1006,7 +1040,7 @@ __device__ __forceinline__ void final_hwb_body(const FinalArgs &a, const Geom &g
     constexpr bool F = decltype(FULL)::value;
     const int r = R0 + rr;
     const T *row = img + (int64_t)r * g.W + C0;
-    uint32_t rc = live ? lc[(int64_t)r * g.bins] : 0u;
+    uint32_t rc = live ? cget(g, a.ws, g.off_rc, lc + (int64_t)r * g.bins) : 0u;
     uint32_t ry = 0;
     if constexpr (MOM) ry = live ? lcy[(int64_t)r * g.bins] : 0u;
     // uniform row base and a 32-bit per-lane offset (TW * P words at most)
@@ -1112,12 +1146,12 @@ __device__ __forceinline__ void final_hwb_wave_staged_body(const FinalArgs &a, c
 #pragma unroll
     for (int c = 0; c < TW; ++c) {
       if (c < cols) {
-        run += a.ws[g.off_cc + ((int64_t)I * g.W + C0 + c) * P + p];
+        run += cget(g, a.ws, g.off_cc, ((int64_t)I * g.W + C0 + c) * P + p);
         col[c] = run;
       }
     }
   }
-  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const int64_t lc = (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;  // in the RC array
   const bool vec = (g.P & 3) == 0 && ((uintptr_t)a.ih & 15) == 0;
   const int nseg = cols * g.P;
   uint32_t pxn[TW], rcn = 0;
@@ -1125,7 +1159,7 @@ __device__ __forceinline__ void final_hwb_wave_staged_body(const FinalArgs &a, c
     const T *row = img + (int64_t)r * g.W + C0;
 #pragma unroll
     for (int c = 0; c < TW; ++c) pxn[c] = c < cols ? (uint32_t)row[c] : 0u;
-    rcn = lc[(int64_t)r * g.bins];
+    rcn = cget(g, a.ws, g.off_rc, lc + (int64_t)r * g.bins);
   };
   if (rows > 0) fetch(R0);
   for (int rr = 0; rr < rows; ++rr) {
@@ -1181,7 +1215,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
     for (int c = 0; c < TW; ++c) {
       if (c < cols) {
         const int64_t o = ((int64_t)I * g.W + C0 + c) * P + p;
-        const uint32_t v = a.ws[g.off_cc + o];
+        const uint32_t v = cget(g, a.ws, g.off_cc, o);
         run += v;
         col[c] = run;
         if constexpr (MOM) {
@@ -1193,7 +1227,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
       }
     }
   }
-  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const int64_t lc = (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;  // in the RC array
   const uint32_t *lcy = a.ws + g.off_rcy + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
   const bool full = cols == TW;
   const bool words = full && ((uintptr_t)a.img & 3) == 0 && ((int64_t)g.W * sizeof(T)) % 4 == 0 &&
@@ -1207,7 +1241,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
     constexpr bool F = decltype(FULL)::value;
     const int r = R0 + rr;
     const T *row = img + (int64_t)r * g.W + C0;
-    uint32_t rc = lc[(int64_t)r * g.bins];
+    uint32_t rc = cget(g, a.ws, g.off_rc, lc + (int64_t)r * g.bins);
     uint32_t ry = 0;
     if constexpr (MOM) ry = lcy[(int64_t)r * g.bins];
     auto pixel = [&](int c, uint32_t val, uint32_t w) {
@@ -1259,7 +1293,7 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
 #pragma unroll
       for (int q = 0; q < TW / PER; ++q) wv[q] = wp[q];
       if constexpr (loads_weights<WK>()) load_weight_words<TW>(a, g, ch, r, C0, wqn);
-      rcn = lc[(int64_t)r * g.bins];
+      rcn = cget(g, a.ws, g.off_rc, lc + (int64_t)r * g.bins);
       if constexpr (MOM) ryn = lcy[(int64_t)r * g.bins];
     };
     if (rows > 0) fetch(R0);
@@ -1384,12 +1418,12 @@ __device__ __forceinline__ void final_hwb_acc_staged_body(const FinalArgs &a, co
 #pragma unroll
     for (int c = 0; c < TW; ++c) {
       if (c < cols) {
-        run += a.ws[g.off_cc + ((int64_t)I * g.W + C0 + c) * P + p];
+        run += cget(g, a.ws, g.off_cc, ((int64_t)I * g.W + C0 + c) * P + p);
         col[c] = run;
       }
     }
   }
-  const uint32_t *lc = a.ws + g.off_rc + (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;
+  const int64_t lc = (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;  // in the RC array
   const bool vec = (g.P & 3) == 0 && ((uintptr_t)a.ih & 15) == 0;
   const int nseg = cols * g.P;
   const bool full = cols == TW;
@@ -1411,7 +1445,7 @@ __device__ __forceinline__ void final_hwb_acc_staged_body(const FinalArgs &a, co
 #pragma unroll
         for (int q = 0; q < TW / PER; ++q) tw[q] = tp[q];
       }
-      rcn = lc[(int64_t)r * g.bins];
+      rcn = cget(g, a.ws, g.off_rc, lc + (int64_t)r * g.bins);
     };
     if (rows > 0) fetch(R0);
     for (int rr = 0; rr < rows; ++rr) {
@@ -1446,7 +1480,7 @@ __device__ __forceinline__ void final_hwb_acc_staged_body(const FinalArgs &a, co
     const int r = R0 + rr;
     const T *row = img + (int64_t)r * g.W + C0;
     const T *trow = timg ? timg + (int64_t)r * g.W + C0 : nullptr;
-    uint32_t rc = lc[(int64_t)r * g.bins];
+    uint32_t rc = cget(g, a.ws, g.off_rc, lc + (int64_t)r * g.bins);
 #pragma unroll
     for (int c = 0; c < TW; ++c) {
       if (c < cols) {

@@ -115,6 +115,7 @@ struct Geom {
   bool diff;            // a second (tail) image counts -1: joint-IH update
   int coord;            // coordinate weight of the tile pass (2: row^2, 3: column^2); 0: none
   bool cum;             // cumulative planes: plane k counts bins <= k (joint-IH update)
+  bool c16;             // count carries (CC, RC) stored as 16-bit values in their 32-bit-sized arrays
   int layout;           // IH_BHW or IH_HWB
   // workspace sections (in 4-byte words)
   size_t off_cc, off_rc, off_tt, off_ccx, off_rcy, off_ttx, off_tty, words;
