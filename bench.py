@@ -1077,7 +1077,10 @@ def main():
         print(json.dumps(tracker_leg(torch, args)), flush=True)
         return
     if args.workloads_only:
-        print(json.dumps(config_legs(torch, ih, synth, args)), flush=True)
+        res = config_legs(torch, ih, synth, args)
+        if args.copy_calib:
+            copy_calibration(torch, args.copy_calib)
+        print(json.dumps(res), flush=True)
         return
     if args.camshift_only:
         print(json.dumps(camshift_leg(torch, ih, synth)), flush=True)
