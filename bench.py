@@ -775,10 +775,14 @@ def batch_leg(torch, ih, synth, args, fixed=False):
         total += f.img.shape[1] * f.img.shape[2] * f.bins
     per_layout = {}
     for lay in ("hwb", "bhw"):
-        tile = (ih.TileCfg(*FIXED_TILES["batch_" + lay]) if fixed
-                else tune.tune_batch(frames, "chi2", layout=lay, reps=2)[0])
-        for fr in frames:
-            fr["tile"] = tile
+        if fixed:
+            tiles = [ih.TileCfg(*FIXED_TILES["batch_" + lay])] * len(frames)
+            by_bins, uniform_ms = {f["bins"]: tiles[0] for f in frames}, None
+        else:
+            # a tile shape per bin count, each chosen by timing the whole batch
+            tiles, by_bins, _, uniform_ms = tune.tune_batch_classes(frames, "chi2", layout=lay, reps=2)
+        for fr, t in zip(frames, tiles):
+            fr["tile"] = t
         batch = ih.Batch(frames, "chi2", layout=lay)
         batch.run("phased")
         torch.cuda.synchronize()
@@ -786,7 +790,9 @@ def batch_leg(torch, ih, synth, args, fixed=False):
         t_graph = graph_median(torch, lambda: batch.run("phased"), 5)
         t_coop = float(np.median([time_calls(torch, lambda: batch.run("cooperative"), 5) for _ in range(3)]))
         same = all(torch.equal(a, b) for a, b in zip(ref, batch.best))
-        per_layout[lay] = {"tile": repr(tile), "graph_phased_ms": round(t_graph, 3),
+        per_layout[lay] = {"tiles_by_bins": {str(k): repr(v) for k, v in sorted(by_bins.items())},
+                           "uniform_tile_ms": None if uniform_ms is None else round(uniform_ms, 3),
+                           "graph_phased_ms": round(t_graph, 3),
                            "cooperative_ms": round(t_coop, 3),
                            "gpxbins_per_s_graph": round(total / t_graph / 1e6, 2),
                            "ih_write_gbs_graph": round(total * 4 / t_graph / 1e6, 1),

@@ -100,12 +100,14 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
     while (PG > 1 && PG > bins) PG >>= 1;
   } else {
     // defaults from device sweeps of the staged write-out: 16-column tiles
-    // with moments, 32-column tiles without; short tiles for small outputs
+    // with moments, 32-column tiles without; short tiles for small outputs;
+    // 64 columns on large outputs with 64 or more bins, whose tile pass then
+    // counts in registers
     PG = 64;
     const int64_t out_bytes = (int64_t)g->P * H * W * 4 * (g->mom ? 3 : 1);
     if (out_bytes < ((int64_t)128 << 20)) { TH = 8; TW = 16; }
     else if (g->mom) { TH = 128; TW = 16; }
-    else if (out_bytes >= ((int64_t)4 << 30)) { TH = 128; TW = 32; }
+    else if (out_bytes >= ((int64_t)4 << 30)) { TH = 128; TW = bins >= 64 ? 64 : 32; }
     else { TH = 32; TW = 32; }
   }
   g->TH = TH; g->TW = TW; g->PG = PG;

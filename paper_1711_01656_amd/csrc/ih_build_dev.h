@@ -84,6 +84,18 @@ inline size_t staged_lds(const Geom &g) {
 // contiguous along bins (planes-innermost column carries, row carries: one
 // 16-byte store per chunk when bins is a multiple of four).
 // tot: 3 x bins words of LDS.
+// Byte-parallel equality of four staged bins with one bin k: the word's bins
+// are split into their low seven bits (lo) and their top bits, the top bits
+// flipped so that a set bit means "equal to k's top bit" (hi).  Adding 0x7f
+// to a byte of lo ^ (k's low seven bits) sets its bit 7 exactly when that
+// byte is nonzero and carries into no other byte, so hi & ~sum leaves 0x80
+// in the bytes that equal k and 0 elsewhere.
+__device__ __forceinline__ uint32_t swar_key(int k) { return (uint32_t)(k & 0x7f) * 0x01010101u; }
+__device__ __forceinline__ uint32_t swar_flip(int k) { return (k & 0x80) ? 0u : 0x80808080u; }
+__device__ __forceinline__ uint32_t swar_match(uint32_t lo, uint32_t hi, uint32_t key) {
+  return hi & ~((lo ^ key) + 0x7f7f7f7fu);
+}
+
 template <bool MOM>
 __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *bin_s, int twp, int ch, int I, int j,
                                                  int R0, int C0, int th, int tw, uint32_t *__restrict__ ws,
@@ -134,17 +146,42 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
         if constexpr (MOM) nx[e][kk] = 0u;
       }
     const uint8_t *col = bin_s + 4 * cg;
+    if constexpr (!MOM) {
+      // the four columns' bins compared with a bin at once (one match flag
+      // per byte) and counted in byte lanes, flushed before a lane can hold
+      // more than 128
+      uint32_t kl[NB];
+      const uint32_t flip = swar_flip(k0);
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk) kl[kk] = swar_key(k0 + kk);
+      for (int r0 = 0; r0 < th; r0 += 128) {
+        const int r1 = min(th, r0 + 128);
+        uint32_t acc[NB] = {0u, 0u, 0u, 0u};
 #pragma unroll 4
-    for (int r = 0; r < th; ++r) {
-      const uint32_t word = *reinterpret_cast<const uint32_t *>(col + r * twp);
+        for (int r = r0; r < r1; ++r) {
+          const uint32_t word = *reinterpret_cast<const uint32_t *>(col + r * twp);
+          const uint32_t lo = word & 0x7f7f7f7fu, hi = (word & 0x80808080u) ^ flip;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int b = (int)((word >> (8 * e)) & 0xffu) - k0;
+          for (int kk = 0; kk < NB; ++kk) acc[kk] += swar_match(lo, hi, kl[kk]) >> 7;
+        }
 #pragma unroll
-        for (int kk = 0; kk < NB; ++kk) {
-          const uint32_t hit = b == kk ? 1u : 0u;
-          n[e][kk] += hit;
-          if constexpr (MOM) nx[e][kk] += hit * (uint32_t)(R0 + r);
+        for (int kk = 0; kk < NB; ++kk)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) n[e][kk] += (acc[kk] >> (8 * e)) & 0xffu;
+      }
+    } else {
+#pragma unroll 4
+      for (int r = 0; r < th; ++r) {
+        const uint32_t word = *reinterpret_cast<const uint32_t *>(col + r * twp);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int b = (int)((word >> (8 * e)) & 0xffu) - k0;
+#pragma unroll
+          for (int kk = 0; kk < NB; ++kk) {
+            const uint32_t hit = b == kk ? 1u : 0u;
+            n[e][kk] += hit;
+            nx[e][kk] += hit * (uint32_t)(R0 + r);
+          }
         }
       }
     }
@@ -191,17 +228,32 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
     uint32_t n[NB] = {0u, 0u, 0u, 0u}, ny[NB] = {0u, 0u, 0u, 0u};
     const uint8_t *row = bin_s + r * twp;
     const int tw4 = tw & ~3;
+    if constexpr (!MOM) {
+      // four pixels against a bin at once: the match flags' bit count
+      uint32_t kl[NB];
+      const uint32_t flip = swar_flip(k0);
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk) kl[kk] = swar_key(k0 + kk);
 #pragma unroll 4
-    for (int c = 0; c < tw4; c += 4) {
-      const uint32_t word = *reinterpret_cast<const uint32_t *>(row + c);
+      for (int c = 0; c < tw4; c += 4) {
+        const uint32_t word = *reinterpret_cast<const uint32_t *>(row + c);
+        const uint32_t lo = word & 0x7f7f7f7fu, hi = (word & 0x80808080u) ^ flip;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int b = (int)((word >> (8 * e)) & 0xffu) - k0;
+        for (int kk = 0; kk < NB; ++kk) n[kk] += (uint32_t)__builtin_popcount(swar_match(lo, hi, kl[kk]));
+      }
+    } else {
+#pragma unroll 4
+      for (int c = 0; c < tw4; c += 4) {
+        const uint32_t word = *reinterpret_cast<const uint32_t *>(row + c);
 #pragma unroll
-        for (int kk = 0; kk < NB; ++kk) {
-          const uint32_t hit = b == kk ? 1u : 0u;
-          n[kk] += hit;
-          if constexpr (MOM) ny[kk] += hit * (uint32_t)(C0 + c + e);
+        for (int e = 0; e < 4; ++e) {
+          const int b = (int)((word >> (8 * e)) & 0xffu) - k0;
+#pragma unroll
+          for (int kk = 0; kk < NB; ++kk) {
+            const uint32_t hit = b == kk ? 1u : 0u;
+            n[kk] += hit;
+            ny[kk] += hit * (uint32_t)(C0 + c + e);
+          }
         }
       }
     }
@@ -691,8 +743,35 @@ __device__ __forceinline__ uint32_t masked_weights(uint32_t w, uint32_t m) {
   return w & keep;
 }
 
+// Stores the CPL consecutive values of a lane at dst (column cf of a row of
+// W).  Called by the whole wavefront (every lane, uniform control flow).
+// Rows that cannot take vector stores (the row length not a multiple of CPL,
+// or the output not 16-byte aligned) are written lane-contiguously: store s
+// writes the wave's columns 64 s + lane, each lane fetching its value from
+// the lane that holds it, so that each store instruction covers whole cache
+// lines; per-lane stores of single ints CPL apart would leave every line
+// half-written by each instruction.
 template <int CPL>
 __device__ __forceinline__ void put(int32_t *dst, const uint32_t (&v)[CPL], int cf, int W, bool vec_ok) {
+  if constexpr (CPL > 1) {
+    if (!vec_ok) {
+      const int lane = threadIdx.x & 63;
+      int32_t *row0 = dst - lane * CPL;  // the wave's first column, cf - lane * CPL
+      const int c0 = cf - lane * CPL;
+#pragma unroll
+      for (int s = 0; s < CPL; ++s) {
+        const int src = ((64 / CPL) * s + lane / CPL) << 2;  // byte address of the holding lane
+        int val = 0;
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          const int t = __builtin_amdgcn_ds_bpermute(src, (int)v[e]);
+          if (lane % CPL == e) val = t;
+        }
+        if (c0 + 64 * s + lane < W) __builtin_nontemporal_store(val, row0 + 64 * s + lane);
+      }
+      return;
+    }
+  }
   if (vec_ok && cf + CPL <= W) {
     int t[CPL];
 #pragma unroll

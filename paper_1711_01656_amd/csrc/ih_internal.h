@@ -181,9 +181,13 @@ constexpr int kCumChunk = 64;
 // fewer bins leave most threads idle there and keep the LDS histograms.  And
 // the LDS bytes that path needs: the staged bins of the tile plus the tile's
 // totals (count, row moment, column moment per bin).
+#ifndef IH_TILE_FAST_MIN
+#define IH_TILE_FAST_MIN 256  // work items (of four columns or one row, by four bins) per 256-thread block
+#endif
 __host__ __device__ __forceinline__ bool tile_fast(const Geom &g) {
   const int nq = (g.bins + 3) / 4;
-  return !g.wgt && !g.diff && !g.cum && g.coord == 0 && ((g.TW + 3) / 4) * nq >= 256 && g.TH * nq >= 256;
+  return !g.wgt && !g.diff && !g.cum && g.coord == 0 && ((g.TW + 3) / 4) * nq >= IH_TILE_FAST_MIN &&
+         g.TH * nq >= IH_TILE_FAST_MIN;
 }
 __host__ __device__ __forceinline__ size_t tile_fast_lds(const Geom &g) {
   return (((size_t)g.TH * (g.TW + 4) + 3) & ~(size_t)3) + (size_t)3 * g.bins * 4;

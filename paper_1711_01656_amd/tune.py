@@ -122,7 +122,7 @@ def tune(img: torch.Tensor, bins: int, value_bits: Optional[int] = None, moments
 def batch_candidates(layout: str) -> List[ih.TileCfg]:
     """Uniform tile shapes tried for a whole batch (every frame gets the same one)."""
     if layout == "hwb":
-        return [ih.TileCfg(th, tw, 64) for th, tw in itertools.product((32, 64, 128), (16, 32))]
+        return [ih.TileCfg(th, tw, 64) for th, tw in itertools.product((32, 64, 128), (16, 32, 64))]
     return [ih.TileCfg(th, tw, pg) for th, tw, pg in itertools.product((32, 64, 128), (64, 128), (1, 2))]
 
 
@@ -153,3 +153,42 @@ def tune_batch(frames, metric: str = "chi2", layout: str = "bhw", reps: int = 3,
     if best is None:
         raise ih.IHError("no tile shape fits every frame of the batch")
     return best, times
+
+
+def tune_batch_classes(frames, metric: str = "chi2", layout: str = "bhw", reps: int = 3, rounds: int = 1,
+                       verbose: bool = False):
+    """A tile shape per class of frames (the frames with the same bin count),
+    chosen by timing the whole batch: start from the best shape for every
+    frame (tune_batch), then for each class in turn try every candidate shape
+    on its frames while the other classes keep theirs, keeping a change only
+    when the whole batch gets faster; `rounds` passes over the classes.
+    Returns (tile per frame, {bins: tile}, batch ms with that choice,
+    batch ms with the uniform shape)."""
+    uniform, _ = tune_batch(frames, metric, layout, reps)
+    classes = sorted({int(f["bins"]) for f in frames})
+    choice = {c: uniform for c in classes}
+
+    def batch_ms(ch):
+        fr = [dict(f, tile=ch[int(f["bins"])], layout=layout) for f in frames]
+        try:
+            b = ih.Batch(fr, metric, layout=layout)
+        except ih.IHError:
+            return float("inf")
+        t = _time(lambda: b.run("phased"), reps)
+        del b
+        return t
+
+    uniform_t = best_t = batch_ms(choice)
+    for _ in range(rounds):
+        for c in classes:
+            for cfg in batch_candidates(layout):
+                if cfg == choice[c] or (layout == "bhw" and cfg.planes_per_wave > max(1, c)):
+                    continue
+                trial = dict(choice)
+                trial[c] = cfg
+                t = batch_ms(trial)
+                if verbose:
+                    print("tune batch class %d %s: %.4f ms" % (c, cfg, t), flush=True)
+                if t < best_t:
+                    best_t, choice = t, trial
+    return [choice[int(f["bins"])] for f in frames], choice, best_t, uniform_t

@@ -196,6 +196,8 @@ def test_build_config3_full_sampled():
     (97, 260, 255, 8, (64, 128, 1)),        # bins not a multiple of four
     (257, 300, 64, 16, (128, 64, 64)),      # planes-innermost tile that counts in registers
     (70, 129, 128, 8, (32, 64, 64)),
+    (600, 260, 256, 8, (256, 128, 1)),      # 256-row tiles: byte counters flushed twice per column
+    (530, 300, 200, 8, (256, 64, 64)),      # bins on both sides of 128
 ])
 def test_build_register_tile_pass(layout, H, W, bins, bits, tile):
     """Tile shapes whose tile pass counts in registers (four columns or one row
@@ -220,3 +222,25 @@ def test_build_register_tile_pass(layout, H, W, bins, bits, tile):
         assert np.array_equal(tr(o), ref)
         assert np.array_equal(tr(mx).astype(np.int64) & 0xFFFFFFFF, np.asarray(omx).astype(np.int64) & 0xFFFFFFFF)
         assert np.array_equal(tr(my).astype(np.int64) & 0xFFFFFFFF, np.asarray(omy).astype(np.int64) & 0xFFFFFFFF)
+
+
+@pytest.mark.parametrize("layout,tile", [("bhw", (256, 128, 1)), ("bhw", (128, 128, 2)), ("hwb", (256, 64, 64))])
+@pytest.mark.parametrize("bins,fill", [(64, 0), (256, 255), (200, 160)])
+def test_build_register_tile_pass_saturated_columns(layout, tile, bins, fill):
+    """A nearly constant image, so that one bin takes (almost) every pixel of a
+    tile column and row: the register tile pass's per-column byte counters
+    reach their largest values; against the oracle."""
+    ih = ihlib()
+    H, W = 515, 389
+    rng = np.random.default_rng(bins + fill)
+    img = np.full((1, H, W), fill, np.uint8)
+    sel = rng.random((H, W)) < 0.01
+    img[0][sel] = rng.integers(0, 256, size=int(sel.sum()))
+    img[0, 256:, 7] = fill                     # whole tile columns of one bin
+    ref = oracle.ih(img, bins, 8)
+    th, tw, pg = tile
+    out = ih.ih_build(gpu(img), bins, 8, cfg=ih.TileCfg(th, tw, pg, 3), layout=layout)
+    got = out.cpu().numpy()
+    if layout == "hwb":
+        got = got.transpose(2, 0, 1)
+    assert np.array_equal(got, ref)
