@@ -19,6 +19,7 @@
 namespace ih {
 
 constexpr int NPH = 6;
+constexpr int kLayStrip = 2;  // write-out class of the frames that take the strip write-out
 constexpr int kBatchLds = 32 * 1024;  // LDS budget of the tile-histogram phase
 #ifndef IH_BATCH_BHW_TH
 #define IH_BATCH_BHW_TH 64
@@ -51,6 +52,8 @@ struct BatchHeader {
   int32_t n, dtype, metric, lds;  // lds: dynamic LDS bytes of the cooperative kernel (all phases)
   int32_t lds_ph[NPH];            // dynamic LDS bytes of each phase's own kernel (phased mode)
   int32_t layouts;                // bit l set: some frame uses layout l
+  int32_t strips;                 // some frame takes the strip write-out
+  int32_t lds_strip;              // dynamic LDS bytes of the strip write-out kernel
   int64_t phase_start[NPH + 1];   // unit numbering: phase-major, frame-minor
   int64_t ws_words;
 };
@@ -74,6 +77,18 @@ __device__ __forceinline__ void final_dispatch(const FinalArgs &a, const Geom &g
   IH_B(2, 1) IH_B(2, 2) IH_B(2, 4) IH_B(2, 8)
   IH_B(4, 1) IH_B(4, 2) IH_B(4, 4) IH_B(4, 8)
 #undef IH_B
+}
+
+// Strip write-out (bin-major plain counts with rows not 64-byte aligned):
+// unit ux of the frame's strips, plane group grp, this wave's LDS ring.
+template <typename T>
+__device__ __forceinline__ void strip_dispatch(const FinalArgs &a, const Geom &g, int64_t ux, int grp, uint32_t *ring) {
+#define IH_S(C_, G_) \
+  if (g.CPL == C_ && g.PG == G_) { final_strip_body<T, C_, G_>(a, g, ux, grp, ring); return; }
+  IH_S(1, 1) IH_S(1, 2) IH_S(1, 4) IH_S(1, 8)
+  IH_S(2, 1) IH_S(2, 2) IH_S(2, 4) IH_S(2, 8)
+  IH_S(4, 1) IH_S(4, 2) IH_S(4, 4) IH_S(4, 8)
+#undef IH_S
 }
 
 // Planes-innermost write-out in a batch: four wave units per workgroup unit;
@@ -107,10 +122,18 @@ __device__ __forceinline__ void run_unit(const FramePlan &F, int ph, int64_t u, 
       break;
     case 2: {
       const FinalArgs a{F.img, F.ih, nullptr, nullptr, fws, F.bits, F.vec_ok};
-      if constexpr (LAY != IH_BHW) {
+      if constexpr (LAY == -1 || LAY == IH_HWB) {
         if (g.layout == IH_HWB) { final_hwb_batch<T>(a, g, u, lds); break; }
       }
-      if constexpr (LAY != IH_HWB) final_dispatch<T>(a, g, (int)(u % F.tiles), (int)(u / F.tiles));
+      if constexpr (LAY == -1 || LAY == kLayStrip) {
+        if (g.strip) {
+          const int wave = uniform((int)(threadIdx.x >> 6));
+          const int64_t X = strip_units(g);
+          strip_dispatch<T>(a, g, u % X, (int)(u / X) * 4 + wave, lds + (size_t)wave * (strip_lds_wave(g) / 4));
+          break;
+        }
+      }
+      if constexpr (LAY == -1 || LAY == IH_BHW) final_dispatch<T>(a, g, (int)(u % F.tiles), (int)(u / F.tiles));
       break;
     }
     case 3:
@@ -141,7 +164,8 @@ __device__ __forceinline__ void run_unit(const FramePlan &F, int ph, int64_t u, 
 // All units of phase ph, grid-stride.  The unit of a workgroup iteration is
 // uniform across the workgroup, so the bodies' barriers are reached by all.
 // LAY >= 0 restricts the phase to frames of that layout (the others' units
-// are skipped, uniformly per workgroup).
+// are skipped, uniformly per workgroup); in the write-out phase kLayStrip
+// takes the bin-major frames of the strip write-out and IH_BHW the others.
 template <typename T, int METRIC, int LAY = -1>
 __device__ __forceinline__ void run_phase(const BatchHeader *__restrict__ hdr, const FramePlan *__restrict__ fr,
                                           uint32_t *__restrict__ ws, int ph, uint32_t *lds) {
@@ -149,7 +173,7 @@ __device__ __forceinline__ void run_phase(const BatchHeader *__restrict__ hdr, c
   const int64_t end = hdr->phase_start[ph + 1];
   for (int64_t t = hdr->phase_start[ph] + blockIdx.x; t < end; t += gridDim.x) {
     const int f = find_frame(fr, n, ph, t);
-    if (LAY >= 0 && fr[f].g.layout != LAY) continue;
+    if (LAY >= 0 && (ph == 2 && fr[f].g.strip ? kLayStrip : fr[f].g.layout) != LAY) continue;
     run_unit<T, METRIC, LAY>(fr[f], ph, t - fr[f].start[ph], ws, lds);
     __syncthreads();
   }
@@ -180,13 +204,15 @@ typedef void (*phase_fn)(const BatchHeader *, const FramePlan *, uint32_t *);
 typedef void (*coop_fn)(const BatchHeader *, const FramePlan *, uint32_t *);
 
 // pf[ph][l]: the phase-ph kernel for frames of layout l (phases 2 and 4 have
-// one kernel per layout; the others serve both layouts, entry [ph][0]).
+// one kernel per layout, phase 2 a third for the strip write-out; the others
+// serve every frame, entry [ph][0]).
 template <typename T, int METRIC>
-static void pick_m(phase_fn (*pf)[2], coop_fn *cf) {
+static void pick_m(phase_fn (*pf)[3], coop_fn *cf) {
   pf[0][0] = &k_batch_phase<T, METRIC, 0, -1>;
   pf[1][0] = &k_batch_phase<T, METRIC, 1, -1>;
   pf[2][0] = &k_batch_phase<T, METRIC, 2, IH_BHW>;
   pf[2][1] = &k_batch_phase<T, METRIC, 2, IH_HWB>;
+  pf[2][2] = &k_batch_phase<T, METRIC, 2, kLayStrip>;
   pf[3][0] = &k_batch_phase<T, METRIC, 3, -1>;
   pf[4][0] = &k_batch_phase<T, METRIC, 4, IH_BHW>;
   pf[4][1] = &k_batch_phase<T, METRIC, 4, IH_HWB>;
@@ -195,7 +221,7 @@ static void pick_m(phase_fn (*pf)[2], coop_fn *cf) {
 }
 
 template <typename T>
-static void pick_t(int metric, phase_fn (*pf)[2], coop_fn *cf) {
+static void pick_t(int metric, phase_fn (*pf)[3], coop_fn *cf) {
   if (metric == IH_CHI2) pick_m<T, IH_CHI2>(pf, cf);
   else if (metric == IH_L1) pick_m<T, IH_L1>(pf, cf);
   else pick_m<T, IH_PMK>(pf, cf);
@@ -224,6 +250,7 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
   size_t carry = 0, lds = (size_t)kMatchWaves * 64 * 16;  // match partials: waves x 64 x (8 + 8) bytes
   if (lds < 256 * 16) lds = 256 * 16;                     // best-candidate reduction: 256 x (4 + 8), 8-aligned
   size_t lph[NPH] = {0, 0, 0, 0, 0, 256 * 16};
+  size_t lds_strip = 0;
   for (int f = 0; f < n; ++f) {
     const ih_frame &F = frames[f];
     FramePlan &P = fp[f];
@@ -248,6 +275,7 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
       return set_error(IH_ERR_UNSUPPORTED, "frame %d: planes_per_wave %d > 8 in a batch", f, P.g.PG);
     size_t l;
     P.g.c16 = F.H < 65536 && F.W < 65536;  // count carries fit 16 bits
+    P.g.strip = use_strip(P.g, F.ih);
     if ((e = pick_bc(P.g, kBatchLds, &P.bc, &l))) return set_error(e, "frame %d: %s", f, ih_last_error());
     if (tile_fast(P.g)) l = tile_fast_lds(P.g);
     if (l > lds) lds = l;
@@ -271,7 +299,13 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
     P.gy = (groups + 3) / 4;
     P.cnt[0] = P.tiles;
     P.cnt[1] = P.nA + P.nB + P.g.P;
-    P.cnt[2] = hwb ? ((int64_t)P.g.nTR * P.g.nTC * ((P.g.P + 63) / 64) + 3) / 4 : P.tiles * P.gy;
+    P.cnt[2] = hwb ? ((int64_t)P.g.nTR * P.g.nTC * ((P.g.P + 63) / 64) + 3) / 4
+                   : (P.g.strip ? strip_units(P.g) : P.tiles) * P.gy;
+    if (P.g.strip) {
+      const size_t rings = 4 * strip_lds_wave(P.g);  // four waves' LDS rings
+      if (rings > lds) lds = rings;
+      if (rings > lds_strip) lds_strip = rings;
+    }
     if (F.n_cand < 0) return set_error(IH_ERR_INVALID_ARG, "frame %d: n_cand < 0", f);
     if (F.n_cand > 0) {
       if (!F.origins || !F.dist || !F.best) return set_error(IH_ERR_INVALID_ARG, "frame %d: NULL search buffer", f);
@@ -311,7 +345,12 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
   h->lds = (int32_t)lds;
   for (int ph = 0; ph < NPH; ++ph) h->lds_ph[ph] = (int32_t)lph[ph];
   h->layouts = 0;
-  for (int f = 0; f < n; ++f) h->layouts |= 1 << fp[f].g.layout;
+  h->strips = 0;
+  for (int f = 0; f < n; ++f) {
+    h->layouts |= 1 << fp[f].g.layout;
+    if (fp[f].g.strip) h->strips = 1;
+  }
+  h->lds_strip = (int32_t)lds_strip;
   h->ws_words = carry > 0 ? (int64_t)carry : 64;
   *ws_bytes = (size_t)h->ws_words * 4;
   return IH_OK;
@@ -328,7 +367,7 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
   if (!ws || ws_bytes < (size_t)h->ws_words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)h->ws_words * 4);
   hipStream_t s = as_stream(stream);
-  phase_fn pf[NPH][2] = {};
+  phase_fn pf[NPH][3] = {};
   coop_fn cf;
   if (h->dtype == IH_U8) pick_t<uint8_t>(h->metric, pf, &cf);
   else pick_t<uint16_t>(h->metric, pf, &cf);
@@ -344,18 +383,18 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
     for (int ph = 0; ph < NPH; ++ph) {
       const int64_t units = h->phase_start[ph + 1] - h->phase_start[ph];
       if (units == 0) continue;
-      for (int l = 0; l < 2; ++l) {
+      for (int l = 0; l < 3; ++l) {
         const bool split = pf[ph][1] != nullptr;
-        if (!split && l == 1) break;
-        if (split && !(h->layouts & (1 << l))) continue;
+        if (!split && l > 0) break;
         phase_fn k = pf[ph][l];
-        if ((e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, h->lds_ph[ph]),
-                           "occupancy")))
+        if (!k || (split && l < 2 && !(h->layouts & (1 << l))) || (l == 2 && !h->strips)) continue;
+        const int lds_k = l == 2 ? h->lds_strip : h->lds_ph[ph];
+        if ((e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds_k), "occupancy")))
           return e;
         if (per_cu < 1) return set_error(IH_ERR_UNSUPPORTED, "batch phase %d cannot be resident", ph);
         const int64_t resident = (int64_t)per_cu * cus;
         const int64_t blocks = units < 4 * resident ? units : 4 * resident;
-        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), h->lds_ph[ph], s, hd, fd, w32);
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds_k, s, hd, fd, w32);
         if ((e = hip_check(hipGetLastError(), "batch phase launch"))) return e;
       }
     }

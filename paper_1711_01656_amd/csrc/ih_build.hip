@@ -70,6 +70,7 @@ int make_geom(int32_t H, int32_t W, int32_t C, int32_t bins, int32_t moments, in
   g->coord = 0;
   g->cum = false;
   g->c16 = false;
+  g->strip = false;
   g->layout = layout;
   int TH, TW, PG;
   if (cfg) {
@@ -192,8 +193,20 @@ static final_fn pick_hwb_t(int TW, bool staged) {
   return nullptr;
 }
 
+template <typename T>
+static final_fn pick_strip_t(int CPL, int PG) {
+#define IH_S(C_, G_) \
+  if (CPL == C_ && PG == G_) return &k_final_strip<T, C_, G_>;
+  IH_S(1, 1) IH_S(1, 2) IH_S(1, 4) IH_S(1, 8) IH_S(1, 16)
+  IH_S(2, 1) IH_S(2, 2) IH_S(2, 4) IH_S(2, 8) IH_S(2, 16)
+  IH_S(4, 1) IH_S(4, 2) IH_S(4, 4) IH_S(4, 8) IH_S(4, 16)
+#undef IH_S
+  return nullptr;
+}
+
 static final_fn pick_final(int dtype, const Geom &g) {
   const bool u8 = dtype == IH_U8;
+  if (g.strip) return u8 ? pick_strip_t<uint8_t>(g.CPL, g.PG) : pick_strip_t<uint16_t>(g.CPL, g.PG);
   if (g.wgt) {
     if (g.layout == IH_HWB) {
       const bool st = staged_lds(g) > 0;
@@ -312,8 +325,14 @@ int ih::launch_build(const Geom &g, int dtype, const void *img, const void *tail
   if ((e = hip_check(hipGetLastError(), "carry_scan launch"))) return e;
 
   dim3 grid, block;
-  const size_t st = staged_lds(g);
-  if (g.layout == IH_BHW) {
+  size_t st = staged_lds(g);
+  if (g.strip) {
+    const int groups = (g.bins + g.PG - 1) / g.PG;
+    const int wpb = groups < 4 ? groups : 4;
+    grid = dim3((unsigned)strip_units(g), (unsigned)((groups + wpb - 1) / wpb));
+    block = dim3(64 * wpb);
+    st = strip_lds_wave(g) * wpb;
+  } else if (g.layout == IH_BHW) {
     const int groups = (g.bins + g.PG - 1) / g.PG;
     const int wpb = groups < 4 ? groups : 4;
     grid = dim3(tiles, (unsigned)((groups + wpb - 1) / wpb));
@@ -327,7 +346,7 @@ int ih::launch_build(const Geom &g, int dtype, const void *img, const void *tail
     block = dim3(256);
   }
   if (g_hook.start && (e = hip_check(hipEventRecord(g_hook.start, s), "profile start"))) return e;
-  hipLaunchKernelGGL(fin, grid, block, g.layout == IH_BHW ? 0 : st, s, fa, g);
+  hipLaunchKernelGGL(fin, grid, block, g.layout == IH_BHW && !g.strip ? 0 : st, s, fa, g);
   if ((e = hip_check(hipGetLastError(), "final launch"))) return e;
   if (g_hook.stop && (e = hip_check(hipEventRecord(g_hook.stop, s), "profile stop"))) return e;
   return IH_OK;
@@ -369,6 +388,8 @@ static int build_impl(const void *img, int32_t dtype, const uint8_t *wt, const u
   if (e) return e;
   // plain counts: every column carry is below H and every row carry below W
   g.c16 = !wt && H < 65536 && W < 65536;
+  // strips run G tiles a wave in sequence: only when they still give many waves
+  g.strip = use_strip(g, ih) && strip_units(g) * ((g.bins + g.PG - 1) / g.PG) >= 8192;
   if (!ws || ws_bytes < g.words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", g.words * 4,
                      ws ? ws_bytes : (size_t)0);

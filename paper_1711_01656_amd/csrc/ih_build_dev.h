@@ -1422,10 +1422,159 @@ __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const 
 }
 
 
+// 3f. Bin-major write-out of plain counts whose rows do not start on 64-byte
+//     boundaries (the row length not a multiple of 16, or the output not
+//     64-byte aligned).  There the tile-per-wave write-out leaves the first
+//     and last 64-byte block of every tile's row segment shared with the
+//     neighbouring tiles' segments, written by other waves at other times,
+//     and each part of a shared block costs a whole block.  Here one
+//     wavefront takes a strip of G consecutive tiles of a tile row (and a
+//     plane group) and walks each row through the strip: the row prefix
+//     runs on from tile to tile in registers (row carries are read at the
+//     strip's left edge only), each tile keeps its column sums in registers,
+//     and each tile's row is stored as a window shifted left by the row's
+//     misalignment d (0..15 ints) so that it starts on a 64-byte boundary:
+//     the window's first d columns are the previous tile's last ones, its
+//     own last d columns go with the next tile's window.  Values pass
+//     through a per-wave LDS ring of two tiles per plane (column c at slot
+//     (c + d) mod 2 TW, so windows read 16-byte groups); only the strip ends
+//     leave shared blocks.  G = 16 / (CPL PG) keeps 16 column-sum registers.
+template <int CPL, int PG>
+__host__ __device__ constexpr int strip_tiles() { return 16 / (CPL * PG) > 0 ? 16 / (CPL * PG) : 1; }
+
+template <typename T, int CPL, int PG>
+__device__ __forceinline__ void final_strip_body(const FinalArgs &a, const Geom &g, int64_t ux, int grp,
+                                                 uint32_t *ring) {
+  constexpr int TW = 64 * CPL, G = strip_tiles<CPL, PG>(), RING = 2 * TW;
+  const int lane = threadIdx.x & 63;
+  const int kb = grp * PG;
+  if (kb >= g.bins) return;
+  const int nk = min(PG, g.bins - kb);
+  const int nS = (g.nTC + G - 1) / G;
+  const int s = (int)(ux % nS);
+  const int64_t rest = ux / nS;
+  const int I = (int)(rest % g.nTR);
+  const int ch = (int)(rest / g.nTR);
+  const int j0 = s * G, nt = min(G, g.nTC - j0);
+  const int R0 = I * g.TH, rows = min(g.TH, g.H - R0);
+  const int64_t HW = (int64_t)g.H * g.W;
+  const T *img = reinterpret_cast<const T *>(a.img) + ch * HW;
+
+  uint32_t col[G][PG][CPL];
+#pragma unroll
+  for (int t = 0; t < G; ++t) {
+    if (t < nt) {
+      const int j = j0 + t, cf = j * TW + lane * CPL;
+#pragma unroll
+      for (int k = 0; k < PG; ++k) {
+        if (k < nk) {
+          const int64_t p = (int64_t)ch * g.bins + kb + k;
+          const int64_t crow = (p * g.nTR + I) * (int64_t)g.W;
+          const int64_t cidx = (p * g.nTR + I) * (int64_t)g.nTC + j;
+          uint32_t v[CPL];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) v[e] = (cf + e < g.W) ? cget(g, a.ws, g.off_cc, crow + cf + e) : 0u;
+#pragma unroll
+          for (int e = 1; e < CPL; ++e) v[e] += v[e - 1];
+          const uint32_t base = a.ws[g.off_tt + cidx] + wave_incl_scan(v[CPL - 1]) - v[CPL - 1];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) col[t][k][e] = base + v[e];
+        }
+      }
+    }
+  }
+
+  const int64_t lc_base = (((int64_t)ch * g.nTC + j0) * g.H) * g.bins + kb;  // row carries at the strip's left edge
+  const uint32_t ihoff = (uint32_t)(((uintptr_t)a.ih >> 2) & 15);
+  uint32_t bad = 0;
+  uint32_t pxn[CPL];
+  auto fetch = [&](int r, int t) {
+    const int cf = (j0 + t) * TW + lane * CPL;
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) pxn[e] = cf + e < g.W ? (uint32_t)img[(int64_t)r * g.W + cf + e] : 0u;
+  };
+  if (rows > 0) fetch(R0, 0);
+  for (int rr = 0; rr < rows; ++rr) {
+    const int r = R0 + rr;
+    uint32_t lcur[PG];
+#pragma unroll
+    for (int k = 0; k < PG; ++k) lcur[k] = k < nk ? cget(g, a.ws, g.off_rc, lc_base + (int64_t)r * g.bins + k) : 0u;
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      if (t < nt) {
+        const int C0 = (j0 + t) * TW, cf = C0 + lane * CPL;
+        uint32_t px[CPL];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) px[e] = pxn[e];
+        if (t + 1 < nt) fetch(r, t + 1);
+        else if (rr + 1 < rows) fetch(r + 1, 0);
+        int b[CPL];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          b[e] = cf + e < g.W ? (int)(((uint64_t)px[e] * g.bins) >> a.bits) - kb : -1;
+          bad |= px[e] >> a.bits;
+        }
+#pragma unroll
+        for (int k = 0; k < PG; ++k) {
+          if (k < nk) {
+            uint32_t tq = lcur[k];
+            uint64_t m[CPL];
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) m[e] = ballot(b[e] == k);
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) tq = lanes_below(m[e], tq);
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) {
+              tq += (b[e] == k) ? 1u : 0u;
+              col[t][k][e] += tq;
+            }
+            lcur[k] = read_lane(tq, 63);
+            const int64_t rowbase = (((int64_t)ch * g.bins + kb + k) * g.H + r) * (int64_t)g.W;  // column 0
+            const int d = (int)((ihoff + (uint64_t)(rowbase + C0)) & 15);
+            uint32_t *rk = ring + k * RING;
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) rk[(C0 + lane * CPL + e + d) % RING] = col[t][k][e];
+            wave_sync();
+            // window [wlo, whi): 4-int groups from the 64-byte aligned column C0 - d
+            const int wlo = t == 0 ? C0 : C0 - d;
+            const int whi = t == nt - 1 ? min(C0 + TW, g.W) : C0 + TW - d;
+            int32_t *orow = a.ih + rowbase;
+#pragma unroll
+            for (int q0 = 0; q0 < (TW + 16) / 4; q0 += 64) {
+              const int q = q0 + lane;
+              const int c = C0 - d + 4 * q;
+              if (c < whi && c + 4 > wlo) {
+                const v4i w = *reinterpret_cast<const v4i *>(rk + (C0 + 4 * q) % RING);
+                if (c >= wlo && c + 4 <= whi) {
+                  __builtin_nontemporal_store(w, reinterpret_cast<v4i *>(orow + c));
+                } else {
+#pragma unroll
+                  for (int i = 0; i < 4; ++i)
+                    if (c + i >= wlo && c + i < whi) __builtin_nontemporal_store(w[i], orow + c + i);
+                }
+              }
+            }
+            wave_sync();
+          }
+        }
+      }
+    }
+  }
+  report_range(a.status, bad);
+}
+
 // ------------------------------------------------ stand-alone kernels --
 template <typename T, int CPL, int PG, bool MOM, int WK>
 __global__ __launch_bounds__(256) void k_final(FinalArgs a, Geom g) {
   final_body<T, CPL, PG, MOM, WK>(a, g, blockIdx.x, blockIdx.y, uniform(threadIdx.x >> 6), blockDim.x >> 6);
+}
+
+template <typename T, int CPL, int PG>
+__global__ __launch_bounds__(256) void k_final_strip(FinalArgs a, Geom g) {
+  extern __shared__ uint32_t ring[];
+  const int wave = uniform(threadIdx.x >> 6);
+  final_strip_body<T, CPL, PG>(a, g, blockIdx.x, blockIdx.y * (blockDim.x >> 6) + wave,
+                               ring + wave * PG * 2 * 64 * CPL);
 }
 
 template <typename T, int TW, bool MOM, int WK>

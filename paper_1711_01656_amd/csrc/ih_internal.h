@@ -116,6 +116,7 @@ struct Geom {
   int coord;            // coordinate weight of the tile pass (2: row^2, 3: column^2); 0: none
   bool cum;             // cumulative planes: plane k counts bins <= k (joint-IH update)
   bool c16;             // count carries (CC, RC) stored as 16-bit values in their 32-bit-sized arrays
+  bool strip;           // bin-major plain counts written by the strip write-out (rows not 64-byte aligned)
   int layout;           // IH_BHW or IH_HWB
   // workspace sections (in 4-byte words)
   size_t off_cc, off_rc, off_tt, off_ccx, off_rcy, off_ttx, off_tty, words;
@@ -192,6 +193,23 @@ __host__ __device__ __forceinline__ bool tile_fast(const Geom &g) {
 __host__ __device__ __forceinline__ size_t tile_fast_lds(const Geom &g) {
   return (((size_t)g.TH * (g.TW + 4) + 3) & ~(size_t)3) + (size_t)3 * g.bins * 4;
 }
+
+// Whether a bin-major build takes the strip write-out: plain counts whose
+// rows do not all start on 64-byte boundaries (ih: the output).
+#ifndef IH_STRIP
+#define IH_STRIP 1
+#endif
+inline bool use_strip(const Geom &g, const void *ih) {
+  return IH_STRIP && g.layout == IH_BHW && !g.mom && !g.wgt && !g.diff && !g.cum && g.coord == 0 &&
+         (g.W % 16 != 0 || ((uintptr_t)ih & 63) != 0);
+}
+// Tiles per strip, units of the strip write-out per channel and plane group,
+// and its LDS bytes per wave (two tiles per plane).
+__host__ __device__ inline int strip_g(const Geom &g) { return 16 / (g.CPL * g.PG) > 0 ? 16 / (g.CPL * g.PG) : 1; }
+__host__ __device__ inline int64_t strip_units(const Geom &g) {
+  return (int64_t)g.C * g.nTR * ((g.nTC + strip_g(g) - 1) / strip_g(g));
+}
+__host__ __device__ inline size_t strip_lds_wave(const Geom &g) { return (size_t)g.PG * 2 * g.TW * 4; }
 
 __host__ __device__ __forceinline__ int tile_chunks(const Geom &g, int bc) {
   return g.cum ? (g.bins + bc - 1) / bc : 1;

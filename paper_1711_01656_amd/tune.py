@@ -123,7 +123,8 @@ def batch_candidates(layout: str) -> List[ih.TileCfg]:
     """Uniform tile shapes tried for a whole batch (every frame gets the same one)."""
     if layout == "hwb":
         return [ih.TileCfg(th, tw, 64) for th, tw in itertools.product((32, 64, 128), (16, 32, 64))]
-    return [ih.TileCfg(th, tw, pg) for th, tw, pg in itertools.product((32, 64, 128), (64, 128), (1, 2))]
+    return [ih.TileCfg(th, tw, pg) for th, tw, pg in itertools.product((32, 64, 128), (64, 128, 256), (1, 2))
+            if th * tw <= 32768]
 
 
 def tune_batch(frames, metric: str = "chi2", layout: str = "bhw", reps: int = 3,

@@ -244,3 +244,41 @@ def test_build_register_tile_pass_saturated_columns(layout, tile, bins, fill):
     if layout == "hwb":
         got = got.transpose(2, 0, 1)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("W,bins,tile", [
+    (1023, 64, (16, 64, 1)),     # 16 tiles a strip, one strip short of the row
+    (4095, 16, (32, 64, 1)),     # two strips of 32 tiles
+    (2049, 64, (32, 128, 2)),    # three strips of 8 tiles, a 1-column last tile
+    (1030, 64, (64, 256, 2)),    # four tiles a strip
+    (1023, 64, (8, 256, 8)),     # one tile a strip
+    (777, 48, (16, 64, 16)),     # 16 planes a wave, last group partial
+    (130, 64, (64, 128, 4)),     # a row of two tiles
+    (97, 5, (16, 64, 2)),        # fewer bins than a full group
+])
+def test_build_strip_writeout(W, bins, tile):
+    """Bin-major plain counts of rows that do not start on 64-byte boundaries
+    (the strip write-out: windows shifted to 64-byte boundaries across a strip
+    of tiles), against the oracle, u8 and u16."""
+    ih = ihlib()
+    th, tw, pg = tile
+    for bits in (8, 16):
+        H = 70 + bits
+        img = rand_img(W + bins + bits, 1, H, W, bits)
+        out = ih.ih_build(gpu(img), bins, bits, cfg=ih.TileCfg(th, tw, pg, 3), layout="bhw")
+        assert np.array_equal(out.cpu().numpy(), oracle.ih(img, bins, bits))
+
+
+@pytest.mark.parametrize("offset", [1, 4, 15])
+def test_build_strip_writeout_misaligned_output(offset):
+    """Rows of a 64-byte multiple written to an output that starts `offset`
+    ints past a 64-byte boundary: every row is shifted the same way."""
+    ih = ihlib()
+    H, W, bins = 90, 512, 32
+    img = rand_img(offset, 2, H, W, 8)
+    P = 2 * bins
+    buf = torch.zeros(P * H * W + 64, dtype=torch.int32, device=DEV)
+    out = buf[offset:offset + P * H * W].view(P, H, W)
+    ih.ih_build(gpu(img), bins, 8, cfg=ih.TileCfg(32, 128, 2, 3), layout="bhw", out=out)
+    assert np.array_equal(out.cpu().numpy(), oracle.ih(img, bins, 8))
+    assert int(buf[:offset].abs().sum()) == 0 and int(buf[offset + P * H * W:].abs().sum()) == 0
