@@ -458,7 +458,7 @@ def time_calls(torch, fn, n):
 
 # tile shapes the autotuners chose for the other workloads on one MI355X
 FIXED_TILES = {"640x480": (16, 16, 64), "8192x8192": (128, 64, 64), "batch_hwb": (128, 32, 64),
-               "batch_bhw": (128, 128, 2)}
+               "batch_bhw": (64, 256, 2)}
 
 
 def phog_leg(torch, ih, synth):
