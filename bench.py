@@ -774,23 +774,27 @@ def batch_leg(torch, ih, synth, args, fixed=False):
                            origins=torch.from_numpy(f.origins).to(dev), win=(32, 32), tmpl_win=f.tmpl_win))
         total += f.img.shape[1] * f.img.shape[2] * f.bins
     per_layout = {}
-    for lay in ("hwb", "bhw"):
+    for lay in ("hwb", "bhw", "any"):
         if fixed:
-            tiles = [ih.TileCfg(*FIXED_TILES["batch_" + lay])] * len(frames)
+            if lay == "any":
+                continue
+            tiles = [(lay, ih.TileCfg(*FIXED_TILES["batch_" + lay]))] * len(frames)
             by_bins, uniform_ms = {f["bins"]: tiles[0] for f in frames}, None
         else:
-            # a tile shape per bin count, each chosen by timing the whole batch
+            # a tile shape (and with "any" a layout) per bin count, each chosen
+            # by timing the whole batch
             tiles, by_bins, _, uniform_ms = tune.tune_batch_classes(frames, "chi2", layout=lay, reps=2)
-        for fr, t in zip(frames, tiles):
-            fr["tile"] = t
-        batch = ih.Batch(frames, "chi2", layout=lay)
+        for fr, (fl, t) in zip(frames, tiles):
+            fr["layout"], fr["tile"] = fl, t
+        batch = ih.Batch(frames, "chi2", layout="bhw" if lay == "any" else lay)
         batch.run("phased")
         torch.cuda.synchronize()
         ref = [b.clone() for b in batch.best]
         t_graph = graph_median(torch, lambda: batch.run("phased"), 5)
         t_coop = float(np.median([time_calls(torch, lambda: batch.run("cooperative"), 5) for _ in range(3)]))
         same = all(torch.equal(a, b) for a, b in zip(ref, batch.best))
-        per_layout[lay] = {"tiles_by_bins": {str(k): repr(v) for k, v in sorted(by_bins.items())},
+        per_layout["per_class_layout" if lay == "any" else lay] = {
+                           "tiles_by_bins": {str(k): "%s %r" % v for k, v in sorted(by_bins.items())},
                            "uniform_tile_ms": None if uniform_ms is None else round(uniform_ms, 3),
                            "graph_phased_ms": round(t_graph, 3),
                            "cooperative_ms": round(t_coop, 3),

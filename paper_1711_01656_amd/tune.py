@@ -162,17 +162,26 @@ def tune_batch_classes(frames, metric: str = "chi2", layout: str = "bhw", reps: 
     chosen by timing the whole batch: start from the best shape for every
     frame (tune_batch), then for each class in turn try every candidate shape
     on its frames while the other classes keep theirs, keeping a change only
-    when the whole batch gets faster; `rounds` passes over the classes.
-    Returns (tile per frame, {bins: tile}, batch ms with that choice,
-    batch ms with the uniform shape)."""
-    uniform, _ = tune_batch(frames, metric, layout, reps)
+    when the whole batch gets faster; `rounds` passes over the classes.  With
+    layout="any" a class's candidates are the shapes of both layouts, so each
+    class also gets its layout (frames whose planes fill few lanes of a
+    planes-innermost wave may build faster bin-major, and the reverse).
+    Returns (a (layout, tile) per frame, {bins: (layout, tile)}, batch ms
+    with that choice, batch ms with the uniform starting shape)."""
+    lays = ("bhw", "hwb") if layout == "any" else (layout,)
+    start = None
+    for lay in lays:
+        cfg, times = tune_batch(frames, metric, lay, reps)
+        t = min(times.values()) if times else float("inf")
+        if start is None or t < start[2]:
+            start = (lay, cfg, t)
     classes = sorted({int(f["bins"]) for f in frames})
-    choice = {c: uniform for c in classes}
+    choice = {c: (start[0], start[1]) for c in classes}
 
     def batch_ms(ch):
-        fr = [dict(f, tile=ch[int(f["bins"])], layout=layout) for f in frames]
+        fr = [dict(f, layout=ch[int(f["bins"])][0], tile=ch[int(f["bins"])][1]) for f in frames]
         try:
-            b = ih.Batch(fr, metric, layout=layout)
+            b = ih.Batch(fr, metric, layout=start[0])
         except ih.IHError:
             return float("inf")
         t = _time(lambda: b.run("phased"), reps)
@@ -182,14 +191,15 @@ def tune_batch_classes(frames, metric: str = "chi2", layout: str = "bhw", reps: 
     uniform_t = best_t = batch_ms(choice)
     for _ in range(rounds):
         for c in classes:
-            for cfg in batch_candidates(layout):
-                if cfg == choice[c] or (layout == "bhw" and cfg.planes_per_wave > max(1, c)):
-                    continue
-                trial = dict(choice)
-                trial[c] = cfg
-                t = batch_ms(trial)
-                if verbose:
-                    print("tune batch class %d %s: %.4f ms" % (c, cfg, t), flush=True)
-                if t < best_t:
-                    best_t, choice = t, trial
+            for lay in lays:
+                for cfg in batch_candidates(lay):
+                    if (lay, cfg) == choice[c] or (lay == "bhw" and cfg.planes_per_wave > max(1, c)):
+                        continue
+                    trial = dict(choice)
+                    trial[c] = (lay, cfg)
+                    t = batch_ms(trial)
+                    if verbose:
+                        print("tune batch class %d %s %s: %.4f ms" % (c, lay, cfg, t), flush=True)
+                    if t < best_t:
+                        best_t, choice = t, trial
     return [choice[int(f["bins"])] for f in frames], choice, best_t, uniform_t

@@ -188,25 +188,27 @@ def test_batch_64_uneven_frames(layout):
         assert np.all(np.abs(d - od) <= 1e-5 * np.abs(od)), i
 
 
-@pytest.mark.parametrize("layout", ["bhw", "hwb"])
+@pytest.mark.parametrize("layout", ["bhw", "hwb", "any"])
 def test_batch_tile_per_bin_class(layout):
-    """tune_batch_classes gives every frame a candidate shape, one per bin
-    count, never slower (as timed) than the uniform shape it starts from; the
-    batch built with those shapes matches the oracle."""
+    """tune_batch_classes gives every frame a candidate shape (and with "any"
+    a layout), one per bin count, never slower (as timed) than the uniform
+    shape it starts from; the batch built with those choices matches the
+    oracle."""
     ih = ihlib()
     from paper_1711_01656_amd import tune
     frames = make_frames(21, np.uint8, n=10)
     say("tune per class", layout)
     tiles, by_bins, best_ms, uniform_ms = tune.tune_batch_classes(frames, "chi2", layout=layout, reps=1)
-    cands = set(map(repr, tune.batch_candidates(layout)))
+    lays = ("bhw", "hwb") if layout == "any" else (layout,)
+    cands = {(l, repr(c)) for l in lays for c in tune.batch_candidates(l)}
     assert len(tiles) == len(frames)
     assert set(by_bins) == {int(f["bins"]) for f in frames}
-    for fr, t in zip(frames, tiles):
-        assert repr(t) in cands and t == by_bins[int(fr["bins"])]
+    for fr, (fl, t) in zip(frames, tiles):
+        assert (fl, repr(t)) in cands and (fl, t) == by_bins[int(fr["bins"])]
     assert best_ms <= uniform_ms
-    for fr, t in zip(frames, tiles):
-        fr["tile"] = t
-    batch = ih.Batch(frames, "chi2", layout=layout)
+    for fr, (fl, t) in zip(frames, tiles):
+        fr["layout"], fr["tile"] = fl, t
+    batch = ih.Batch(frames, "chi2", layout="bhw")
     batch.run()
     torch.cuda.synchronize()
-    check(batch, frames, "chi2", layout)
+    check(batch, frames, "chi2", "bhw")
