@@ -19,13 +19,14 @@ namespace ih {
 // one kernel per layout, phase 2 a third for the strip write-out; the others
 // serve every frame, entry [ph][0]).
 template <typename T, int METRIC>
-static void pick_m(phase_fn (*pf)[3]) {
+static void pick_m(phase_fn (*pf)[4]) {
   // phases 0-3 do not depend on the metric: one instance serves all three
   pf[0][0] = &k_batch_phase<T, IH_CHI2, 0, -1>;
   pf[1][0] = &k_batch_phase<T, IH_CHI2, 1, -1>;
   pf[2][0] = &k_batch_phase<T, IH_CHI2, 2, IH_BHW>;
   pf[2][1] = &k_batch_phase<T, IH_CHI2, 2, IH_HWB>;
   pf[2][2] = &k_batch_phase<T, IH_CHI2, 2, kLayStrip>;
+  pf[2][3] = &k_batch_phase<T, IH_CHI2, 2, kLayStreams>;
   pf[3][0] = &k_batch_phase<T, IH_CHI2, 3, -1>;
   pf[4][0] = &k_batch_phase<T, METRIC, 4, IH_BHW>;
   pf[4][1] = &k_batch_phase<T, METRIC, 4, IH_HWB>;
@@ -33,7 +34,7 @@ static void pick_m(phase_fn (*pf)[3]) {
 }
 
 template <typename T>
-static void pick_t(int metric, phase_fn (*pf)[3]) {
+static void pick_t(int metric, phase_fn (*pf)[4]) {
   if (metric == IH_CHI2) pick_m<T, IH_CHI2>(pf);
   else if (metric == IH_L1) pick_m<T, IH_L1>(pf);
   else pick_m<T, IH_PMK>(pf);
@@ -157,10 +158,10 @@ extern "C" int ih_batch_plan(const ih_frame *frames, int32_t n, int32_t dtype, i
   h->lds = (int32_t)lds;
   for (int ph = 0; ph < NPH; ++ph) h->lds_ph[ph] = (int32_t)lph[ph];
   h->layouts = 0;
-  h->strips = 0;
+  h->wclasses = 0;
   for (int f = 0; f < n; ++f) {
     h->layouts |= 1 << fp[f].g.layout;
-    if (fp[f].g.strip) h->strips = 1;
+    h->wclasses |= 1 << batch_wclass(fp[f].g);
   }
   h->lds_strip = (int32_t)lds_strip;
   h->ws_words = carry > 0 ? (int64_t)carry : 64;
@@ -179,7 +180,7 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
   if (!ws || ws_bytes < (size_t)h->ws_words * 4)
     return set_error(IH_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)h->ws_words * 4);
   hipStream_t s = as_stream(stream);
-  phase_fn pf[NPH][3] = {};
+  phase_fn pf[NPH][4] = {};
   if (h->dtype == IH_U8) pick_t<uint8_t>(h->metric, pf);
   else pick_t<uint16_t>(h->metric, pf);
   const coop_fn cf = h->dtype == IH_U8 ? pick_coop_u8(h->metric) : pick_coop_u16(h->metric);
@@ -195,11 +196,14 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
     for (int ph = 0; ph < NPH; ++ph) {
       const int64_t units = h->phase_start[ph + 1] - h->phase_start[ph];
       if (units == 0) continue;
-      for (int l = 0; l < 3; ++l) {
+      for (int l = 0; l < 4; ++l) {
         const bool split = pf[ph][1] != nullptr;
         if (!split && l > 0) break;
         phase_fn k = pf[ph][l];
-        if (!k || (split && l < 2 && !(h->layouts & (1 << l))) || (l == 2 && !h->strips)) continue;
+        // the write-out phase runs one kernel per write-out class present, the
+        // scoring phase one per layout
+        const int present = ph == 2 ? h->wclasses : h->layouts;
+        if (!k || (split && !(present & (1 << l)))) continue;
         const int lds_k = l == 2 ? h->lds_strip : h->lds_ph[ph];
         if ((e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds_k), "occupancy")))
           return e;
