@@ -204,8 +204,19 @@ static final_fn pick_strip_t(int CPL, int PG) {
   return nullptr;
 }
 
+template <typename T, int WK>
+static final_fn pick_streams_t(int TW, int P) {
+  if (P <= 8) return TW == 16 ? &k_final_hwb_streams<T, 16, 8, WK> : &k_final_hwb_streams<T, 32, 8, WK>;
+  if (P <= 16) return TW == 16 ? &k_final_hwb_streams<T, 16, 4, WK> : &k_final_hwb_streams<T, 32, 4, WK>;
+  return TW == 16 ? &k_final_hwb_streams<T, 16, 2, WK> : &k_final_hwb_streams<T, 32, 2, WK>;
+}
+
 static final_fn pick_final(int dtype, const Geom &g) {
   const bool u8 = dtype == IH_U8;
+  if (hwb_streams(g)) {
+    if (g.wgt) return u8 ? pick_streams_t<uint8_t, 1>(g.TW, g.P) : pick_streams_t<uint16_t, 1>(g.TW, g.P);
+    return u8 ? pick_streams_t<uint8_t, 0>(g.TW, g.P) : pick_streams_t<uint16_t, 0>(g.TW, g.P);
+  }
   if (g.strip) return u8 ? pick_strip_t<uint8_t>(g.CPL, g.PG) : pick_strip_t<uint16_t>(g.CPL, g.PG);
   if (g.wgt) {
     if (g.layout == IH_HWB) {
@@ -326,7 +337,11 @@ int ih::launch_build(const Geom &g, int dtype, const void *img, const void *tail
 
   dim3 grid, block;
   size_t st = staged_lds(g);
-  if (g.strip) {
+  if (hwb_streams(g)) {  // the column-stream write-out picked for it: four tiles a block
+    grid = dim3((unsigned)(((int64_t)g.nTR * g.nTC + 3) / 4));
+    block = dim3(256);
+    st = (size_t)4 * g.TW * 64 * 4;
+  } else if (g.strip) {
     const int groups = (g.bins + g.PG - 1) / g.PG;
     const int wpb = groups < 4 ? groups : 4;
     grid = dim3((unsigned)strip_units(g), (unsigned)((groups + wpb - 1) / wpb));

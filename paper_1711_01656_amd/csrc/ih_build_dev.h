@@ -57,6 +57,17 @@ typedef void (*final_fn)(FinalArgs, Geom);
 #ifndef IH_HWB_STAGED
 #define IH_HWB_STAGED 1
 #endif
+// Whether a single-frame planes-innermost build writes out in column
+// streams (3d'): counts or masked u8 weights, at most 32 planes, 16- or
+// 32-column tiles.
+#ifndef IH_HWB_STREAMS
+#define IH_HWB_STREAMS 1
+#endif
+inline bool hwb_streams(const Geom &g) {
+  return IH_HWB_STREAMS && g.layout == IH_HWB && !g.mom && !g.diff && !g.cum && g.coord == 0 && g.P <= 32 &&
+         (g.TW == 16 || g.TW == 32);
+}
+
 inline size_t staged_lds(const Geom &g) {
   if (!IH_HWB_STAGED || g.layout != IH_HWB) return 0;
   const int nchunk = (g.P + 63) / 64;
@@ -1263,6 +1274,98 @@ __device__ __forceinline__ void final_hwb_wave_staged_body(const FinalArgs &a, c
   }
 }
 
+// 3d'. The wave-staged planes-innermost write-out for P <= 32 planes: the wavefront splits
+//      into S = 64 / P2 column streams (P2 the power of two >= P; lane =
+//      stream * P2 + plane), each owning a run of TW / S consecutive columns
+//      of the tile, so a row takes TW / S steps instead of TW.  Each stream
+//      counts its run's hits, an exclusive scan of those counts across the
+//      streams (lanes P2 apart) gives each run the row prefix at its start,
+//      and the run is then accumulated and staged; the tile's top boundary
+//      is assembled the same way from the column carries.
+template <int S>
+__device__ __forceinline__ uint32_t stream_excl_scan(uint32_t v, int lane, int q, int p2) {
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < S; d <<= 1) {
+    const uint32_t t = (uint32_t)__builtin_amdgcn_ds_bpermute(((lane - d * p2) & 63) << 2, (int)incl);
+    if (q >= d) incl += t;
+  }
+  return incl - v;
+}
+
+template <typename T, int TW, int S, int WK = 0>
+__device__ __forceinline__ void final_hwb_wave_streams_body(const FinalArgs &a, const Geom &g, int64_t tile,
+                                                            uint32_t *lds) {
+  constexpr int L = TW / S, P2 = 64 / S;
+  const int lane = threadIdx.x & 63;
+  if (tile >= (int64_t)g.nTR * g.nTC) return;
+  const int q = lane / P2, pl = lane % P2;
+  const bool live = pl < g.P;
+  const int p = min(pl, g.P - 1);  // lanes past the last plane repeat it
+  const int ch = p / g.bins;
+  const int k = p - ch * g.bins;
+  const int j = (int)(tile % g.nTC), I = (int)(tile / g.nTC);
+  const int R0 = I * g.TH, C0 = j * TW;
+  const int cols = min(TW, g.W - C0), rows = min(g.TH, g.H - R0);
+  const int cs = q * L;  // the stream's first column in the tile
+  const uint32_t lo = (uint32_t)((((uint64_t)k << a.bits) + g.bins - 1) / g.bins);
+  const uint32_t width = (uint32_t)((((uint64_t)(k + 1) << a.bits) + g.bins - 1) / g.bins) - lo;
+  const T *img = reinterpret_cast<const T *>(a.img) + (int64_t)ch * g.H * g.W;
+  const int64_t P = g.P;
+  uint32_t col[L];
+  {
+    uint32_t v[L], sum = 0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      v[i] = cs + i < cols ? cget(g, a.ws, g.off_cc, ((int64_t)I * g.W + C0 + cs + i) * P + p) : 0u;
+      sum += v[i];
+    }
+    uint32_t run = a.ws[g.off_tt + ((int64_t)p * g.nTR + I) * g.nTC + j] + stream_excl_scan<S>(sum, lane, q, P2);
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      run += v[i];
+      col[i] = run;
+    }
+  }
+  const int64_t lc = (((int64_t)ch * g.nTC + j) * g.H) * g.bins + k;  // in the RC array
+  const bool vec = (g.P & 3) == 0 && ((uintptr_t)a.ih & 15) == 0;
+  const int nseg = cols * g.P;
+  uint32_t pxn[L], wn[WK ? L : 1], rcn = 0, bad = 0;
+  auto fetch = [&](int r) {
+    const T *row = img + (int64_t)r * g.W + C0 + cs;
+#pragma unroll
+    for (int i = 0; i < L; ++i) pxn[i] = cs + i < cols ? (uint32_t)row[i] : 0u;
+    if constexpr (WK != 0) {
+#pragma unroll
+      for (int i = 0; i < L; ++i) wn[i] = cs + i < cols ? pixel_weight_of<WK>(a, g, ch, r, C0 + cs + i) : 0u;
+    }
+    rcn = cget(g, a.ws, g.off_rc, lc + (int64_t)r * g.bins);
+  };
+  if (rows > 0) fetch(R0);
+  for (int rr = 0; rr < rows; ++rr) {
+    const int r = R0 + rr;
+    uint32_t h[L], n = 0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      if constexpr (WK == 0) bad |= pxn[i] >> a.bits;
+      h[i] = (cs + i < cols && (pxn[i] - lo) < width) ? (WK ? wn[i] : 1u) : 0u;
+      n += h[i];
+    }
+    uint32_t rc = rcn + stream_excl_scan<S>(n, lane, q, P2);
+    if (rr + 1 < rows) fetch(r + 1);
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      rc += h[i];
+      col[i] += rc;
+      if (live && cs + i < cols) lds[(cs + i) * g.P + p] = col[i];
+    }
+    wave_sync();
+    copy_out(a.ih + ((int64_t)r * g.W + C0) * P, lds, nseg, vec, lane, 64);
+    wave_sync();
+  }
+  if constexpr (WK == 0) report_range(a.status, bad);
+}
+
 template <typename T, int TW, bool MOM, int WK = 0>
 __device__ __forceinline__ void final_hwb_staged_body(const FinalArgs &a, const Geom &g, int64_t tile,
                                                       uint32_t *lds) {
@@ -1580,6 +1683,14 @@ __global__ __launch_bounds__(256) void k_final_strip(FinalArgs a, Geom g) {
 template <typename T, int TW, bool MOM, int WK>
 __global__ __launch_bounds__(256) void k_final_hwb(FinalArgs a, Geom g) {
   final_hwb_body<T, TW, MOM, WK>(a, g, (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform(threadIdx.x >> 6));
+}
+
+// Four tiles a block, one wavefront each, in column streams (3d').
+template <typename T, int TW, int S, int WK>
+__global__ __launch_bounds__(256) void k_final_hwb_streams(FinalArgs a, Geom g) {
+  extern __shared__ uint32_t seg[];
+  const int wave = uniform((int)(threadIdx.x >> 6));
+  final_hwb_wave_streams_body<T, TW, S, WK>(a, g, (int64_t)blockIdx.x * 4 + wave, seg + wave * TW * 64);
 }
 
 template <typename T, int TW, bool MOM, int WK>
