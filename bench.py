@@ -1075,7 +1075,7 @@ def tracker_leg(torch, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
+        print("bench.py measures one GPU only: the library runs on a single MI355X and has no "
               "multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

@@ -1,6 +1,6 @@
 """Tracker with exhaustive and learned candidate search on a synthetic video.
 
-The exhaustive search is the judge: its per-frame result is checked against
+The exhaustive search is the reference: its per-frame result is checked against
 the oracle's candidate search, and the learned search is measured by how
 often it reaches the same window.
 """
