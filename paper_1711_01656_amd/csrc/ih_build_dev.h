@@ -87,7 +87,8 @@ inline size_t staged_lds(const Geom &g) {
 // Tile pass of a plain count build (with or without coordinate moments),
 // from the tile's bins staged in LDS: per-column counts over the tile's rows,
 // per-row counts over its columns and per-bin tile totals, counted in
-// registers four bins at a time (compares and adds, no histogram atomics),
+// registers four bins at a time (byte-parallel compares and adds, no
+// histogram atomics; coordinate moments from the same match flags),
 // each LDS word read bringing four bins.  Threads take (four columns or a
 // row, chunk of four bins) in the order that makes the stores coalesce:
 // column groups fastest for bin-major column carries (unit stride along
@@ -181,19 +182,44 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
           for (int e = 0; e < 4; ++e) n[e][kk] += (acc[kk] >> (8 * e)) & 0xffu;
       }
     } else {
-#pragma unroll 4
-      for (int r = 0; r < th; ++r) {
-        const uint32_t word = *reinterpret_cast<const uint32_t *>(col + r * twp);
+      // as above, and the tile-local row index summed per column in two
+      // 16-bit halves (columns 0 and 2, columns 1 and 3): a tile has at most
+      // 256 rows, so a half holds at most 255 * 256 / 2 < 2^16; the tile's
+      // first row R0 times the count is added at the end
+      uint32_t kl[NB], ax02[NB], ax13[NB];
+      const uint32_t flip = swar_flip(k0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int b = (int)((word >> (8 * e)) & 0xffu) - k0;
+      for (int kk = 0; kk < NB; ++kk) {
+        kl[kk] = swar_key(k0 + kk);
+        ax02[kk] = 0u;
+        ax13[kk] = 0u;
+      }
+      for (int r0 = 0; r0 < th; r0 += 128) {
+        const int r1 = min(th, r0 + 128);
+        uint32_t acc[NB] = {0u, 0u, 0u, 0u};
+#pragma unroll 4
+        for (int r = r0; r < r1; ++r) {
+          const uint32_t word = *reinterpret_cast<const uint32_t *>(col + r * twp);
+          const uint32_t lo = word & 0x7f7f7f7fu, hi = (word & 0x80808080u) ^ flip;
 #pragma unroll
           for (int kk = 0; kk < NB; ++kk) {
-            const uint32_t hit = b == kk ? 1u : 0u;
-            n[e][kk] += hit;
-            nx[e][kk] += hit * (uint32_t)(R0 + r);
+            const uint32_t m = swar_match(lo, hi, kl[kk]) >> 7;
+            acc[kk] += m;
+            ax02[kk] += __umul24(m & 0x00010001u, (uint32_t)r);
+            ax13[kk] += __umul24((m >> 8) & 0x00010001u, (uint32_t)r);
           }
         }
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) n[e][kk] += (acc[kk] >> (8 * e)) & 0xffu;
+      }
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk) {
+        nx[0][kk] = n[0][kk] * (uint32_t)R0 + (ax02[kk] & 0xffffu);
+        nx[1][kk] = n[1][kk] * (uint32_t)R0 + (ax13[kk] & 0xffffu);
+        nx[2][kk] = n[2][kk] * (uint32_t)R0 + (ax02[kk] >> 16);
+        nx[3][kk] = n[3][kk] * (uint32_t)R0 + (ax13[kk] >> 16);
       }
     }
     const int64_t p0 = (int64_t)ch * g.bins + k0;
@@ -253,18 +279,24 @@ __device__ __forceinline__ void tile_counts_fast(const Geom &g, const uint8_t *b
         for (int kk = 0; kk < NB; ++kk) n[kk] += (uint32_t)__builtin_popcount(swar_match(lo, hi, kl[kk]));
       }
     } else {
+      // as above; the matches' column offsets within the word, sum of e over
+      // the matching bytes e, come from one 24-bit product: with the flags of
+      // bytes 1-3 as u = b1 + b2 2^8 + b3 2^16, byte 2 of u * 0x010203 is
+      // b1 + 2 b2 + 3 b3 (no byte of the product exceeds 6, so none carries)
+      uint32_t kl[NB];
+      const uint32_t flip = swar_flip(k0);
+#pragma unroll
+      for (int kk = 0; kk < NB; ++kk) kl[kk] = swar_key(k0 + kk);
 #pragma unroll 4
       for (int c = 0; c < tw4; c += 4) {
         const uint32_t word = *reinterpret_cast<const uint32_t *>(row + c);
+        const uint32_t lo = word & 0x7f7f7f7fu, hi = (word & 0x80808080u) ^ flip;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int b = (int)((word >> (8 * e)) & 0xffu) - k0;
-#pragma unroll
-          for (int kk = 0; kk < NB; ++kk) {
-            const uint32_t hit = b == kk ? 1u : 0u;
-            n[kk] += hit;
-            ny[kk] += hit * (uint32_t)(C0 + c + e);
-          }
+        for (int kk = 0; kk < NB; ++kk) {
+          const uint32_t m = swar_match(lo, hi, kl[kk]);
+          const uint32_t pc = (uint32_t)__builtin_popcount(m);
+          n[kk] += pc;
+          ny[kk] += pc * (uint32_t)(C0 + c) + ((__umul24(m >> 15, 0x010203u) >> 16) & 0xffu);
         }
       }
     }
