@@ -229,7 +229,9 @@ def test_build_register_tile_pass(layout, H, W, bins, bits, tile):
 def test_build_register_tile_pass_saturated_columns(layout, tile, bins, fill):
     """A nearly constant image, so that one bin takes (almost) every pixel of a
     tile column and row: the register tile pass's per-column byte counters
-    reach their largest values; against the oracle."""
+    reach their largest values, and with moments (bin-major tiles) so do its
+    per-column sums of the tile-local row (up to 255 * 256 / 2 in a 16-bit
+    half); against the oracle."""
     ih = ihlib()
     H, W = 515, 389
     rng = np.random.default_rng(bins + fill)
@@ -244,6 +246,12 @@ def test_build_register_tile_pass_saturated_columns(layout, tile, bins, fill):
     if layout == "hwb":
         got = got.transpose(2, 0, 1)
     assert np.array_equal(got, ref)
+    if layout == "bhw":
+        o, mx, my = ih.ih_build(gpu(img), bins, 8, cfg=ih.TileCfg(th, tw, pg, 3), layout=layout, moments=True)
+        omx, omy = oracle.moments(img, bins, 8)
+        assert np.array_equal(o.cpu().numpy(), ref)
+        assert np.array_equal(mx.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, np.asarray(omx).astype(np.int64) & 0xFFFFFFFF)
+        assert np.array_equal(my.cpu().numpy().astype(np.int64) & 0xFFFFFFFF, np.asarray(omy).astype(np.int64) & 0xFFFFFFFF)
 
 
 @pytest.mark.parametrize("W,bins,tile", [
