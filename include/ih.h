@@ -383,8 +383,20 @@ typedef enum {
  *   mode       ih_batch_mode; both produce identical results.
  * Phases: tile histograms, carry scans, write-out, template descriptors,
  * candidate scoring, best candidate; each phase of a frame depends only on
- * earlier phases of the same frame.  The phased mode allocates and
- * synchronises nothing and may be captured in a HIP graph.  The cooperative
+ * earlier phases of the same frame.  The phased mode allocates no memory,
+ * synchronises nothing and may be captured in a HIP graph.  When the plan has
+ * frames of several write-out classes (bin-major tiles, bin-major strips,
+ * planes innermost, planes innermost in column streams), the write-out phase
+ * runs each class's kernel as a branch of its own: the first on stream, the
+ * others on up to three auxiliary streams (default priority) that the
+ * library creates once per device, on the first call whose stream is not
+ * being captured, and keeps until the process ends; the branches are forked
+ * from and joined back into stream with events, so all work stays ordered
+ * with stream.  Before those streams exist the classes run one after another
+ * on stream.  Every call on a device shares them: the enqueueing of that
+ * phase is serialised between host threads, and a call on one thread while
+ * another thread captures a batch on the same device may fail with an
+ * error.  The cooperative
  * mode returns IH_ERR_UNSUPPORTED, enqueuing nothing, when the stream is
  * capturing: a captured cooperative launch becomes a plain kernel node whose
  * grid barrier has no co-residency guarantee.

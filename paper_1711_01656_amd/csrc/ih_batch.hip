@@ -13,6 +13,8 @@
 // The unit bodies are the same device code as the stand-alone kernels.
 #include "ih_batch_dev.h"
 
+#include <mutex>
+
 namespace ih {
 
 // pf[ph][l]: the phase-ph kernel for frames of layout l (phases 2 and 4 have
@@ -41,6 +43,43 @@ static void pick_t(int metric, phase_fn (*pf)[4]) {
 }
 
 static size_t a64(size_t w) { return (w + 63) & ~(size_t)63; }
+
+// Auxiliary streams (default priority) and events that let the write-out
+// classes of a phased batch run as parallel branches of the caller's stream;
+// created once per device, outside stream capture, and kept until the process
+// ends.  The mutex makes each fork-launch-join sequence atomic with respect
+// to other host threads, which share these events.
+#ifndef IH_BATCH_BRANCHES
+#define IH_BATCH_BRANCHES 1  // 0: the write-out classes run one after another
+#endif
+constexpr int kAuxDevs = 64, kAux = 3;
+struct AuxStreams {
+  bool ok, failed;
+  hipStream_t s[kAux];
+  hipEvent_t fork, join[kAux];
+};
+static AuxStreams g_aux[kAuxDevs];
+static std::mutex g_aux_mu;
+
+// Returns the device's auxiliary streams, creating them unless the caller's
+// stream is being captured; nullptr when they are not available (the write-out
+// classes then run one after another on the caller's stream).  Call with
+// g_aux_mu held.
+static const AuxStreams *aux_streams(int dev, bool capturing) {
+  if (dev < 0 || dev >= kAuxDevs) return nullptr;
+  AuxStreams &x = g_aux[dev];
+  if (x.ok) return &x;
+  if (x.failed || capturing) return nullptr;
+  x.failed = true;  // until every object below exists
+  for (int i = 0; i < kAux; ++i)
+    if (hipStreamCreateWithFlags(&x.s[i], hipStreamNonBlocking) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+  for (int i = 0; i < kAux; ++i)
+    if (hipEventCreateWithFlags(&x.join[i], hipEventDisableTiming) != hipSuccess) return nullptr;
+  x.failed = false;
+  x.ok = true;
+  return &x;
+}
 
 }  // namespace ih
 
@@ -193,9 +232,24 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
   uint32_t *w32 = reinterpret_cast<uint32_t *>(ws);
   int per_cu = 0;
   if (mode == IH_BATCH_PHASED) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if ((e = hip_check(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing"))) return e;
+    int nclass = 0;
+    for (int l = 0; l < 4; ++l) nclass += (h->wclasses >> l) & 1;
     for (int ph = 0; ph < NPH; ++ph) {
       const int64_t units = h->phase_start[ph + 1] - h->phase_start[ph];
       if (units == 0) continue;
+      // several write-out classes: the first on the caller's stream, the
+      // others on auxiliary streams forked after the carry scans and joined
+      // before the next phase (they write disjoint frames)
+      std::unique_lock<std::mutex> lk(g_aux_mu, std::defer_lock);
+      const AuxStreams *ax = nullptr;
+      if (IH_BATCH_BRANCHES && ph == 2 && nclass > 1) {
+        lk.lock();
+        ax = aux_streams(dev, cs != hipStreamCaptureStatusNone);
+        if (ax && (e = hip_check(hipEventRecord(ax->fork, s), "fork event"))) return e;
+      }
+      int branch = 0;
       for (int l = 0; l < 4; ++l) {
         const bool split = pf[ph][1] != nullptr;
         if (!split && l > 0) break;
@@ -210,9 +264,18 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
         if (per_cu < 1) return set_error(IH_ERR_UNSUPPORTED, "batch phase %d cannot be resident", ph);
         const int64_t resident = (int64_t)per_cu * cus;
         const int64_t blocks = units < 4 * resident ? units : 4 * resident;
-        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds_k, s, hd, fd, w32);
+        hipStream_t sk = s;
+        if (ax && branch > 0) {
+          sk = ax->s[branch - 1];
+          if ((e = hip_check(hipStreamWaitEvent(sk, ax->fork, 0), "fork wait"))) return e;
+        }
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds_k, sk, hd, fd, w32);
         if ((e = hip_check(hipGetLastError(), "batch phase launch"))) return e;
+        if (ax && branch > 0 && (e = hip_check(hipEventRecord(ax->join[branch - 1], sk), "join event"))) return e;
+        if (ax) ++branch;
       }
+      for (int b = 1; ax && b < branch; ++b)
+        if ((e = hip_check(hipStreamWaitEvent(s, ax->join[b - 1], 0), "join wait"))) return e;
     }
     return IH_OK;
   }
@@ -224,9 +287,9 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
   // node, whose grid barrier then has no co-residency guarantee, so the
   // cooperative mode refuses to be captured (the phased mode is the one to
   // capture in a graph).
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if ((e = hip_check(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing"))) return e;
-  if (cs != hipStreamCaptureStatusNone)
+  hipStreamCaptureStatus ccs = hipStreamCaptureStatusNone;
+  if ((e = hip_check(hipStreamIsCapturing(s, &ccs), "hipStreamIsCapturing"))) return e;
+  if (ccs != hipStreamCaptureStatusNone)
     return set_error(IH_ERR_UNSUPPORTED,
                      "the cooperative batch launch cannot be captured in a graph (capture the phased mode)");
   return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(cf), dim3((unsigned)resident),
