@@ -163,6 +163,51 @@ def test_batch_graph_replays(layout):
 
 
 @pytest.mark.parametrize("layout", ["bhw", "hwb"])
+def test_batch_64_graph_replays_parallel_classes(layout):
+    """The 64 uneven frames hold two write-out classes in either layout
+    (planes innermost staged and in column streams; bin-major tiles and
+    strips), whose kernels run as parallel branches forked from and joined
+    into the caller's stream.  A graph captured from that stream, replayed
+    with eager work in between, reproduces the eager histograms, distances
+    and picks bit for bit (the eager batch is checked against the oracle in
+    test_batch_64_uneven_frames)."""
+    ih = ihlib()
+    say("64 uneven frames, graph replays", layout)
+    fr4 = synth.config4()
+    frames = []
+    for f in fr4:
+        frames.append(dict(np_img=f.img, img=gpu(f.img), bins=f.bins, value_bits=f.bits,
+                           np_origins=f.origins, origins=gpu(f.origins), win=(32, 32), tmpl_win=f.tmpl_win))
+    batch = ih.Batch(frames, "chi2", layout=layout)
+    batch.run()
+    torch.cuda.synchronize()
+    ref_ih = [t.clone() for t in batch.ih]
+    ref_d = [d.clone() for d in batch.dist]
+    ref_b = [b.clone() for b in batch.best]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.run()
+    for rep in range(3):
+        for t in batch.ih:                      # eager work between replays
+            t.fill_(-5)
+        for d in batch.dist:
+            d.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(frames)):
+            assert torch.equal(batch.ih[i], ref_ih[i]), (rep, i)
+            assert torch.equal(batch.dist[i], ref_d[i]), (rep, i)
+            assert torch.equal(batch.best[i], ref_b[i]), (rep, i)
+
+
+@pytest.mark.parametrize("layout", ["bhw", "hwb"])
 def test_batch_64_uneven_frames(layout):
     ih = ihlib()
     say("64 uneven frames, 4096 candidates each", layout)
