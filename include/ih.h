@@ -387,7 +387,8 @@ typedef enum {
  * synchronises nothing and may be captured in a HIP graph.  When the plan has
  * frames of several write-out classes (bin-major tiles, bin-major strips,
  * planes innermost, planes innermost in column streams), the write-out phase
- * runs each class's kernel as a branch of its own: the first on stream, the
+ * runs each class's kernel as a branch of its own, and so does the scoring
+ * phase for each layout when the plan has both: the first on stream, the
  * others on up to three auxiliary streams (default priority) that the
  * library creates once per device, on the first call whose stream is not
  * being captured, and keeps until the process ends; the branches are forked

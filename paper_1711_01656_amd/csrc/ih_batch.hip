@@ -50,7 +50,7 @@ static size_t a64(size_t w) { return (w + 63) & ~(size_t)63; }
 // ends.  The mutex makes each fork-launch-join sequence atomic with respect
 // to other host threads, which share these events.
 #ifndef IH_BATCH_BRANCHES
-#define IH_BATCH_BRANCHES 1  // 0: the write-out classes run one after another
+#define IH_BATCH_BRANCHES 2  // 0: none; 1: write-out classes only; 2: also the scoring layouts
 #endif
 constexpr int kAuxDevs = 64, kAux = 3;
 struct AuxStreams {
@@ -234,17 +234,20 @@ extern "C" int ih_build_batch(const void *plan_host, const void *plan_dev, void 
   if (mode == IH_BATCH_PHASED) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if ((e = hip_check(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing"))) return e;
-    int nclass = 0;
-    for (int l = 0; l < 4; ++l) nclass += (h->wclasses >> l) & 1;
+    int nclass = 0, nlay = 0;
+    for (int l = 0; l < 4; ++l) {
+      nclass += (h->wclasses >> l) & 1;
+      nlay += (h->layouts >> l) & 1;
+    }
     for (int ph = 0; ph < NPH; ++ph) {
       const int64_t units = h->phase_start[ph + 1] - h->phase_start[ph];
       if (units == 0) continue;
-      // several write-out classes: the first on the caller's stream, the
-      // others on auxiliary streams forked after the carry scans and joined
-      // before the next phase (they write disjoint frames)
+      // several write-out classes (or scoring layouts): the first on the
+      // caller's stream, the others on auxiliary streams forked after the
+      // previous phase and joined before the next (they write disjoint frames)
       std::unique_lock<std::mutex> lk(g_aux_mu, std::defer_lock);
       const AuxStreams *ax = nullptr;
-      if (IH_BATCH_BRANCHES && ph == 2 && nclass > 1) {
+      if ((IH_BATCH_BRANCHES >= 1 && ph == 2 && nclass > 1) || (IH_BATCH_BRANCHES >= 2 && ph == 4 && nlay > 1)) {
         lk.lock();
         ax = aux_streams(dev, cs != hipStreamCaptureStatusNone);
         if (ax && (e = hip_check(hipEventRecord(ax->fork, s), "fork event"))) return e;
